@@ -1,0 +1,160 @@
+"""Throughput of the RQC amplitude contraction on one MI355X.
+
+Workload (default): 7x7 grid, depth 1+32+1 (bond dimension 16 on every link), the quadrant
+plan with 2 cut bonds (256 slices, all summed: fidelity 1), a 6-qubit open batch (64
+amplitudes per bit-string), complex64 arithmetic.  One step = one contraction call over the
+next `--bitstrings` bit-strings of a seeded set of 1024, every slice included.
+
+Prints one JSON line: amplitudes/s (whole job), sustained TFLOP/s of the plan, the roofline of
+the dominant kernel measured with HIP events around its launches in the timed region, and the
+CPU oracle timed on a bounded sample of the same work.
+
+    python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--bitstrings 4]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"mfma": (157.3, "TFLOP/s"), "alu": (78.6, "TFLOP/s"), "hbm": (8000.0, "GB/s")}
+
+
+def kernel_bound(name):
+    if name.startswith("gemm_mfma"):
+        return "mfma"
+    if name.startswith("gemm_simt"):
+        return "alu"
+    return "hbm"
+
+
+def roofline(prof):
+    name = max(prof, key=lambda k: prof[k]["ms"])
+    k = prof[name]
+    bound = kernel_bound(name)
+    peak, unit = PEAK[bound]
+    if bound == "hbm":
+        achieved = k["bytes"] / (k["ms"] * 1e-3) / 1e9
+    else:
+        achieved = k["flops"] / (k["ms"] * 1e-3) / 1e12
+    return name, {"bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": unit,
+                  "frac": round(achieved / peak, 4), "traffic": None}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--bitstrings", type=int, default=4, help="bit-strings per step")
+    ap.add_argument("--cpu-slices", type=int, default=3, help="oracle sample size (slices)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import rqc_inputs as R
+    from paper_1811_09599_amd import build_grid, plan_describe
+
+    torch.cuda.set_device(0)
+    rows = cols = 7
+    depth = 32
+    circ = R.grid_rqc(rows, cols, depth, 2000)
+    open_q = R.grid_ids((rows, cols), [(5, 0), (5, 1), (5, 2), (6, 0), (6, 1), (6, 2)])
+    all_bits = R.bitstrings(rows * cols, 1024, 2500, open_q)
+    plan = plan_describe(circ, open_qubits=open_q)
+    t0 = time.time()
+    grid = build_grid(circ, open_qubits=open_q)
+    torch.cuda.synchronize()
+    build_s = time.time() - t0
+    B = args.bitstrings
+    out = torch.empty((B, 64), dtype=torch.complex128, device="cuda")
+
+    def step(i):
+        lo = (i * B) % 1024
+        grid.contract_amplitudes(all_bits[lo:lo + B], out=out)
+        return grid.last_stats()["flops"]
+
+    for i in range(args.warmup):
+        step(i)
+    torch.cuda.synchronize()
+    grid.set_profiling(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    flops = 0.0
+    for i in range(args.steps):
+        flops += step(args.warmup + i)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = grid.profile_read()
+    grid.set_profiling(False)
+    amps = args.steps * B * 64
+    dom, roof = roofline(prof)
+    kernels = {k: {"launches": v["launches"], "ms": round(v["ms"], 3),
+                   "avg_us": round(1e3 * v["ms"] / max(v["launches"], 1), 3),
+                   "tflops": round(v["flops"] / max(v["ms"], 1e-9) / 1e9, 3),
+                   "gbps": round(v["bytes"] / max(v["ms"], 1e-9) / 1e6, 1)}
+               for k, v in sorted(prof.items(), key=lambda kv: -kv[1]["ms"])}
+    res = {
+        "metric": "amplitudes/s", "value": amps / dt, "unit": "amplitudes/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * dt / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "c64",
+        "data": "synthetic",
+        "config": {"workload": "7x7 RQC depth 1+32+1 (bond dim 16), quadrant plan with 2 cuts "
+                               "(256 slices, fidelity 1), 6-qubit open batch (64 amplitudes "
+                               "per bit-string), %d bit-strings per step" % B,
+                   "grid": "7x7", "depth": "1+32+1", "slices": plan["num_slices"],
+                   "fidelity": 1.0, "amplitudes_per_bitstring": 64, "bitstrings_per_step": B,
+                   "plan_flops_per_bitstring": plan["flops_all_slices"], "precision": "c64"},
+        "tflops": flops / dt / 1e12,
+        "tflops_frac_fp32_mfma_peak": flops / dt / 1e12 / PEAK["mfma"][0],
+        "dominant_kernel": dom, "roofline": roof, "kernels": kernels,
+        "grid_build_s": build_s,
+    }
+    if not args.no_cpu_baseline:
+        res.update(cpu_baseline(circ, grid, all_bits[:1], open_q, args.cpu_slices, rows, cols))
+    print(json.dumps(res), flush=True)
+
+
+def cpu_baseline(circ, grid, bits, open_q, n_slices, rows, cols):
+    """The FP64 oracle (E2) on a bounded sample: n_slices slices of one bit-string batch,
+    extrapolated to all slices; plus the GPU-vs-oracle error on the same slices."""
+    import numpy as np
+    import torch
+
+    from oracle import metrics
+    from oracle import tn as E2
+
+    S = grid.num_slices()
+    ids = sorted(set(int(round(x)) for x in np.linspace(0, S - 1, n_slices)))
+    cuts = grid.plan_cuts()
+    net = E2.Network(circ)
+    t0 = time.perf_counter()
+    with torch.no_grad():
+        ref = net.amplitudes(bits, open_q, cuts=cuts, slice_ids=ids,
+                             order=E2.quadrant_order(rows, cols)).numpy()
+    dt = time.perf_counter() - t0
+    gpu = grid.contract_amplitudes(bits, slice_ids=ids).cpu().numpy()
+    err = metrics.amp_errors(gpu, ref, rows * cols)
+    per_slice = dt / len(ids)
+    rate = 64.0 / (per_slice * S)
+    return {"cpu_baseline": {"value": rate, "unit": "amplitudes/s",
+                             "cores": torch.get_num_threads(), "kind": "oracle",
+                             "sample": "%d of %d slices of one 64-amplitude batch (FP64 tensor "
+                                       "network, no reuse across slices), %.1f s; rate "
+                                       "extrapolated to all %d slices" % (len(ids), S, dt, S)},
+            "parity": {"slices": ids, "amplitudes": int(gpu.size), "max_rel_err": err["max"],
+                       "median_rel_err": err["median"], "l2_rel_err": err["l2"],
+                       "tol": 1e-5}}
+
+
+if __name__ == "__main__":
+    main()

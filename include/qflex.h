@@ -1,0 +1,196 @@
+/*
+ * qflex.h - C ABI of an MI355X (gfx950) library that computes amplitudes of random quantum
+ * circuits (RQCs) on 2D qubit layouts by tensor-network contraction, after qFlex
+ * (Villalonga et al., "A flexible high-performance simulator for verifying and
+ * benchmarking quantum circuits implemented on real hardware", arXiv:1811.09599).
+ *
+ * What the calls compute (paper, Methods B and C.1):
+ *   - A circuit with input |0...0> and output bit-string x is a tensor network whose value is
+ *     the amplitude psi(x) = <x|U|0...0>.
+ *   - qflex_build_grid collapses each qubit's gates along time into one tensor per qubit
+ *     (Methods B.1: contraction in the time direction first, at negligible cost), leaving
+ *     the output bit of every qubit open so that one grid serves every bit-string.
+ *   - qflex_contract_amplitudes contracts the grid for given output bit-strings in a fixed
+ *     pairwise order.  Each pairwise step is an index permutation followed by a complex
+ *     matrix product (Methods B.2).  Cut bonds are fixed to explicit values ("paths") and
+ *     the amplitude is the sum over paths (Methods B.1, cutting indexes); summing a
+ *     fraction f of the paths yields fidelity-f amplitudes (Methods C.1, Eq. 1).  Qubits
+ *     listed as open keep their output bit free, giving a batch of 2^n_open amplitudes per
+ *     bit-string (Methods C.2 and SI A, fast sampling).
+ *
+ * Conventions
+ *   - Qubit q's output bit in a bit-string row is bits[q] (0 or 1).
+ *   - Two-qubit gate matrices are 4x4 in the basis |q0 q1> = 00, 01, 10, 11.
+ *   - The bond of a two-qubit gate is its decomposition G = sum_k A_k (x) B_k in the
+ *     elementary basis of the lower-id qubit: k in {0,1} (A_k = |k><k|) when both
+ *     off-diagonal 2x2 blocks of G are exactly zero, else k = 2i+j (A_k = |i><j|).  A link's
+ *     bond value is the mixed-radix index of its gates' k, earliest gate most significant.
+ *   - A slice (path) id is the mixed-radix index of the cut links' bond values, in the
+ *     order reported by qflex_plan_cuts (first cut most significant).
+ *   - The open-qubit batch index is big-endian over open_qubits in the order given.
+ *   - Amplitudes are complex128, interleaved (re, im).
+ *
+ * Ownership: the caller owns every input array; the library copies what it needs before a
+ * call returns.  A qflex_grid owns all device memory it allocates until qflex_grid_free.
+ * Output buffers are caller-allocated (device memory when *_on_device is 1, host memory
+ * otherwise).
+ *
+ * Errors: every call validates its arguments before launching any GPU work.  On a non-OK
+ * status, qflex_last_error() returns a message for the calling thread.  A grid handle may
+ * not be used from two threads at once; distinct handles may.
+ */
+#ifndef QFLEX_H
+#define QFLEX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  QFLEX_OK = 0,
+  QFLEX_E_INVALID = 1,     /* argument or circuit fails validation; nothing was launched */
+  QFLEX_E_PLAN = 2,        /* no contraction plan fits max_tensor_elems, or fidelity*slices
+                              is not an integer >= 1 */
+  QFLEX_E_NOMEM = 3,       /* a device or host allocation failed */
+  QFLEX_E_DEVICE = 4,      /* a HIP runtime error (also an asynchronous one from earlier work) */
+  QFLEX_E_UNSUPPORTED = 5  /* valid request this build does not implement */
+} qflex_status;
+
+typedef enum {
+  QFLEX_PREC_C64 = 0,        /* complex64 operands, FP32 MFMA, FP32 accumulation */
+  QFLEX_PREC_SPLIT_BF16 = 1, /* complex64 operands split into hi+lo bf16, FP32 accumulation */
+  QFLEX_PREC_SPLIT_FP16 = 2  /* hi + scaled lo fp16 parts, FP32 accumulation */
+} qflex_precision;
+
+/* Gate kinds (matrices as in the paper's Methods A; fSim as in the comment below). */
+typedef enum {
+  QFLEX_G_H = 0,    /* (1/sqrt2)[[1,1],[1,-1]] */
+  QFLEX_G_X12 = 1,  /* 1/2[[1+i,1-i],[1-i,1+i]] */
+  QFLEX_G_Y12 = 2,  /* 1/2[[1+i,-1-i],[1+i,1+i]] */
+  QFLEX_G_T = 3,    /* diag(1, e^{i pi/4}) */
+  QFLEX_G_CZ = 4,   /* diag(1,1,1,-1) */
+  QFLEX_G_FSIM = 5, /* [[1,0,0,0],[0,cos t,-i sin t,0],[0,-i sin t,cos t,0],[0,0,0,e^{-i phi}]] */
+  QFLEX_G_MAT1 = 6, /* explicit 2x2 matrix in qflex_gate.mat */
+  QFLEX_G_MAT2 = 7  /* explicit 4x4 matrix in qflex_gate.mat */
+} qflex_gate_kind;
+
+typedef enum {
+  QFLEX_PLAN_AUTO = 0,     /* SWEEP if it fits max_tensor_elems, else QUADRANT */
+  QFLEX_PLAN_SWEEP = 1,    /* absorb every qubit into one tensor, no cuts */
+  QFLEX_PLAN_QUADRANT = 2  /* four regions A|B over C|D, one cut between B and D in the last
+                              column and one between C and D in the last row (SI A) */
+} qflex_plan_kind;
+
+typedef struct {
+  int32_t cycle;     /* time step; gates of one cycle must act on disjoint qubits */
+  int32_t kind;      /* qflex_gate_kind */
+  int32_t q0, q1;    /* qubit ids; q1 = -1 for one-qubit gates */
+  double theta, phi; /* fSim angles in radians (QFLEX_G_FSIM only) */
+  const double* mat; /* MAT1: 2x2, MAT2: 4x4 complex128 interleaved row-major; else NULL */
+} qflex_gate;
+
+typedef struct {
+  int32_t n_qubits;         /* 1 .. 4096 */
+  const int32_t* xy;        /* [n_qubits][2] integer (row, col) coordinates, distinct; two
+                               qubits may share a gate only if they are at unit distance */
+  const qflex_gate* gates;  /* [n_gates] in any order */
+  int64_t n_gates;
+} qflex_circuit;
+
+typedef struct {
+  int32_t precision;         /* qflex_precision */
+  int32_t plan_kind;         /* qflex_plan_kind */
+  int64_t max_tensor_elems;  /* largest intermediate tensor per bit-string (0 = 2^30) */
+  const int32_t* open_qubits;/* qubits whose output bit stays open (may be NULL) */
+  int32_t n_open;            /* 0 .. 16; the same ids are used for every circuit */
+  int32_t bitstring_batch;   /* most bit-strings contracted together (0 = automatic) */
+} qflex_options;
+
+typedef struct qflex_grid qflex_grid;
+
+/* Statistics of the most recent contract call on a grid (algorithmic counts). */
+typedef struct {
+  double flops;          /* 8 real flops per complex multiply-add of every matrix product run */
+  double permute_bytes;  /* bytes read + written by index permutations */
+  int64_t n_gemm;        /* matrix products launched */
+  int64_t n_permute;     /* permutation kernels launched */
+  int64_t n_slices;      /* slices summed, over all circuits */
+  int64_t n_bitstrings;  /* bit-strings contracted, over all circuits */
+} qflex_stats;
+
+/* Validate circuits, plan their contractions, collapse every qubit's gates along time on the
+ * GPU and keep the per-qubit tensors in device memory.  stream: a hipStream_t (NULL = the
+ * null stream).  Returns QFLEX_E_INVALID for: n_circuits < 1, a NULL pointer, coordinates
+ * repeated, a qubit id out of range, a gate between qubits not at unit distance, a qubit used
+ * twice in one cycle, an unknown kind, a missing matrix, n_open > 16 or an open id out of
+ * range.  QFLEX_E_PLAN when no plan fits max_tensor_elems. */
+qflex_status qflex_build_grid(const qflex_circuit* circuits, int32_t n_circuits,
+                              const qflex_options* opt, void* stream, qflex_grid** out);
+
+/* Number of slices S (paths) of circuit `circuit`'s plan (1 when it has no cuts). */
+qflex_status qflex_num_slices(const qflex_grid* g, int32_t circuit, int64_t* total);
+
+/* Cut links of circuit `circuit`'s plan, in slice-radix order (first = most significant):
+ * pairs[2*i], pairs[2*i+1] = lower and higher qubit id of cut i.  At most max_cuts are
+ * written; *n_cuts receives the count. */
+qflex_status qflex_plan_cuts(const qflex_grid* g, int32_t circuit, int32_t* pairs,
+                             int32_t max_cuts, int32_t* n_cuts);
+
+/* Validate and plan one circuit without touching the GPU; writes a JSON description of the
+ * plan (cuts, steps with their matrix-product shapes, flops per bit-string, memory) into buf
+ * (NUL-terminated, truncated to len).  *needed receives the full length + 1. */
+qflex_status qflex_plan_describe(const qflex_circuit* circuit, const qflex_options* opt,
+                                 char* buf, int64_t len, int64_t* needed);
+
+/* Contract amplitudes.
+ *   bits        uint8 rows, concatenated per circuit: circuit c contributes
+ *               bs_offsets[c+1]-bs_offsets[c] rows of n_qubits(c) bytes each (host memory).
+ *   bs_offsets  [n_circuits+1] prefix offsets of bit-string rows (host memory).
+ *   fidelity    f in (0, 1]: k = f*S_c slices are summed for circuit c, chosen by SplitMix64
+ *               (seed slice_seed) driving a Fisher-Yates shuffle of [0, S_c): for i from
+ *               S_c-1 down to 1, j = next() mod (i+1), swap; the first k entries are used.
+ *               Ignored when slice_ids is given.
+ *   slice_ids, slice_offsets  optional explicit slice lists per circuit (host memory,
+ *               concatenated; slice_offsets has n_circuits+1 entries), else NULL.
+ *   amps        complex128 [total bit-strings][2^n_open] (device if amps_on_device).
+ * The sum over slices is accumulated in FP64. */
+qflex_status qflex_contract_amplitudes(qflex_grid* g, const uint8_t* bits,
+                                       const int64_t* bs_offsets, double fidelity,
+                                       uint64_t slice_seed, const int64_t* slice_ids,
+                                       const int64_t* slice_offsets, double* amps,
+                                       int32_t amps_on_device, void* stream);
+
+/* Statistics of the last contract call. */
+qflex_status qflex_last_stats(const qflex_grid* g, qflex_stats* out);
+
+/* Per-kernel timing of contract calls (tracing).  When enabled, every kernel launch of a
+ * contract call is bracketed by HIP events on the call's stream; the call then waits for its
+ * work to finish and adds each launch's duration to the statistics of its kernel.  Enabling
+ * clears the statistics. */
+typedef struct {
+  char name[48];     /* kernel name, e.g. "gemm_mfma_128x128_nn", "permute" */
+  int64_t launches;
+  double ms;         /* summed launch durations */
+  double flops;      /* algorithmic flops (8 per complex multiply-add) */
+  double bytes;      /* algorithmic bytes: operands read once + result written once */
+} qflex_kernel_stat;
+
+qflex_status qflex_set_profiling(qflex_grid* g, int32_t enable);
+
+/* Copy up to max entries of the per-kernel statistics; *n receives the number of kernels. */
+qflex_status qflex_profile_read(const qflex_grid* g, qflex_kernel_stat* out, int32_t max,
+                                int32_t* n);
+
+/* Release every resource of a grid (NULL is ignored).  Waits for its work to finish. */
+void qflex_grid_free(qflex_grid* g);
+
+/* Message for the calling thread's most recent non-OK status ("" if none). */
+const char* qflex_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QFLEX_H */

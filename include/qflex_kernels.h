@@ -1,0 +1,50 @@
+/*
+ * qflex_kernels.h - the two kernels of every pairwise contraction step of libqflex, exposed on
+ * their own (paper, Methods B.2: an index permutation that makes the contracted indexes
+ * contiguous, then a matrix multiplication), plus the seeded slice subset of Methods C.1.
+ *
+ * Pointers marked "device" are HIP device memory owned by the caller; complex64 values are
+ * interleaved (re, im) floats.  Every call checks its arguments on the host before launching
+ * and returns QFLEX_E_INVALID without launching anything when they are wrong.  Work is
+ * enqueued on `stream` (a hipStream_t, NULL = null stream) and is not waited for.
+ */
+#ifndef QFLEX_KERNELS_H
+#define QFLEX_KERNELS_H
+
+#include <stdint.h>
+
+#include "qflex.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Permute the binary indexes of `batch` tensors of 2^nbits complex64 elements each
+ * (row-major, batch-major, device).  perm[j] (j = 0 .. nbits-1, counted from the least
+ * significant bit) is the input bit position that becomes output bit position j:
+ * out[sum_j b_j 2^j] = in[sum_j b_j 2^perm[j]].  1 <= nbits <= 40, perm a permutation,
+ * 1 <= batch <= 65535, in and out must not overlap. */
+qflex_status qflex_permute_c64(const void* in, void* out, int32_t nbits, const int32_t* perm,
+                               int64_t batch, void* stream);
+
+/* Batched complex64 matrix product C[b] = op(A[b]) op(B[b]) with FP32 accumulation (device).
+ * A[b] is stored [M][K] (ta = 0) or [K][M] (ta = 1), B[b] is [K][N] (tb = 0) or [N][K]
+ * (tb = 1), C[b] is [M][N]; all row-major and densely packed, batch b at offset b*size.
+ * M, N, K >= 1, 1 <= batch <= 65535.  C must not overlap A or B. */
+qflex_status qflex_gemm_c64(const void* A, const void* B, void* C, int64_t M, int64_t N,
+                            int64_t K, int32_t ta, int32_t tb, int64_t batch, void* stream);
+
+/* Kernel variant qflex_gemm_c64 uses for a shape: 0 SIMT, 1 MFMA 64x64, 2 MFMA 128x128. */
+int32_t qflex_gemm_variant(int64_t M, int64_t N, int64_t K);
+
+/* The slice subset that qflex_contract_amplitudes sums for a fidelity (host only): writes up to
+ * max_ids ascending ids into ids and their count into *n.  QFLEX_E_INVALID if fidelity is
+ * outside (0, 1], QFLEX_E_PLAN if fidelity*total is not an integer >= 1. */
+qflex_status qflex_select_slices(int64_t total, double fidelity, uint64_t seed, int64_t* ids,
+                                 int64_t max_ids, int64_t* n);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QFLEX_KERNELS_H */

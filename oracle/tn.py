@@ -200,20 +200,28 @@ class Network:
             out[q] = (t, lab)
         return out
 
+    def _in_order(self, acc, items: dict, qs):
+        for q in qs:
+            acc = items[q] if acc is None else self._pair(acc, items[q])
+        return acc
+
     def contract(self, items: dict, order=None, open_qubits=()):
-        """Contract labelled tensors; ``order`` is a list of ("region"|"sweep", qubits):
-        a region is contracted on its own and then merged into the running result, a sweep
-        absorbs its qubits into the running result one by one."""
+        """Contract labelled tensors; ``order`` is a list of ("region"|"sweep", qubits[,
+        "fixed"]): a region is contracted on its own and then merged into the running result,
+        a sweep absorbs its qubits into the running result one by one.  Qubits are taken
+        smallest-result-first unless the segment is marked "fixed" (then in list order)."""
         if order is None:
             order = [("sweep", sorted(items))]
         acc = None
-        for kind, qs in order:
+        for seg in order:
+            kind, qs = seg[0], seg[1]
+            fixed = len(seg) > 2 and seg[2] == "fixed"
             sub = {q: items[q] for q in qs}
             if kind == "region":
-                r = self._sweep(None, sub)
+                r = self._in_order(None, sub, qs) if fixed else self._sweep(None, sub)
                 acc = r if acc is None else self._pair(acc, r)
             else:
-                acc = self._sweep(acc, sub)
+                acc = self._in_order(acc, sub, qs) if fixed else self._sweep(acc, sub)
         t, lab = acc
         want = ["o%d" % q for q in open_qubits]
         if sorted(lab) != sorted(want):
@@ -250,6 +258,22 @@ class Network:
             rows.append(acc)
         out = torch.stack([torch.as_tensor(r, dtype=CDT).reshape(-1) for r in rows])
         return out if open_qubits else out[:, 0]
+
+
+def quadrant_order(rows: int, cols: int):
+    """A contraction order for a rows x cols grid split into quadrants A|B over C|D at
+    (rows//2, cols//2), used only to bound memory (any order gives the same value): A row by
+    row; B from its right edge inwards, its first column last; D bottom-up, each row right to
+    left; finally C swept into the running result row by row, right to left."""
+    rs, cs = rows // 2, cols // 2
+    q = lambda r, c: r * cols + c  # noqa: E731
+    A = [q(r, c) for r in range(rs) for c in range(cs)]
+    B = [q(r, c) for r in range(rs) for c in range(cols - 1, cs, -1)] + \
+        [q(r, cs) for r in range(rs)]
+    D = [q(r, c) for r in range(rows - 1, rs - 1, -1) for c in range(cols - 1, cs - 1, -1)]
+    C = [q(r, c) for r in range(rs, rows) for c in range(cs - 1, -1, -1)]
+    return [("region", A, "fixed"), ("region", B, "fixed"), ("region", D, "fixed"),
+            ("sweep", C, "fixed")]
 
 
 def amplitudes(circ, bits, open_qubits=(), cuts=(), slice_ids=None, order=None):

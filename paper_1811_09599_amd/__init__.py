@@ -1,0 +1,6 @@
+"""MI355X (gfx950) amplitudes of random quantum circuits by sliced tensor-network contraction.
+
+The compute path is libqflex.so (HIP kernels behind the C ABI in include/qflex.h); this
+package only marshals arguments to it.  Nothing here falls back to a CPU implementation.
+"""
+from .qflex import Grid, build_grid, plan_describe  # noqa: F401

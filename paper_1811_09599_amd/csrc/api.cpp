@@ -1,0 +1,247 @@
+// C entry points: argument checks, status codes, thread-local error messages.
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "../../include/qflex_kernels.h"
+#include "grid.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+qflex_status set_error(qflex_status s, const std::string& m) {
+  g_last_error = m;
+  return s;
+}
+
+template <class F>
+qflex_status guarded(F&& f) {
+  try {
+    f();
+    g_last_error.clear();
+    return QFLEX_OK;
+  } catch (const qflex::Error& e) {
+    return set_error(e.status, e.what());
+  } catch (const std::bad_alloc&) {
+    return set_error(QFLEX_E_NOMEM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return set_error(QFLEX_E_DEVICE, e.what());
+  }
+}
+
+void release(qflex_grid* g) {
+  if (!g) return;
+  (void)hipDeviceSynchronize();
+  if (g->grid) (void)hipFree(g->grid);
+  if (g->bidx) (void)hipFree(g->bidx);
+  g->arena.release();
+  g->amps64.release();
+  g->offs.release();
+  g->offs_host.release();
+  if (g->offs_done) (void)hipEventDestroy(g->offs_done);
+  g->prof.release();
+  delete g;
+}
+
+void check_options(const qflex_options& o) {
+  if (o.precision != QFLEX_PREC_C64 && o.precision != QFLEX_PREC_SPLIT_BF16 &&
+      o.precision != QFLEX_PREC_SPLIT_FP16)
+    qflex::fail(QFLEX_E_INVALID, "unknown precision");
+  if (o.plan_kind < QFLEX_PLAN_AUTO || o.plan_kind > QFLEX_PLAN_QUADRANT)
+    qflex::fail(QFLEX_E_INVALID, "unknown plan_kind");
+  if (o.bitstring_batch < 0) qflex::fail(QFLEX_E_INVALID, "bitstring_batch < 0");
+}
+
+}  // namespace
+
+extern "C" {
+
+qflex_status qflex_build_grid(const qflex_circuit* circuits, int32_t n_circuits,
+                              const qflex_options* opt, void* stream, qflex_grid** out) {
+  if (out) *out = nullptr;
+  return guarded([&] {
+    if (!circuits || !opt || !out) qflex::fail(QFLEX_E_INVALID, "NULL argument");
+    if (n_circuits < 1) qflex::fail(QFLEX_E_INVALID, "n_circuits must be >= 1");
+    check_options(*opt);
+    auto* g = new qflex_grid();
+    try {
+      g->precision = opt->precision;
+      g->bitstring_batch = opt->bitstring_batch;
+      for (int c = 0; c < n_circuits; ++c) {
+        qflex::CircuitState cs;
+        cs.model = qflex::build_model(circuits[c]);
+        cs.plan = qflex::make_plan(cs.model, *opt);
+        g->circ.push_back(std::move(cs));
+      }
+      if (opt->precision != QFLEX_PREC_C64)
+        qflex::fail(QFLEX_E_UNSUPPORTED, "split-precision products are not built in");
+      int dev = 0;
+      hipError_t e = hipGetDevice(&dev);
+      if (e != hipSuccess) qflex::fail(QFLEX_E_DEVICE, std::string("no HIP device: ") + hipGetErrorString(e));
+      g->device = dev;
+      qflex::build_grid_device(g, static_cast<hipStream_t>(stream));
+    } catch (...) {
+      release(g);
+      throw;
+    }
+    *out = g;
+  });
+}
+
+qflex_status qflex_num_slices(const qflex_grid* g, int32_t circuit, int64_t* total) {
+  return guarded([&] {
+    if (!g || !total) qflex::fail(QFLEX_E_INVALID, "NULL argument");
+    if (circuit < 0 || circuit >= (int)g->circ.size()) qflex::fail(QFLEX_E_INVALID, "bad circuit");
+    *total = g->circ[circuit].plan.num_slices();
+  });
+}
+
+qflex_status qflex_plan_cuts(const qflex_grid* g, int32_t circuit, int32_t* pairs,
+                             int32_t max_cuts, int32_t* n_cuts) {
+  return guarded([&] {
+    if (!g || !n_cuts || (max_cuts > 0 && !pairs)) qflex::fail(QFLEX_E_INVALID, "NULL argument");
+    if (circuit < 0 || circuit >= (int)g->circ.size()) qflex::fail(QFLEX_E_INVALID, "bad circuit");
+    const auto& cs = g->circ[circuit];
+    *n_cuts = (int32_t)cs.plan.cuts.size();
+    for (int i = 0; i < (int)cs.plan.cuts.size() && i < max_cuts; ++i) {
+      pairs[2 * i] = cs.model.links[cs.plan.cuts[i]].lo;
+      pairs[2 * i + 1] = cs.model.links[cs.plan.cuts[i]].hi;
+    }
+  });
+}
+
+qflex_status qflex_plan_describe(const qflex_circuit* circuit, const qflex_options* opt,
+                                 char* buf, int64_t len, int64_t* needed) {
+  return guarded([&] {
+    if (!circuit || !opt) qflex::fail(QFLEX_E_INVALID, "NULL argument");
+    check_options(*opt);
+    qflex::Model m = qflex::build_model(*circuit);
+    qflex::Plan p = qflex::make_plan(m, *opt);
+    const std::string s = p.describe(m);
+    if (needed) *needed = (int64_t)s.size() + 1;
+    if (buf && len > 0) {
+      const size_t n = std::min<size_t>(s.size(), (size_t)len - 1);
+      std::memcpy(buf, s.data(), n);
+      buf[n] = '\0';
+    }
+  });
+}
+
+qflex_status qflex_contract_amplitudes(qflex_grid* g, const uint8_t* bits,
+                                       const int64_t* bs_offsets, double fidelity,
+                                       uint64_t slice_seed, const int64_t* slice_ids,
+                                       const int64_t* slice_offsets, double* amps,
+                                       int32_t amps_on_device, void* stream) {
+  return guarded([&] {
+    if (!g) qflex::fail(QFLEX_E_INVALID, "NULL grid");
+    qflex::contract(g, bits, bs_offsets, fidelity, slice_seed, slice_ids, slice_offsets, amps,
+                    amps_on_device != 0, static_cast<hipStream_t>(stream));
+  });
+}
+
+qflex_status qflex_last_stats(const qflex_grid* g, qflex_stats* out) {
+  return guarded([&] {
+    if (!g || !out) qflex::fail(QFLEX_E_INVALID, "NULL argument");
+    *out = g->last;
+  });
+}
+
+qflex_status qflex_set_profiling(qflex_grid* g, int32_t enable) {
+  return guarded([&] {
+    if (!g) qflex::fail(QFLEX_E_INVALID, "NULL grid");
+    g->prof.on = enable != 0;
+    g->prof.sums.clear();
+  });
+}
+
+qflex_status qflex_profile_read(const qflex_grid* g, qflex_kernel_stat* out, int32_t max,
+                                int32_t* n) {
+  return guarded([&] {
+    if (!g || !n || (max > 0 && !out)) qflex::fail(QFLEX_E_INVALID, "NULL argument");
+    *n = (int32_t)g->prof.sums.size();
+    int i = 0;
+    for (const auto& kv : g->prof.sums) {
+      if (i >= max) break;
+      qflex_kernel_stat& k = out[i++];
+      std::memset(&k, 0, sizeof(k));
+      std::strncpy(k.name, kv.first.c_str(), sizeof(k.name) - 1);
+      k.launches = kv.second.launches;
+      k.ms = kv.second.ms;
+      k.flops = kv.second.flops;
+      k.bytes = kv.second.bytes;
+    }
+  });
+}
+
+void qflex_grid_free(qflex_grid* g) { release(g); }
+
+qflex_status qflex_permute_c64(const void* in, void* out, int32_t nbits, const int32_t* perm,
+                               int64_t batch, void* stream) {
+  return guarded([&] {
+    if (!in || !out || !perm) qflex::fail(QFLEX_E_INVALID, "NULL argument");
+    if (nbits < 1 || nbits > 40) qflex::fail(QFLEX_E_INVALID, "nbits must be in [1, 40]");
+    if (batch < 1 || batch > 65535) qflex::fail(QFLEX_E_INVALID, "batch must be in [1, 65535]");
+    std::vector<int> p(perm, perm + nbits), seen(nbits, 0);
+    for (int v : p) {
+      if (v < 0 || v >= nbits || seen[v]) qflex::fail(QFLEX_E_INVALID, "perm is not a permutation");
+      seen[v] = 1;
+    }
+    const auto t = qflex::dev::make_perm_tile(nbits, p.data());
+    qflex::dev::permute(static_cast<const float2*>(in), static_cast<float2*>(out), batch, t,
+                        static_cast<hipStream_t>(stream));
+  });
+}
+
+qflex_status qflex_gemm_c64(const void* A, const void* B, void* C, int64_t M, int64_t N,
+                            int64_t K, int32_t ta, int32_t tb, int64_t batch, void* stream) {
+  return guarded([&] {
+    if (!A || !B || !C) qflex::fail(QFLEX_E_INVALID, "NULL argument");
+    if (M < 1 || N < 1 || K < 1) qflex::fail(QFLEX_E_INVALID, "M, N, K must be >= 1");
+    if (batch < 1 || batch > 65535) qflex::fail(QFLEX_E_INVALID, "batch must be in [1, 65535]");
+    if ((ta != 0 && ta != 1) || (tb != 0 && tb != 1)) qflex::fail(QFLEX_E_INVALID, "ta/tb must be 0 or 1");
+    qflex::dev::Gemm g;
+    g.A = static_cast<const float2*>(A);
+    g.B = static_cast<const float2*>(B);
+    g.C = static_cast<float2*>(C);
+    g.M = M;
+    g.N = N;
+    g.K = K;
+    g.ta = ta;
+    g.tb = tb;
+    g.lda = ta ? M : K;
+    g.ldb = tb ? K : N;
+    g.ldc = N;
+    g.a_bs = M * K;
+    g.b_bs = K * N;
+    g.c_bs = M * N;
+    g.batch = (int)batch;
+    if (qflex::dev::gemm_variant(g) > 0 &&
+        ((reinterpret_cast<uintptr_t>(A) | reinterpret_cast<uintptr_t>(B)) & 15))
+      qflex::fail(QFLEX_E_INVALID, "A and B must be 16-byte aligned");
+    qflex::dev::gemm(g, static_cast<hipStream_t>(stream));
+  });
+}
+
+int32_t qflex_gemm_variant(int64_t M, int64_t N, int64_t K) {
+  qflex::dev::Gemm g;
+  g.M = M;
+  g.N = N;
+  g.K = K;
+  return qflex::dev::gemm_variant(g);
+}
+
+qflex_status qflex_select_slices(int64_t total, double fidelity, uint64_t seed, int64_t* ids,
+                                 int64_t max_ids, int64_t* n) {
+  return guarded([&] {
+    if (!n || (max_ids > 0 && !ids)) qflex::fail(QFLEX_E_INVALID, "NULL argument");
+    if (total < 1 || total > (int64_t(1) << 32)) qflex::fail(QFLEX_E_INVALID, "total out of range");
+    const auto v = qflex::select_slices(total, fidelity, seed);
+    *n = (int64_t)v.size();
+    for (int64_t i = 0; i < (int64_t)v.size() && i < max_ids; ++i) ids[i] = v[i];
+  });
+}
+
+const char* qflex_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

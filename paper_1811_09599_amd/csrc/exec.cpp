@@ -1,0 +1,450 @@
+// Executor: builds the device grid and runs a plan over bit-strings and slices.
+//
+// Loop nest (paper, SI A): for each batch of bit-strings, for each selected slice in
+// ascending id order, re-run only the steps whose result depends on a cut whose value changed
+// since the previous slice; every other intermediate is reused from device memory.  The last
+// step's result is added into an FP64 amplitude accumulator after every slice.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "grid.h"
+
+namespace qflex {
+
+#define QHIP(expr)                                                                         \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      fail(e_ == hipErrorOutOfMemory ? QFLEX_E_NOMEM : QFLEX_E_DEVICE,                      \
+           std::string(#expr) + ": " + hipGetErrorString(e_));                              \
+  } while (0)
+
+void DevBuf::reserve(size_t n) {
+  if (n <= bytes) return;
+  if (p) {
+    QHIP(hipDeviceSynchronize());
+    QHIP(hipFree(p));
+    p = nullptr;
+    bytes = 0;
+  }
+  QHIP(hipMalloc(&p, n));
+  bytes = n;
+}
+
+void DevBuf::release() {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+  bytes = 0;
+}
+
+void HostPinned::reserve(size_t n) {
+  if (n <= bytes) return;
+  if (p) QHIP(hipHostFree(p));
+  p = nullptr;
+  bytes = 0;
+  QHIP(hipHostMalloc(&p, n, hipHostMallocDefault));
+  bytes = n;
+}
+
+void HostPinned::release() {
+  if (p) (void)hipHostFree(p);
+  p = nullptr;
+  bytes = 0;
+}
+
+// ------------------------------------------------------------------------------ profiler
+hipEvent_t Profiler::take() {
+  if (used == pool.size()) {
+    hipEvent_t e;
+    QHIP(hipEventCreate(&e));
+    pool.push_back(e);
+  }
+  return pool[used++];
+}
+
+void Profiler::begin(const char* name, double flops, double bytes, hipStream_t s) {
+  if (!on) return;
+  Rec r{name, take(), take(), flops, bytes};
+  QHIP(hipEventRecord(r.a, s));
+  pending.push_back(r);
+}
+
+void Profiler::end(hipStream_t s) {
+  if (!on) return;
+  QHIP(hipEventRecord(pending.back().b, s));
+}
+
+void Profiler::resolve() {
+  for (const Rec& r : pending) {
+    float ms = 0;
+    QHIP(hipEventElapsedTime(&ms, r.a, r.b));
+    Sum& x = sums[r.name];
+    x.launches += 1;
+    x.ms += ms;
+    x.flops += r.flops;
+    x.bytes += r.bytes;
+  }
+  pending.clear();
+  used = 0;
+}
+
+void Profiler::release() {
+  for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+  pool.clear();
+  pending.clear();
+  used = 0;
+}
+
+// ------------------------------------------------------------------------------ grid build
+void build_grid_device(qflex_grid* g, hipStream_t s) {
+  std::vector<dev::GridPiece> pieces;
+  std::vector<double2> mats;
+  std::vector<int32_t> pos;
+  std::vector<std::vector<dev::GridQubit>> qds(g->circ.size());
+  std::vector<uint32_t> bidx;
+  std::vector<int> max_nlb(g->circ.size(), 0);
+  int64_t total = 0;
+  for (size_t ci = 0; ci < g->circ.size(); ++ci) {
+    CircuitState& cs = g->circ[ci];
+    const Model& m = cs.model;
+    const Plan& P = cs.plan;
+    cs.grid_offset = total;
+    cs.qubit_offset.assign(m.n, 0);
+    const int mat_base = (int)(mats.size() / 4);
+    for (const cdouble& z : m.mats) mats.push_back(make_double2(z.real(), z.imag()));
+    int64_t off = 0;
+    for (int q = 0; q < m.n; ++q) {
+      const QubitLayout& L = P.qubits[q];
+      const int nb = (int)L.storage.size();
+      cs.qubit_offset[q] = off;
+      dev::GridQubit d{};
+      d.offset = total + off;
+      off += int64_t(1) << nb;
+      off = (off + 63) & ~int64_t(63);  // keep every tensor 512-byte aligned
+      auto where = [&](int label) {
+        const int i = int(std::find(L.storage.begin(), L.storage.end(), label) - L.storage.begin());
+        if (i >= nb) fail(QFLEX_E_DEVICE, "internal: label missing from a qubit layout");
+        return nb - 1 - i;
+      };
+      d.pos_out = where(P.out_label(q));
+      d.pos_base = (int)pos.size();
+      int nlb = 0;
+      std::vector<int> link_start(m.links.size(), 0);
+      for (int l : m.qlinks[q]) {
+        link_start[l] = nlb;
+        for (int j = 0; j < m.links[l].bits; ++j) pos.push_back(where(P.link_base[l] + j));
+        nlb += m.links[l].bits;
+      }
+      d.nlb = nlb;
+      max_nlb[ci] = std::max(max_nlb[ci], nlb);
+      d.piece_begin = (int)pieces.size();
+      for (const Piece& pc : m.timeline[q]) {
+        dev::GridPiece gp{};
+        gp.mat = mat_base + pc.mat;
+        if (pc.link >= 0) {
+          gp.kshift = nlb - (link_start[pc.link] + pc.koff + pc.kbits);
+          gp.kmask = (1 << pc.kbits) - 1;
+        }
+        pieces.push_back(gp);
+      }
+      d.piece_end = (int)pieces.size();
+      qds[ci].push_back(d);
+    }
+    total += off;
+    cs.bidx_offset = (int64_t)bidx.size();
+    bidx.insert(bidx.end(), P.batch_index.begin(), P.batch_index.end());
+  }
+  g->grid_elems = total;
+  QHIP(hipMalloc(&g->grid, sizeof(float2) * std::max<int64_t>(total, 1)));
+  QHIP(hipMalloc(&g->bidx, sizeof(uint32_t) * std::max<size_t>(bidx.size(), 1)));
+  DevBuf dq, dp, dm, dpos;
+  size_t nq = 0;
+  for (auto& v : qds) nq += v.size();
+  std::vector<dev::GridQubit> allq;
+  for (auto& v : qds) allq.insert(allq.end(), v.begin(), v.end());
+  try {
+    dq.reserve(sizeof(dev::GridQubit) * std::max<size_t>(nq, 1));
+    dp.reserve(sizeof(dev::GridPiece) * std::max<size_t>(pieces.size(), 1));
+    dm.reserve(sizeof(double2) * std::max<size_t>(mats.size(), 1));
+    dpos.reserve(sizeof(int32_t) * std::max<size_t>(pos.size(), 1));
+    QHIP(hipMemcpyAsync(dq.p, allq.data(), sizeof(dev::GridQubit) * nq, hipMemcpyHostToDevice, s));
+    QHIP(hipMemcpyAsync(dp.p, pieces.data(), sizeof(dev::GridPiece) * pieces.size(),
+                        hipMemcpyHostToDevice, s));
+    QHIP(hipMemcpyAsync(dm.p, mats.data(), sizeof(double2) * mats.size(), hipMemcpyHostToDevice, s));
+    QHIP(hipMemcpyAsync(dpos.p, pos.data(), sizeof(int32_t) * pos.size(), hipMemcpyHostToDevice, s));
+    if (!bidx.empty())
+      QHIP(hipMemcpyAsync(g->bidx, bidx.data(), sizeof(uint32_t) * bidx.size(),
+                          hipMemcpyHostToDevice, s));
+    size_t qbase = 0;
+    for (size_t ci = 0; ci < g->circ.size(); ++ci) {
+      const int n = (int)qds[ci].size();
+      dev::grid_build(static_cast<const dev::GridQubit*>(dq.p) + qbase, n, max_nlb[ci],
+                      static_cast<const dev::GridPiece*>(dp.p), static_cast<const double2*>(dm.p),
+                      static_cast<const int32_t*>(dpos.p), g->grid, s);
+      qbase += n;
+    }
+    QHIP(hipStreamSynchronize(s));
+  } catch (...) {
+    (void)hipStreamSynchronize(s);
+    dq.release();
+    dp.release();
+    dm.release();
+    dpos.release();
+    throw;
+  }
+  dq.release();
+  dp.release();
+  dm.release();
+  dpos.release();
+  // permutation tiles of every step
+  for (auto& cs : g->circ) {
+    cs.px.assign(cs.plan.steps.size(), dev::PermTile{});
+    cs.py.assign(cs.plan.steps.size(), dev::PermTile{});
+    for (size_t i = 0; i < cs.plan.steps.size(); ++i) {
+      const Step& st = cs.plan.steps[i];
+      if (st.scratch_x >= 0) cs.px[i] = dev::make_perm_tile(st.px.nbits, st.px.perm.data());
+      if (st.scratch_y >= 0) cs.py[i] = dev::make_perm_tile(st.py.nbits, st.py.perm.data());
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------ slices
+std::vector<int64_t> select_slices(int64_t total, double fidelity, uint64_t seed) {
+  if (!(fidelity > 0.0 && fidelity <= 1.0)) fail(QFLEX_E_INVALID, "fidelity must be in (0, 1]");
+  const double k = fidelity * (double)total;
+  const double kr = std::round(k);
+  if (std::fabs(k - kr) > 1e-9 * std::max(1.0, k) || kr < 1)
+    fail(QFLEX_E_PLAN, "fidelity * slices must be an integer >= 1");
+  std::vector<int64_t> a(total);
+  std::iota(a.begin(), a.end(), 0);
+  uint64_t state = seed;
+  auto next = [&]() {  // SplitMix64
+    state += 0x9E3779B97F4A7C15ull;
+    uint64_t z = state;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+  };
+  for (int64_t i = total - 1; i > 0; --i) {
+    const int64_t j = (int64_t)(next() % (uint64_t)(i + 1));
+    std::swap(a[i], a[j]);
+  }
+  a.resize((size_t)kr);
+  std::sort(a.begin(), a.end());
+  return a;
+}
+
+// ------------------------------------------------------------------------------ contract
+namespace {
+
+struct View {
+  const float2* base = nullptr;
+  const int64_t* off = nullptr;
+  int64_t bs = 0, add = 0;
+};
+
+}  // namespace
+
+void contract(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets, double fidelity,
+              uint64_t seed, const int64_t* slice_ids, const int64_t* slice_offsets,
+              double* amps, bool amps_on_device, hipStream_t s) {
+  const int nc = (int)g->circ.size();
+  // ---- validation (host only)
+  if (!bs_offsets) fail(QFLEX_E_INVALID, "NULL argument");
+  if (bs_offsets[0] != 0) fail(QFLEX_E_INVALID, "bs_offsets[0] must be 0");
+  if (bs_offsets[nc] > 0 && (!bits || !amps)) fail(QFLEX_E_INVALID, "NULL argument");
+  std::vector<int64_t> byte_off(nc + 1, 0);
+  for (int c = 0; c < nc; ++c) {
+    if (bs_offsets[c + 1] < bs_offsets[c]) fail(QFLEX_E_INVALID, "bs_offsets must not decrease");
+    byte_off[c + 1] = byte_off[c] + (bs_offsets[c + 1] - bs_offsets[c]) * g->circ[c].model.n;
+  }
+  for (int64_t i = 0; i < byte_off[nc]; ++i)
+    if (bits[i] > 1) fail(QFLEX_E_INVALID, "bit-string entries must be 0 or 1");
+  std::vector<std::vector<int64_t>> sel(nc);
+  for (int c = 0; c < nc; ++c) {
+    const int64_t S = g->circ[c].plan.num_slices();
+    if (slice_ids) {
+      if (!slice_offsets) fail(QFLEX_E_INVALID, "slice_ids given without slice_offsets");
+      if (slice_offsets[c + 1] < slice_offsets[c] || (c == 0 && slice_offsets[0] != 0))
+        fail(QFLEX_E_INVALID, "bad slice_offsets");
+      sel[c].assign(slice_ids + slice_offsets[c], slice_ids + slice_offsets[c + 1]);
+      std::sort(sel[c].begin(), sel[c].end());
+      for (size_t i = 0; i < sel[c].size(); ++i) {
+        if (sel[c][i] < 0 || sel[c][i] >= S) fail(QFLEX_E_INVALID, "slice id out of range");
+        if (i && sel[c][i] == sel[c][i - 1]) fail(QFLEX_E_INVALID, "slice id repeated");
+      }
+    } else {
+      sel[c] = select_slices(S, fidelity, seed);
+    }
+  }
+  QHIP(hipGetLastError());
+  qflex_stats st{};
+  // ---- per-bit-string output offsets of every closed qubit tensor, all circuits
+  std::vector<int64_t> offs_base(nc + 1, 0);
+  for (int c = 0; c < nc; ++c)
+    offs_base[c + 1] = offs_base[c] + (bs_offsets[c + 1] - bs_offsets[c]) * g->circ[c].model.n;
+  const size_t offs_bytes = sizeof(int64_t) * std::max<int64_t>(offs_base[nc], 1);
+  if (g->offs_done) QHIP(hipEventSynchronize(g->offs_done));
+  g->offs_host.reserve(offs_bytes);
+  g->offs.reserve(offs_bytes);
+  int64_t* oh = static_cast<int64_t*>(g->offs_host.p);
+  for (int c = 0; c < nc; ++c) {
+    const CircuitState& cs = g->circ[c];
+    const int n = cs.model.n;
+    const int64_t nbs = bs_offsets[c + 1] - bs_offsets[c];
+    for (int q = 0; q < n; ++q) {
+      const int sh = cs.plan.qubits[q].out_shift;
+      for (int64_t b = 0; b < nbs; ++b)
+        oh[offs_base[c] + q * nbs + b] =
+            sh < 0 ? 0 : (int64_t)bits[byte_off[c] + b * n + q] << sh;
+    }
+  }
+  QHIP(hipMemcpyAsync(g->offs.p, oh, offs_bytes, hipMemcpyHostToDevice, s));
+  if (!g->offs_done) QHIP(hipEventCreateWithFlags(&g->offs_done, hipEventDisableTiming));
+  QHIP(hipEventRecord(g->offs_done, s));
+  const int64_t* offs_dev = static_cast<const int64_t*>(g->offs.p);
+
+  size_t free_b = 0, total_b = 0;
+  QHIP(hipMemGetInfo(&free_b, &total_b));
+  // ---- batch of bit-strings contracted together, per circuit; one arena for the largest
+  std::vector<int64_t> batch(nc, 1);
+  size_t arena_need = sizeof(float2);
+  int64_t amp_total = 0;
+  for (int c = 0; c < nc; ++c) {
+    const Plan& P = g->circ[c].plan;
+    const int64_t nbs = bs_offsets[c + 1] - bs_offsets[c];
+    amp_total += nbs * (int64_t(1) << P.open.size());
+    int64_t B = g->bitstring_batch > 0 ? g->bitstring_batch : 0;
+    if (B == 0) {
+      const double per = 8.0 * (double)std::max<int64_t>(P.arena_elems, 1);
+      const double budget = std::min(0.5 * ((double)free_b + (double)g->arena.bytes),
+                                     96.0 * (1ull << 30));
+      B = (int64_t)std::max(1.0, std::floor(budget / per));
+      B = std::min<int64_t>(B, 256);
+    }
+    B = std::min<int64_t>(std::max<int64_t>(B, 1), std::max<int64_t>(nbs, 1));
+    B = std::min<int64_t>(B, 65535);
+    batch[c] = B;
+    arena_need = std::max(arena_need, sizeof(float2) * (size_t)(P.arena_elems * B));
+  }
+  g->arena.reserve(arena_need);
+  g->amps64.reserve(sizeof(double2) * std::max<int64_t>(amp_total, 1));
+  float2* arena = static_cast<float2*>(g->arena.p);
+  double2* acc_all = static_cast<double2*>(g->amps64.p);
+  dev::fill_zero(reinterpret_cast<double*>(acc_all), 2 * amp_total, s);
+  for (int c = 0; c < nc; ++c) {
+    CircuitState& cs = g->circ[c];
+    const Plan& P = cs.plan;
+    const int64_t nbs = bs_offsets[c + 1] - bs_offsets[c];
+    if (nbs == 0) continue;
+    const int no = (int)P.open.size();
+    const int64_t namp = int64_t(1) << no;
+    const int64_t B = batch[c];
+    double2* acc = acc_all + bs_offsets[c] * namp;
+    const float2* grid = g->grid + cs.grid_offset;
+    const auto& slices = sel[c];
+    const int ncut = (int)P.cuts.size();
+    for (int64_t b0 = 0; b0 < nbs; b0 += B) {
+      const int nb = (int)std::min<int64_t>(B, nbs - b0);
+      std::vector<int64_t> digit(ncut, -1), prev(ncut, -1);
+      auto view = [&](const Operand& o) {
+        View v;
+        if (o.qubit) {
+          const QubitLayout& L = P.qubits[o.id];
+          v.base = grid + cs.qubit_offset[o.id];
+          for (auto& cshift : L.cut_shift) v.add += digit[cshift.first] << cshift.second;
+          if (L.out_shift >= 0) v.off = offs_dev + offs_base[c] + (int64_t)o.id * nbs + b0;
+        } else {
+          const Node& nd = P.nodes[o.id];
+          v.base = arena + nd.offset * B;
+          v.bs = nd.elems();
+        }
+        return v;
+      };
+      for (size_t si = 0; si < slices.size(); ++si) {
+        int64_t rem = slices[si];
+        for (int ct = ncut - 1; ct >= 0; --ct) {
+          digit[ct] = rem & ((int64_t(1) << P.cut_bits[ct]) - 1);
+          rem >>= P.cut_bits[ct];
+        }
+        uint32_t changed = 0;
+        for (int ct = 0; ct < ncut; ++ct)
+          if (digit[ct] != prev[ct]) changed |= 1u << ct;
+        prev = digit;
+        for (size_t k = 0; k < P.steps.size(); ++k) {
+          const Step& stp = P.steps[k];
+          if (si > 0 && !(stp.deps & changed)) continue;
+          View x = view(stp.x), y = view(stp.y);
+          if (stp.scratch_x >= 0) {
+            if (stp.x.qubit) fail(QFLEX_E_DEVICE, "internal: permutation of a qubit tensor");
+            float2* dst = arena + P.nodes[stp.scratch_x].offset * B;
+            g->prof.begin("permute", 0, 16.0 * (double)P.nodes[stp.scratch_x].elems() * nb, s);
+            dev::permute(x.base, dst, nb, cs.px[k], s);
+            g->prof.end(s);
+            x.base = dst;
+            st.permute_bytes += 16.0 * (double)P.nodes[stp.scratch_x].elems() * nb;
+            ++st.n_permute;
+          }
+          if (stp.scratch_y >= 0) {
+            if (stp.y.qubit) fail(QFLEX_E_DEVICE, "internal: permutation of a qubit tensor");
+            float2* dst = arena + P.nodes[stp.scratch_y].offset * B;
+            g->prof.begin("permute", 0, 16.0 * (double)P.nodes[stp.scratch_y].elems() * nb, s);
+            dev::permute(y.base, dst, nb, cs.py[k], s);
+            g->prof.end(s);
+            y.base = dst;
+            st.permute_bytes += 16.0 * (double)P.nodes[stp.scratch_y].elems() * nb;
+            ++st.n_permute;
+          }
+          dev::Gemm gm;
+          gm.A = x.base;
+          gm.a_off = x.off;
+          gm.a_bs = x.bs;
+          gm.a_add = x.add;
+          gm.B = y.base;
+          gm.b_off = y.off;
+          gm.b_bs = y.bs;
+          gm.b_add = y.add;
+          const Node& out = P.nodes[stp.out];
+          gm.C = arena + out.offset * B;
+          gm.c_bs = out.elems();
+          gm.M = int64_t(1) << stp.mb;
+          gm.K = int64_t(1) << stp.kb;
+          gm.N = int64_t(1) << stp.nb;
+          gm.ta = stp.ta;
+          gm.tb = stp.tb;
+          gm.lda = stp.ta ? gm.M : gm.K;
+          gm.ldb = stp.tb ? gm.K : gm.N;
+          gm.ldc = gm.N;
+          gm.batch = nb;
+          g->prof.begin(dev::gemm_name(gm), stp.flops() * nb,
+                        8.0 * nb * (double)(gm.M * gm.K + gm.K * gm.N + gm.M * gm.N), s);
+          dev::gemm(gm, s);
+          g->prof.end(s);
+          st.flops += stp.flops() * nb;
+          ++st.n_gemm;
+        }
+        View r = view(P.result);
+        g->prof.begin("accumulate", 0, 40.0 * namp * nb, s);
+        dev::accumulate(r.base, r.off, r.bs, r.add, namp, g->bidx + cs.bidx_offset,
+                        acc + b0 * namp, namp, nb, s);
+        g->prof.end(s);
+      }
+    }
+    st.n_slices += (int64_t)slices.size();
+    st.n_bitstrings += nbs;
+  }
+  if (amp_total > 0) {
+    QHIP(hipMemcpyAsync(amps, acc_all, sizeof(double2) * amp_total,
+                        amps_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
+    if (!amps_on_device) QHIP(hipStreamSynchronize(s));
+  }
+  if (g->prof.on) {
+    QHIP(hipStreamSynchronize(s));
+    g->prof.resolve();
+  }
+  g->last = st;
+}
+
+}  // namespace qflex

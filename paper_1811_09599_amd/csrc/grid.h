@@ -1,0 +1,91 @@
+// The qflex_grid handle: per-circuit models, plans and device-resident qubit tensors, plus
+// the device arena and staging buffers reused by contract calls.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+#include "model.h"
+#include "plan.h"
+
+namespace qflex {
+
+struct CircuitState {
+  Model model;
+  Plan plan;
+  int64_t grid_offset = 0;           // element offset of this circuit's qubit tensors
+  std::vector<int64_t> qubit_offset; // element offset of each qubit tensor (within the grid)
+  int64_t bidx_offset = 0;           // offset of its batch-index table in the device table
+  std::vector<dev::PermTile> px, py; // per step (valid when the step permutes x / y)
+};
+
+// Device buffer that only grows; freed with the grid.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  void reserve(size_t n);  // throws Error(QFLEX_E_NOMEM / QFLEX_E_DEVICE)
+  void release();
+};
+
+// Launch timing (qflex_set_profiling): events bracket each launch; durations are summed per
+// kernel name once the call's work has finished.
+struct Profiler {
+  struct Rec {
+    const char* name;
+    hipEvent_t a, b;
+    double flops, bytes;
+  };
+  struct Sum {
+    int64_t launches = 0;
+    double ms = 0, flops = 0, bytes = 0;
+  };
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  std::vector<Rec> pending;
+  std::map<std::string, Sum> sums;
+  hipEvent_t take();
+  void begin(const char* name, double flops, double bytes, hipStream_t s);
+  void end(hipStream_t s);
+  void resolve();  // after the stream has finished
+  void release();
+};
+
+struct HostPinned {
+  void* p = nullptr;
+  size_t bytes = 0;
+  void reserve(size_t n);
+  void release();
+};
+
+}  // namespace qflex
+
+struct qflex_grid {
+  int device = 0;
+  int precision = QFLEX_PREC_C64;
+  int bitstring_batch = 0;
+  std::vector<qflex::CircuitState> circ;
+  float2* grid = nullptr;                // all qubit tensors
+  int64_t grid_elems = 0;
+  uint32_t* bidx = nullptr;              // batch-index tables of all circuits
+  qflex::DevBuf arena;                   // intermediates
+  qflex::DevBuf amps64;                  // FP64 amplitude accumulator
+  qflex::DevBuf offs;                    // per-bit-string output offsets of the qubit tensors
+  qflex::HostPinned offs_host;
+  hipEvent_t offs_done = nullptr;        // the last upload out of offs_host has finished
+  qflex_stats last{};
+  qflex::Profiler prof;
+};
+
+namespace qflex {
+void build_grid_device(qflex_grid* g, hipStream_t s);
+void contract(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets, double fidelity,
+              uint64_t seed, const int64_t* slice_ids, const int64_t* slice_offsets,
+              double* amps, bool amps_on_device, hipStream_t s);
+std::vector<int64_t> select_slices(int64_t total, double fidelity, uint64_t seed);
+}  // namespace qflex

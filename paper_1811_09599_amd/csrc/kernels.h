@@ -1,0 +1,75 @@
+// Device kernels of the contraction path and their host launchers (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace qflex {
+namespace dev {
+
+// ---------------------------------------------------------------- grid build (time collapse)
+struct GridQubit {
+  int32_t nlb;          // link bits of the qubit (the combo index has nlb binary digits)
+  int32_t piece_begin;  // pieces [piece_begin, piece_end) in time order
+  int32_t piece_end;
+  int32_t pos_out;      // storage bit position (from the LSB) of the output bit
+  int32_t pos_base;     // first entry in the position table (nlb entries, combo MSB first)
+  int32_t pad;
+  int64_t offset;       // element offset of the qubit tensor in the grid buffer
+};
+struct GridPiece {
+  int32_t mat;    // first 2x2 matrix of the piece
+  int32_t kshift; // bond digits of the piece: k = (combo >> kshift) & kmask
+  int32_t kmask;
+  int32_t pad;
+};
+void grid_build(const GridQubit* q, int n_qubits, int max_nlb, const GridPiece* pieces,
+                const double2* mats, const int32_t* pos, float2* out, hipStream_t s);
+
+// ---------------------------------------------------------------- binary index permutation
+constexpr int kPermMaxTile = 10;
+constexpr int kPermMaxBits = 48;
+struct PermTile {
+  int32_t nbits, tile_bits, nrest, pad;
+  int8_t tile_in[kPermMaxTile];   // read order: bit t of i -> input bit position
+  int8_t tile_out[kPermMaxTile];  // write order: bit t of j -> output bit position
+  int8_t j2i[kPermMaxTile];       // bit t of j is bit j2i[t] of i
+  int8_t rest_in[kPermMaxBits];   // other bits: input position
+  int8_t rest_out[kPermMaxBits];  //             output position
+};
+// perm[j] = input bit position that feeds output bit position j (LSB = 0)
+PermTile make_perm_tile(int nbits, const int* perm);
+void permute(const float2* in, float2* out, int64_t batch, const PermTile& t, hipStream_t s);
+
+// ---------------------------------------------------------------- complex GEMM
+// C[b] = op(A[b]) * op(B[b]); A stored [M][K] (ta=0) or [K][M] (ta=1) with row stride lda,
+// B stored [K][N] (tb=0) or [N][K] (tb=1) with row stride ldb, C stored [M][N].
+// Batch element b starts at A + (a_off ? a_off[b] : b*a_bs) (same for B); C + b*c_bs.
+struct Gemm {
+  const float2* A = nullptr;
+  const float2* B = nullptr;
+  float2* C = nullptr;
+  const int64_t* a_off = nullptr;
+  const int64_t* b_off = nullptr;
+  int64_t a_bs = 0, b_bs = 0, c_bs = 0;
+  int64_t M = 1, N = 1, K = 1;
+  int64_t lda = 1, ldb = 1, ldc = 1;
+  int ta = 0, tb = 0;
+  int batch = 1;
+  int64_t a_add = 0, b_add = 0;  // extra element offset added to every batch element
+};
+// which kernel gemm() would pick: 0 = SIMT, 1 = MFMA 64x64 tile, 2 = MFMA 128x128 tile
+int gemm_variant(const Gemm& g);
+const char* gemm_name(const Gemm& g);  // kernel name used by the profiler
+void gemm(const Gemm& g, hipStream_t s);
+
+// ---------------------------------------------------------------- reductions
+// amps[b*amp_stride + bidx[e]] += res[b][e] for e < n, b < batch (FP64 accumulation)
+void accumulate(const float2* res, const int64_t* r_off, int64_t r_bs, int64_t r_add, int64_t n,
+                const uint32_t* bidx, double2* amps, int64_t amp_stride, int batch,
+                hipStream_t s);
+void fill_zero(double* p, int64_t n, hipStream_t s);
+
+}  // namespace dev
+}  // namespace qflex

@@ -1,0 +1,440 @@
+// Device kernels of the contraction path, written for gfx950 (CDNA4: 64-lane wavefronts,
+// FP32 MFMA, 160 KB LDS per CU).
+#include "kernels.h"
+
+#include <algorithm>
+#include <stdexcept>
+#include <string>
+
+namespace qflex {
+namespace dev {
+
+static void check_launch(const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) throw std::runtime_error(std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// =============================================================================================
+// Grid build: time collapse of every qubit's gates (paper, Methods B.1).
+// One thread per (qubit, value of the qubit's link bonds): it carries the 2-vector
+// |v> = P_t(k_t) ... P_1(k_1) |0> in FP64 through the qubit's pieces, each piece's matrix picked
+// by that piece's bond digits, and stores <0|v>, <1|v> as complex64 at the addresses the
+// plan's layout assigns to (output bit, bond values).
+// =============================================================================================
+__device__ inline double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+__global__ void __launch_bounds__(256) grid_build_kernel(const GridQubit* __restrict__ qd,
+                                                         const GridPiece* __restrict__ pieces,
+                                                         const double2* __restrict__ mats,
+                                                         const int32_t* __restrict__ pos,
+                                                         float2* __restrict__ out) {
+  const GridQubit d = qd[blockIdx.y];
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= (int64_t(1) << d.nlb)) return;
+  double2 v0 = make_double2(1.0, 0.0), v1 = make_double2(0.0, 0.0);
+  for (int p = d.piece_begin; p < d.piece_end; ++p) {
+    const GridPiece pc = pieces[p];
+    const int k = (int)((c >> pc.kshift) & pc.kmask);
+    const double2* M = mats + 4 * (pc.mat + k);
+    const double2 a = cmul(M[0], v0), b = cmul(M[1], v1);
+    const double2 e = cmul(M[2], v0), f = cmul(M[3], v1);
+    v0 = make_double2(a.x + b.x, a.y + b.y);
+    v1 = make_double2(e.x + f.x, e.y + f.y);
+  }
+  int64_t addr = 0;
+  for (int j = 0; j < d.nlb; ++j) addr |= ((c >> (d.nlb - 1 - j)) & 1) << pos[d.pos_base + j];
+  out[d.offset + addr] = make_float2((float)v0.x, (float)v0.y);
+  out[d.offset + (addr | (int64_t(1) << d.pos_out))] = make_float2((float)v1.x, (float)v1.y);
+}
+
+void grid_build(const GridQubit* q, int n_qubits, int max_nlb, const GridPiece* pieces,
+                const double2* mats, const int32_t* pos, float2* out, hipStream_t s) {
+  const int64_t combos = int64_t(1) << max_nlb;
+  dim3 grid((unsigned)((combos + 255) / 256), (unsigned)n_qubits);
+  hipLaunchKernelGGL(grid_build_kernel, grid, dim3(256), 0, s, q, pieces, mats, pos, out);
+  check_launch("grid_build");
+}
+
+// =============================================================================================
+// Binary index permutation (paper, Methods B.2: reordering so that contracted indexes are
+// contiguous for the matrix product).  GPU form: each workgroup moves one tile of 2^tile_bits
+// elements through LDS.  The tile holds the lowest input bits (so every read is a run of
+// consecutive addresses) and the lowest output bits (so every write is too); the remaining
+// bits enumerate tiles.  A permutation that keeps the low bits in place degenerates into a
+// block copy.
+// =============================================================================================
+PermTile make_perm_tile(int nbits, const int* perm) {
+  if (nbits > kPermMaxBits) throw std::runtime_error("permute: too many index bits");
+  PermTile t{};
+  t.nbits = nbits;
+  int inv[kPermMaxBits];
+  for (int j = 0; j < nbits; ++j) inv[perm[j]] = j;
+  const int T = std::min(nbits, kPermMaxTile);
+  bool in_tile[kPermMaxBits] = {false};
+  int size = 0;
+  for (int p = 0; p < std::min(nbits, 5); ++p) in_tile[p] = true, ++size;
+  for (int j = 0; j < nbits && size < T; ++j)
+    if (!in_tile[perm[j]]) in_tile[perm[j]] = true, ++size;
+  for (int p = 0; p < nbits && size < T; ++p)
+    if (!in_tile[p]) in_tile[p] = true, ++size;
+  t.tile_bits = size;
+  int ti = 0;
+  int read_index_of[kPermMaxBits];
+  for (int p = 0; p < nbits; ++p)
+    if (in_tile[p]) read_index_of[p] = ti, t.tile_in[ti++] = (int8_t)p;
+  // write order: tile bits by output position
+  int to = 0;
+  for (int j = 0; j < nbits; ++j)
+    if (in_tile[perm[j]]) {
+      t.tile_out[to] = (int8_t)j;
+      t.j2i[to] = (int8_t)read_index_of[perm[j]];
+      ++to;
+    }
+  int r = 0;
+  for (int p = 0; p < nbits; ++p)
+    if (!in_tile[p]) {
+      t.rest_in[r] = (int8_t)p;
+      t.rest_out[r] = (int8_t)inv[p];
+      ++r;
+    }
+  t.nrest = r;
+  return t;
+}
+
+__device__ inline int lds_pad(int i) { return i + (i >> 5); }
+
+__global__ void __launch_bounds__(256) permute_kernel(const float2* __restrict__ in,
+                                                      float2* __restrict__ out,
+                                                      const PermTile t) {
+  __shared__ float2 tile[(1 << kPermMaxTile) + (1 << kPermMaxTile) / 32];
+  const int64_t batch_stride = int64_t(1) << t.nbits;
+  in += (int64_t)blockIdx.y * batch_stride;
+  out += (int64_t)blockIdx.y * batch_stride;
+  const int64_t T = blockIdx.x;
+  int64_t in_base = 0, out_base = 0;
+  for (int r = 0; r < t.nrest; ++r) {
+    const int64_t bit = (T >> r) & 1;
+    in_base |= bit << t.rest_in[r];
+    out_base |= bit << t.rest_out[r];
+  }
+  const int tsize = 1 << t.tile_bits;
+  for (int i = threadIdx.x; i < tsize; i += blockDim.x) {
+    int64_t off = in_base;
+#pragma unroll
+    for (int b = 0; b < kPermMaxTile; ++b)
+      if (b < t.tile_bits) off |= (int64_t)((i >> b) & 1) << t.tile_in[b];
+    tile[lds_pad(i)] = in[off];
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < tsize; j += blockDim.x) {
+    int i = 0;
+    int64_t off = out_base;
+#pragma unroll
+    for (int b = 0; b < kPermMaxTile; ++b)
+      if (b < t.tile_bits) {
+        const int bit = (j >> b) & 1;
+        i |= bit << t.j2i[b];
+        off |= (int64_t)bit << t.tile_out[b];
+      }
+    out[off] = tile[lds_pad(i)];
+  }
+}
+
+void permute(const float2* in, float2* out, int64_t batch, const PermTile& t, hipStream_t s) {
+  const int64_t tiles = int64_t(1) << t.nrest;
+  if (batch < 1 || batch > 65535) throw std::runtime_error("permute: bad batch");
+  hipLaunchKernelGGL(permute_kernel, dim3((unsigned)tiles, (unsigned)batch), dim3(256), 0, s, in,
+                     out, t);
+  check_launch("permute");
+}
+
+// =============================================================================================
+// Complex64 matrix product (paper, Methods B.2: each pairwise contraction is one matrix
+// multiplication after the permutation).
+//
+// MFMA kernel: 256 threads = 4 wavefronts in 2x2, each owning a (BM/2)x(BN/2) complex block
+// made of 32x32 sub-tiles of v_mfma_f32_32x32x2f32.  The complex product runs in 4M form on
+// the real instruction: Cr += ar*br + (-ai)*bi, Ci += ar*bi + ai*br.  Operand tiles of
+// BK = 16 complex k-values are staged in LDS with k contiguous for both operands (rows padded
+// to 144 bytes), double buffered with one barrier per k-tile; the global loads of tile t+1
+// are issued before the MFMAs of tile t.  Within a k-tile, lanes 0-31 take k = 0..7 and
+// lanes 32-63 take k = 8..15 (the two halves of the instruction's K=2), so each lane reads its
+// operands as 16-byte vectors.
+// =============================================================================================
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+template <bool TA, bool TB, int BM, int BN>
+__global__ void __launch_bounds__(256) gemm_mfma_kernel(const Gemm g) {
+  constexpr int BK = 16, LDK = BK + 2;
+  constexpr int TMI = BM / 64, TNI = BN / 64;
+  constexpr int AV = BM / 32, BV = BN / 32;  // float4 (2 complex) loads per thread per tile
+  __shared__ __attribute__((aligned(16))) float2 As[2][BM * LDK];
+  __shared__ __attribute__((aligned(16))) float2 Bs[2][BN * LDK];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int h = lane >> 5, r = lane & 31;
+  const int64_t tiles_n = g.N / BN;
+  const int64_t tm = (int64_t)blockIdx.x / tiles_n, tn = (int64_t)blockIdx.x % tiles_n;
+  const int b = blockIdx.y;
+  const float2* __restrict__ A = g.A + g.a_add + (g.a_off ? g.a_off[b] : b * g.a_bs);
+  const float2* __restrict__ B = g.B + g.b_add + (g.b_off ? g.b_off[b] : b * g.b_bs);
+  float2* __restrict__ C = g.C + b * g.c_bs;
+  const int64_t m0 = tm * BM, n0 = tn * BN;
+
+  float4 ra[AV], rb[BV];
+  auto gload = [&](int64_t k0) {
+#pragma unroll
+    for (int v = 0; v < AV; ++v) {
+      const int e = tid + v * 256;
+      if (!TA) {
+        const int row = e >> 3, kp = e & 7;
+        ra[v] = *reinterpret_cast<const float4*>(A + (m0 + row) * g.lda + k0 + 2 * kp);
+      } else {
+        const int kr = e / (BM / 2), mp = e % (BM / 2);
+        ra[v] = *reinterpret_cast<const float4*>(A + (k0 + kr) * g.lda + m0 + 2 * mp);
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < BV; ++v) {
+      const int e = tid + v * 256;
+      if (!TB) {
+        const int kr = e / (BN / 2), np = e % (BN / 2);
+        rb[v] = *reinterpret_cast<const float4*>(B + (k0 + kr) * g.ldb + n0 + 2 * np);
+      } else {
+        const int row = e >> 3, kp = e & 7;
+        rb[v] = *reinterpret_cast<const float4*>(B + (n0 + row) * g.ldb + k0 + 2 * kp);
+      }
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int v = 0; v < AV; ++v) {
+      const int e = tid + v * 256;
+      if (!TA) {
+        const int row = e >> 3, kp = e & 7;
+        *reinterpret_cast<float4*>(&As[buf][row * LDK + 2 * kp]) = ra[v];
+      } else {
+        const int kr = e / (BM / 2), mp = e % (BM / 2);
+        As[buf][(2 * mp) * LDK + kr] = make_float2(ra[v].x, ra[v].y);
+        As[buf][(2 * mp + 1) * LDK + kr] = make_float2(ra[v].z, ra[v].w);
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < BV; ++v) {
+      const int e = tid + v * 256;
+      if (!TB) {
+        const int kr = e / (BN / 2), np = e % (BN / 2);
+        Bs[buf][(2 * np) * LDK + kr] = make_float2(rb[v].x, rb[v].y);
+        Bs[buf][(2 * np + 1) * LDK + kr] = make_float2(rb[v].z, rb[v].w);
+      } else {
+        const int row = e >> 3, kp = e & 7;
+        *reinterpret_cast<float4*>(&Bs[buf][row * LDK + 2 * kp]) = rb[v];
+      }
+    }
+  };
+
+  floatx16 cr[TMI][TNI], ci[TMI][TNI];
+#pragma unroll
+  for (int i = 0; i < TMI; ++i)
+#pragma unroll
+    for (int j = 0; j < TNI; ++j)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) cr[i][j][v] = ci[i][j][v] = 0.f;
+
+  const int nk = (int)(g.K / BK);
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < nk) gload((int64_t)(kt + 1) * BK);
+    const float2* as = As[buf];
+    const float2* bs = Bs[buf];
+#pragma unroll
+    for (int s2 = 0; s2 < 4; ++s2) {
+      float4 af[TMI], bf[TNI];
+#pragma unroll
+      for (int i = 0; i < TMI; ++i)
+        af[i] = *reinterpret_cast<const float4*>(
+            &as[(wm * (BM / 2) + i * 32 + r) * LDK + h * 8 + 2 * s2]);
+#pragma unroll
+      for (int j = 0; j < TNI; ++j)
+        bf[j] = *reinterpret_cast<const float4*>(
+            &bs[(wn * (BN / 2) + j * 32 + r) * LDK + h * 8 + 2 * s2]);
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+#pragma unroll
+        for (int i = 0; i < TMI; ++i) {
+          const float ar = u ? af[i].z : af[i].x;
+          const float ai = u ? af[i].w : af[i].y;
+#pragma unroll
+          for (int j = 0; j < TNI; ++j) {
+            const float br = u ? bf[j].z : bf[j].x;
+            const float bi = u ? bf[j].w : bf[j].y;
+            cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, br, cr[i][j], 0, 0, 0);
+            cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(-ai, bi, cr[i][j], 0, 0, 0);
+            ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, bi, ci[i][j], 0, 0, 0);
+            ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai, br, ci[i][j], 0, 0, 0);
+          }
+        }
+      }
+    }
+    if (kt + 1 < nk) sstore(buf ^ 1);
+    __syncthreads();
+  }
+  // D layout of the 32x32 instruction: lane -> column r, register v -> row 8*(v/4)+4*h+(v%4)
+#pragma unroll
+  for (int i = 0; i < TMI; ++i)
+#pragma unroll
+    for (int j = 0; j < TNI; ++j)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int row = wm * (BM / 2) + i * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
+        const int col = wn * (BN / 2) + j * 32 + r;
+        C[(m0 + row) * g.ldc + n0 + col] = make_float2(cr[i][j][v], ci[i][j][v]);
+      }
+}
+
+// SIMT fallback for shapes too small or thin for MFMA tiles: BM x BN outputs per workgroup,
+// one per thread, k-tiles of 16 staged through LDS with bounds checks on every dimension.
+template <int BM, int BN, bool TA, bool TB>
+__global__ void __launch_bounds__(256) gemm_simt_kernel(const Gemm g) {
+  static_assert(BM * BN == 256, "one output per thread");
+  constexpr int BK = 16;
+  __shared__ float2 As[BM][BK + 1];
+  __shared__ float2 Bs[BK][BN + 1];
+  const int tid = threadIdx.x;
+  const int64_t tiles_n = (g.N + BN - 1) / BN;
+  const int64_t m0 = (int64_t)(blockIdx.x / tiles_n) * BM, n0 = (int64_t)(blockIdx.x % tiles_n) * BN;
+  const int b = blockIdx.y;
+  const float2* A = g.A + g.a_add + (g.a_off ? g.a_off[b] : b * g.a_bs);
+  const float2* B = g.B + g.b_add + (g.b_off ? g.b_off[b] : b * g.b_bs);
+  float2* C = g.C + b * g.c_bs;
+  const int tm = tid / BN, tn = tid % BN;
+  float accr = 0.f, acci = 0.f;
+  for (int64_t k0 = 0; k0 < g.K; k0 += BK) {
+    for (int e = tid; e < BM * BK; e += 256) {
+      int mm, kk;
+      if (!TA) mm = e / BK, kk = e % BK;
+      else kk = e / BM, mm = e % BM;
+      const int64_t m = m0 + mm, k = k0 + kk;
+      float2 v = make_float2(0.f, 0.f);
+      if (m < g.M && k < g.K) v = TA ? A[k * g.lda + m] : A[m * g.lda + k];
+      As[mm][kk] = v;
+    }
+    for (int e = tid; e < BN * BK; e += 256) {
+      int nn, kk;
+      if (!TB) kk = e / BN, nn = e % BN;
+      else nn = e / BK, kk = e % BK;
+      const int64_t n = n0 + nn, k = k0 + kk;
+      float2 v = make_float2(0.f, 0.f);
+      if (n < g.N && k < g.K) v = TB ? B[n * g.ldb + k] : B[k * g.ldb + n];
+      Bs[kk][nn] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < BK; ++kk) {
+      const float2 a = As[tm][kk], bb = Bs[kk][tn];
+      accr = fmaf(a.x, bb.x, accr);
+      accr = fmaf(-a.y, bb.y, accr);
+      acci = fmaf(a.x, bb.y, acci);
+      acci = fmaf(a.y, bb.x, acci);
+    }
+    __syncthreads();
+  }
+  const int64_t m = m0 + tm, n = n0 + tn;
+  if (m < g.M && n < g.N) C[m * g.ldc + n] = make_float2(accr, acci);
+}
+
+int gemm_variant(const Gemm& g) {
+  if (g.K % 16 == 0 && g.M % 128 == 0 && g.N % 128 == 0) return 2;
+  if (g.K % 16 == 0 && g.M % 64 == 0 && g.N % 64 == 0) return 1;
+  return 0;
+}
+
+const char* gemm_name(const Gemm& g) {
+  static const char* names[3][4] = {
+      {"gemm_simt_nn", "gemm_simt_nt", "gemm_simt_tn", "gemm_simt_tt"},
+      {"gemm_mfma_64x64_nn", "gemm_mfma_64x64_nt", "gemm_mfma_64x64_tn", "gemm_mfma_64x64_tt"},
+      {"gemm_mfma_128x128_nn", "gemm_mfma_128x128_nt", "gemm_mfma_128x128_tn",
+       "gemm_mfma_128x128_tt"}};
+  return names[gemm_variant(g)][(g.ta ? 2 : 0) + (g.tb ? 1 : 0)];
+}
+
+template <bool TA, bool TB>
+static void gemm_t(const Gemm& g, hipStream_t s) {
+  if (g.batch < 1 || g.batch > 65535) throw std::runtime_error("gemm: bad batch");
+  const int v = gemm_variant(g);
+  if (v == 2) {
+    dim3 grid((unsigned)((g.M / 128) * (g.N / 128)), (unsigned)g.batch);
+    hipLaunchKernelGGL((gemm_mfma_kernel<TA, TB, 128, 128>), grid, dim3(256), 0, s, g);
+  } else if (v == 1) {
+    dim3 grid((unsigned)((g.M / 64) * (g.N / 64)), (unsigned)g.batch);
+    hipLaunchKernelGGL((gemm_mfma_kernel<TA, TB, 64, 64>), grid, dim3(256), 0, s, g);
+  } else {
+    auto launch = [&](auto kern, int bm, int bn) {
+      const int64_t tiles = ((g.M + bm - 1) / bm) * ((g.N + bn - 1) / bn);
+      hipLaunchKernelGGL(kern, dim3((unsigned)tiles, (unsigned)g.batch), dim3(256), 0, s, g);
+    };
+    if (g.N >= 16 && g.M >= 16) launch(gemm_simt_kernel<16, 16, TA, TB>, 16, 16);
+    else if (g.N >= 8) launch(gemm_simt_kernel<32, 8, TA, TB>, 32, 8);
+    else if (g.N >= 4) launch(gemm_simt_kernel<64, 4, TA, TB>, 64, 4);
+    else if (g.N >= 2) launch(gemm_simt_kernel<128, 2, TA, TB>, 128, 2);
+    else launch(gemm_simt_kernel<256, 1, TA, TB>, 256, 1);
+  }
+  check_launch("gemm");
+}
+
+void gemm(const Gemm& g, hipStream_t s) {
+  if (g.ta) {
+    if (g.tb) gemm_t<true, true>(g, s);
+    else gemm_t<true, false>(g, s);
+  } else {
+    if (g.tb) gemm_t<false, true>(g, s);
+    else gemm_t<false, false>(g, s);
+  }
+}
+
+// =============================================================================================
+// FP64 accumulation of a slice's result into the amplitude batch (paper, Methods B.1: the
+// amplitude is the sum of the path contributions; Methods C.1: a fraction of them).
+// =============================================================================================
+__global__ void accumulate_kernel(const float2* __restrict__ res, const int64_t* __restrict__ r_off,
+                                  int64_t r_bs, int64_t r_add, int64_t n,
+                                  const uint32_t* __restrict__ bidx, double2* __restrict__ amps,
+                                  int64_t amp_stride) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const int b = blockIdx.y;
+  const float2 v = res[r_add + (r_off ? r_off[b] : b * r_bs) + e];
+  double2* a = amps + b * amp_stride + bidx[e];
+  double2 t = *a;
+  t.x += (double)v.x;
+  t.y += (double)v.y;
+  *a = t;
+}
+
+void accumulate(const float2* res, const int64_t* r_off, int64_t r_bs, int64_t r_add, int64_t n,
+                const uint32_t* bidx, double2* amps, int64_t amp_stride, int batch,
+                hipStream_t s) {
+  dim3 grid((unsigned)((n + 255) / 256), (unsigned)batch);
+  hipLaunchKernelGGL(accumulate_kernel, grid, dim3(256), 0, s, res, r_off, r_bs, r_add, n, bidx,
+                     amps, amp_stride);
+  check_launch("accumulate");
+}
+
+__global__ void fill_zero_kernel(double* p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.0;
+}
+
+void fill_zero(double* p, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(fill_zero_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n);
+  check_launch("fill_zero");
+}
+
+}  // namespace dev
+}  // namespace qflex

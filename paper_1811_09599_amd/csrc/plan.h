@@ -1,0 +1,85 @@
+// Contraction plan: which bonds are cut, in which order tensors are contracted pairwise, how
+// each operand is laid out (and permuted when it must be), and where every intermediate
+// lives in the device arena.
+//
+// Every tensor index here is binary: a link bond of 2^b values is b binary labels (most
+// significant first) and a qubit's open output bit is one label.  A tensor layout is the
+// list of its labels in storage order, most significant first (row-major).
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "model.h"
+
+namespace qflex {
+
+struct QubitLayout {
+  std::vector<int> storage;   // labels in storage order: fixed labels first, then free ones
+  int n_fixed = 0;            // leading fixed labels (closed output bit, cut bonds)
+  int out_shift = -1;         // bit position (from the LSB) of the output label; -1 if open
+  std::vector<std::pair<int, int>> cut_shift;  // (cut index, bit position of its LSB)
+  uint32_t deps = 0;          // cuts this tensor depends on
+  int free_bits() const { return (int)storage.size() - n_fixed; }
+};
+
+struct Operand {
+  bool qubit = false;  // qubit tensor view, else an intermediate node
+  int id = -1;
+};
+
+struct PermDesc {
+  int nbits = 0;
+  std::vector<int> perm;  // perm[j] = input bit position feeding output bit position j (LSB=0)
+};
+
+struct Step {
+  Operand x, y;
+  int out = -1;                 // node produced
+  int scratch_x = -1, scratch_y = -1;  // scratch node receiving a permuted operand, or -1
+  PermDesc px, py;
+  bool ta = false, tb = false;  // operand stored transposed ([K][M] / [N][K])
+  int mb = 0, kb = 0, nb = 0;   // log2 of M, K, N
+  uint32_t deps = 0;
+  double flops() const { return 8.0 * std::ldexp(1.0, mb + kb + nb); }
+};
+
+struct Node {
+  std::vector<int> labels;
+  uint32_t deps = 0;
+  int producer = -1, last_use = -1;
+  bool persistent = false;
+  int64_t offset = 0;  // elements, per bit-string, inside the arena
+  int64_t elems() const { return int64_t(1) << labels.size(); }
+};
+
+struct Plan {
+  int kind = QFLEX_PLAN_SWEEP;
+  std::vector<int> cuts;       // link ids, slice-radix order (first most significant)
+  std::vector<int> cut_bits;
+  int total_link_bits = 0;     // labels [0, total_link_bits) are link bits
+  std::vector<int> link_base;  // first label of each link
+  std::vector<QubitLayout> qubits;
+  std::vector<Node> nodes;
+  std::vector<Step> steps;
+  Operand result;              // tensor holding the open-qubit batch at the end
+  std::vector<int> result_labels;
+  std::vector<int> open;       // open qubit ids in the caller's order
+  std::vector<uint32_t> batch_index;  // result element -> open-batch index (big-endian)
+  int max_bits = 0;
+  int64_t arena_elems = 0;     // per bit-string
+  double flops_all_slices = 0; // per bit-string, f = 1, with reuse across slices
+
+  int out_label(int q) const { return total_link_bits + q; }
+  int64_t num_slices() const {
+    int b = 0;
+    for (int c : cut_bits) b += c;
+    return int64_t(1) << b;
+  }
+  std::string describe(const Model& m) const;
+};
+
+Plan make_plan(const Model& m, const qflex_options& opt);
+
+}  // namespace qflex

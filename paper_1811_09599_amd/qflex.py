@@ -1,0 +1,185 @@
+"""Python binding of libqflex (names follow the C ABI; every step runs in the library).
+
+    grid = build_grid(circuits, open_qubits=[...])
+    amps = grid.contract_amplitudes(bits)            # torch complex128 on the GPU
+"""
+from __future__ import annotations
+
+import ctypes as C
+import json
+
+import numpy as np
+
+from . import _ffi as F
+
+
+class _CircuitPack:
+    """Keeps the ctypes arrays of circuits alive while the library reads them."""
+
+    def __init__(self, circuits):
+        self.keep = []
+        arr = (F.Circuit * len(circuits))()
+        for i, c in enumerate(circuits):
+            n = int(c["n_qubits"])
+            xy = (C.c_int32 * (2 * n))(*[int(v) for p in c["xy"] for v in p])
+            gates = (F.Gate * max(1, len(c["gates"])))()
+            for j, g in enumerate(c["gates"]):
+                qs = list(g["qubits"])
+                gates[j].cycle = int(g["cycle"])
+                gates[j].kind = F.KIND[g["kind"]]
+                gates[j].q0 = int(qs[0])
+                gates[j].q1 = int(qs[1]) if len(qs) > 1 else -1
+                gates[j].theta = float(g.get("theta", 0.0))
+                gates[j].phi = float(g.get("phi", 0.0))
+                if "mat" in g:
+                    m = np.asarray(g["mat"], dtype=np.complex128).ravel()
+                    buf = (C.c_double * (2 * m.size))(*np.stack([m.real, m.imag], 1).ravel())
+                    self.keep.append(buf)
+                    gates[j].mat = C.cast(buf, C.POINTER(C.c_double))
+            self.keep += [xy, gates]
+            arr[i].n_qubits = n
+            arr[i].xy = C.cast(xy, C.POINTER(C.c_int32))
+            arr[i].gates = C.cast(gates, C.POINTER(F.Gate))
+            arr[i].n_gates = len(c["gates"])
+        self.arr = arr
+
+
+def _options(precision="c64", plan="auto", max_tensor_elems=0, open_qubits=(),
+             bitstring_batch=0):
+    o = F.Options()
+    o.precision = F.PREC[precision]
+    o.plan_kind = F.PLAN[plan]
+    o.max_tensor_elems = int(max_tensor_elems or 0)
+    op = (C.c_int32 * max(1, len(open_qubits)))(*[int(q) for q in open_qubits])
+    o.open_qubits = C.cast(op, C.POINTER(C.c_int32))
+    o.n_open = len(open_qubits)
+    o.bitstring_batch = int(bitstring_batch)
+    return o, op
+
+
+def _stream(stream):
+    if stream is not None:
+        return C.c_void_p(int(stream))
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    except ImportError:
+        pass
+    return C.c_void_p(0)
+
+
+def plan_describe(circuit: dict, **opts) -> dict:
+    """qflex_plan_describe: validate and plan one circuit on the host, without a GPU."""
+    L = F.lib()
+    pack = _CircuitPack([circuit])
+    o, keep = _options(**opts)
+    need = C.c_int64(0)
+    F.check(L.qflex_plan_describe(pack.arr, C.byref(o), None, 0, C.byref(need)))
+    buf = C.create_string_buffer(int(need.value))
+    F.check(L.qflex_plan_describe(pack.arr, C.byref(o), buf, need.value, C.byref(need)))
+    return json.loads(buf.value.decode())
+
+
+class Grid:
+    """qflex_grid handle (device-resident time-collapsed tensors of a batch of circuits)."""
+
+    def __init__(self, circuits, precision="c64", plan="auto", max_tensor_elems=0,
+                 open_qubits=(), bitstring_batch=0, stream=None):
+        L = F.lib()
+        if isinstance(circuits, dict):
+            circuits = [circuits]
+        self.circuits = list(circuits)
+        self.n_open = len(open_qubits)
+        self.open_qubits = list(open_qubits)
+        pack = _CircuitPack(self.circuits)
+        o, keep = _options(precision, plan, max_tensor_elems, open_qubits, bitstring_batch)
+        h = C.c_void_p()
+        F.check(L.qflex_build_grid(pack.arr, len(self.circuits), C.byref(o), _stream(stream),
+                                   C.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            F.lib().qflex_grid_free(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def num_slices(self, circuit: int = 0) -> int:
+        t = C.c_int64()
+        F.check(F.lib().qflex_num_slices(self._h, circuit, C.byref(t)))
+        return int(t.value)
+
+    def plan_cuts(self, circuit: int = 0) -> list[tuple[int, int]]:
+        buf = (C.c_int32 * 128)()
+        n = C.c_int32()
+        F.check(F.lib().qflex_plan_cuts(self._h, circuit, buf, 64, C.byref(n)))
+        return [(buf[2 * i], buf[2 * i + 1]) for i in range(n.value)]
+
+    def last_stats(self) -> dict:
+        s = F.Stats()
+        F.check(F.lib().qflex_last_stats(self._h, C.byref(s)))
+        return {k: getattr(s, k) for k, _ in F.Stats._fields_}
+
+    def set_profiling(self, enable: bool = True):
+        F.check(F.lib().qflex_set_profiling(self._h, 1 if enable else 0))
+
+    def profile_read(self) -> dict:
+        buf = (F.KernelStat * 64)()
+        n = C.c_int32()
+        F.check(F.lib().qflex_profile_read(self._h, buf, 64, C.byref(n)))
+        return {buf[i].name.decode(): {"launches": buf[i].launches, "ms": buf[i].ms,
+                                       "flops": buf[i].flops, "bytes": buf[i].bytes}
+                for i in range(min(n.value, 64))}
+
+    def contract_amplitudes(self, bits, fidelity: float = 1.0, seed: int = 0, slice_ids=None,
+                            device: bool = True, stream=None, out=None):
+        """Amplitudes [total bit-strings, 2^n_open] complex128 (a torch CUDA tensor when
+        ``device``, else numpy).  ``bits``: one uint8 array [m_c, n_c] per circuit (or a
+        single array for one circuit).  ``slice_ids``: optional list per circuit."""
+        L = F.lib()
+        if isinstance(bits, np.ndarray) or (len(self.circuits) == 1 and not isinstance(bits, list)):
+            bits = [bits]
+        bits = [np.ascontiguousarray(np.asarray(b, dtype=np.uint8)) for b in bits]
+        if len(bits) != len(self.circuits):
+            raise ValueError("need one bit-string array per circuit")
+        offs = np.zeros(len(bits) + 1, dtype=np.int64)
+        for i, b in enumerate(bits):
+            offs[i + 1] = offs[i] + (b.shape[0] if b.size else 0)
+        flat = np.concatenate([b.ravel() for b in bits]) if offs[-1] else np.zeros(1, np.uint8)
+        namp = 1 << self.n_open
+        sid = soff = None
+        if slice_ids is not None:
+            if len(self.circuits) == 1 and (len(slice_ids) == 0 or np.isscalar(slice_ids[0])):
+                slice_ids = [slice_ids]
+            so = np.zeros(len(slice_ids) + 1, dtype=np.int64)
+            for i, s in enumerate(slice_ids):
+                so[i + 1] = so[i] + len(s)
+            si = np.concatenate([np.asarray(s, dtype=np.int64) for s in slice_ids]) \
+                if so[-1] else np.zeros(1, np.int64)
+            sid = si.ctypes.data_as(C.POINTER(C.c_int64))
+            soff = so.ctypes.data_as(C.POINTER(C.c_int64))
+        total = int(offs[-1])
+        if device:
+            import torch
+            res = out if out is not None else torch.empty((total, namp), dtype=torch.complex128,
+                                                          device="cuda")
+            ptr = C.c_void_p(res.data_ptr())
+        else:
+            res = np.empty((total, namp), dtype=np.complex128)
+            ptr = C.c_void_p(res.ctypes.data)
+        F.check(L.qflex_contract_amplitudes(
+            self._h, flat.ctypes.data_as(C.POINTER(C.c_uint8)),
+            offs.ctypes.data_as(C.POINTER(C.c_int64)), float(fidelity), C.c_uint64(int(seed)),
+            sid, soff, ptr, 1 if device else 0, _stream(stream)))
+        return res
+
+
+def build_grid(circuits, **kw) -> Grid:
+    """qflex_build_grid."""
+    return Grid(circuits, **kw)

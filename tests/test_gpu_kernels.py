@@ -1,0 +1,132 @@
+"""GPU: the two kernels of a contraction step through the C ABI (qflex_permute_c64,
+qflex_gemm_c64) against numpy in FP64."""
+import ctypes as C
+import os
+
+import numpy as np
+import pytest
+
+from paper_1811_09599_amd import _ffi as F
+
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _perm_np(x, nbits, perm):
+    """out[sum_j b_j 2^j] = in[sum_j b_j 2^perm[j]] via numpy.transpose on the bit axes."""
+    t = x.reshape((-1,) + (2,) * nbits)  # axis 1 + i holds input bit nbits-1-i
+    axes = [0] + [1 + (nbits - 1 - perm[nbits - 1 - i]) for i in range(nbits)]
+    return np.transpose(t, axes).reshape(x.shape)
+
+
+def _permute(x_np, nbits, perm, batch):
+    torch = _torch()
+    x = torch.from_numpy(x_np).cuda()
+    y = torch.empty_like(x)
+    p = (C.c_int32 * nbits)(*perm)
+    F.check(F.lib().qflex_permute_c64(C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()), nbits,
+                                      p, batch, None))
+    torch.cuda.synchronize()
+    return y.cpu().numpy()
+
+
+@pytest.mark.parametrize("nbits,batch,seed", [(1, 1, 0), (3, 2, 1), (7, 1, 2), (10, 3, 3),
+                                              (12, 1, 4), (16, 2, 5), (20, 1, 6), (24, 1, 7)])
+def test_permute_matches_numpy_transpose(nbits, batch, seed):
+    rng = np.random.default_rng(seed)
+    for trial in range(3):
+        perm = list(rng.permutation(nbits)) if trial else list(range(nbits))[::-1]
+        _say("permute", nbits, batch, perm)
+        x = (rng.standard_normal((batch, 1 << nbits)) +
+             1j * rng.standard_normal((batch, 1 << nbits))).astype(np.complex64)
+        got = _permute(x, nbits, perm, batch)
+        assert np.array_equal(got, _perm_np(x, nbits, perm))
+
+
+def test_permute_identity_low_bits_and_worked_example():
+    # Methods B.2 worked example abcdefg -> cfeadgb, each index of dimension 4 (2 bits)
+    steps = [l.split() for l in open(os.path.join(GOLD, "permutation_b2.txt"))
+             if l.strip() and not l.startswith("#")]
+    src = steps[0][1].replace("|", "")
+    dst = steps[-1][1]
+    d = 2
+    nbits = d * len(src)
+    # label bits MSB-first: index letter i occupies bits [d*i, d*i+d) from the MSB
+    in_pos = {}
+    for i, ch in enumerate(src):
+        for j in range(d):
+            in_pos[(ch, j)] = nbits - 1 - (d * i + j)
+    perm = [0] * nbits
+    for i, ch in enumerate(dst):
+        for j in range(d):
+            perm[nbits - 1 - (d * i + j)] = in_pos[(ch, j)]
+    rng = np.random.default_rng(11)
+    x = (rng.standard_normal(1 << nbits) + 1j * rng.standard_normal(1 << nbits)).astype(np.complex64)
+    got = _permute(x[None], nbits, perm, 1)[0]
+    want = np.transpose(x.reshape((4,) * 7), [src.index(c) for c in dst]).ravel()
+    assert np.array_equal(got, want)
+    # a permutation that keeps the 12 low bits in place
+    perm = list(range(12)) + [15, 12, 14, 13]
+    y = (rng.standard_normal((2, 1 << 16)) + 0j).astype(np.complex64)
+    assert np.array_equal(_permute(y, 16, perm, 2), _perm_np(y, 16, perm))
+
+
+def test_permute_rejects_bad_arguments():
+    torch = _torch()
+    x = torch.zeros(16, dtype=torch.complex64, device="cuda")
+    p = (C.c_int32 * 4)(0, 1, 1, 3)
+    st = F.lib().qflex_permute_c64(C.c_void_p(x.data_ptr()), C.c_void_p(x.data_ptr()), 4, p, 1,
+                                   None)
+    assert st == F.E_INVALID
+
+
+def _gemm(a, b, M, N, K, ta, tb, batch):
+    torch = _torch()
+    A = torch.from_numpy(a).cuda()
+    B = torch.from_numpy(b).cuda()
+    Cm = torch.empty((batch, M, N), dtype=torch.complex64, device="cuda")
+    F.check(F.lib().qflex_gemm_c64(C.c_void_p(A.data_ptr()), C.c_void_p(B.data_ptr()),
+                                   C.c_void_p(Cm.data_ptr()), M, N, K, ta, tb, batch, None))
+    torch.cuda.synchronize()
+    return Cm.cpu().numpy()
+
+
+SHAPES = [(1, 1, 1, 1), (3, 5, 7, 2), (64, 64, 16, 1), (64, 64, 64, 3), (128, 128, 32, 1),
+          (256, 128, 48, 2), (128, 256, 1024, 1), (1024, 256, 256, 1), (4096, 16, 256, 1),
+          (16, 4096, 256, 1), (1 << 14, 1, 256, 2), (64, 2, 8, 5), (512, 512, 4096, 1)]
+
+
+@pytest.mark.parametrize("M,N,K,batch", SHAPES)
+@pytest.mark.parametrize("ta,tb", [(0, 0), (1, 0), (0, 1), (1, 1)])
+def test_gemm_matches_fp64(M, N, K, batch, ta, tb):
+    variant = F.lib().qflex_gemm_variant(M, N, K)
+    _say("gemm", M, N, K, batch, ta, tb, "variant", variant)
+    rng = np.random.default_rng(M * 7 + N * 3 + K + batch)
+    sa = (batch, K, M) if ta else (batch, M, K)
+    sb = (batch, N, K) if tb else (batch, K, N)
+    a = (rng.standard_normal(sa) + 1j * rng.standard_normal(sa)).astype(np.complex64)
+    b = (rng.standard_normal(sb) + 1j * rng.standard_normal(sb)).astype(np.complex64)
+    got = _gemm(a, b, M, N, K, ta, tb, batch)
+    A = a.astype(np.complex128)
+    B = b.astype(np.complex128)
+    if ta:
+        A = np.transpose(A, (0, 2, 1))
+    if tb:
+        B = np.transpose(B, (0, 2, 1))
+    want = A @ B
+    # FP32 accumulation of K products of O(1) terms: error ~ 1e-7 * sqrt(K) relative to |C|
+    rel = np.linalg.norm(got - want) / np.linalg.norm(want)
+    assert rel < 2e-6, rel
+    rms = np.sqrt(np.mean(np.abs(want) ** 2))
+    assert np.max(np.abs(got - want)) < 2e-5 * rms * max(1.0, np.sqrt(K / 64))

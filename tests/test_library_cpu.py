@@ -1,0 +1,163 @@
+"""Host-side checks of libqflex: exported symbols, argument validation, planner, slice subset.
+None of these launch GPU work."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import rqc_inputs as R
+from oracle import slices as OS
+from paper_1811_09599_amd import _ffi as F
+from paper_1811_09599_amd import plan_describe
+from paper_1811_09599_amd.qflex import _CircuitPack, _options
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = set()
+    for h in ("qflex.h", "qflex_kernels.h"):
+        txt = open(os.path.join(ROOT, "include", h)).read()
+        names |= set(re.findall(r"\b(qflex_[a-z0-9_]+)\s*\(", txt))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = F.lib()
+    declared = _declared()
+    assert {"qflex_build_grid", "qflex_contract_amplitudes", "qflex_permute_c64",
+            "qflex_gemm_c64"} <= declared
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert set(F.EXPORTS) == declared
+
+
+def _status_describe(circ, **opts):
+    L = F.lib()
+    pack = _CircuitPack([circ])
+    o, keep = _options(**opts)
+    need = C.c_int64(0)
+    st = L.qflex_plan_describe(pack.arr, C.byref(o), None, 0, C.byref(need))
+    return st, L.qflex_last_error().decode()
+
+
+def _status_build(circ, **opts):
+    L = F.lib()
+    pack = _CircuitPack([circ])
+    o, keep = _options(**opts)
+    h = C.c_void_p()
+    st = L.qflex_build_grid(pack.arr, 1, C.byref(o), None, C.byref(h))
+    assert not h.value or st == F.OK
+    return st, L.qflex_last_error().decode()
+
+
+def _bad_circuits():
+    base = R.grid_rqc(3, 3, 8, 1)
+    out = []
+    c = dict(base, gates=[dict(g) for g in base["gates"]])
+    c["gates"].append({"cycle": 3, "kind": "cz", "qubits": [0, 4]})  # diagonal pair
+    out.append(("not unit distance", c))
+    c = dict(base, gates=[dict(g) for g in base["gates"]])
+    c["gates"].append({"cycle": 0, "kind": "t", "qubits": [2]})  # qubit 2 twice in cycle 0
+    out.append(("used twice", c))
+    c = dict(base, xy=[list(p) for p in base["xy"]])
+    c["xy"][1] = list(c["xy"][0])
+    out.append(("coordinates repeated", c))
+    c = dict(base, gates=[dict(g) for g in base["gates"]])
+    c["gates"].append({"cycle": 50, "kind": "h", "qubits": [9]})
+    out.append(("out of range", c))
+    return out
+
+
+@pytest.mark.parametrize("why,circ", _bad_circuits())
+def test_invalid_circuits_rejected_before_any_device_work(why, circ):
+    for fn in (_status_describe, _status_build):
+        st, msg = fn(circ)
+        assert st == F.E_INVALID, (why, st, msg)
+        assert msg
+
+
+def test_invalid_options_rejected():
+    c = R.grid_rqc(3, 3, 8, 1)
+    assert _status_describe(c, open_qubits=list(range(9)) + [0])[0] == F.E_INVALID
+    assert _status_describe(c, open_qubits=[12])[0] == F.E_INVALID
+    assert _status_build(c, open_qubits=[3, 3])[0] == F.E_INVALID
+    big = R.grid_rqc(5, 5, 8, 1)
+    assert _status_describe(big, open_qubits=list(range(17)))[0] == F.E_INVALID
+
+
+def test_plan_that_cannot_fit_is_reported():
+    c = R.grid_rqc(4, 4, 16, 1)
+    st, msg = _status_describe(c, plan="sweep", max_tensor_elems=64)
+    assert st == F.E_PLAN and "max_tensor_elems" in msg
+    st, msg = _status_build(c, plan="sweep", max_tensor_elems=64)
+    assert st == F.E_PLAN
+
+
+def test_build_without_gpu_fails_loudly():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("GPU present")
+    st, msg = _status_build(R.grid_rqc(3, 3, 8, 1))
+    assert st == F.E_DEVICE and msg
+
+
+def test_planner_7x7_quadrant_matches_the_paper_structure():
+    """SI A: two cuts on the 7x7 grid, four regions, every region tensor 2^(6 log2 D)."""
+    for depth, d in ((32, 16), (40, 32)):
+        c = R.grid_rqc(7, 7, depth, 2001)
+        op = R.grid_ids((7, 7), [(5, 0), (5, 1), (5, 2), (6, 0), (6, 1), (6, 2)])
+        p = plan_describe(c, open_qubits=op)
+        assert p["kind"] == "quadrant"
+        assert [x[:2] for x in p["cuts"]] == [[20, 27], [44, 45]]
+        assert [x[2] for x in p["cuts"]] == [int(np.log2(d))] * 2
+        assert p["num_slices"] == d * d
+        assert p["max_bits"] == 6 * int(np.log2(d))
+        big = [s for s in p["steps"] if s["mb"] == s["kb"] == s["nb"] == 3 * int(np.log2(d))]
+        assert len(big) == 2  # A.B and AB.D
+        assert [s["deps"] for s in big] == [1, 3]
+
+
+def test_planner_small_grid_is_a_single_sweep():
+    p = plan_describe(R.grid_rqc(4, 4, 16, 1))
+    assert p["kind"] == "sweep" and p["num_slices"] == 1 and p["max_bits"] <= 12
+    q = plan_describe(R.grid_rqc(4, 4, 16, 1), plan="quadrant")
+    assert q["kind"] == "quadrant" and q["num_slices"] == 16
+
+
+def test_planner_reuse_lowers_flops():
+    """Steps that do not depend on a cut are charged once per bit-string."""
+    c = R.grid_rqc(7, 7, 32, 2001)
+    p = plan_describe(c)
+    per_slice = sum(s["flops"] for s in p["steps"])
+    assert p["flops_all_slices"] < p["num_slices"] * per_slice / 1.2
+
+
+@pytest.mark.parametrize("total,f,seed", [(1024, 1 / 64, 2700), (256, 1.0, 1), (96, 0.25, 7),
+                                          (1, 1.0, 3), (4096, 1 / 256, 4700)])
+def test_slice_subset_matches_oracle(total, f, seed):
+    L = F.lib()
+    k = int(round(total * f))
+    ids = (C.c_int64 * k)()
+    n = C.c_int64()
+    F.check(L.qflex_select_slices(total, f, seed, ids, k, C.byref(n)))
+    assert n.value == k
+    assert list(ids) == OS.select(total, f, seed)
+
+
+def test_slice_subset_rejects_bad_fidelity():
+    L = F.lib()
+    n = C.c_int64()
+    assert L.qflex_select_slices(10, 0.25, 1, None, 0, C.byref(n)) == F.E_PLAN
+    assert L.qflex_select_slices(10, 0.0, 1, None, 0, C.byref(n)) == F.E_INVALID
+    assert L.qflex_select_slices(10, 1.5, 1, None, 0, C.byref(n)) == F.E_INVALID
+
+
+def test_gemm_variant_choice():
+    L = F.lib()
+    assert L.qflex_gemm_variant(4096, 4096, 4096) == 2
+    assert L.qflex_gemm_variant(64, 64, 16) == 1
+    assert L.qflex_gemm_variant(64, 8, 256) == 0
+    assert L.qflex_gemm_variant(1 << 20, 256, 8) == 0
