@@ -1,13 +1,15 @@
 """Throughput of the RQC amplitude contraction on one MI355X.
 
-Workload (default): 7x7 grid, depth 1+32+1 (bond dimension 16 on every link), the quadrant
-plan with 2 cut bonds (256 slices, all summed: fidelity 1), a 6-qubit open batch (64
-amplitudes per bit-string), complex64 arithmetic.  One step = one contraction call over the
-next `--bitstrings` bit-strings of a seeded set of 1024, every slice included.
+Workload: 7x7 grid, depth 1+32+1 (bond dimension 16 on every link), the quadrant plan with
+2 cut bonds (256 slices, all summed: fidelity 1), a 6-qubit open batch (64 amplitudes per
+bit-string).  One step = one contraction call over the next `--bitstrings` bit-strings of a
+seeded set of 1024, every slice included.  Both precisions are measured: split-bf16 (the
+headline `value`) and complex64 (reported alongside), each with its error against the FP64
+oracle on sampled slices.
 
-Prints one JSON line: amplitudes/s (whole job), sustained TFLOP/s of the plan, the roofline of
-the dominant kernel measured with HIP events around its launches in the timed region, and the
-CPU oracle timed on a bounded sample of the same work.
+Prints one JSON line: amplitudes/s (whole job), sustained TFLOP/s of the plan (8 real flops
+per complex multiply-add), the roofline of the dominant kernel measured with HIP events around
+its launches in the timed region, and the CPU oracle timed on a bounded sample.
 
     python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--bitstrings 4]
 """
@@ -20,66 +22,51 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK = {"mfma": (157.3, "TFLOP/s"), "alu": (78.6, "TFLOP/s"), "hbm": (8000.0, "GB/s")}
+# MI355X published peaks: dense MFMA fp32 / bf16, fp32 vector without packed math, HBM3E
+PEAK = {"mfma_fp32": (157.3, "TFLOP/s"), "mfma_bf16": (2500.0, "TFLOP/s"),
+        "alu": (78.6, "TFLOP/s"), "hbm": (8000.0, "GB/s")}
+SPLIT_TOL = 2e-4
+C64_TOL = 1e-5
 
 
 def kernel_bound(name):
+    if name.startswith("gemm_split_bf16"):
+        return "mfma", PEAK["mfma_bf16"]
     if name.startswith("gemm_mfma"):
-        return "mfma"
+        return "mfma", PEAK["mfma_fp32"]
     if name.startswith("gemm_simt"):
-        return "alu"
-    return "hbm"
+        return "alu", PEAK["alu"]
+    return "hbm", PEAK["hbm"]
 
 
 def roofline(prof):
     name = max(prof, key=lambda k: prof[k]["ms"])
     k = prof[name]
-    bound = kernel_bound(name)
-    peak, unit = PEAK[bound]
+    bound, (peak, unit) = kernel_bound(name)
     if bound == "hbm":
         achieved = k["bytes"] / (k["ms"] * 1e-3) / 1e9
     else:
         achieved = k["flops"] / (k["ms"] * 1e-3) / 1e12
     return name, {"bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": unit,
-                  "frac": round(achieved / peak, 4), "traffic": None}
+                  "frac": round(achieved / peak, 4), "traffic": None,
+                  "avg_launch_us": round(1e3 * k["ms"] / max(k["launches"], 1), 3),
+                  "launches": k["launches"]}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--bitstrings", type=int, default=4, help="bit-strings per step")
-    ap.add_argument("--cpu-slices", type=int, default=3, help="oracle sample size (slices)")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
-        sys.exit(2)
-
-    import numpy as np
+def run_precision(precision, circ, open_q, all_bits, args):
     import torch
 
-    import rqc_inputs as R
-    from paper_1811_09599_amd import build_grid, plan_describe
+    from paper_1811_09599_amd import build_grid
 
-    torch.cuda.set_device(0)
-    rows = cols = 7
-    depth = 32
-    circ = R.grid_rqc(rows, cols, depth, 2000)
-    open_q = R.grid_ids((rows, cols), [(5, 0), (5, 1), (5, 2), (6, 0), (6, 1), (6, 2)])
-    all_bits = R.bitstrings(rows * cols, 1024, 2500, open_q)
-    plan = plan_describe(circ, open_qubits=open_q)
     t0 = time.time()
-    grid = build_grid(circ, open_qubits=open_q)
+    grid = build_grid(circ, open_qubits=open_q, precision=precision)
     torch.cuda.synchronize()
     build_s = time.time() - t0
     B = args.bitstrings
     out = torch.empty((B, 64), dtype=torch.complex128, device="cuda")
 
     def step(i):
-        lo = (i * B) % 1024
+        lo = (i * B) % len(all_bits)
         grid.contract_amplitudes(all_bits[lo:lo + B], out=out)
         return grid.last_stats()["flops"]
 
@@ -96,43 +83,85 @@ def main():
     dt = time.perf_counter() - t0
     prof = grid.profile_read()
     grid.set_profiling(False)
-    amps = args.steps * B * 64
     dom, roof = roofline(prof)
     kernels = {k: {"launches": v["launches"], "ms": round(v["ms"], 3),
                    "avg_us": round(1e3 * v["ms"] / max(v["launches"], 1), 3),
                    "tflops": round(v["flops"] / max(v["ms"], 1e-9) / 1e9, 3),
                    "gbps": round(v["bytes"] / max(v["ms"], 1e-9) / 1e6, 1)}
                for k, v in sorted(prof.items(), key=lambda kv: -kv[1]["ms"])}
+    amps = args.steps * B * 64
+    return grid, {"value": amps / dt, "ms_per_step": 1e3 * dt / args.steps,
+                  "tflops": flops / dt / 1e12, "dominant_kernel": dom, "roofline": roof,
+                  "kernels": kernels, "grid_build_s": build_s}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--bitstrings", type=int, default=4, help="bit-strings per step")
+    ap.add_argument("--precision", default="both", choices=["both", "c64", "split_bf16"])
+    ap.add_argument("--cpu-slices", type=int, default=3, help="oracle sample size (slices)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import rqc_inputs as R
+    from paper_1811_09599_amd import plan_describe
+
+    torch.cuda.set_device(0)
+    rows = cols = 7
+    circ = R.grid_rqc(rows, cols, 32, 2000)
+    open_q = R.grid_ids((rows, cols), [(5, 0), (5, 1), (5, 2), (6, 0), (6, 1), (6, 2)])
+    all_bits = R.bitstrings(rows * cols, 1024, 2500, open_q)
+    plan = plan_describe(circ, open_qubits=open_q)
+    precs = ["split_bf16", "c64"] if args.precision == "both" else [args.precision]
+    results, grids = {}, {}
+    for p in precs:
+        grids[p], results[p] = run_precision(p, circ, open_q, all_bits, args)
+    head = precs[0]
+    r = results[head]
     res = {
-        "metric": "amplitudes/s", "value": amps / dt, "unit": "amplitudes/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * dt / args.steps,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "c64",
-        "data": "synthetic",
+        "metric": "amplitudes/s", "value": r["value"], "unit": "amplitudes/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16x3" if head == "split_bf16" else "c64", "data": "synthetic",
         "config": {"workload": "7x7 RQC depth 1+32+1 (bond dim 16), quadrant plan with 2 cuts "
                                "(256 slices, fidelity 1), 6-qubit open batch (64 amplitudes "
-                               "per bit-string), %d bit-strings per step" % B,
+                               "per bit-string), %d bit-strings per step" % args.bitstrings,
                    "grid": "7x7", "depth": "1+32+1", "slices": plan["num_slices"],
-                   "fidelity": 1.0, "amplitudes_per_bitstring": 64, "bitstrings_per_step": B,
-                   "plan_flops_per_bitstring": plan["flops_all_slices"], "precision": "c64"},
-        "tflops": flops / dt / 1e12,
-        "tflops_frac_fp32_mfma_peak": flops / dt / 1e12 / PEAK["mfma"][0],
-        "dominant_kernel": dom, "roofline": roof, "kernels": kernels,
-        "grid_build_s": build_s,
+                   "fidelity": 1.0, "amplitudes_per_bitstring": 64,
+                   "bitstrings_per_step": args.bitstrings,
+                   "plan_flops_per_bitstring": plan["flops_all_slices"], "precision": head},
+        "tflops": r["tflops"], "tflops_frac_fp32_mfma_peak": r["tflops"] / PEAK["mfma_fp32"][0],
+        "dominant_kernel": r["dominant_kernel"], "roofline": r["roofline"],
+        "kernels": r["kernels"], "grid_build_s": r["grid_build_s"],
+        "precisions": {p: {k: v for k, v in results[p].items() if k != "kernels"}
+                       for p in precs},
     }
+    if len(precs) == 2:
+        res["speedup_split_bf16_vs_c64"] = results["split_bf16"]["value"] / results["c64"]["value"]
     if not args.no_cpu_baseline:
-        res.update(cpu_baseline(circ, grid, all_bits[:1], open_q, args.cpu_slices, rows, cols))
+        res.update(cpu_baseline(circ, grids, all_bits[:1], open_q, args.cpu_slices, rows, cols))
     print(json.dumps(res), flush=True)
 
 
-def cpu_baseline(circ, grid, bits, open_q, n_slices, rows, cols):
+def cpu_baseline(circ, grids, bits, open_q, n_slices, rows, cols):
     """The FP64 oracle (E2) on a bounded sample: n_slices slices of one bit-string batch,
-    extrapolated to all slices; plus the GPU-vs-oracle error on the same slices."""
+    extrapolated to all slices; plus each precision's error against it on the same slices."""
     import numpy as np
     import torch
 
     from oracle import metrics
     from oracle import tn as E2
 
+    grid = next(iter(grids.values()))
     S = grid.num_slices()
     ids = sorted(set(int(round(x)) for x in np.linspace(0, S - 1, n_slices)))
     cuts = grid.plan_cuts()
@@ -142,8 +171,12 @@ def cpu_baseline(circ, grid, bits, open_q, n_slices, rows, cols):
         ref = net.amplitudes(bits, open_q, cuts=cuts, slice_ids=ids,
                              order=E2.quadrant_order(rows, cols)).numpy()
     dt = time.perf_counter() - t0
-    gpu = grid.contract_amplitudes(bits, slice_ids=ids).cpu().numpy()
-    err = metrics.amp_errors(gpu, ref, rows * cols)
+    parity = {"slices": ids, "amplitudes": int(ref.size)}
+    for p, g in grids.items():
+        gpu = g.contract_amplitudes(bits, slice_ids=ids).cpu().numpy()
+        err = metrics.amp_errors(gpu, ref, rows * cols)
+        parity[p] = {"max_rel_err": err["max"], "median_rel_err": err["median"],
+                     "l2_rel_err": err["l2"], "tol": SPLIT_TOL if p == "split_bf16" else C64_TOL}
     per_slice = dt / len(ids)
     rate = 64.0 / (per_slice * S)
     return {"cpu_baseline": {"value": rate, "unit": "amplitudes/s",
@@ -151,9 +184,7 @@ def cpu_baseline(circ, grid, bits, open_q, n_slices, rows, cols):
                              "sample": "%d of %d slices of one 64-amplitude batch (FP64 tensor "
                                        "network, no reuse across slices), %.1f s; rate "
                                        "extrapolated to all %d slices" % (len(ids), S, dt, S)},
-            "parity": {"slices": ids, "amplitudes": int(gpu.size), "max_rel_err": err["max"],
-                       "median_rel_err": err["median"], "l2_rel_err": err["l2"],
-                       "tol": 1e-5}}
+            "parity": parity}
 
 
 if __name__ == "__main__":

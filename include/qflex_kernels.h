@@ -34,6 +34,17 @@ qflex_status qflex_permute_c64(const void* in, void* out, int32_t nbits, const i
 qflex_status qflex_gemm_c64(const void* A, const void* B, void* C, int64_t M, int64_t N,
                             int64_t K, int32_t ta, int32_t tb, int64_t batch, void* stream);
 
+/* The same product in split precision (QFLEX_PREC_SPLIT_BF16): each complex64 operand is
+ * split into hi + lo bf16 parts, the three products hi*hi + hi*lo + lo*hi of each real part
+ * run on bf16 MFMA with FP32 accumulation (lo*lo is dropped), giving about 16 significant bits
+ * per operand instead of 24.  M, N, K must be powers of two with M >= 128, N >= 64, K >= 16.
+ * workspace: device memory of at least qflex_gemm_split_workspace(M, N, K, batch) bytes that
+ * the call uses for the split operands (it allocates nothing itself). */
+qflex_status qflex_gemm_split_c64(const void* A, const void* B, void* C, int64_t M, int64_t N,
+                                  int64_t K, int32_t ta, int32_t tb, int64_t batch,
+                                  void* workspace, int64_t workspace_bytes, void* stream);
+int64_t qflex_gemm_split_workspace(int64_t M, int64_t N, int64_t K, int64_t batch);
+
 /* Kernel variant qflex_gemm_c64 uses for a shape: 0 SIMT, 1 MFMA 64x64, 2 MFMA 128x128. */
 int32_t qflex_gemm_variant(int64_t M, int64_t N, int64_t K);
 

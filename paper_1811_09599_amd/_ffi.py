@@ -43,8 +43,9 @@ class KernelStat(C.Structure):
 
 EXPORTS = ("qflex_build_grid", "qflex_num_slices", "qflex_plan_cuts", "qflex_plan_describe",
            "qflex_contract_amplitudes", "qflex_last_stats", "qflex_set_profiling",
-           "qflex_profile_read", "qflex_permute_c64",
-           "qflex_gemm_c64", "qflex_select_slices", "qflex_gemm_variant", "qflex_grid_free",
+           "qflex_profile_read", "qflex_permute_c64", "qflex_gemm_split_c64",
+           "qflex_gemm_c64", "qflex_select_slices", "qflex_gemm_split_workspace",
+           "qflex_gemm_variant", "qflex_grid_free",
            "qflex_last_error")
 
 _lib = None
@@ -83,7 +84,11 @@ def lib():
     L.qflex_grid_free.argtypes = [P]
     L.qflex_grid_free.restype = None
     L.qflex_last_error.restype = C.c_char_p
-    for name in EXPORTS[:-3]:
+    L.qflex_gemm_split_c64.argtypes = [P, P, P, C.c_int64, C.c_int64, C.c_int64, C.c_int32,
+                                       C.c_int32, C.c_int64, P, C.c_int64, P]
+    L.qflex_gemm_split_workspace.argtypes = [C.c_int64] * 4
+    L.qflex_gemm_split_workspace.restype = C.c_int64
+    for name in EXPORTS[:-4]:
         getattr(L, name).restype = C.c_int
     _lib = L
     return L

@@ -35,6 +35,8 @@ void release(qflex_grid* g) {
   (void)hipDeviceSynchronize();
   if (g->grid) (void)hipFree(g->grid);
   if (g->bidx) (void)hipFree(g->bidx);
+  if (g->grid_split) (void)hipFree(g->grid_split);
+  g->split_scratch.release();
   g->arena.release();
   g->amps64.release();
   g->offs.release();
@@ -74,8 +76,8 @@ qflex_status qflex_build_grid(const qflex_circuit* circuits, int32_t n_circuits,
         cs.plan = qflex::make_plan(cs.model, *opt);
         g->circ.push_back(std::move(cs));
       }
-      if (opt->precision != QFLEX_PREC_C64)
-        qflex::fail(QFLEX_E_UNSUPPORTED, "split-precision products are not built in");
+      if (opt->precision == QFLEX_PREC_SPLIT_FP16)
+        qflex::fail(QFLEX_E_UNSUPPORTED, "split fp16 products are not built in");
       int dev = 0;
       hipError_t e = hipGetDevice(&dev);
       if (e != hipSuccess) qflex::fail(QFLEX_E_DEVICE, std::string("no HIP device: ") + hipGetErrorString(e));
@@ -220,6 +222,64 @@ qflex_status qflex_gemm_c64(const void* A, const void* B, void* C, int64_t M, in
         ((reinterpret_cast<uintptr_t>(A) | reinterpret_cast<uintptr_t>(B)) & 15))
       qflex::fail(QFLEX_E_INVALID, "A and B must be 16-byte aligned");
     qflex::dev::gemm(g, static_cast<hipStream_t>(stream));
+  });
+}
+
+int64_t qflex_gemm_split_workspace(int64_t M, int64_t N, int64_t K, int64_t batch) {
+  if (M < 1 || N < 1 || K < 1 || batch < 1) return 0;
+  return (int64_t)sizeof(uint16_t) * 4 * batch * (M * K + N * K);
+}
+
+qflex_status qflex_gemm_split_c64(const void* A, const void* B, void* C, int64_t M, int64_t N,
+                                  int64_t K, int32_t ta, int32_t tb, int64_t batch,
+                                  void* workspace, int64_t workspace_bytes, void* stream) {
+  return guarded([&] {
+    if (!A || !B || !C || !workspace) qflex::fail(QFLEX_E_INVALID, "NULL argument");
+    auto log2i = [](int64_t v) {
+      int b = 0;
+      while ((int64_t(1) << b) < v) ++b;
+      return ((int64_t(1) << b) == v) ? b : -1;
+    };
+    const int mb = log2i(M), nb = log2i(N), kb = log2i(K);
+    if (mb < 0 || nb < 0 || kb < 0) qflex::fail(QFLEX_E_INVALID, "M, N, K must be powers of two");
+    if (!qflex::dev::gemm_split_ok(M, N, K) || mb + kb > 40 || nb + kb > 40)
+      qflex::fail(QFLEX_E_INVALID, "shape too small or too large for the split product");
+    if (batch < 1 || batch > 65535) qflex::fail(QFLEX_E_INVALID, "batch must be in [1, 65535]");
+    if ((ta != 0 && ta != 1) || (tb != 0 && tb != 1)) qflex::fail(QFLEX_E_INVALID, "ta/tb must be 0 or 1");
+    if (workspace_bytes < qflex_gemm_split_workspace(M, N, K, batch))
+      qflex::fail(QFLEX_E_INVALID, "workspace too small");
+    if (reinterpret_cast<uintptr_t>(workspace) & 15)
+      qflex::fail(QFLEX_E_INVALID, "workspace must be 16-byte aligned");
+    // bit permutation transposing [R][C] (rb, cb bits) into [C][R]
+    auto transpose = [](int rb, int cb) {
+      std::vector<int> p(rb + cb);
+      for (int j = 0; j < rb + cb; ++j) p[j] = j < rb ? cb + j : j - rb;
+      return p;
+    };
+    std::vector<int> pa(mb + kb), pbv(nb + kb);
+    for (int j = 0; j < mb + kb; ++j) pa[j] = j;
+    for (int j = 0; j < nb + kb; ++j) pbv[j] = j;
+    if (ta) pa = transpose(kb, mb);   // stored [K][M] -> [M][K]
+    if (!tb) pbv = transpose(kb, nb); // stored [K][N] -> [N][K]
+    auto* sa = static_cast<uint16_t*>(workspace);
+    auto* sb = sa + 4 * batch * M * K;
+    const hipStream_t st = static_cast<hipStream_t>(stream);
+    qflex::dev::split_permute(static_cast<const float2*>(A), sa, batch,
+                              qflex::dev::make_perm_tile(mb + kb, pa.data()), kb, st);
+    qflex::dev::split_permute(static_cast<const float2*>(B), sb, batch,
+                              qflex::dev::make_perm_tile(nb + kb, pbv.data()), kb, st);
+    qflex::dev::GemmSplit g;
+    g.A = sa;
+    g.B = sb;
+    g.C = static_cast<float2*>(C);
+    g.M = M;
+    g.N = N;
+    g.K = K;
+    g.a_bs = M * K;
+    g.b_bs = N * K;
+    g.c_bs = M * N;
+    g.batch = (int)batch;
+    qflex::dev::gemm_split(g, st);
   });
 }
 

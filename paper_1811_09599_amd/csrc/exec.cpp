@@ -98,6 +98,8 @@ void Profiler::release() {
 }
 
 // ------------------------------------------------------------------------------ grid build
+void prepare_split(qflex_grid* g, hipStream_t s);
+
 void build_grid_device(qflex_grid* g, hipStream_t s) {
   std::vector<dev::GridPiece> pieces;
   std::vector<double2> mats;
@@ -208,6 +210,66 @@ void build_grid_device(qflex_grid* g, hipStream_t s) {
       if (st.scratch_y >= 0) cs.py[i] = dev::make_perm_tile(st.py.nbits, st.py.perm.data());
     }
   }
+  if (g->precision == QFLEX_PREC_SPLIT_BF16) prepare_split(g, s);
+}
+
+// Split-precision set-up: choose the steps that run as bf16 products, pre-split the qubit
+// tensors they read (A layout for a row operand, B layout for a column operand; the fixed
+// leading bits stay leading so that bit-string and cut offsets only scale), and build the
+// permute+split descriptors of intermediate operands.
+void prepare_split(qflex_grid* g, hipStream_t s) {
+  int64_t total = 0;
+  struct Job {
+    int64_t src, dst;
+    int nfixed, nbits, kbits;
+    bool role_b;
+    PermDesc pd;
+  };
+  std::vector<Job> jobs;
+  for (auto& cs : g->circ) {
+    const Plan& P = cs.plan;
+    const size_t ns = P.steps.size();
+    cs.split.assign(ns, 0);
+    cs.sx.assign(ns, dev::PermTile{});
+    cs.sy.assign(ns, dev::PermTile{});
+    cs.qsplit_offset.assign(cs.model.n, -1);
+    cs.split_a_elems = cs.split_b_elems = 0;
+    for (size_t i = 0; i < ns; ++i) {
+      const Step& st = P.steps[i];
+      const int64_t M = int64_t(1) << st.mb, N = int64_t(1) << st.nb, K = int64_t(1) << st.kb;
+      if (!dev::gemm_split_ok(M, N, K)) continue;
+      cs.split[i] = 1;
+      const std::vector<int> xa = [&] { auto v = st.mlab; v.insert(v.end(), st.klab.begin(), st.klab.end()); return v; }();
+      const std::vector<int> yb = [&] { auto v = st.nlab; v.insert(v.end(), st.klab.begin(), st.klab.end()); return v; }();
+      for (int side = 0; side < 2; ++side) {
+        const Operand& o = side ? st.y : st.x;
+        const std::vector<int>& in = side ? st.y_in : st.x_in;
+        const std::vector<int>& want = side ? yb : xa;
+        const PermDesc pd = make_perm_desc(in, want);
+        if (o.qubit) {
+          const QubitLayout& L = P.qubits[o.id];
+          Job j{cs.grid_offset + cs.qubit_offset[o.id], total, L.n_fixed, L.free_bits(), st.kb,
+                side == 1, pd};
+          cs.qsplit_offset[o.id] = total;
+          total += ((int64_t(4) << L.storage.size()) + 63) & ~int64_t(63);
+          jobs.push_back(j);
+        } else {
+          (side ? cs.sy[i] : cs.sx[i]) = dev::make_perm_tile(pd.nbits, pd.perm.data());
+          const int64_t e = int64_t(4) << P.nodes[o.id].labels.size();
+          if (side) cs.split_b_elems = std::max(cs.split_b_elems, e);
+          else cs.split_a_elems = std::max(cs.split_a_elems, e);
+        }
+      }
+    }
+  }
+  if (total == 0) return;
+  QHIP(hipMalloc(&g->grid_split, sizeof(uint16_t) * total));
+  for (const Job& j : jobs) {
+    const dev::PermTile t = dev::make_perm_tile(j.nbits, j.pd.perm.data());
+    dev::split_permute(g->grid + j.src, g->grid_split + j.dst, int64_t(1) << j.nfixed, t,
+                       j.kbits, s);
+  }
+  QHIP(hipStreamSynchronize(s));
 }
 
 // ------------------------------------------------------------------------------ slices
@@ -330,6 +392,12 @@ void contract(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets, dou
     arena_need = std::max(arena_need, sizeof(float2) * (size_t)(P.arena_elems * B));
   }
   g->arena.reserve(arena_need);
+  size_t split_need = 0;
+  for (int c = 0; c < nc; ++c)
+    split_need = std::max(split_need, sizeof(uint16_t) * (size_t)batch[c] *
+                                          (size_t)(g->circ[c].split_a_elems +
+                                                   g->circ[c].split_b_elems));
+  if (split_need) g->split_scratch.reserve(split_need);
   g->amps64.reserve(sizeof(double2) * std::max<int64_t>(amp_total, 1));
   float2* arena = static_cast<float2*>(g->arena.p);
   double2* acc_all = static_cast<double2*>(g->amps64.p);
@@ -377,6 +445,54 @@ void contract(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets, dou
           const Step& stp = P.steps[k];
           if (si > 0 && !(stp.deps & changed)) continue;
           View x = view(stp.x), y = view(stp.y);
+          if (!cs.split.empty() && cs.split[k]) {
+            uint16_t* sa = static_cast<uint16_t*>(g->split_scratch.p);
+            uint16_t* sb = sa + B * cs.split_a_elems;
+            dev::GemmSplit gs;
+            const int64_t M = int64_t(1) << stp.mb, N = int64_t(1) << stp.nb;
+            const int64_t K = int64_t(1) << stp.kb;
+            if (stp.x.qubit) {
+              gs.A = g->grid_split + cs.qsplit_offset[stp.x.id];
+              gs.a_add = x.add;
+              gs.a_off = x.off;
+            } else {
+              g->prof.begin("split_permute", 0, 16.0 * M * K * nb, s);
+              dev::split_permute(x.base, sa, nb, cs.sx[k], stp.kb, s);
+              g->prof.end(s);
+              st.permute_bytes += 16.0 * M * K * nb;
+              ++st.n_permute;
+              gs.A = sa;
+              gs.a_bs = M * K;
+            }
+            if (stp.y.qubit) {
+              gs.B = g->grid_split + cs.qsplit_offset[stp.y.id];
+              gs.b_add = y.add;
+              gs.b_off = y.off;
+            } else {
+              g->prof.begin("split_permute", 0, 16.0 * N * K * nb, s);
+              dev::split_permute(y.base, sb, nb, cs.sy[k], stp.kb, s);
+              g->prof.end(s);
+              st.permute_bytes += 16.0 * N * K * nb;
+              ++st.n_permute;
+              gs.B = sb;
+              gs.b_bs = N * K;
+            }
+            const Node& out = P.nodes[stp.out];
+            gs.C = arena + out.offset * B;
+            gs.c_bs = out.elems();
+            gs.M = M;
+            gs.N = N;
+            gs.K = K;
+            gs.batch = nb;
+            // the kernel's own arithmetic: 3 bf16 products per real product, 24*M*N*K flops
+            g->prof.begin(dev::gemm_split_name(gs), 3.0 * stp.flops() * nb,
+                          8.0 * nb * (double)(M * K + N * K + M * N), s);
+            dev::gemm_split(gs, s);
+            g->prof.end(s);
+            st.flops += stp.flops() * nb;
+            ++st.n_gemm;
+            continue;
+          }
           if (stp.scratch_x >= 0) {
             if (stp.x.qubit) fail(QFLEX_E_DEVICE, "internal: permutation of a qubit tensor");
             float2* dst = arena + P.nodes[stp.scratch_x].offset * B;

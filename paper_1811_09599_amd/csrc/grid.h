@@ -22,6 +22,11 @@ struct CircuitState {
   std::vector<int64_t> qubit_offset; // element offset of each qubit tensor (within the grid)
   int64_t bidx_offset = 0;           // offset of its batch-index table in the device table
   std::vector<dev::PermTile> px, py; // per step (valid when the step permutes x / y)
+  // split-precision products
+  std::vector<char> split;           // per step: runs as a split bf16 product
+  std::vector<dev::PermTile> sx, sy; // per step: node operand -> split operand layout
+  std::vector<int64_t> qsplit_offset;// per qubit: bf16 offset in grid_split, -1 if none
+  int64_t split_a_elems = 0, split_b_elems = 0;  // scratch per bit-string (bf16 values)
 };
 
 // Device buffer that only grows; freed with the grid.
@@ -73,6 +78,8 @@ struct qflex_grid {
   float2* grid = nullptr;                // all qubit tensors
   int64_t grid_elems = 0;
   uint32_t* bidx = nullptr;              // batch-index tables of all circuits
+  uint16_t* grid_split = nullptr;        // qubit tensors pre-split for bf16 products
+  qflex::DevBuf split_scratch;           // split operands of intermediates
   qflex::DevBuf arena;                   // intermediates
   qflex::DevBuf amps64;                  // FP64 amplitude accumulator
   qflex::DevBuf offs;                    // per-bit-string output offsets of the qubit tensors

@@ -64,6 +64,32 @@ int gemm_variant(const Gemm& g);
 const char* gemm_name(const Gemm& g);  // kernel name used by the profiler
 void gemm(const Gemm& g, hipStream_t s);
 
+// ---------------------------------------------------------------- split-precision products
+// A complex product C = A B runs with both operands stored "K-major" ([rows][K]) in a compact
+// split layout: each complex value x = xr + i xi is split per part into hi = bf16(x) and
+// lo = bf16(x - hi), and every group of 4 consecutive k of a row is stored as 16 bf16
+//   [rh(k0..k3), ih(k0..k3), rl(k0..k3), il(k0..k3)]            (32 bytes, 8 per complex)
+// The product accumulates hi*hi + hi*lo + lo*hi of every real part in FP32 on bf16 MFMA
+// (lo*lo is dropped): about 16 significant bits per operand instead of 24.
+// Permute (as permute()) into [rows][K] order, K the low kbits bits, and split.
+void split_permute(const float2* in, uint16_t* out, int64_t batch, const PermTile& t, int kbits,
+                   hipStream_t s);
+
+struct GemmSplit {
+  const uint16_t* A = nullptr;  // [M][K] split, row stride 4K bf16
+  const uint16_t* B = nullptr;  // [N][K] split
+  float2* C = nullptr;          // [M][N] complex64
+  const int64_t* a_off = nullptr;  // per-batch offsets in complex elements (x4 bf16)
+  const int64_t* b_off = nullptr;
+  int64_t a_bs = 0, b_bs = 0, c_bs = 0;  // batch strides: complex elements
+  int64_t a_add = 0, b_add = 0;          // complex elements
+  int64_t M = 0, N = 0, K = 0;
+  int batch = 1;
+};
+bool gemm_split_ok(int64_t M, int64_t N, int64_t K);  // shape fits the tiled kernel
+void gemm_split(const GemmSplit& g, hipStream_t s);
+const char* gemm_split_name(const GemmSplit& g);
+
 // ---------------------------------------------------------------- reductions
 // amps[b*amp_stride + bidx[e]] += res[b][e] for e < n, b < batch (FP64 accumulation)
 void accumulate(const float2* res, const int64_t* r_off, int64_t r_bs, int64_t r_add, int64_t n,

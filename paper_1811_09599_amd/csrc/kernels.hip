@@ -398,6 +398,239 @@ void gemm(const Gemm& g, hipStream_t s) {
 }
 
 // =============================================================================================
+// Split-precision complex products on bf16 MFMA (see kernels.h for the operand layouts).
+// =============================================================================================
+__device__ inline uint16_t bf16_rne(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even (finite inputs)
+  return (uint16_t)(u >> 16);
+}
+__device__ inline float bf16_to_f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// One thread per group of 4 consecutive k of a row: the tile's write order starts with the
+// lowest output bits, so a group is 4 consecutive write indices and is stored as two 16-byte
+// vectors.
+__global__ void __launch_bounds__(256) split_permute_kernel(const float2* __restrict__ in,
+                                                            uint16_t* __restrict__ out,
+                                                            const PermTile t) {
+  __shared__ float2 tile[(1 << kPermMaxTile) + (1 << kPermMaxTile) / 32];
+  const int64_t n_el = int64_t(1) << t.nbits;
+  in += (int64_t)blockIdx.y * n_el;
+  out += (int64_t)blockIdx.y * n_el * 4;
+  const int64_t T = blockIdx.x;
+  int64_t in_base = 0, out_base = 0;
+  for (int r = 0; r < t.nrest; ++r) {
+    const int64_t bit = (T >> r) & 1;
+    in_base |= bit << t.rest_in[r];
+    out_base |= bit << t.rest_out[r];
+  }
+  const int tsize = 1 << t.tile_bits;
+  for (int i = threadIdx.x; i < tsize; i += blockDim.x) {
+    int64_t off = in_base;
+#pragma unroll
+    for (int b = 0; b < kPermMaxTile; ++b)
+      if (b < t.tile_bits) off |= (int64_t)((i >> b) & 1) << t.tile_in[b];
+    tile[lds_pad(i)] = in[off];
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < tsize / 4; q += blockDim.x) {
+    uint16_t h[16];
+    int64_t e0 = 0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int j = 4 * q + u;
+      int i = 0;
+      int64_t e = out_base;
+#pragma unroll
+      for (int b = 0; b < kPermMaxTile; ++b)
+        if (b < t.tile_bits) {
+          const int bit = (j >> b) & 1;
+          i |= bit << t.j2i[b];
+          e |= (int64_t)bit << t.tile_out[b];
+        }
+      if (u == 0) e0 = e;
+      const float2 v = tile[lds_pad(i)];
+      const uint16_t rh = bf16_rne(v.x), ih = bf16_rne(v.y);
+      h[u] = rh;
+      h[4 + u] = ih;
+      h[8 + u] = bf16_rne(v.x - bf16_to_f(rh));
+      h[12 + u] = bf16_rne(v.y - bf16_to_f(ih));
+    }
+    uint4 lo, hi;
+    lo.x = h[0] | ((uint32_t)h[1] << 16);
+    lo.y = h[2] | ((uint32_t)h[3] << 16);
+    lo.z = h[4] | ((uint32_t)h[5] << 16);
+    lo.w = h[6] | ((uint32_t)h[7] << 16);
+    hi.x = h[8] | ((uint32_t)h[9] << 16);
+    hi.y = h[10] | ((uint32_t)h[11] << 16);
+    hi.z = h[12] | ((uint32_t)h[13] << 16);
+    hi.w = h[14] | ((uint32_t)h[15] << 16);
+    uint4* o = reinterpret_cast<uint4*>(out + 4 * e0);  // e0 is a multiple of 4
+    o[0] = lo;
+    o[1] = hi;
+  }
+}
+
+void split_permute(const float2* in, uint16_t* out, int64_t batch, const PermTile& t, int kbits,
+                   hipStream_t s) {
+  if (batch < 1 || batch > 65535) throw std::runtime_error("split_permute: bad batch");
+  // a thread's 4 consecutive write indices must be the 4 lowest k of one row
+  if (kbits < 2 || t.tile_bits < 2 || t.tile_out[0] != 0 || t.tile_out[1] != 1)
+    throw std::runtime_error("split_permute: K must be >= 4 and the tile must hold the 2 lowest bits");
+  const int64_t tiles = int64_t(1) << t.nrest;
+  hipLaunchKernelGGL(split_permute_kernel, dim3((unsigned)tiles, (unsigned)batch), dim3(256), 0,
+                     s, in, out, t);
+  check_launch("split_permute");
+}
+
+// Complex product on bf16 MFMA from the compact split layout.  256 threads = 2x2 wavefronts,
+// each owning a 64x64 complex block = 2x2 sub-tiles of v_mfma_f32_32x32x16_bf16 with separate
+// real and imaginary accumulators.  One instruction step covers 8 complex k: lanes 0-31 hold
+// k-group g, lanes 32-63 group g+1, each lane's 8 bf16 being [re(4 k), im(4 k)] of one part:
+//   Cr += Ah.Brh + Ah.Brl + Al.Brh,  Brh = [Br_h, -Bi_h]
+//   Ci += Ah.Bih + Ah.Bil + Al.Bih,  Bih = [Bi_h,  Br_h]
+// (Brh / Bih are built from one 16-byte LDS read by a sign flip / a half swap).  k-tiles of
+// 16 complex are staged in LDS (rows of 128 bytes padded to 144), double buffered; the next
+// tile's global loads are issued before the current tile's MFMAs.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+__device__ inline bf16x8 as_bf16x8(uint4 v) {
+  bf16x8 r;
+  __builtin_memcpy(&r, &v, 16);
+  return r;
+}
+
+template <int BM, int BN>
+__global__ void __launch_bounds__(256) gemm_split_kernel(const GemmSplit g) {
+  constexpr int BK = 16;                 // complex k per tile
+  constexpr int ROW = BK * 4;            // bf16 per row per tile (128 bytes)
+  constexpr int LDR = ROW + 8;           // padded row (144 bytes)
+  constexpr int TMI = BM / 64, TNI = BN / 64;
+  constexpr int AV = BM * ROW / 8 / 256, BV = BN * ROW / 8 / 256;  // uint4 loads per thread
+  __shared__ __attribute__((aligned(16))) uint16_t As[2][BM * LDR];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[2][BN * LDR];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int h = lane >> 5, r = lane & 31;
+  const int64_t tiles_n = g.N / BN;
+  const int64_t tm = (int64_t)blockIdx.x / tiles_n, tn = (int64_t)blockIdx.x % tiles_n;
+  const int b = blockIdx.y;
+  const uint16_t* __restrict__ A = g.A + 4 * (g.a_add + (g.a_off ? g.a_off[b] : b * g.a_bs));
+  const uint16_t* __restrict__ B = g.B + 4 * (g.b_add + (g.b_off ? g.b_off[b] : b * g.b_bs));
+  float2* __restrict__ C = g.C + b * g.c_bs;
+  const int64_t lda = 4 * g.K, ldb = 4 * g.K;
+  const int64_t m0 = tm * BM, n0 = tn * BN;
+
+  uint4 ra[AV], rb[BV];
+  auto gload = [&](int64_t k0) {  // k0 in bf16 units along the row
+#pragma unroll
+    for (int v = 0; v < AV; ++v) {
+      const int e = tid + v * 256, row = e >> 3, ch = e & 7;
+      ra[v] = *reinterpret_cast<const uint4*>(A + (m0 + row) * lda + k0 + 8 * ch);
+    }
+#pragma unroll
+    for (int v = 0; v < BV; ++v) {
+      const int e = tid + v * 256, row = e >> 3, ch = e & 7;
+      rb[v] = *reinterpret_cast<const uint4*>(B + (n0 + row) * ldb + k0 + 8 * ch);
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int v = 0; v < AV; ++v) {
+      const int e = tid + v * 256, row = e >> 3, ch = e & 7;
+      *reinterpret_cast<uint4*>(&As[buf][row * LDR + 8 * ch]) = ra[v];
+    }
+#pragma unroll
+    for (int v = 0; v < BV; ++v) {
+      const int e = tid + v * 256, row = e >> 3, ch = e & 7;
+      *reinterpret_cast<uint4*>(&Bs[buf][row * LDR + 8 * ch]) = rb[v];
+    }
+  };
+  floatx16 cr[TMI][TNI], ci[TMI][TNI];
+#pragma unroll
+  for (int i = 0; i < TMI; ++i)
+#pragma unroll
+    for (int j = 0; j < TNI; ++j)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) cr[i][j][v] = ci[i][j][v] = 0.f;
+  const int nk = (int)(g.K / BK);
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < nk) gload((int64_t)(kt + 1) * ROW);
+    const uint16_t* as = As[buf];
+    const uint16_t* bs = Bs[buf];
+#pragma unroll
+    for (int s2 = 0; s2 < BK / 8; ++s2) {
+      const int col = 16 * (2 * s2 + h);  // this lane's 4-k group, in bf16
+      bf16x8 ah[TMI], al[TMI], brh[TNI], brl[TNI], bih[TNI], bil[TNI];
+#pragma unroll
+      for (int i = 0; i < TMI; ++i) {
+        const uint16_t* p = &as[(wm * (BM / 2) + i * 32 + r) * LDR + col];
+        ah[i] = as_bf16x8(*reinterpret_cast<const uint4*>(p));
+        al[i] = as_bf16x8(*reinterpret_cast<const uint4*>(p + 8));
+      }
+#pragma unroll
+      for (int j = 0; j < TNI; ++j) {
+        const uint16_t* p = &bs[(wn * (BN / 2) + j * 32 + r) * LDR + col];
+        const uint4 vh = *reinterpret_cast<const uint4*>(p);
+        const uint4 vl = *reinterpret_cast<const uint4*>(p + 8);
+        brh[j] = as_bf16x8(make_uint4(vh.x, vh.y, vh.z ^ 0x80008000u, vh.w ^ 0x80008000u));
+        brl[j] = as_bf16x8(make_uint4(vl.x, vl.y, vl.z ^ 0x80008000u, vl.w ^ 0x80008000u));
+        bih[j] = as_bf16x8(make_uint4(vh.z, vh.w, vh.x, vh.y));
+        bil[j] = as_bf16x8(make_uint4(vl.z, vl.w, vl.x, vl.y));
+      }
+#pragma unroll
+      for (int i = 0; i < TMI; ++i)
+#pragma unroll
+        for (int j = 0; j < TNI; ++j) {
+          cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], brh[j], cr[i][j], 0, 0, 0);
+          ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bih[j], ci[i][j], 0, 0, 0);
+          cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], brl[j], cr[i][j], 0, 0, 0);
+          ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bil[j], ci[i][j], 0, 0, 0);
+          cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], brh[j], cr[i][j], 0, 0, 0);
+          ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], bih[j], ci[i][j], 0, 0, 0);
+        }
+    }
+    if (kt + 1 < nk) sstore(buf ^ 1);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < TMI; ++i)
+#pragma unroll
+    for (int j = 0; j < TNI; ++j)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int row = wm * (BM / 2) + i * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
+        const int col = wn * (BN / 2) + j * 32 + r;
+        C[(m0 + row) * g.N + n0 + col] = make_float2(cr[i][j][v], ci[i][j][v]);
+      }
+}
+
+bool gemm_split_ok(int64_t M, int64_t N, int64_t K) {
+  return M > 0 && N > 0 && K > 0 && M % 64 == 0 && N % 64 == 0 && K % 16 == 0;
+}
+
+const char* gemm_split_name(const GemmSplit& g) {
+  return (g.M % 128 == 0 && g.N % 128 == 0) ? "gemm_split_bf16_128x128" : "gemm_split_bf16_64x64";
+}
+
+void gemm_split(const GemmSplit& g, hipStream_t s) {
+  if (!gemm_split_ok(g.M, g.N, g.K)) throw std::runtime_error("gemm_split: unsupported shape");
+  if (g.batch < 1 || g.batch > 65535) throw std::runtime_error("gemm_split: bad batch");
+  if (g.M % 128 == 0 && g.N % 128 == 0) {
+    dim3 grid((unsigned)((g.M / 128) * (g.N / 128)), (unsigned)g.batch);
+    hipLaunchKernelGGL((gemm_split_kernel<128, 128>), grid, dim3(256), 0, s, g);
+  } else {
+    dim3 grid((unsigned)((g.M / 64) * (g.N / 64)), (unsigned)g.batch);
+    hipLaunchKernelGGL((gemm_split_kernel<64, 64>), grid, dim3(256), 0, s, g);
+  }
+  check_launch("gemm_split");
+}
+
+// =============================================================================================
 // FP64 accumulation of a slice's result into the amplitude batch (paper, Methods B.1: the
 // amplitude is the sum of the path contributions; Methods C.1: a fraction of them).
 // =============================================================================================

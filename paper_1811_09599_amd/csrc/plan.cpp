@@ -464,6 +464,13 @@ struct Planner {
       }
     }
     std::vector<int> M = pick(xs, S, false), N = pick(ys, S, false);
+    st.mlab = M;
+    st.klab = pick(xs, S, true);
+    st.nlab = N;
+    st.x_in = x.flexible ? P.qubits[x.op.id].storage : x.labels;
+    st.y_in = y.flexible ? P.qubits[y.op.id].storage : y.labels;
+    if (x.flexible) st.x_in.erase(st.x_in.begin(), st.x_in.begin() + P.qubits[x.op.id].n_fixed);
+    if (y.flexible) st.y_in.erase(st.y_in.begin(), st.y_in.begin() + P.qubits[y.op.id].n_fixed);
     st.mb = (int)M.size();
     st.kb = (int)S.size();
     st.nb = (int)N.size();
@@ -677,6 +684,19 @@ struct Planner {
 };
 
 }  // namespace
+
+PermDesc make_perm_desc(const std::vector<int>& in, const std::vector<int>& out) {
+  PermDesc d;
+  d.nbits = (int)in.size();
+  d.perm.assign(d.nbits, 0);
+  for (int j = 0; j < d.nbits; ++j) {
+    const int lab = out[d.nbits - 1 - j];
+    const int pos = int(std::find(in.begin(), in.end(), lab) - in.begin());
+    if (pos >= d.nbits) fail(QFLEX_E_PLAN, "internal: permutation between different label sets");
+    d.perm[j] = d.nbits - 1 - pos;
+  }
+  return d;
+}
 
 Plan make_plan(const Model& m, const qflex_options& opt) {
   if (opt.n_open < 0 || opt.n_open > 16) fail(QFLEX_E_INVALID, "n_open must be in [0, 16]");

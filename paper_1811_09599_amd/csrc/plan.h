@@ -42,6 +42,9 @@ struct Step {
   bool ta = false, tb = false;  // operand stored transposed ([K][M] / [N][K])
   int mb = 0, kb = 0, nb = 0;   // log2 of M, K, N
   uint32_t deps = 0;
+  // label orders of the product: rows (M), contracted (K), columns (N); and the storage
+  // orders of x and y as they come in (free labels only for qubit tensors)
+  std::vector<int> mlab, klab, nlab, x_in, y_in;
   double flops() const { return 8.0 * std::ldexp(1.0, mb + kb + nb); }
 };
 
@@ -81,5 +84,8 @@ struct Plan {
 };
 
 Plan make_plan(const Model& m, const qflex_options& opt);
+
+// Permutation taking a tensor stored with labels `in` to storage order `out` (same labels).
+PermDesc make_perm_desc(const std::vector<int>& in, const std::vector<int>& out);
 
 }  // namespace qflex

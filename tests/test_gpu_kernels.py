@@ -130,3 +130,45 @@ def test_gemm_matches_fp64(M, N, K, batch, ta, tb):
     assert rel < 2e-6, rel
     rms = np.sqrt(np.mean(np.abs(want) ** 2))
     assert np.max(np.abs(got - want)) < 2e-5 * rms * max(1.0, np.sqrt(K / 64))
+
+
+SPLIT_SHAPES = [(128, 64, 16, 1), (256, 128, 64, 2), (512, 256, 256, 1), (128, 512, 1024, 1),
+                (1024, 1024, 512, 1), (2048, 64, 4096, 1)]
+
+
+@pytest.mark.parametrize("M,N,K,batch", SPLIT_SHAPES)
+@pytest.mark.parametrize("ta,tb", [(0, 0), (1, 1), (0, 1)])
+def test_split_bf16_gemm_error_bound(M, N, K, batch, ta, tb):
+    """bf16x3 (hi*hi + hi*lo + lo*hi per real part): each operand keeps ~16 significant bits,
+    so the product's relative L2 error is ~1e-5 on random data (measured bound: 3e-5)."""
+    torch = _torch()
+    _say("split gemm", M, N, K, batch, ta, tb)
+    rng = np.random.default_rng(M + 3 * N + 7 * K + batch + 11 * ta + 13 * tb)
+    sa = (batch, K, M) if ta else (batch, M, K)
+    sb = (batch, N, K) if tb else (batch, K, N)
+    a = (rng.standard_normal(sa) + 1j * rng.standard_normal(sa)).astype(np.complex64)
+    b = (rng.standard_normal(sb) + 1j * rng.standard_normal(sb)).astype(np.complex64)
+    A = torch.from_numpy(a).cuda()
+    B = torch.from_numpy(b).cuda()
+    Cm = torch.empty((batch, M, N), dtype=torch.complex64, device="cuda")
+    L = F.lib()
+    ws_bytes = L.qflex_gemm_split_workspace(M, N, K, batch)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+    assert L.qflex_gemm_split_c64(C.c_void_p(A.data_ptr()), C.c_void_p(B.data_ptr()),
+                                  C.c_void_p(Cm.data_ptr()), M, N, K, ta, tb, batch,
+                                  C.c_void_p(ws.data_ptr()), ws_bytes - 1, None) == F.E_INVALID
+    F.check(L.qflex_gemm_split_c64(C.c_void_p(A.data_ptr()), C.c_void_p(B.data_ptr()),
+                                   C.c_void_p(Cm.data_ptr()), M, N, K, ta, tb, batch,
+                                   C.c_void_p(ws.data_ptr()), ws_bytes, None))
+    torch.cuda.synchronize()
+    got = Cm.cpu().numpy()
+    A64 = a.astype(np.complex128)
+    B64 = b.astype(np.complex128)
+    if ta:
+        A64 = np.transpose(A64, (0, 2, 1))
+    if tb:
+        B64 = np.transpose(B64, (0, 2, 1))
+    want = A64 @ B64
+    rel = np.linalg.norm(got - want) / np.linalg.norm(want)
+    _say("  rel_l2", rel)
+    assert rel < 3e-5, rel
