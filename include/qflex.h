@@ -162,6 +162,35 @@ qflex_status qflex_contract_amplitudes(qflex_grid* g, const uint8_t* bits,
                                        const int64_t* slice_offsets, double* amps,
                                        int32_t amps_on_device, void* stream);
 
+/* Gradients of a real loss L of the amplitudes (adjoint contraction).
+ *   bits ... slice_offsets   as for qflex_contract_amplitudes (the same slices are summed).
+ *   cotangent  complex128 [total bit-strings][2^n_open] dL/dRe(amp) + i dL/dIm(amp) (the
+ *              convention of PyTorch's complex autograd, = 2 dL/d(conj amp)), on the device if
+ *              cotangent_on_device; or NULL for the linear cross-entropy of each circuit,
+ *              F = (2^n/m) sum |amp|^2 - 1 over its m amplitudes, as the loss (summed over
+ *              circuits).
+ *   amps       complex128 [total bit-strings][2^n_open] amplitudes (may be NULL).
+ *   grad_gates complex128 dL/dRe(G) + i dL/dIm(G) (same convention) for every entry of every
+ *              gate, circuits in order and
+ *              gates in their input order, 4 entries for a one-qubit gate and 16 for a
+ *              two-qubit gate (row-major, basis ordered by (q0, q1)); may be NULL.  For a gate
+ *              whose off-diagonal 2x2 blocks are exactly zero the entries of those blocks are
+ *              not part of the bond decomposition and get 0.
+ *   grad_params double [total gates][2]: dL/dtheta, dL/dphi of every fSim gate (0 for other
+ *              kinds); may be NULL.
+ *   loss       double [n_circuits]: the linear cross-entropy F of each circuit when cotangent
+ *              is NULL, else NaN; may be NULL.
+ * Outputs are device memory when out_on_device, else host memory; the call returns when they
+ * are written.  Products run in complex64 (FP32 MFMA) whatever the grid's precision; the sum
+ * over bond values and the cross-entropy are reduced in FP64.  QFLEX_E_UNSUPPORTED if a
+ * qubit carries more than 64 gates. */
+qflex_status qflex_contract_grad(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets,
+                                 double fidelity, uint64_t slice_seed, const int64_t* slice_ids,
+                                 const int64_t* slice_offsets, const double* cotangent,
+                                 int32_t cotangent_on_device, double* amps, double* grad_gates,
+                                 double* grad_params, double* loss, int32_t out_on_device,
+                                 void* stream);
+
 /* Statistics of the last contract call. */
 qflex_status qflex_last_stats(const qflex_grid* g, qflex_stats* out);
 

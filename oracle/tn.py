@@ -301,15 +301,16 @@ def linear_xeb_grad(circ, bits, order=None):
     return float(f.detach()), params.grad.numpy().copy()
 
 
-def amplitude_gate_grads(circ, bits, cot, order=None):
-    """E3 for gate entries: with psi_i the amplitudes and cot_i = dL/d(conj psi_i), return
-    dL/d(theta, phi) [n_fsim, 2] = 2 Re sum_i conj(cot_i) dpsi_i/d(theta, phi)."""
+def amplitude_gate_grads(circ, bits, cot, open_qubits=(), cuts=(), slice_ids=None, order=None):
+    """E3 for angles: with psi_i the amplitudes (the partial sum over ``slice_ids`` when
+    given) and cot_i = dL/dRe(psi_i) + i dL/dIm(psi_i), return dL/d(theta, phi) [n_fsim, 2] =
+    Re sum_i conj(cot_i) dpsi_i/d(theta, phi)."""
     params0 = np.array([[g["theta"], g["phi"]] for g in circ["gates"] if g["kind"] == "fsim"],
                        dtype=np.float64).reshape(-1, 2)
     params = torch.tensor(params0, requires_grad=True)
-    psi = Network(circ, params).amplitudes(bits, order=order)
+    psi = Network(circ, params).amplitudes(bits, open_qubits, cuts, slice_ids, order)
     c = torch.as_tensor(np.asarray(cot), dtype=CDT)
-    # L = 2 Re sum conj(cot) psi has dL/dtheta = 2 Re sum conj(cot) dpsi/dtheta
-    loss = 2.0 * torch.real(torch.sum(torch.conj(c) * psi))
+    # L = Re sum conj(cot) psi has dL/dRe psi + i dL/dIm psi = cot
+    loss = torch.real(torch.sum(torch.conj(c) * psi))
     loss.backward()
     return params.grad.numpy().copy()

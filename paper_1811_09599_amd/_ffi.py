@@ -42,7 +42,8 @@ class KernelStat(C.Structure):
 
 
 EXPORTS = ("qflex_build_grid", "qflex_num_slices", "qflex_plan_cuts", "qflex_plan_describe",
-           "qflex_contract_amplitudes", "qflex_last_stats", "qflex_set_profiling",
+           "qflex_contract_amplitudes", "qflex_contract_grad", "qflex_last_stats",
+           "qflex_set_profiling",
            "qflex_profile_read", "qflex_permute_c64", "qflex_gemm_split_c64",
            "qflex_gemm_c64", "qflex_select_slices", "qflex_gemm_split_workspace",
            "qflex_gemm_variant", "qflex_grid_free",
@@ -59,6 +60,13 @@ def lib():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError("libqflex.so is not built (run __graft_entry__.build() or "
                            "python -m paper_1811_09599_amd.build)")
+    # One HIP runtime per process: torch ships its own libamdhip64; loading it first makes
+    # libqflex bind to that same runtime instead of bringing in a second one, so that device
+    # pointers and streams from torch are valid in the library.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = C.CDLL(LIB_PATH)
     P = C.c_void_p
     L.qflex_build_grid.argtypes = [C.POINTER(Circuit), C.c_int32, C.POINTER(Options), P,
@@ -71,6 +79,9 @@ def lib():
     L.qflex_contract_amplitudes.argtypes = [P, C.POINTER(C.c_uint8), C.POINTER(C.c_int64),
                                             C.c_double, C.c_uint64, C.POINTER(C.c_int64),
                                             C.POINTER(C.c_int64), P, C.c_int32, P]
+    L.qflex_contract_grad.argtypes = [P, C.POINTER(C.c_uint8), C.POINTER(C.c_int64), C.c_double,
+                                      C.c_uint64, C.POINTER(C.c_int64), C.POINTER(C.c_int64), P,
+                                      C.c_int32, P, P, P, P, C.c_int32, P]
     L.qflex_last_stats.argtypes = [P, C.POINTER(Stats)]
     L.qflex_set_profiling.argtypes = [P, C.c_int32]
     L.qflex_profile_read.argtypes = [P, C.POINTER(KernelStat), C.c_int32, C.POINTER(C.c_int32)]

@@ -17,7 +17,7 @@ OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libqflex.so")
 
 HIP_SOURCES = ["kernels.hip"]
-HOST_SOURCES = ["model.cpp", "plan.cpp", "exec.cpp", "api.cpp"]
+HOST_SOURCES = ["model.cpp", "plan.cpp", "exec.cpp", "exec_grad.cpp", "api.cpp"]
 ARCH = "gfx950"
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result",

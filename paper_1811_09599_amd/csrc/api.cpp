@@ -37,6 +37,9 @@ void release(qflex_grid* g) {
   if (g->bidx) (void)hipFree(g->bidx);
   if (g->grid_split) (void)hipFree(g->grid_split);
   g->split_scratch.release();
+  for (qflex::DevBuf* b : {&g->gq, &g->gpieces, &g->gmats, &g->gpos, &g->grad_arena, &g->tbar,
+                           &g->pbar, &g->gbar, &g->amps_dev, &g->xeb})
+    b->release();
   g->arena.release();
   g->amps64.release();
   g->offs.release();
@@ -139,6 +142,20 @@ qflex_status qflex_contract_amplitudes(qflex_grid* g, const uint8_t* bits,
     if (!g) qflex::fail(QFLEX_E_INVALID, "NULL grid");
     qflex::contract(g, bits, bs_offsets, fidelity, slice_seed, slice_ids, slice_offsets, amps,
                     amps_on_device != 0, static_cast<hipStream_t>(stream));
+  });
+}
+
+qflex_status qflex_contract_grad(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets,
+                                 double fidelity, uint64_t slice_seed, const int64_t* slice_ids,
+                                 const int64_t* slice_offsets, const double* cotangent,
+                                 int32_t cotangent_on_device, double* amps, double* grad_gates,
+                                 double* grad_params, double* loss, int32_t out_on_device,
+                                 void* stream) {
+  return guarded([&] {
+    if (!g) qflex::fail(QFLEX_E_INVALID, "NULL grid");
+    qflex::contract_grad(g, bits, bs_offsets, fidelity, slice_seed, slice_ids, slice_offsets,
+                         cotangent, cotangent_on_device, amps, grad_gates, grad_params, loss,
+                         out_on_device != 0, static_cast<hipStream_t>(stream));
   });
 }
 

@@ -115,6 +115,7 @@ void build_grid_device(qflex_grid* g, hipStream_t s) {
     cs.grid_offset = total;
     cs.qubit_offset.assign(m.n, 0);
     const int mat_base = (int)(mats.size() / 4);
+    cs.mat_base = mat_base;
     for (const cdouble& z : m.mats) mats.push_back(make_double2(z.real(), z.imag()));
     int64_t off = 0;
     for (int q = 0; q < m.n; ++q) {
@@ -161,11 +162,20 @@ void build_grid_device(qflex_grid* g, hipStream_t s) {
   g->grid_elems = total;
   QHIP(hipMalloc(&g->grid, sizeof(float2) * std::max<int64_t>(total, 1)));
   QHIP(hipMalloc(&g->bidx, sizeof(uint32_t) * std::max<size_t>(bidx.size(), 1)));
-  DevBuf dq, dp, dm, dpos;
+  DevBuf& dq = g->gq;
+  DevBuf& dp = g->gpieces;
+  DevBuf& dm = g->gmats;
+  DevBuf& dpos = g->gpos;
   size_t nq = 0;
   for (auto& v : qds) nq += v.size();
   std::vector<dev::GridQubit> allq;
-  for (auto& v : qds) allq.insert(allq.end(), v.begin(), v.end());
+  for (size_t ci = 0; ci < qds.size(); ++ci) {
+    g->circ[ci].qdesc_base = (int64_t)allq.size();
+    g->circ[ci].max_nlb = max_nlb[ci];
+    for (auto& d : qds[ci]) g->max_pieces = std::max(g->max_pieces, d.piece_end - d.piece_begin);
+    allq.insert(allq.end(), qds[ci].begin(), qds[ci].end());
+  }
+  g->n_mats = (int64_t)(mats.size() / 4);
   try {
     dq.reserve(sizeof(dev::GridQubit) * std::max<size_t>(nq, 1));
     dp.reserve(sizeof(dev::GridPiece) * std::max<size_t>(pieces.size(), 1));
@@ -190,16 +200,8 @@ void build_grid_device(qflex_grid* g, hipStream_t s) {
     QHIP(hipStreamSynchronize(s));
   } catch (...) {
     (void)hipStreamSynchronize(s);
-    dq.release();
-    dp.release();
-    dm.release();
-    dpos.release();
     throw;
   }
-  dq.release();
-  dp.release();
-  dm.release();
-  dpos.release();
   // permutation tiles of every step
   for (auto& cs : g->circ) {
     cs.px.assign(cs.plan.steps.size(), dev::PermTile{});

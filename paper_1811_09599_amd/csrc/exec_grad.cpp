@@ -1,0 +1,379 @@
+// Adjoint contraction: gradients of a real loss of the amplitudes with respect to gate
+// entries and fSim angles.
+//
+// The paper computes amplitudes only; this is the reverse-mode counterpart of the same plan.
+// With W = conj(dL/d conj psi) per amplitude (holomorphic seed), every step Z = X Y of the
+// forward plan is reversed as Xbar = Zbar Y^T and Ybar = X^T Zbar (plain transposes: the
+// contraction is holomorphic in its tensors) followed by the inverse permutation.  For each
+// batch of bit-strings and each selected slice, the slice's forward intermediates are kept as
+// its checkpoint and the reverse sweep reads them; the qubit-tensor cotangents are summed in
+// FP64.  The time collapse is then reversed per qubit (the per-piece kets are recomputed, not
+// stored), giving the cotangent of every 2x2 piece matrix, and the host maps pieces back to
+// gate entries: dL/dtheta = 2 Re sum_e Gbar[e] dG[e]/dtheta.
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+
+#include "grid.h"
+
+namespace qflex {
+
+#define QHIPG(expr)                                                                        \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      fail(e_ == hipErrorOutOfMemory ? QFLEX_E_NOMEM : QFLEX_E_DEVICE,                      \
+           std::string(#expr) + ": " + hipGetErrorString(e_));                              \
+  } while (0)
+
+namespace {
+
+struct GView {
+  const float2* base = nullptr;
+  const int64_t* off = nullptr;
+  int64_t bs = 0, add = 0;
+};
+
+std::vector<int> cat(std::vector<int> a, const std::vector<int>& b) {
+  a.insert(a.end(), b.begin(), b.end());
+  return a;
+}
+
+int64_t pad64(int64_t e) { return (e + 63) & ~int64_t(63); }
+
+}  // namespace
+
+void contract_grad(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets,
+                   double fidelity, uint64_t seed, const int64_t* slice_ids,
+                   const int64_t* slice_offsets, const double* cot, int32_t cot_on_device,
+                   double* amps_out, double* grad_gates, double* grad_params, double* loss,
+                   bool out_on_device, hipStream_t s) {
+  const int nc = (int)g->circ.size();
+  if (!bs_offsets) fail(QFLEX_E_INVALID, "NULL argument");
+  if (g->max_pieces > dev::kMaxPiecesGrad)
+    fail(QFLEX_E_UNSUPPORTED, "gradients support at most " +
+                                  std::to_string(dev::kMaxPiecesGrad) + " gates per qubit");
+  const int no = (int)g->circ[0].plan.open.size();
+  const int64_t namp = int64_t(1) << no;
+  const int64_t total_bs = bs_offsets[nc];
+  const int64_t total_amp = total_bs * namp;
+  // ---- forward amplitudes (validates the call and uploads the output-bit offsets)
+  g->amps_dev.reserve(sizeof(double2) * std::max<int64_t>(total_amp, 1));
+  contract(g, bits, bs_offsets, fidelity, seed, slice_ids, slice_offsets,
+           static_cast<double*>(g->amps_dev.p), true, s);
+  const qflex_stats fwd = g->last;
+  const double2* amps = static_cast<const double2*>(g->amps_dev.p);
+  // ---- cotangent of the amplitudes, kept as dL/d(conj psi)
+  g->gbar.reserve(sizeof(double2) * std::max<int64_t>(total_amp, 1));
+  double2* gbar = static_cast<double2*>(g->gbar.p);
+  g->xeb.reserve(sizeof(double) * std::max(nc, 1));
+  double* xeb_sum = static_cast<double*>(g->xeb.p);
+  std::vector<double> scale(nc, 0.0);
+  if (cot) {
+    // the caller's cotangent is dL/dRe + i dL/dIm = 2 dL/d(conj amp); keep dL/d(conj amp)
+    if (total_amp > 0) {
+      QHIPG(hipMemcpyAsync(gbar, cot, sizeof(double2) * total_amp,
+                           cot_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+      dev::fill_zero(xeb_sum, nc, s);
+      dev::xeb_cotangent(gbar, total_amp, 0.5, gbar, xeb_sum, s);
+    }
+  } else {
+    dev::fill_zero(xeb_sum, nc, s);
+    for (int c = 0; c < nc; ++c) {
+      const int64_t m = (bs_offsets[c + 1] - bs_offsets[c]) * namp;
+      if (m == 0) continue;
+      scale[c] = std::ldexp(1.0, g->circ[c].model.n) / (double)m;  // linear XEB 2^n/m
+      dev::xeb_cotangent(amps + bs_offsets[c] * namp, m, scale[c], gbar + bs_offsets[c] * namp,
+                         xeb_sum + c, s);
+    }
+  }
+  // ---- FP64 cotangents of the qubit tensors and of the piece matrices
+  g->tbar.reserve(sizeof(double2) * std::max<int64_t>(g->grid_elems, 1));
+  g->pbar.reserve(sizeof(double2) * 4 * std::max<int64_t>(g->n_mats, 1));
+  double2* tbar = static_cast<double2*>(g->tbar.p);
+  double2* pbar = static_cast<double2*>(g->pbar.p);
+  dev::fill_zero(reinterpret_cast<double*>(tbar), 2 * g->grid_elems, s);
+  dev::fill_zero(reinterpret_cast<double*>(pbar), 8 * g->n_mats, s);
+  // slices (same rule as the forward call) and output-offset table layout
+  std::vector<int64_t> offs_base(nc + 1, 0);
+  for (int c = 0; c < nc; ++c)
+    offs_base[c + 1] = offs_base[c] + (bs_offsets[c + 1] - bs_offsets[c]) * g->circ[c].model.n;
+  const int64_t* offs_dev = static_cast<const int64_t*>(g->offs.p);
+  size_t free_b = 0, total_b = 0;
+  QHIPG(hipMemGetInfo(&free_b, &total_b));
+  qflex_stats st = fwd;
+  for (int c = 0; c < nc; ++c) {
+    CircuitState& cs = g->circ[c];
+    const Plan& P = cs.plan;
+    const int64_t nbs = bs_offsets[c + 1] - bs_offsets[c];
+    if (nbs == 0) continue;
+    std::vector<int64_t> slices;
+    if (slice_ids) {
+      slices.assign(slice_ids + slice_offsets[c], slice_ids + slice_offsets[c + 1]);
+      std::sort(slices.begin(), slices.end());
+    } else {
+      slices = select_slices(P.num_slices(), fidelity, seed);
+    }
+    // ---- memory: every node keeps its value and its cotangent; two product scratches
+    const size_t nn = P.nodes.size();
+    std::vector<int64_t> voff(nn), coff(nn);
+    int64_t top = 0, s1 = 0, s2 = 0;
+    for (size_t i = 0; i < nn; ++i) {
+      voff[i] = top;
+      top += pad64(P.nodes[i].elems());
+    }
+    for (size_t i = 0; i < nn; ++i) {
+      coff[i] = top;
+      top += pad64(P.nodes[i].elems());
+    }
+    for (const Step& stp : P.steps) {
+      s1 = std::max(s1, pad64(int64_t(1) << (stp.mb + stp.kb)));
+      s2 = std::max(s2, pad64(int64_t(1) << (stp.kb + stp.nb)));
+    }
+    s1 = std::max<int64_t>(s1, pad64(namp));
+    const int64_t s1off = top;
+    top += s1;
+    const int64_t s2off = top;
+    top += s2;
+    const double per = 8.0 * (double)top;
+    int64_t B = (int64_t)std::max(1.0, std::floor(std::min(0.5 * ((double)free_b + g->grad_arena.bytes),
+                                                           96.0 * (1ull << 30)) / per));
+    B = std::min<int64_t>(std::min<int64_t>(B, nbs), 1024);
+    g->grad_arena.reserve(sizeof(float2) * (size_t)(top * B));
+    float2* ar = static_cast<float2*>(g->grad_arena.p);
+    // permutations routing each product cotangent back to its operand's storage order
+    std::vector<dev::PermTile> rx(P.steps.size()), ry(P.steps.size());
+    std::vector<PermDesc> dx(P.steps.size()), dy(P.steps.size());
+    for (size_t k = 0; k < P.steps.size(); ++k) {
+      const Step& stp = P.steps[k];
+      dx[k] = make_perm_desc(cat(stp.mlab, stp.klab), stp.x_in);
+      dy[k] = make_perm_desc(cat(stp.klab, stp.nlab), stp.y_in);
+      if (!stp.x.qubit) rx[k] = dev::make_perm_tile(dx[k].nbits, dx[k].perm.data());
+      if (!stp.y.qubit) ry[k] = dev::make_perm_tile(dy[k].nbits, dy[k].perm.data());
+    }
+    const float2* grid = g->grid + cs.grid_offset;
+    double2* tgrid = tbar + cs.grid_offset;
+    const int ncut = (int)P.cuts.size();
+    for (int64_t b0 = 0; b0 < nbs; b0 += B) {
+      const int nb = (int)std::min<int64_t>(B, nbs - b0);
+      std::vector<int64_t> digit(ncut, 0);
+      auto view = [&](const Operand& o) {
+        GView v;
+        if (o.qubit) {
+          const QubitLayout& L = P.qubits[o.id];
+          v.base = grid + cs.qubit_offset[o.id];
+          for (auto& cshift : L.cut_shift) v.add += digit[cshift.first] << cshift.second;
+          if (L.out_shift >= 0) v.off = offs_dev + offs_base[c] + (int64_t)o.id * nbs + b0;
+        } else {
+          v.base = ar + voff[o.id] * B;
+          v.bs = P.nodes[o.id].elems();
+        }
+        return v;
+      };
+      auto nodev = [&](int id) {
+        GView v;
+        v.base = ar + voff[id] * B;
+        v.bs = P.nodes[id].elems();
+        return v;
+      };
+      auto route = [&](const Operand& o, const float2* src, const PermDesc& d,
+                       const dev::PermTile& t) {
+        if (o.qubit) {
+          const QubitLayout& L = P.qubits[o.id];
+          int64_t add = cs.qubit_offset[o.id];
+          for (auto& cshift : L.cut_shift) add += digit[cshift.first] << cshift.second;
+          const int64_t* off =
+              L.out_shift >= 0 ? offs_dev + offs_base[c] + (int64_t)o.id * nbs + b0 : nullptr;
+          std::vector<int8_t> p8(d.perm.begin(), d.perm.end());
+          dev::scatter_add_perm(src, d.nbits, p8.data(), nb, tgrid, off, add, s);
+        } else {
+          dev::permute(src, ar + coff[o.id] * B, nb, t, s);
+          ++st.n_permute;
+        }
+      };
+      for (int64_t sid : slices) {
+        int64_t rem = sid;
+        for (int ct = ncut - 1; ct >= 0; --ct) {
+          digit[ct] = rem & ((int64_t(1) << P.cut_bits[ct]) - 1);
+          rem >>= P.cut_bits[ct];
+        }
+        // forward, keeping every intermediate of this slice
+        for (size_t k = 0; k < P.steps.size(); ++k) {
+          const Step& stp = P.steps[k];
+          GView x = view(stp.x), y = view(stp.y);
+          if (stp.scratch_x >= 0) {
+            float2* dst = ar + voff[stp.scratch_x] * B;
+            dev::permute(x.base, dst, nb, cs.px[k], s);
+            x = nodev(stp.scratch_x);
+          }
+          if (stp.scratch_y >= 0) {
+            float2* dst = ar + voff[stp.scratch_y] * B;
+            dev::permute(y.base, dst, nb, cs.py[k], s);
+            y = nodev(stp.scratch_y);
+          }
+          dev::Gemm gm;
+          gm.A = x.base;
+          gm.a_off = x.off;
+          gm.a_bs = x.bs;
+          gm.a_add = x.add;
+          gm.B = y.base;
+          gm.b_off = y.off;
+          gm.b_bs = y.bs;
+          gm.b_add = y.add;
+          gm.C = ar + voff[stp.out] * B;
+          gm.c_bs = P.nodes[stp.out].elems();
+          gm.M = int64_t(1) << stp.mb;
+          gm.K = int64_t(1) << stp.kb;
+          gm.N = int64_t(1) << stp.nb;
+          gm.ta = stp.ta;
+          gm.tb = stp.tb;
+          gm.lda = stp.ta ? gm.M : gm.K;
+          gm.ldb = stp.tb ? gm.K : gm.N;
+          gm.ldc = gm.N;
+          gm.batch = nb;
+          dev::gemm(gm, s);
+          st.flops += stp.flops() * nb;
+          ++st.n_gemm;
+        }
+        // seed: cotangent of the result = conj(gbar) of this batch's amplitudes
+        const double2* gb = gbar + (bs_offsets[c] + b0) * namp;
+        if (P.result.qubit) {
+          float2* tmp = ar + s1off * B;
+          dev::seed_cotangent(gb, g->bidx + cs.bidx_offset, namp, namp, nb, tmp, s);
+          const QubitLayout& L = P.qubits[P.result.id];
+          PermDesc idp;
+          idp.nbits = L.free_bits();
+          idp.perm.resize(idp.nbits);
+          std::iota(idp.perm.begin(), idp.perm.end(), 0);
+          route(P.result, tmp, idp, dev::PermTile{});
+          continue;
+        }
+        dev::seed_cotangent(gb, g->bidx + cs.bidx_offset, namp, namp, nb,
+                            ar + coff[P.result.id] * B, s);
+        // reverse sweep
+        for (size_t kk = P.steps.size(); kk-- > 0;) {
+          const Step& stp = P.steps[kk];
+          const int64_t M = int64_t(1) << stp.mb, K = int64_t(1) << stp.kb,
+                        N = int64_t(1) << stp.nb;
+          GView x = stp.scratch_x >= 0 ? nodev(stp.scratch_x) : view(stp.x);
+          GView y = stp.scratch_y >= 0 ? nodev(stp.scratch_y) : view(stp.y);
+          const float2* zbar = ar + coff[stp.out] * B;
+          float2* xbar = ar + s1off * B;  // [M][K]
+          float2* ybar = ar + s2off * B;  // [K][N]
+          dev::Gemm g1;  // Xbar = Zbar Y'^T
+          g1.A = zbar;
+          g1.a_bs = M * N;
+          g1.lda = N;
+          g1.B = y.base;
+          g1.b_off = y.off;
+          g1.b_bs = y.bs;
+          g1.b_add = y.add;
+          g1.tb = stp.tb ? 0 : 1;
+          g1.M = M;
+          g1.N = K;
+          g1.K = N;
+          g1.ldb = g1.tb ? N : K;
+          g1.C = xbar;
+          g1.c_bs = M * K;
+          g1.ldc = K;
+          g1.batch = nb;
+          dev::gemm(g1, s);
+          dev::Gemm g2;  // Ybar = X'^T Zbar
+          g2.A = x.base;
+          g2.a_off = x.off;
+          g2.a_bs = x.bs;
+          g2.a_add = x.add;
+          g2.ta = stp.ta ? 0 : 1;
+          g2.M = K;
+          g2.N = N;
+          g2.K = M;
+          g2.lda = g2.ta ? K : M;
+          g2.B = zbar;
+          g2.b_bs = M * N;
+          g2.ldb = N;
+          g2.C = ybar;
+          g2.c_bs = K * N;
+          g2.ldc = N;
+          g2.batch = nb;
+          dev::gemm(g2, s);
+          st.flops += 2.0 * stp.flops() * nb;
+          st.n_gemm += 2;
+          route(stp.x, xbar, dx[kk], rx[kk]);
+          route(stp.y, ybar, dy[kk], ry[kk]);
+        }
+      }
+    }
+    // reverse the time collapse of this circuit's qubits
+    dev::grid_adjoint(static_cast<const dev::GridQubit*>(g->gq.p) + cs.qdesc_base, cs.model.n,
+                      cs.max_nlb, static_cast<const dev::GridPiece*>(g->gpieces.p),
+                      static_cast<const double2*>(g->gmats.p),
+                      static_cast<const int32_t*>(g->gpos.p), tbar, pbar, s);
+  }
+  // ---- host: piece cotangents -> gate entries -> angles (FP64)
+  std::vector<double2> hp(4 * std::max<int64_t>(g->n_mats, 1));
+  std::vector<double> hx(std::max(nc, 1), 0.0);
+  QHIPG(hipMemcpyAsync(hp.data(), pbar, sizeof(double2) * 4 * g->n_mats, hipMemcpyDeviceToHost, s));
+  if (!cot) QHIPG(hipMemcpyAsync(hx.data(), xeb_sum, sizeof(double) * nc, hipMemcpyDeviceToHost, s));
+  QHIPG(hipStreamSynchronize(s));
+  std::vector<cdouble> gg;      // gate-entry gradients, PyTorch convention
+  std::vector<double> gpar;     // [gates][2]
+  std::vector<double> lossv(nc, std::nan(""));
+  for (int c = 0; c < nc; ++c) {
+    const CircuitState& cs = g->circ[c];
+    const Model& m = cs.model;
+    std::vector<std::vector<cdouble>> gb(m.gates.size());
+    for (size_t gi = 0; gi < m.gates.size(); ++gi) gb[gi].assign(m.gates[gi].q1 < 0 ? 4 : 16, 0.0);
+    for (int q = 0; q < m.n; ++q)
+      for (const Piece& pc : m.timeline[q]) {
+        const int mi = cs.mat_base + pc.mat;
+        auto P = [&](int k, int e) { return cdouble(hp[4 * (mi + k) + e].x, hp[4 * (mi + k) + e].y); };
+        const Gate& G = m.gates[pc.gate];
+        if (G.q1 < 0) {
+          for (int e = 0; e < 4; ++e) gb[pc.gate][e] += P(0, e);
+        } else if (pc.hi_side) {
+          const int rank = 1 << pc.kbits;
+          for (int k = 0; k < rank; ++k) {
+            const int i = rank == 2 ? k : k >> 1, j = rank == 2 ? k : k & 1;
+            for (int a = 0; a < 2; ++a)
+              for (int b = 0; b < 2; ++b) gb[pc.gate][(2 * i + a) * 4 + 2 * j + b] += P(k, 2 * a + b);
+          }
+        }
+      }
+    for (size_t gi = 0; gi < m.gates.size(); ++gi) {
+      const Gate& G = m.gates[gi];
+      std::vector<cdouble> d = gb[gi];
+      if (G.q1 >= 0 && G.q0 > G.q1) {  // back from the |lo hi> basis to the gate's own order
+        static const int sw[4] = {0, 2, 1, 3};
+        for (int r = 0; r < 4; ++r)
+          for (int t = 0; t < 4; ++t) d[r * 4 + t] = gb[gi][sw[r] * 4 + sw[t]];
+      }
+      double dth = 0, dph = 0;
+      if (G.kind == QFLEX_G_FSIM) {
+        const double cth = std::cos(G.theta), sth = std::sin(G.theta);
+        const cdouble I(0, 1);
+        // dG/dtheta and dG/dphi of fSim, entries (1,1),(1,2),(2,1),(2,2),(3,3)
+        const cdouble dt5 = -sth, dt6 = -I * cth, dt9 = -I * cth, dt10 = -sth;
+        const cdouble dp15 = -I * std::exp(-I * G.phi);
+        dth = 2.0 * std::real(d[5] * dt5 + d[6] * dt6 + d[9] * dt9 + d[10] * dt10);
+        dph = 2.0 * std::real(d[15] * dp15);
+      }
+      gpar.push_back(dth);
+      gpar.push_back(dph);
+      for (const cdouble& z : d) gg.push_back(2.0 * std::conj(z));  // dL/dRe + i dL/dIm
+    }
+    if (!cot && bs_offsets[c + 1] > bs_offsets[c]) lossv[c] = scale[c] * hx[c] - 1.0;
+  }
+  const hipMemcpyKind kind = out_on_device ? hipMemcpyHostToDevice : hipMemcpyHostToHost;
+  if (grad_gates && !gg.empty())
+    QHIPG(hipMemcpyAsync(grad_gates, gg.data(), sizeof(cdouble) * gg.size(), kind, s));
+  if (grad_params && !gpar.empty())
+    QHIPG(hipMemcpyAsync(grad_params, gpar.data(), sizeof(double) * gpar.size(), kind, s));
+  if (loss) QHIPG(hipMemcpyAsync(loss, lossv.data(), sizeof(double) * nc, kind, s));
+  if (amps_out && total_amp > 0)
+    QHIPG(hipMemcpyAsync(amps_out, amps, sizeof(double2) * total_amp,
+                         out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
+  QHIPG(hipStreamSynchronize(s));
+  g->last = st;
+}
+
+}  // namespace qflex

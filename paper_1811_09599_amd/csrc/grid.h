@@ -18,6 +18,9 @@ namespace qflex {
 struct CircuitState {
   Model model;
   Plan plan;
+  int64_t qdesc_base = 0;            // first GridQubit of this circuit in the device table
+  int max_nlb = 0;
+  int mat_base = 0;                  // first 2x2 matrix of this circuit in the device table
   int64_t grid_offset = 0;           // element offset of this circuit's qubit tensors
   std::vector<int64_t> qubit_offset; // element offset of each qubit tensor (within the grid)
   int64_t bidx_offset = 0;           // offset of its batch-index table in the device table
@@ -79,6 +82,12 @@ struct qflex_grid {
   int64_t grid_elems = 0;
   uint32_t* bidx = nullptr;              // batch-index tables of all circuits
   uint16_t* grid_split = nullptr;        // qubit tensors pre-split for bf16 products
+  // time-collapse descriptors, kept for the adjoint of the grid build
+  qflex::DevBuf gq, gpieces, gmats, gpos;
+  int64_t n_mats = 0;
+  int max_pieces = 0;                    // longest qubit time line
+  // gradient buffers
+  qflex::DevBuf grad_arena, tbar, pbar, gbar, amps_dev, xeb;
   qflex::DevBuf split_scratch;           // split operands of intermediates
   qflex::DevBuf arena;                   // intermediates
   qflex::DevBuf amps64;                  // FP64 amplitude accumulator
@@ -95,4 +104,9 @@ void contract(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets, dou
               uint64_t seed, const int64_t* slice_ids, const int64_t* slice_offsets,
               double* amps, bool amps_on_device, hipStream_t s);
 std::vector<int64_t> select_slices(int64_t total, double fidelity, uint64_t seed);
+void contract_grad(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets,
+                   double fidelity, uint64_t seed, const int64_t* slice_ids,
+                   const int64_t* slice_offsets, const double* cot, int32_t cot_on_device,
+                   double* amps, double* grad_gates, double* grad_params, double* loss,
+                   bool out_on_device, hipStream_t s);
 }  // namespace qflex

@@ -90,6 +90,25 @@ bool gemm_split_ok(int64_t M, int64_t N, int64_t K);  // shape fits the tiled ke
 void gemm_split(const GemmSplit& g, hipStream_t s);
 const char* gemm_split_name(const GemmSplit& g);
 
+// ---------------------------------------------------------------- adjoint (gradients)
+constexpr int kMaxPiecesGrad = 64;  // pieces per qubit time line supported by grid_adjoint
+// Cotangent of the grid build: given tbar (FP64 cotangent of every qubit tensor, laid out like
+// the grid), accumulate into pbar[4*m + e] the cotangent of entry e of every 2x2 matrix m of
+// the pieces (sum over all bond values of the contributions of each thread).
+void grid_adjoint(const GridQubit* q, int n_qubits, int max_nlb, const GridPiece* pieces,
+                  const double2* mats, const int32_t* pos, const double2* tbar, double2* pbar,
+                  hipStream_t s);
+// out[base + add + (off ? off[b] : 0) + o(e)] += in[b*n + e] (FP64), o(e) = the index whose
+// output bit j is bit perm[j] of e; n = 2^nbits
+void scatter_add_perm(const float2* in, int nbits, const int8_t* perm, int batch,
+                      double2* out, const int64_t* off, int64_t add, hipStream_t s);
+// dst[b*n + e] = conj(gbar[b*namp + bidx[e]]) as complex64 (seed of the reverse sweep)
+void seed_cotangent(const double2* gbar, const uint32_t* bidx, int64_t n, int64_t namp,
+                    int batch, float2* dst, hipStream_t s);
+// gbar = scale * amps for n values; sum_sq += scale_sum * sum |amps|^2 (FP64)
+void xeb_cotangent(const double2* amps, int64_t n, double scale, double2* gbar, double* sum_sq,
+                   hipStream_t s);
+
 // ---------------------------------------------------------------- reductions
 // amps[b*amp_stride + bidx[e]] += res[b][e] for e < n, b < batch (FP64 accumulation)
 void accumulate(const float2* res, const int64_t* r_off, int64_t r_bs, int64_t r_add, int64_t n,

@@ -263,22 +263,29 @@ __global__ void __launch_bounds__(256) gemm_mfma_kernel(const Gemm g) {
       for (int j = 0; j < TNI; ++j)
         bf[j] = *reinterpret_cast<const float4*>(
             &bs[(wn * (BN / 2) + j * 32 + r) * LDK + h * 8 + 2 * s2]);
+      // the two terms of each part are issued in separate passes over the sub-tiles, so that
+      // consecutive MFMAs never feed the same accumulator
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
 #pragma unroll
-        for (int i = 0; i < TMI; ++i) {
-          const float ar = u ? af[i].z : af[i].x;
-          const float ai = u ? af[i].w : af[i].y;
+        for (int pass = 0; pass < 2; ++pass)
 #pragma unroll
-          for (int j = 0; j < TNI; ++j) {
-            const float br = u ? bf[j].z : bf[j].x;
-            const float bi = u ? bf[j].w : bf[j].y;
-            cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, br, cr[i][j], 0, 0, 0);
-            cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(-ai, bi, cr[i][j], 0, 0, 0);
-            ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, bi, ci[i][j], 0, 0, 0);
-            ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai, br, ci[i][j], 0, 0, 0);
+          for (int i = 0; i < TMI; ++i) {
+            const float ar = u ? af[i].z : af[i].x;
+            const float ai = u ? af[i].w : af[i].y;
+#pragma unroll
+            for (int j = 0; j < TNI; ++j) {
+              const float br = u ? bf[j].z : bf[j].x;
+              const float bi = u ? bf[j].w : bf[j].y;
+              if (pass == 0) {
+                cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, br, cr[i][j], 0, 0, 0);
+                ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, bi, ci[i][j], 0, 0, 0);
+              } else {
+                cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(-ai, bi, cr[i][j], 0, 0, 0);
+                ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai, br, ci[i][j], 0, 0, 0);
+              }
+            }
           }
-        }
       }
     }
     if (kt + 1 < nk) sstore(buf ^ 1);
@@ -582,14 +589,26 @@ __global__ void __launch_bounds__(256) gemm_split_kernel(const GemmSplit g) {
         bih[j] = as_bf16x8(make_uint4(vh.z, vh.w, vh.x, vh.y));
         bil[j] = as_bf16x8(make_uint4(vl.z, vl.w, vl.x, vl.y));
       }
+      // term by term over all sub-tiles, so that consecutive MFMAs never feed the same
+      // accumulator (each chain has 2*TMI*TNI-1 independent instructions between its links)
 #pragma unroll
       for (int i = 0; i < TMI; ++i)
 #pragma unroll
         for (int j = 0; j < TNI; ++j) {
           cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], brh[j], cr[i][j], 0, 0, 0);
           ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bih[j], ci[i][j], 0, 0, 0);
+        }
+#pragma unroll
+      for (int i = 0; i < TMI; ++i)
+#pragma unroll
+        for (int j = 0; j < TNI; ++j) {
           cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], brl[j], cr[i][j], 0, 0, 0);
           ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bil[j], ci[i][j], 0, 0, 0);
+        }
+#pragma unroll
+      for (int i = 0; i < TMI; ++i)
+#pragma unroll
+        for (int j = 0; j < TNI; ++j) {
           cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], brh[j], cr[i][j], 0, 0, 0);
           ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], bih[j], ci[i][j], 0, 0, 0);
         }
@@ -667,6 +686,153 @@ void fill_zero(double* p, int64_t n, hipStream_t s) {
   if (n <= 0) return;
   hipLaunchKernelGGL(fill_zero_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n);
   check_launch("fill_zero");
+}
+
+// =============================================================================================
+// Adjoint of the contraction (gradients).
+// =============================================================================================
+__device__ inline double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// One thread per (qubit, bond values): recompute the kets v_t = P_t ... P_1 |0> of the qubit's
+// time line (kept in private memory), then carry the cotangent row vector
+// u_L = (tbar[o=0], tbar[o=1]) backwards: dP_t[a][b] += u_t[a] v_{t-1}[b], u_{t-1} = u_t P_t.
+// Contributions to each piece matrix are summed over the wavefront, then added atomically.
+__global__ void __launch_bounds__(256) grid_adjoint_kernel(const GridQubit* __restrict__ qd,
+                                                           const GridPiece* __restrict__ pieces,
+                                                           const double2* __restrict__ mats,
+                                                           const int32_t* __restrict__ pos,
+                                                           const double2* __restrict__ tbar,
+                                                           double2* __restrict__ pbar) {
+  const GridQubit d = qd[blockIdx.y];
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool active = c < (int64_t(1) << d.nlb);
+  if ((int64_t)blockIdx.x * blockDim.x >= (int64_t(1) << d.nlb)) return;  // whole block idle
+  const int np = d.piece_end - d.piece_begin;
+  double2 v0[kMaxPiecesGrad + 1], v1[kMaxPiecesGrad + 1];
+  v0[0] = make_double2(1.0, 0.0);
+  v1[0] = make_double2(0.0, 0.0);
+  for (int t = 0; t < np; ++t) {
+    const GridPiece pc = pieces[d.piece_begin + t];
+    const int k = active ? (int)((c >> pc.kshift) & pc.kmask) : 0;
+    const double2* M = mats + 4 * (pc.mat + k);
+    v0[t + 1] = cadd(cmul(M[0], v0[t]), cmul(M[1], v1[t]));
+    v1[t + 1] = cadd(cmul(M[2], v0[t]), cmul(M[3], v1[t]));
+  }
+  double2 u0 = make_double2(0, 0), u1 = make_double2(0, 0);
+  if (active) {
+    int64_t addr = 0;
+    for (int j = 0; j < d.nlb; ++j) addr |= ((c >> (d.nlb - 1 - j)) & 1) << pos[d.pos_base + j];
+    u0 = tbar[d.offset + addr];
+    u1 = tbar[d.offset + (addr | (int64_t(1) << d.pos_out))];
+  }
+  const int lane = threadIdx.x & 63;
+  for (int t = np - 1; t >= 0; --t) {
+    const GridPiece pc = pieces[d.piece_begin + t];
+    const int k = active ? (int)((c >> pc.kshift) & pc.kmask) : 0;
+    const double2 a0 = v0[t], a1 = v1[t];
+    // outer product u (row) x v_{t-1} (column)
+    const double2 g[4] = {cmul(u0, a0), cmul(u0, a1), cmul(u1, a0), cmul(u1, a1)};
+    for (int kk = 0; kk <= pc.kmask; ++kk) {
+      const bool mine = active && k == kk;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const double re = wave_sum(mine ? g[e].x : 0.0);
+        const double im = wave_sum(mine ? g[e].y : 0.0);
+        if (lane == 0 && (re != 0.0 || im != 0.0)) {
+          atomicAdd(&pbar[4 * (pc.mat + kk) + e].x, re);
+          atomicAdd(&pbar[4 * (pc.mat + kk) + e].y, im);
+        }
+      }
+    }
+    const double2* M = mats + 4 * (pc.mat + k);
+    const double2 n0 = cadd(cmul(u0, M[0]), cmul(u1, M[2]));
+    const double2 n1 = cadd(cmul(u0, M[1]), cmul(u1, M[3]));
+    u0 = n0;
+    u1 = n1;
+  }
+}
+
+void grid_adjoint(const GridQubit* q, int n_qubits, int max_nlb, const GridPiece* pieces,
+                  const double2* mats, const int32_t* pos, const double2* tbar, double2* pbar,
+                  hipStream_t s) {
+  const int64_t combos = int64_t(1) << max_nlb;
+  dim3 grid((unsigned)((combos + 255) / 256), (unsigned)n_qubits);
+  hipLaunchKernelGGL(grid_adjoint_kernel, grid, dim3(256), 0, s, q, pieces, mats, pos, tbar, pbar);
+  check_launch("grid_adjoint");
+}
+
+struct PermBits {
+  int8_t p[kPermMaxBits];
+};
+
+__global__ void scatter_add_perm_kernel(const float2* __restrict__ in, int nbits, PermBits pb,
+                                        double2* __restrict__ out, const int64_t* __restrict__ off,
+                                        int64_t add) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n = int64_t(1) << nbits;
+  if (e >= n) return;
+  const int b = blockIdx.y;
+  int64_t o = 0;
+  for (int j = 0; j < nbits; ++j) o |= ((e >> pb.p[j]) & 1) << j;
+  const float2 v = in[(int64_t)b * n + e];
+  double2* dst = out + add + (off ? off[b] : 0) + o;
+  atomicAdd(&dst->x, (double)v.x);
+  atomicAdd(&dst->y, (double)v.y);
+}
+
+void scatter_add_perm(const float2* in, int nbits, const int8_t* perm, int batch, double2* out,
+                      const int64_t* off, int64_t add, hipStream_t s) {
+  if (nbits > kPermMaxBits) throw std::runtime_error("scatter_add_perm: too many bits");
+  PermBits pb{};
+  for (int j = 0; j < nbits; ++j) pb.p[j] = perm[j];
+  const int64_t n = int64_t(1) << nbits;
+  hipLaunchKernelGGL(scatter_add_perm_kernel, dim3((unsigned)((n + 255) / 256), (unsigned)batch),
+                     dim3(256), 0, s, in, nbits, pb, out, off, add);
+  check_launch("scatter_add_perm");
+}
+
+__global__ void seed_cotangent_kernel(const double2* __restrict__ gbar,
+                                      const uint32_t* __restrict__ bidx, int64_t n, int64_t namp,
+                                      float2* __restrict__ dst) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const int b = blockIdx.y;
+  const double2 v = gbar[(int64_t)b * namp + bidx[e]];
+  dst[(int64_t)b * n + e] = make_float2((float)v.x, (float)-v.y);
+}
+
+void seed_cotangent(const double2* gbar, const uint32_t* bidx, int64_t n, int64_t namp,
+                    int batch, float2* dst, hipStream_t s) {
+  hipLaunchKernelGGL(seed_cotangent_kernel, dim3((unsigned)((n + 255) / 256), (unsigned)batch),
+                     dim3(256), 0, s, gbar, bidx, n, namp, dst);
+  check_launch("seed_cotangent");
+}
+
+__global__ void xeb_cotangent_kernel(const double2* __restrict__ amps, int64_t n, double scale,
+                                     double2* __restrict__ gbar, double* __restrict__ sum_sq) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double v = 0.0;
+  if (i < n) {
+    const double2 a = amps[i];
+    gbar[i] = make_double2(scale * a.x, scale * a.y);
+    v = a.x * a.x + a.y * a.y;
+  }
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0 && v != 0.0) atomicAdd(sum_sq, v);
+}
+
+void xeb_cotangent(const double2* amps, int64_t n, double scale, double2* gbar, double* sum_sq,
+                   hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(xeb_cotangent_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                     amps, n, scale, gbar, sum_sq);
+  check_launch("xeb_cotangent");
 }
 
 }  // namespace dev

@@ -180,6 +180,131 @@ class Grid:
         return res
 
 
+def _gate_grad_sizes(circ):
+    return [4 if len(g["qubits"]) == 1 else 16 for g in circ["gates"]]
+
+
+def _contract_grad(self, bits, cotangent=None, fidelity: float = 1.0, seed: int = 0,
+                   slice_ids=None, stream=None):
+    """qflex_contract_grad with host outputs: dict with ``amps`` [total, 2^n_open],
+    ``grad_gates`` (per circuit, list of 2x2 / 4x4 arrays, dL/dRe G + i dL/dIm G),
+    ``grad_params`` (per circuit [n_gates, 2]: dL/dtheta, dL/dphi), ``loss`` (per circuit
+    linear XEB when no cotangent is given).  ``cotangent``: dL/dRe(amp) + i dL/dIm(amp) (what
+    torch autograd passes for a complex tensor), numpy or torch (CPU or CUDA)."""
+    L = F.lib()
+    if isinstance(bits, np.ndarray) or (len(self.circuits) == 1 and not isinstance(bits, list)):
+        bits = [bits]
+    bits = [np.ascontiguousarray(np.asarray(b, dtype=np.uint8)) for b in bits]
+    offs = np.zeros(len(bits) + 1, dtype=np.int64)
+    for i, b in enumerate(bits):
+        offs[i + 1] = offs[i] + (b.shape[0] if b.size else 0)
+    flat = np.concatenate([b.ravel() for b in bits]) if offs[-1] else np.zeros(1, np.uint8)
+    namp = 1 << self.n_open
+    total = int(offs[-1])
+    sid = soff = None
+    keep = []
+    if slice_ids is not None:
+        if len(self.circuits) == 1 and (len(slice_ids) == 0 or np.isscalar(slice_ids[0])):
+            slice_ids = [slice_ids]
+        so = np.zeros(len(slice_ids) + 1, dtype=np.int64)
+        for i, sl in enumerate(slice_ids):
+            so[i + 1] = so[i] + len(sl)
+        si = np.concatenate([np.asarray(sl, dtype=np.int64) for sl in slice_ids]) \
+            if so[-1] else np.zeros(1, np.int64)
+        keep += [so, si]
+        sid = si.ctypes.data_as(C.POINTER(C.c_int64))
+        soff = so.ctypes.data_as(C.POINTER(C.c_int64))
+    cot_ptr, cot_dev = None, 0
+    if cotangent is not None:
+        if hasattr(cotangent, "is_cuda") and cotangent.is_cuda:
+            import torch
+            cotangent = cotangent.to(torch.complex128).contiguous()
+            keep.append(cotangent)
+            cot_ptr, cot_dev = C.c_void_p(cotangent.data_ptr()), 1
+        else:
+            if hasattr(cotangent, "detach"):
+                cotangent = cotangent.detach().cpu().numpy()
+            c = np.ascontiguousarray(np.asarray(cotangent, dtype=np.complex128).reshape(total, namp))
+            keep.append(c)
+            cot_ptr = C.c_void_p(c.ctypes.data)
+    amps = np.empty((total, namp), dtype=np.complex128)
+    sizes = [_gate_grad_sizes(c) for c in self.circuits]
+    n_entries = sum(sum(z) for z in sizes)
+    n_gates = sum(len(z) for z in sizes)
+    gg = np.empty(max(n_entries, 1), dtype=np.complex128)
+    gp = np.empty((max(n_gates, 1), 2), dtype=np.float64)
+    loss = np.empty(len(self.circuits), dtype=np.float64)
+    F.check(L.qflex_contract_grad(
+        self._h, flat.ctypes.data_as(C.POINTER(C.c_uint8)),
+        offs.ctypes.data_as(C.POINTER(C.c_int64)), float(fidelity), C.c_uint64(int(seed)),
+        sid, soff, cot_ptr, cot_dev, C.c_void_p(amps.ctypes.data), C.c_void_p(gg.ctypes.data),
+        C.c_void_p(gp.ctypes.data), C.c_void_p(loss.ctypes.data), 0, _stream(stream)))
+    out_gg, out_gp = [], []
+    e0 = g0 = 0
+    for z in sizes:
+        lst = []
+        for sz in z:
+            d = 2 if sz == 4 else 4
+            lst.append(gg[e0:e0 + sz].reshape(d, d).copy())
+            e0 += sz
+        out_gg.append(lst)
+        out_gp.append(gp[g0:g0 + len(z)].copy())
+        g0 += len(z)
+    return {"amps": amps, "grad_gates": out_gg, "grad_params": out_gp, "loss": loss}
+
+
+Grid.contract_grad = _contract_grad
+
+
+def with_fsim_angles(circ: dict, params) -> dict:
+    """Copy of a circuit with the angles of its fSim gates (in gate order) set from an
+    [n_fsim, 2] array of (theta, phi)."""
+    params = np.asarray(params, dtype=np.float64).reshape(-1, 2)
+    out = dict(circ)
+    gates, i = [], 0
+    for g in circ["gates"]:
+        g = dict(g)
+        if g["kind"] == "fsim":
+            g["theta"], g["phi"] = float(params[i, 0]), float(params[i, 1])
+            i += 1
+        gates.append(g)
+    if i != len(params):
+        raise ValueError("circuit has %d fSim gates, got %d angle pairs" % (i, len(params)))
+    out["gates"] = gates
+    return out
+
+
+def _fsim_rows(circ):
+    return [i for i, g in enumerate(circ["gates"]) if g["kind"] == "fsim"]
+
+
+try:
+    import torch
+
+    class Amplitudes(torch.autograd.Function):
+        """amplitudes = Amplitudes.apply(angles, circuit, bits, open_qubits, plan):
+        complex128 amplitudes [m, 2^n_open] of ``circuit`` with its fSim angles replaced by
+        ``angles`` ([n_fsim, 2] real tensor of (theta, phi)); differentiable in ``angles``
+        through the adjoint contraction of libqflex."""
+
+        @staticmethod
+        def forward(ctx, angles, circuit, bits, open_qubits=(), plan="auto"):
+            circ = with_fsim_angles(circuit, angles.detach().cpu().numpy())
+            grid = Grid(circ, plan=plan, open_qubits=open_qubits)
+            ctx.grid, ctx.bits, ctx.rows = grid, np.asarray(bits, np.uint8), _fsim_rows(circ)
+            ctx.dtype, ctx.device = angles.dtype, angles.device
+            amps = grid.contract_amplitudes(ctx.bits, device=torch.cuda.is_available())
+            return amps.to(angles.device) if hasattr(amps, "to") else torch.from_numpy(amps)
+
+        @staticmethod
+        def backward(ctx, grad_amps):
+            res = ctx.grid.contract_grad(ctx.bits, cotangent=grad_amps)
+            gp = torch.from_numpy(res["grad_params"][0][ctx.rows]).to(ctx.dtype).to(ctx.device)
+            return gp, None, None, None, None
+except ImportError:  # pragma: no cover
+    pass
+
+
 def build_grid(circuits, **kw) -> Grid:
     """qflex_build_grid."""
     return Grid(circuits, **kw)
