@@ -132,3 +132,56 @@ def linear_xeb_grad(circ: dict, bits: np.ndarray):
     dth, dph, _ = vjp_params(circ, bits, scale * np.conj(psi))
     grad = np.stack([2.0 * dth.real, 2.0 * dph.real], axis=1)
     return float(scale * np.sum(np.abs(psi) ** 2) - 1.0), grad
+
+
+def identity_coupled_path_amplitudes(circ: dict, bits: np.ndarray, open_qubits=(), cuts=(),
+                                     slice_id: int = 0) -> np.ndarray:
+    """Closed form of one path of a circuit whose two-qubit gates are all the identity
+    (fSim(0, 0), whose bond has two values, like CZ's).
+
+    Such a circuit is a product state, and fixing the bonds of the cut links keeps it one:
+    with the bond of the lower-id qubit q0 written as |k><k| and that of q1 as G_kk = I, a
+    path is the product over qubits of <x_q| U_q |0>, where U_q is the qubit's one-qubit
+    gates in time order with the projector |k_g><k_g| inserted at every cut gate g of which
+    q is the lower-id qubit (k_g: that gate's digit of its link's value, earliest gate most
+    significant; links in ``cuts`` order form the slice id, first most significant).
+    Returns [m, 2^n_open] (batch index big-endian over ``open_qubits``)."""
+    n = circ["n_qubits"]
+    cuts = [tuple(sorted(c)) for c in cuts]
+    link_gates = {c: [] for c in cuts}
+    for i, g in sorted(enumerate(circ["gates"]), key=lambda t: t[1]["cycle"]):
+        if len(g["qubits"]) == 2:
+            if not np.allclose(G.matrix(g), np.eye(4), atol=0):
+                raise ValueError("two-qubit gates must be the identity")
+            key = tuple(sorted(g["qubits"]))
+            if key in link_gates:
+                link_gates[key].append(i)
+    proj = {}  # gate index -> projector value on its lower-id qubit
+    rem = int(slice_id)
+    for c in reversed(cuts):
+        gs = link_gates[c]
+        v = rem % (1 << len(gs))
+        rem >>= len(gs)
+        for t, gi in enumerate(gs):
+            proj[gi] = (v >> (len(gs) - 1 - t)) & 1
+    vec = {q: np.array([1, 0], dtype=np.complex128) for q in range(n)}
+    for i, g in sorted(enumerate(circ["gates"]), key=lambda t: t[1]["cycle"]):
+        if len(g["qubits"]) == 1:
+            q = g["qubits"][0]
+            vec[q] = G.matrix(g) @ vec[q]
+        elif i in proj:
+            lo = min(g["qubits"])
+            p = np.zeros((2, 2))
+            p[proj[i], proj[i]] = 1
+            vec[lo] = p @ vec[lo]
+    open_qubits = list(open_qubits)
+    no = len(open_qubits)
+    out = np.empty((len(bits), 1 << no), dtype=np.complex128)
+    for b, x in enumerate(np.asarray(bits)):
+        base = np.prod([vec[q][int(x[q])] for q in range(n) if q not in open_qubits])
+        for j in range(1 << no):
+            v = base
+            for t, q in enumerate(open_qubits):
+                v = v * vec[q][(j >> (no - 1 - t)) & 1]
+            out[b, j] = v
+    return out

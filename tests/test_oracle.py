@@ -380,3 +380,20 @@ def test_e3_sliced_gradient_sums_to_full():
     parts = [E2.amplitude_gate_grads(c, bits, cot, [8], cuts, [s]) for s in range(S)]
     full = E2.amplitude_gate_grads(c, bits, cot, [8])
     assert np.allclose(np.sum(parts, axis=0), full, atol=1e-12)
+
+
+def test_identity_coupled_path_closed_form_matches_state_vector_paths():
+    c = R.replace_two_qubit(R.grid_rqc(3, 3, 16, 23), "fsim", 0.0, 0.0)
+    cuts = [(2, 5), (6, 7)]
+    op = [8, 7]
+    bits = R.bitstrings(9, 3, 4, op)
+    dims = E2.Network(c).cut_dims(cuts)
+    for s in (0, 3, dims[0] * dims[1] - 1, 6):
+        vals = [s // dims[1], s % dims[1]]
+        psi_p = E1.state(c, _path_replacements(c, cuts, vals))
+        want = np.array([[psi_p[tuple(np.where(np.arange(9) == 8, (j >> 1) & 1,
+                                                np.where(np.arange(9) == 7, j & 1, x)))]
+                          for j in range(4)] for x in bits])
+        got = E1.identity_coupled_path_amplitudes(c, bits, op, cuts, s)
+        assert np.allclose(got, want, atol=1e-14), s
+        assert np.allclose(got, E2.amplitudes(c, bits, op, cuts=cuts, slice_ids=[s]), atol=1e-14)
