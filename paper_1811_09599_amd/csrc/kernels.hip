@@ -490,9 +490,11 @@ void split_permute(const float2* in, uint16_t* out, int64_t batch, const PermTil
   check_launch("split_permute");
 }
 
-// Complex product on bf16 MFMA from the compact split layout.  256 threads = 2x2 wavefronts,
-// each owning a 64x64 complex block = 2x2 sub-tiles of v_mfma_f32_32x32x16_bf16 with separate
-// real and imaginary accumulators.  One instruction step covers 8 complex k: lanes 0-31 hold
+// Complex product on bf16 MFMA from the compact split layout.  WM x WN wavefronts per
+// workgroup (8 for the 256x128 complex tile: two per SIMD hide each other's barrier and LDS
+// latency, and the larger tile halves the bytes loaded per MFMA), each owning a 64x64 complex
+// block = 2x2 sub-tiles of v_mfma_f32_32x32x16_bf16 with separate real and imaginary
+// accumulators.  One instruction step covers 8 complex k: lanes 0-31 hold
 // k-group g, lanes 32-63 group g+1, each lane's 8 bf16 being [re(4 k), im(4 k)] of one part:
 //   Cr += Ah.Brh + Ah.Brl + Al.Brh,  Brh = [Br_h, -Bi_h]
 //   Ci += Ah.Bih + Ah.Bil + Al.Bih,  Bih = [Bi_h,  Br_h]
@@ -507,17 +509,19 @@ __device__ inline bf16x8 as_bf16x8(uint4 v) {
   return r;
 }
 
-template <int BM, int BN>
-__global__ void __launch_bounds__(256) gemm_split_kernel(const GemmSplit g) {
+template <int BM, int BN, int WM, int WN>
+__global__ void __launch_bounds__(64 * WM * WN) gemm_split_kernel(const GemmSplit g) {
+  constexpr int NT = 64 * WM * WN;       // threads: WM x WN wavefronts
   constexpr int BK = 16;                 // complex k per tile
   constexpr int ROW = BK * 4;            // bf16 per row per tile (128 bytes)
   constexpr int LDR = ROW + 8;           // padded row (144 bytes)
-  constexpr int TMI = BM / 64, TNI = BN / 64;
-  constexpr int AV = BM * ROW / 8 / 256, BV = BN * ROW / 8 / 256;  // uint4 loads per thread
+  constexpr int WTM = BM / WM, WTN = BN / WN;  // wavefront tile (complex)
+  constexpr int TMI = WTM / 32, TNI = WTN / 32;
+  constexpr int AV = BM * ROW / 8 / NT, BV = BN * ROW / 8 / NT;  // uint4 loads per thread
   __shared__ __attribute__((aligned(16))) uint16_t As[2][BM * LDR];
   __shared__ __attribute__((aligned(16))) uint16_t Bs[2][BN * LDR];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
+  const int wm = wave / WN, wn = wave % WN;
   const int h = lane >> 5, r = lane & 31;
   const int64_t tiles_n = g.N / BN;
   const int64_t tm = (int64_t)blockIdx.x / tiles_n, tn = (int64_t)blockIdx.x % tiles_n;
@@ -532,24 +536,24 @@ __global__ void __launch_bounds__(256) gemm_split_kernel(const GemmSplit g) {
   auto gload = [&](int64_t k0) {  // k0 in bf16 units along the row
 #pragma unroll
     for (int v = 0; v < AV; ++v) {
-      const int e = tid + v * 256, row = e >> 3, ch = e & 7;
+      const int e = tid + v * NT, row = e >> 3, ch = e & 7;
       ra[v] = *reinterpret_cast<const uint4*>(A + (m0 + row) * lda + k0 + 8 * ch);
     }
 #pragma unroll
     for (int v = 0; v < BV; ++v) {
-      const int e = tid + v * 256, row = e >> 3, ch = e & 7;
+      const int e = tid + v * NT, row = e >> 3, ch = e & 7;
       rb[v] = *reinterpret_cast<const uint4*>(B + (n0 + row) * ldb + k0 + 8 * ch);
     }
   };
   auto sstore = [&](int buf) {
 #pragma unroll
     for (int v = 0; v < AV; ++v) {
-      const int e = tid + v * 256, row = e >> 3, ch = e & 7;
+      const int e = tid + v * NT, row = e >> 3, ch = e & 7;
       *reinterpret_cast<uint4*>(&As[buf][row * LDR + 8 * ch]) = ra[v];
     }
 #pragma unroll
     for (int v = 0; v < BV; ++v) {
-      const int e = tid + v * 256, row = e >> 3, ch = e & 7;
+      const int e = tid + v * NT, row = e >> 3, ch = e & 7;
       *reinterpret_cast<uint4*>(&Bs[buf][row * LDR + 8 * ch]) = rb[v];
     }
   };
@@ -575,13 +579,13 @@ __global__ void __launch_bounds__(256) gemm_split_kernel(const GemmSplit g) {
       bf16x8 ah[TMI], al[TMI], brh[TNI], brl[TNI], bih[TNI], bil[TNI];
 #pragma unroll
       for (int i = 0; i < TMI; ++i) {
-        const uint16_t* p = &as[(wm * (BM / 2) + i * 32 + r) * LDR + col];
+        const uint16_t* p = &as[(wm * WTM + i * 32 + r) * LDR + col];
         ah[i] = as_bf16x8(*reinterpret_cast<const uint4*>(p));
         al[i] = as_bf16x8(*reinterpret_cast<const uint4*>(p + 8));
       }
 #pragma unroll
       for (int j = 0; j < TNI; ++j) {
-        const uint16_t* p = &bs[(wn * (BN / 2) + j * 32 + r) * LDR + col];
+        const uint16_t* p = &bs[(wn * WTN + j * 32 + r) * LDR + col];
         const uint4 vh = *reinterpret_cast<const uint4*>(p);
         const uint4 vl = *reinterpret_cast<const uint4*>(p + 8);
         brh[j] = as_bf16x8(make_uint4(vh.x, vh.y, vh.z ^ 0x80008000u, vh.w ^ 0x80008000u));
@@ -622,8 +626,8 @@ __global__ void __launch_bounds__(256) gemm_split_kernel(const GemmSplit g) {
     for (int j = 0; j < TNI; ++j)
 #pragma unroll
       for (int v = 0; v < 16; ++v) {
-        const int row = wm * (BM / 2) + i * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
-        const int col = wn * (BN / 2) + j * 32 + r;
+        const int row = wm * WTM + i * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
+        const int col = wn * WTN + j * 32 + r;
         C[(m0 + row) * g.N + n0 + col] = make_float2(cr[i][j][v], ci[i][j][v]);
       }
 }
@@ -633,18 +637,23 @@ bool gemm_split_ok(int64_t M, int64_t N, int64_t K) {
 }
 
 const char* gemm_split_name(const GemmSplit& g) {
-  return (g.M % 128 == 0 && g.N % 128 == 0) ? "gemm_split_bf16_128x128" : "gemm_split_bf16_64x64";
+  if (g.M % 256 == 0 && g.N % 128 == 0) return "gemm_split_bf16_256x128";
+  if (g.M % 128 == 0 && g.N % 128 == 0) return "gemm_split_bf16_128x128";
+  return "gemm_split_bf16_64x64";
 }
 
 void gemm_split(const GemmSplit& g, hipStream_t s) {
   if (!gemm_split_ok(g.M, g.N, g.K)) throw std::runtime_error("gemm_split: unsupported shape");
   if (g.batch < 1 || g.batch > 65535) throw std::runtime_error("gemm_split: bad batch");
-  if (g.M % 128 == 0 && g.N % 128 == 0) {
+  if (g.M % 256 == 0 && g.N % 128 == 0) {
+    dim3 grid((unsigned)((g.M / 256) * (g.N / 128)), (unsigned)g.batch);
+    hipLaunchKernelGGL((gemm_split_kernel<256, 128, 4, 2>), grid, dim3(512), 0, s, g);
+  } else if (g.M % 128 == 0 && g.N % 128 == 0) {
     dim3 grid((unsigned)((g.M / 128) * (g.N / 128)), (unsigned)g.batch);
-    hipLaunchKernelGGL((gemm_split_kernel<128, 128>), grid, dim3(256), 0, s, g);
+    hipLaunchKernelGGL((gemm_split_kernel<128, 128, 2, 2>), grid, dim3(256), 0, s, g);
   } else {
     dim3 grid((unsigned)((g.M / 64) * (g.N / 64)), (unsigned)g.batch);
-    hipLaunchKernelGGL((gemm_split_kernel<64, 64>), grid, dim3(256), 0, s, g);
+    hipLaunchKernelGGL((gemm_split_kernel<64, 64, 2, 2>), grid, dim3(256), 0, s, g);
   }
   check_launch("gemm_split");
 }
