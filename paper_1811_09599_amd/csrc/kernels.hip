@@ -105,6 +105,37 @@ PermTile make_perm_tile(int nbits, const int* perm) {
 
 __device__ inline int lds_pad(int i) { return i + (i >> 5); }
 
+// Offsets of tile element i = t + 256*k are split into a per-thread part (bits 0..7 of i,
+// computed once) and a per-k part (bits 8..9), so that each element costs one add instead of
+// a loop over the tile bits.  Every loop over descriptor entries is fully unrolled with a
+// static index, so the descriptor stays in scalar registers.
+__device__ inline int64_t rest_offset(int64_t T, const int8_t* pos, int n) {
+  int64_t o = 0;
+#pragma unroll
+  for (int r = 0; r < kPermMaxBits; ++r)
+    if (r < n) o |= ((T >> r) & 1) << pos[r];
+  return o;
+}
+
+// bits [from, to) of v (v's bit 0 is bit `from`) deposited at positions pos[from..to)
+template <int FROM, int TO>
+__device__ inline int64_t deposit(int v, const int8_t* pos, int limit) {
+  int64_t o = 0;
+#pragma unroll
+  for (int b = FROM; b < TO; ++b)
+    if (b < limit) o |= (int64_t)((v >> (b - FROM)) & 1) << pos[b];
+  return o;
+}
+
+template <int FROM, int TO>
+__device__ inline int deposit_i(int v, const int8_t* pos, int limit) {
+  int o = 0;
+#pragma unroll
+  for (int b = FROM; b < TO; ++b)
+    if (b < limit) o |= ((v >> (b - FROM)) & 1) << pos[b];
+  return o;
+}
+
 __global__ void __launch_bounds__(256) permute_kernel(const float2* __restrict__ in,
                                                       float2* __restrict__ out,
                                                       const PermTile t) {
@@ -113,32 +144,25 @@ __global__ void __launch_bounds__(256) permute_kernel(const float2* __restrict__
   in += (int64_t)blockIdx.y * batch_stride;
   out += (int64_t)blockIdx.y * batch_stride;
   const int64_t T = blockIdx.x;
-  int64_t in_base = 0, out_base = 0;
-  for (int r = 0; r < t.nrest; ++r) {
-    const int64_t bit = (T >> r) & 1;
-    in_base |= bit << t.rest_in[r];
-    out_base |= bit << t.rest_out[r];
-  }
-  const int tsize = 1 << t.tile_bits;
-  for (int i = threadIdx.x; i < tsize; i += blockDim.x) {
-    int64_t off = in_base;
-#pragma unroll
-    for (int b = 0; b < kPermMaxTile; ++b)
-      if (b < t.tile_bits) off |= (int64_t)((i >> b) & 1) << t.tile_in[b];
-    tile[lds_pad(i)] = in[off];
+  const int64_t in_base = rest_offset(T, t.rest_in, t.nrest);
+  const int64_t out_base = rest_offset(T, t.rest_out, t.nrest);
+  const int tb = t.tile_bits;
+  const int tsize = 1 << tb;
+  const int tid = threadIdx.x;
+  const int nk = tsize > 256 ? tsize >> 8 : 1;
+  if (tid < tsize) {
+    const int64_t in_lo = in_base + deposit<0, 8>(tid, t.tile_in, tb);
+    for (int k = 0; k < nk; ++k)
+      tile[lds_pad(tid + (k << 8))] = in[in_lo + deposit<8, kPermMaxTile>(k, t.tile_in, tb)];
   }
   __syncthreads();
-  for (int j = threadIdx.x; j < tsize; j += blockDim.x) {
-    int i = 0;
-    int64_t off = out_base;
-#pragma unroll
-    for (int b = 0; b < kPermMaxTile; ++b)
-      if (b < t.tile_bits) {
-        const int bit = (j >> b) & 1;
-        i |= bit << t.j2i[b];
-        off |= (int64_t)bit << t.tile_out[b];
-      }
-    out[off] = tile[lds_pad(i)];
+  if (tid < tsize) {
+    const int i_lo = deposit_i<0, 8>(tid, t.j2i, tb);
+    const int64_t out_lo = out_base + deposit<0, 8>(tid, t.tile_out, tb);
+    for (int k = 0; k < nk; ++k) {
+      const int i = i_lo | deposit_i<8, kPermMaxTile>(k, t.j2i, tb);
+      out[out_lo + deposit<8, kPermMaxTile>(k, t.tile_out, tb)] = tile[lds_pad(i)];
+    }
   }
 }
 
@@ -425,37 +449,37 @@ __global__ void __launch_bounds__(256) split_permute_kernel(const float2* __rest
   in += (int64_t)blockIdx.y * n_el;
   out += (int64_t)blockIdx.y * n_el * 4;
   const int64_t T = blockIdx.x;
-  int64_t in_base = 0, out_base = 0;
-  for (int r = 0; r < t.nrest; ++r) {
-    const int64_t bit = (T >> r) & 1;
-    in_base |= bit << t.rest_in[r];
-    out_base |= bit << t.rest_out[r];
-  }
-  const int tsize = 1 << t.tile_bits;
-  for (int i = threadIdx.x; i < tsize; i += blockDim.x) {
-    int64_t off = in_base;
-#pragma unroll
-    for (int b = 0; b < kPermMaxTile; ++b)
-      if (b < t.tile_bits) off |= (int64_t)((i >> b) & 1) << t.tile_in[b];
-    tile[lds_pad(i)] = in[off];
+  const int64_t in_base = rest_offset(T, t.rest_in, t.nrest);
+  const int64_t out_base = rest_offset(T, t.rest_out, t.nrest);
+  const int tb = t.tile_bits;
+  const int tsize = 1 << tb;
+  const int tid = threadIdx.x;
+  const int nk = tsize > 256 ? tsize >> 8 : 1;
+  if (tid < tsize) {
+    const int64_t in_lo = in_base + deposit<0, 8>(tid, t.tile_in, tb);
+    for (int k = 0; k < nk; ++k)
+      tile[lds_pad(tid + (k << 8))] = in[in_lo + deposit<8, kPermMaxTile>(k, t.tile_in, tb)];
   }
   __syncthreads();
-  for (int q = threadIdx.x; q < tsize / 4; q += blockDim.x) {
+  // group q holds write indices 4q..4q+3 (write bits 0 and 1 are the two lowest k bits);
+  // q = tid + 256*k2, k2 < 1 for tiles of up to 1024 elements
+  const int ngroups = tsize >> 2;
+  if (tid < ngroups) {
+    const int q = tid;
+    // write index bits 2.. come from q
+    int ig = 0;
+    int64_t e0 = out_base;
+#pragma unroll
+    for (int b = 2; b < kPermMaxTile; ++b)
+      if (b < tb) {
+        const int bit = (q >> (b - 2)) & 1;
+        ig |= bit << t.j2i[b];
+        e0 |= (int64_t)bit << t.tile_out[b];
+      }
     uint16_t h[16];
-    int64_t e0 = 0;
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const int j = 4 * q + u;
-      int i = 0;
-      int64_t e = out_base;
-#pragma unroll
-      for (int b = 0; b < kPermMaxTile; ++b)
-        if (b < t.tile_bits) {
-          const int bit = (j >> b) & 1;
-          i |= bit << t.j2i[b];
-          e |= (int64_t)bit << t.tile_out[b];
-        }
-      if (u == 0) e0 = e;
+      const int i = ig | ((u & 1) << t.j2i[0]) | (((u >> 1) & 1) << t.j2i[1]);
       const float2 v = tile[lds_pad(i)];
       const uint16_t rh = bf16_rne(v.x), ih = bf16_rne(v.y);
       h[u] = rh;
