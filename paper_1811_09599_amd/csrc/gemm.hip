@@ -1,0 +1,260 @@
+// Complex64 matrix products: FP32 MFMA tiles and a SIMT kernel for thin shapes.
+#include "kernel_util.h"
+
+namespace qflex {
+namespace dev {
+
+// =============================================================================================
+// Complex64 matrix product (paper, Methods B.2: each pairwise contraction is one matrix
+// multiplication after the permutation).
+//
+// MFMA kernel: 256 threads = 4 wavefronts in 2x2, each owning a (BM/2)x(BN/2) complex block
+// made of 32x32 sub-tiles of v_mfma_f32_32x32x2f32.  The complex product runs in 4M form on
+// the real instruction: Cr += ar*br + (-ai)*bi, Ci += ar*bi + ai*br.  Operand tiles of
+// BK = 16 complex k-values are staged in LDS with k contiguous for both operands (rows padded
+// to 144 bytes), double buffered with one barrier per k-tile; the global loads of tile t+1
+// are issued before the MFMAs of tile t.  Within a k-tile, lanes 0-31 take k = 0..7 and
+// lanes 32-63 take k = 8..15 (the two halves of the instruction's K=2), so each lane reads its
+// operands as 16-byte vectors.
+// =============================================================================================
+
+template <bool TA, bool TB, int BM, int BN>
+__global__ void __launch_bounds__(256) gemm_mfma_kernel(const Gemm g) {
+  constexpr int BK = 16, LDK = BK + 2;
+  constexpr int TMI = BM / 64, TNI = BN / 64;
+  constexpr int AV = BM / 32, BV = BN / 32;  // float4 (2 complex) loads per thread per tile
+  __shared__ __attribute__((aligned(16))) float2 As[2][BM * LDK];
+  __shared__ __attribute__((aligned(16))) float2 Bs[2][BN * LDK];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int h = lane >> 5, r = lane & 31;
+  const int64_t tiles_n = g.N / BN;
+  const int64_t tm = (int64_t)blockIdx.x / tiles_n, tn = (int64_t)blockIdx.x % tiles_n;
+  const int b = blockIdx.y;
+  const float2* __restrict__ A = g.A + g.a_add + (g.a_off ? g.a_off[b] : b * g.a_bs);
+  const float2* __restrict__ B = g.B + g.b_add + (g.b_off ? g.b_off[b] : b * g.b_bs);
+  float2* __restrict__ C = g.C + b * g.c_bs;
+  const int64_t m0 = tm * BM, n0 = tn * BN;
+
+  float4 ra[AV], rb[BV];
+  auto gload = [&](int64_t k0) {
+#pragma unroll
+    for (int v = 0; v < AV; ++v) {
+      const int e = tid + v * 256;
+      if (!TA) {
+        const int row = e >> 3, kp = e & 7;
+        ra[v] = *reinterpret_cast<const float4*>(A + (m0 + row) * g.lda + k0 + 2 * kp);
+      } else {
+        const int kr = e / (BM / 2), mp = e % (BM / 2);
+        ra[v] = *reinterpret_cast<const float4*>(A + (k0 + kr) * g.lda + m0 + 2 * mp);
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < BV; ++v) {
+      const int e = tid + v * 256;
+      if (!TB) {
+        const int kr = e / (BN / 2), np = e % (BN / 2);
+        rb[v] = *reinterpret_cast<const float4*>(B + (k0 + kr) * g.ldb + n0 + 2 * np);
+      } else {
+        const int row = e >> 3, kp = e & 7;
+        rb[v] = *reinterpret_cast<const float4*>(B + (n0 + row) * g.ldb + k0 + 2 * kp);
+      }
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int v = 0; v < AV; ++v) {
+      const int e = tid + v * 256;
+      if (!TA) {
+        const int row = e >> 3, kp = e & 7;
+        *reinterpret_cast<float4*>(&As[buf][row * LDK + 2 * kp]) = ra[v];
+      } else {
+        const int kr = e / (BM / 2), mp = e % (BM / 2);
+        As[buf][(2 * mp) * LDK + kr] = make_float2(ra[v].x, ra[v].y);
+        As[buf][(2 * mp + 1) * LDK + kr] = make_float2(ra[v].z, ra[v].w);
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < BV; ++v) {
+      const int e = tid + v * 256;
+      if (!TB) {
+        const int kr = e / (BN / 2), np = e % (BN / 2);
+        Bs[buf][(2 * np) * LDK + kr] = make_float2(rb[v].x, rb[v].y);
+        Bs[buf][(2 * np + 1) * LDK + kr] = make_float2(rb[v].z, rb[v].w);
+      } else {
+        const int row = e >> 3, kp = e & 7;
+        *reinterpret_cast<float4*>(&Bs[buf][row * LDK + 2 * kp]) = rb[v];
+      }
+    }
+  };
+
+  floatx16 cr[TMI][TNI], ci[TMI][TNI];
+#pragma unroll
+  for (int i = 0; i < TMI; ++i)
+#pragma unroll
+    for (int j = 0; j < TNI; ++j)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) cr[i][j][v] = ci[i][j][v] = 0.f;
+
+  const int nk = (int)(g.K / BK);
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < nk) gload((int64_t)(kt + 1) * BK);
+    const float2* as = As[buf];
+    const float2* bs = Bs[buf];
+#pragma unroll
+    for (int s2 = 0; s2 < 4; ++s2) {
+      float4 af[TMI], bf[TNI];
+#pragma unroll
+      for (int i = 0; i < TMI; ++i)
+        af[i] = *reinterpret_cast<const float4*>(
+            &as[(wm * (BM / 2) + i * 32 + r) * LDK + h * 8 + 2 * s2]);
+#pragma unroll
+      for (int j = 0; j < TNI; ++j)
+        bf[j] = *reinterpret_cast<const float4*>(
+            &bs[(wn * (BN / 2) + j * 32 + r) * LDK + h * 8 + 2 * s2]);
+      // the two terms of each part are issued in separate passes over the sub-tiles, so that
+      // consecutive MFMAs never feed the same accumulator
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+#pragma unroll
+        for (int pass = 0; pass < 2; ++pass)
+#pragma unroll
+          for (int i = 0; i < TMI; ++i) {
+            const float ar = u ? af[i].z : af[i].x;
+            const float ai = u ? af[i].w : af[i].y;
+#pragma unroll
+            for (int j = 0; j < TNI; ++j) {
+              const float br = u ? bf[j].z : bf[j].x;
+              const float bi = u ? bf[j].w : bf[j].y;
+              if (pass == 0) {
+                cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, br, cr[i][j], 0, 0, 0);
+                ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, bi, ci[i][j], 0, 0, 0);
+              } else {
+                cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(-ai, bi, cr[i][j], 0, 0, 0);
+                ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai, br, ci[i][j], 0, 0, 0);
+              }
+            }
+          }
+      }
+    }
+    if (kt + 1 < nk) sstore(buf ^ 1);
+    __syncthreads();
+  }
+  // D layout of the 32x32 instruction: lane -> column r, register v -> row 8*(v/4)+4*h+(v%4)
+#pragma unroll
+  for (int i = 0; i < TMI; ++i)
+#pragma unroll
+    for (int j = 0; j < TNI; ++j)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int row = wm * (BM / 2) + i * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
+        const int col = wn * (BN / 2) + j * 32 + r;
+        C[(m0 + row) * g.ldc + n0 + col] = make_float2(cr[i][j][v], ci[i][j][v]);
+      }
+}
+
+// SIMT fallback for shapes too small or thin for MFMA tiles: BM x BN outputs per workgroup,
+// one per thread, k-tiles of 16 staged through LDS with bounds checks on every dimension.
+template <int BM, int BN, bool TA, bool TB>
+__global__ void __launch_bounds__(256) gemm_simt_kernel(const Gemm g) {
+  static_assert(BM * BN == 256, "one output per thread");
+  constexpr int BK = 16;
+  __shared__ float2 As[BM][BK + 1];
+  __shared__ float2 Bs[BK][BN + 1];
+  const int tid = threadIdx.x;
+  const int64_t tiles_n = (g.N + BN - 1) / BN;
+  const int64_t m0 = (int64_t)(blockIdx.x / tiles_n) * BM, n0 = (int64_t)(blockIdx.x % tiles_n) * BN;
+  const int b = blockIdx.y;
+  const float2* A = g.A + g.a_add + (g.a_off ? g.a_off[b] : b * g.a_bs);
+  const float2* B = g.B + g.b_add + (g.b_off ? g.b_off[b] : b * g.b_bs);
+  float2* C = g.C + b * g.c_bs;
+  const int tm = tid / BN, tn = tid % BN;
+  float accr = 0.f, acci = 0.f;
+  for (int64_t k0 = 0; k0 < g.K; k0 += BK) {
+    for (int e = tid; e < BM * BK; e += 256) {
+      int mm, kk;
+      if (!TA) mm = e / BK, kk = e % BK;
+      else kk = e / BM, mm = e % BM;
+      const int64_t m = m0 + mm, k = k0 + kk;
+      float2 v = make_float2(0.f, 0.f);
+      if (m < g.M && k < g.K) v = TA ? A[k * g.lda + m] : A[m * g.lda + k];
+      As[mm][kk] = v;
+    }
+    for (int e = tid; e < BN * BK; e += 256) {
+      int nn, kk;
+      if (!TB) kk = e / BN, nn = e % BN;
+      else nn = e / BK, kk = e % BK;
+      const int64_t n = n0 + nn, k = k0 + kk;
+      float2 v = make_float2(0.f, 0.f);
+      if (n < g.N && k < g.K) v = TB ? B[n * g.ldb + k] : B[k * g.ldb + n];
+      Bs[kk][nn] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < BK; ++kk) {
+      const float2 a = As[tm][kk], bb = Bs[kk][tn];
+      accr = fmaf(a.x, bb.x, accr);
+      accr = fmaf(-a.y, bb.y, accr);
+      acci = fmaf(a.x, bb.y, acci);
+      acci = fmaf(a.y, bb.x, acci);
+    }
+    __syncthreads();
+  }
+  const int64_t m = m0 + tm, n = n0 + tn;
+  if (m < g.M && n < g.N) C[m * g.ldc + n] = make_float2(accr, acci);
+}
+
+int gemm_variant(const Gemm& g) {
+  if (g.K % 16 == 0 && g.M % 128 == 0 && g.N % 128 == 0) return 2;
+  if (g.K % 16 == 0 && g.M % 64 == 0 && g.N % 64 == 0) return 1;
+  return 0;
+}
+
+const char* gemm_name(const Gemm& g) {
+  static const char* names[3][4] = {
+      {"gemm_simt_nn", "gemm_simt_nt", "gemm_simt_tn", "gemm_simt_tt"},
+      {"gemm_mfma_64x64_nn", "gemm_mfma_64x64_nt", "gemm_mfma_64x64_tn", "gemm_mfma_64x64_tt"},
+      {"gemm_mfma_128x128_nn", "gemm_mfma_128x128_nt", "gemm_mfma_128x128_tn",
+       "gemm_mfma_128x128_tt"}};
+  return names[gemm_variant(g)][(g.ta ? 2 : 0) + (g.tb ? 1 : 0)];
+}
+
+template <bool TA, bool TB>
+static void gemm_t(const Gemm& g, hipStream_t s) {
+  if (g.batch < 1 || g.batch > 65535) throw std::runtime_error("gemm: bad batch");
+  const int v = gemm_variant(g);
+  if (v == 2) {
+    dim3 grid((unsigned)((g.M / 128) * (g.N / 128)), (unsigned)g.batch);
+    hipLaunchKernelGGL((gemm_mfma_kernel<TA, TB, 128, 128>), grid, dim3(256), 0, s, g);
+  } else if (v == 1) {
+    dim3 grid((unsigned)((g.M / 64) * (g.N / 64)), (unsigned)g.batch);
+    hipLaunchKernelGGL((gemm_mfma_kernel<TA, TB, 64, 64>), grid, dim3(256), 0, s, g);
+  } else {
+    auto launch = [&](auto kern, int bm, int bn) {
+      const int64_t tiles = ((g.M + bm - 1) / bm) * ((g.N + bn - 1) / bn);
+      hipLaunchKernelGGL(kern, dim3((unsigned)tiles, (unsigned)g.batch), dim3(256), 0, s, g);
+    };
+    if (g.N >= 16 && g.M >= 16) launch(gemm_simt_kernel<16, 16, TA, TB>, 16, 16);
+    else if (g.N >= 8) launch(gemm_simt_kernel<32, 8, TA, TB>, 32, 8);
+    else if (g.N >= 4) launch(gemm_simt_kernel<64, 4, TA, TB>, 64, 4);
+    else if (g.N >= 2) launch(gemm_simt_kernel<128, 2, TA, TB>, 128, 2);
+    else launch(gemm_simt_kernel<256, 1, TA, TB>, 256, 1);
+  }
+  check_launch("gemm");
+}
+
+void gemm(const Gemm& g, hipStream_t s) {
+  if (g.ta) {
+    if (g.tb) gemm_t<true, true>(g, s);
+    else gemm_t<true, false>(g, s);
+  } else {
+    if (g.tb) gemm_t<false, true>(g, s);
+    else gemm_t<false, false>(g, s);
+  }
+}
+}  // namespace dev
+}  // namespace qflex

@@ -1,0 +1,165 @@
+// Split-precision complex products on 16-bit MFMA.
+#include "kernel_util.h"
+
+namespace qflex {
+namespace dev {
+
+// tile's global loads are issued before the current tile's MFMAs.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+__device__ inline bf16x8 as_bf16x8(uint4 v) {
+  bf16x8 r;
+  __builtin_memcpy(&r, &v, 16);
+  return r;
+}
+
+template <int BM, int BN, int WM, int WN>
+__global__ void __launch_bounds__(64 * WM * WN) gemm_split_kernel(const GemmSplit g) {
+  constexpr int NT = 64 * WM * WN;       // threads: WM x WN wavefronts
+  constexpr int BK = 16;                 // complex k per tile
+  constexpr int ROW = BK * 4;            // bf16 per row per tile (128 bytes)
+  constexpr int LDR = ROW + 8;           // padded row (144 bytes)
+  constexpr int WTM = BM / WM, WTN = BN / WN;  // wavefront tile (complex)
+  constexpr int TMI = WTM / 32, TNI = WTN / 32;
+  constexpr int AV = BM * ROW / 8 / NT, BV = BN * ROW / 8 / NT;  // uint4 loads per thread
+  __shared__ __attribute__((aligned(16))) uint16_t As[2][BM * LDR];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[2][BN * LDR];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave / WN, wn = wave % WN;
+  const int h = lane >> 5, r = lane & 31;
+  const int64_t tiles_n = g.N / BN;
+  const int64_t tm = (int64_t)blockIdx.x / tiles_n, tn = (int64_t)blockIdx.x % tiles_n;
+  const int b = blockIdx.y;
+  const uint16_t* __restrict__ A = g.A + 4 * (g.a_add + (g.a_off ? g.a_off[b] : b * g.a_bs));
+  const uint16_t* __restrict__ B = g.B + 4 * (g.b_add + (g.b_off ? g.b_off[b] : b * g.b_bs));
+  float2* __restrict__ C = g.C + b * g.c_bs;
+  const int64_t lda = 4 * g.K, ldb = 4 * g.K;
+  const int64_t m0 = tm * BM, n0 = tn * BN;
+
+  uint4 ra[AV], rb[BV];
+  auto gload = [&](int64_t k0) {  // k0 in bf16 units along the row
+#pragma unroll
+    for (int v = 0; v < AV; ++v) {
+      const int e = tid + v * NT, row = e >> 3, ch = e & 7;
+      ra[v] = *reinterpret_cast<const uint4*>(A + (m0 + row) * lda + k0 + 8 * ch);
+    }
+#pragma unroll
+    for (int v = 0; v < BV; ++v) {
+      const int e = tid + v * NT, row = e >> 3, ch = e & 7;
+      rb[v] = *reinterpret_cast<const uint4*>(B + (n0 + row) * ldb + k0 + 8 * ch);
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int v = 0; v < AV; ++v) {
+      const int e = tid + v * NT, row = e >> 3, ch = e & 7;
+      *reinterpret_cast<uint4*>(&As[buf][row * LDR + 8 * ch]) = ra[v];
+    }
+#pragma unroll
+    for (int v = 0; v < BV; ++v) {
+      const int e = tid + v * NT, row = e >> 3, ch = e & 7;
+      *reinterpret_cast<uint4*>(&Bs[buf][row * LDR + 8 * ch]) = rb[v];
+    }
+  };
+  floatx16 cr[TMI][TNI], ci[TMI][TNI];
+#pragma unroll
+  for (int i = 0; i < TMI; ++i)
+#pragma unroll
+    for (int j = 0; j < TNI; ++j)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) cr[i][j][v] = ci[i][j][v] = 0.f;
+  const int nk = (int)(g.K / BK);
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < nk) gload((int64_t)(kt + 1) * ROW);
+    const uint16_t* as = As[buf];
+    const uint16_t* bs = Bs[buf];
+#pragma unroll
+    for (int s2 = 0; s2 < BK / 8; ++s2) {
+      const int col = 16 * (2 * s2 + h);  // this lane's 4-k group, in bf16
+      bf16x8 ah[TMI], al[TMI], brh[TNI], brl[TNI], bih[TNI], bil[TNI];
+#pragma unroll
+      for (int i = 0; i < TMI; ++i) {
+        const uint16_t* p = &as[(wm * WTM + i * 32 + r) * LDR + col];
+        ah[i] = as_bf16x8(*reinterpret_cast<const uint4*>(p));
+        al[i] = as_bf16x8(*reinterpret_cast<const uint4*>(p + 8));
+      }
+#pragma unroll
+      for (int j = 0; j < TNI; ++j) {
+        const uint16_t* p = &bs[(wn * WTN + j * 32 + r) * LDR + col];
+        const uint4 vh = *reinterpret_cast<const uint4*>(p);
+        const uint4 vl = *reinterpret_cast<const uint4*>(p + 8);
+        brh[j] = as_bf16x8(make_uint4(vh.x, vh.y, vh.z ^ 0x80008000u, vh.w ^ 0x80008000u));
+        brl[j] = as_bf16x8(make_uint4(vl.x, vl.y, vl.z ^ 0x80008000u, vl.w ^ 0x80008000u));
+        bih[j] = as_bf16x8(make_uint4(vh.z, vh.w, vh.x, vh.y));
+        bil[j] = as_bf16x8(make_uint4(vl.z, vl.w, vl.x, vl.y));
+      }
+      // term by term over all sub-tiles, so that consecutive MFMAs never feed the same
+      // accumulator (each chain has 2*TMI*TNI-1 independent instructions between its links)
+#pragma unroll
+      for (int i = 0; i < TMI; ++i)
+#pragma unroll
+        for (int j = 0; j < TNI; ++j) {
+          cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], brh[j], cr[i][j], 0, 0, 0);
+          ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bih[j], ci[i][j], 0, 0, 0);
+        }
+#pragma unroll
+      for (int i = 0; i < TMI; ++i)
+#pragma unroll
+        for (int j = 0; j < TNI; ++j) {
+          cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], brl[j], cr[i][j], 0, 0, 0);
+          ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bil[j], ci[i][j], 0, 0, 0);
+        }
+#pragma unroll
+      for (int i = 0; i < TMI; ++i)
+#pragma unroll
+        for (int j = 0; j < TNI; ++j) {
+          cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], brh[j], cr[i][j], 0, 0, 0);
+          ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], bih[j], ci[i][j], 0, 0, 0);
+        }
+    }
+    if (kt + 1 < nk) sstore(buf ^ 1);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < TMI; ++i)
+#pragma unroll
+    for (int j = 0; j < TNI; ++j)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int row = wm * WTM + i * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
+        const int col = wn * WTN + j * 32 + r;
+        C[(m0 + row) * g.N + n0 + col] = make_float2(cr[i][j][v], ci[i][j][v]);
+      }
+}
+
+bool gemm_split_ok(int64_t M, int64_t N, int64_t K) {
+  return M > 0 && N > 0 && K > 0 && M % 64 == 0 && N % 64 == 0 && K % 16 == 0;
+}
+
+const char* gemm_split_name(const GemmSplit& g) {
+  if (g.M % 256 == 0 && g.N % 128 == 0) return "gemm_split_bf16_256x128";
+  if (g.M % 128 == 0 && g.N % 128 == 0) return "gemm_split_bf16_128x128";
+  return "gemm_split_bf16_64x64";
+}
+
+void gemm_split(const GemmSplit& g, hipStream_t s) {
+  if (!gemm_split_ok(g.M, g.N, g.K)) throw std::runtime_error("gemm_split: unsupported shape");
+  if (g.batch < 1 || g.batch > 65535) throw std::runtime_error("gemm_split: bad batch");
+  if (g.M % 256 == 0 && g.N % 128 == 0) {
+    dim3 grid((unsigned)((g.M / 256) * (g.N / 128)), (unsigned)g.batch);
+    hipLaunchKernelGGL((gemm_split_kernel<256, 128, 4, 2>), grid, dim3(512), 0, s, g);
+  } else if (g.M % 128 == 0 && g.N % 128 == 0) {
+    dim3 grid((unsigned)((g.M / 128) * (g.N / 128)), (unsigned)g.batch);
+    hipLaunchKernelGGL((gemm_split_kernel<128, 128, 2, 2>), grid, dim3(256), 0, s, g);
+  } else {
+    dim3 grid((unsigned)((g.M / 64) * (g.N / 64)), (unsigned)g.batch);
+    hipLaunchKernelGGL((gemm_split_kernel<64, 64, 2, 2>), grid, dim3(256), 0, s, g);
+  }
+  check_launch("gemm_split");
+}
+}  // namespace dev
+}  // namespace qflex

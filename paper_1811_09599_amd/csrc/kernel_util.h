@@ -1,0 +1,64 @@
+// Device helpers shared by the kernel sources of the contraction path (gfx950).
+#pragma once
+
+#include <stdexcept>
+#include <string>
+
+#include "kernels.h"
+
+namespace qflex {
+namespace dev {
+
+inline void check_launch(const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) throw std::runtime_error(std::string(what) + ": " + hipGetErrorString(e));
+}
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+__device__ inline double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ inline double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// ---- binary index tiles (see permute.hip)
+__device__ inline int lds_pad(int i) { return i + (i >> 5); }
+
+// Offsets of tile element i = t + 256*k are split into a per-thread part (bits 0..7 of i,
+// computed once) and a per-k part (bits 8..9), so that each element costs one add instead of
+// a loop over the tile bits.  Every loop over descriptor entries is fully unrolled with a
+// static index, so the descriptor stays in scalar registers.
+__device__ inline int64_t rest_offset(int64_t T, const int8_t* pos, int n) {
+  int64_t o = 0;
+#pragma unroll
+  for (int r = 0; r < kPermMaxBits; ++r)
+    if (r < n) o |= ((T >> r) & 1) << pos[r];
+  return o;
+}
+
+// bits [from, to) of v (v's bit 0 is bit `from`) deposited at positions pos[from..to)
+template <int FROM, int TO>
+__device__ inline int64_t deposit(int v, const int8_t* pos, int limit) {
+  int64_t o = 0;
+#pragma unroll
+  for (int b = FROM; b < TO; ++b)
+    if (b < limit) o |= (int64_t)((v >> (b - FROM)) & 1) << pos[b];
+  return o;
+}
+
+template <int FROM, int TO>
+__device__ inline int deposit_i(int v, const int8_t* pos, int limit) {
+  int o = 0;
+#pragma unroll
+  for (int b = FROM; b < TO; ++b)
+    if (b < limit) o |= ((v >> (b - FROM)) & 1) << pos[b];
+  return o;
+}
+}  // namespace dev
+}  // namespace qflex

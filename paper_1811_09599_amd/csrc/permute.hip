@@ -1,0 +1,218 @@
+// Binary index permutations of complex64 tensors (plain, and into the split layouts).
+#include "kernel_util.h"
+
+namespace qflex {
+namespace dev {
+
+// =============================================================================================
+// Binary index permutation (paper, Methods B.2: reordering so that contracted indexes are
+// contiguous for the matrix product).  GPU form: each workgroup moves one tile of 2^tile_bits
+// elements through LDS.  The tile holds the lowest input bits (so every read is a run of
+// consecutive addresses) and the lowest output bits (so every write is too); the remaining
+// bits enumerate tiles.  A permutation that keeps the low bits in place degenerates into a
+// block copy.
+// =============================================================================================
+PermTile make_perm_tile(int nbits, const int* perm) {
+  if (nbits > kPermMaxBits) throw std::runtime_error("permute: too many index bits");
+  PermTile t{};
+  t.nbits = nbits;
+  int inv[kPermMaxBits];
+  for (int j = 0; j < nbits; ++j) inv[perm[j]] = j;
+  const int T = std::min(nbits, kPermMaxTile);
+  bool in_tile[kPermMaxBits] = {false};
+  int size = 0;
+  for (int p = 0; p < std::min(nbits, 5); ++p) in_tile[p] = true, ++size;
+  for (int j = 0; j < nbits && size < T; ++j)
+    if (!in_tile[perm[j]]) in_tile[perm[j]] = true, ++size;
+  for (int p = 0; p < nbits && size < T; ++p)
+    if (!in_tile[p]) in_tile[p] = true, ++size;
+  t.tile_bits = size;
+  int ti = 0;
+  int read_index_of[kPermMaxBits];
+  for (int p = 0; p < nbits; ++p)
+    if (in_tile[p]) read_index_of[p] = ti, t.tile_in[ti++] = (int8_t)p;
+  // write order: tile bits by output position
+  int to = 0;
+  for (int j = 0; j < nbits; ++j)
+    if (in_tile[perm[j]]) {
+      t.tile_out[to] = (int8_t)j;
+      t.j2i[to] = (int8_t)read_index_of[perm[j]];
+      ++to;
+    }
+  int r = 0;
+  for (int p = 0; p < nbits; ++p)
+    if (!in_tile[p]) {
+      t.rest_in[r] = (int8_t)p;
+      t.rest_out[r] = (int8_t)inv[p];
+      ++r;
+    }
+  t.nrest = r;
+  return t;
+}
+
+
+__global__ void __launch_bounds__(256) permute_kernel(const float2* __restrict__ in,
+                                                      float2* __restrict__ out,
+                                                      const PermTile t) {
+  __shared__ float2 tile[(1 << kPermMaxTile) + (1 << kPermMaxTile) / 32];
+  const int64_t batch_stride = int64_t(1) << t.nbits;
+  in += (int64_t)blockIdx.y * batch_stride;
+  out += (int64_t)blockIdx.y * batch_stride;
+  const int64_t T = blockIdx.x;
+  const int64_t in_base = rest_offset(T, t.rest_in, t.nrest);
+  const int64_t out_base = rest_offset(T, t.rest_out, t.nrest);
+  const int tb = t.tile_bits;
+  const int tsize = 1 << tb;
+  const int tid = threadIdx.x;
+  const int nk = tsize > 256 ? tsize >> 8 : 1;
+  if (tid < tsize) {
+    const int64_t in_lo = in_base + deposit<0, 8>(tid, t.tile_in, tb);
+    for (int k = 0; k < nk; ++k)
+      tile[lds_pad(tid + (k << 8))] = in[in_lo + deposit<8, kPermMaxTile>(k, t.tile_in, tb)];
+  }
+  __syncthreads();
+  if (tid < tsize) {
+    const int i_lo = deposit_i<0, 8>(tid, t.j2i, tb);
+    const int64_t out_lo = out_base + deposit<0, 8>(tid, t.tile_out, tb);
+    for (int k = 0; k < nk; ++k) {
+      const int i = i_lo | deposit_i<8, kPermMaxTile>(k, t.j2i, tb);
+      out[out_lo + deposit<8, kPermMaxTile>(k, t.tile_out, tb)] = tile[lds_pad(i)];
+    }
+  }
+}
+
+void permute(const float2* in, float2* out, int64_t batch, const PermTile& t, hipStream_t s) {
+  const int64_t tiles = int64_t(1) << t.nrest;
+  if (batch < 1 || batch > 65535) throw std::runtime_error("permute: bad batch");
+  hipLaunchKernelGGL(permute_kernel, dim3((unsigned)tiles, (unsigned)batch), dim3(256), 0, s, in,
+                     out, t);
+  check_launch("permute");
+}
+
+// =============================================================================================
+// Split-precision complex products on bf16 MFMA (see kernels.h for the operand layouts).
+// =============================================================================================
+__device__ inline uint16_t bf16_rne(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even (finite inputs)
+  return (uint16_t)(u >> 16);
+}
+__device__ inline float bf16_to_f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// One thread per group of 4 consecutive k of a row: the tile's write order starts with the
+// lowest output bits, so a group is 4 consecutive write indices and is stored as two 16-byte
+// vectors.
+__global__ void __launch_bounds__(256) split_permute_kernel(const float2* __restrict__ in,
+                                                            uint16_t* __restrict__ out,
+                                                            const PermTile t) {
+  __shared__ float2 tile[(1 << kPermMaxTile) + (1 << kPermMaxTile) / 32];
+  const int64_t n_el = int64_t(1) << t.nbits;
+  in += (int64_t)blockIdx.y * n_el;
+  out += (int64_t)blockIdx.y * n_el * 4;
+  const int64_t T = blockIdx.x;
+  const int64_t in_base = rest_offset(T, t.rest_in, t.nrest);
+  const int64_t out_base = rest_offset(T, t.rest_out, t.nrest);
+  const int tb = t.tile_bits;
+  const int tsize = 1 << tb;
+  const int tid = threadIdx.x;
+  const int nk = tsize > 256 ? tsize >> 8 : 1;
+  if (tid < tsize) {
+    const int64_t in_lo = in_base + deposit<0, 8>(tid, t.tile_in, tb);
+    for (int k = 0; k < nk; ++k)
+      tile[lds_pad(tid + (k << 8))] = in[in_lo + deposit<8, kPermMaxTile>(k, t.tile_in, tb)];
+  }
+  __syncthreads();
+  // group q holds write indices 4q..4q+3 (write bits 0 and 1 are the two lowest k bits);
+  // q = tid + 256*k2, k2 < 1 for tiles of up to 1024 elements
+  const int ngroups = tsize >> 2;
+  if (tid < ngroups) {
+    const int q = tid;
+    // write index bits 2.. come from q
+    int ig = 0;
+    int64_t e0 = out_base;
+#pragma unroll
+    for (int b = 2; b < kPermMaxTile; ++b)
+      if (b < tb) {
+        const int bit = (q >> (b - 2)) & 1;
+        ig |= bit << t.j2i[b];
+        e0 |= (int64_t)bit << t.tile_out[b];
+      }
+    uint16_t h[16];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = ig | ((u & 1) << t.j2i[0]) | (((u >> 1) & 1) << t.j2i[1]);
+      const float2 v = tile[lds_pad(i)];
+      const uint16_t rh = bf16_rne(v.x), ih = bf16_rne(v.y);
+      h[u] = rh;
+      h[4 + u] = ih;
+      h[8 + u] = bf16_rne(v.x - bf16_to_f(rh));
+      h[12 + u] = bf16_rne(v.y - bf16_to_f(ih));
+    }
+    uint4 lo, hi;
+    lo.x = h[0] | ((uint32_t)h[1] << 16);
+    lo.y = h[2] | ((uint32_t)h[3] << 16);
+    lo.z = h[4] | ((uint32_t)h[5] << 16);
+    lo.w = h[6] | ((uint32_t)h[7] << 16);
+    hi.x = h[8] | ((uint32_t)h[9] << 16);
+    hi.y = h[10] | ((uint32_t)h[11] << 16);
+    hi.z = h[12] | ((uint32_t)h[13] << 16);
+    hi.w = h[14] | ((uint32_t)h[15] << 16);
+    uint4* o = reinterpret_cast<uint4*>(out + 4 * e0);  // e0 is a multiple of 4
+    o[0] = lo;
+    o[1] = hi;
+  }
+}
+
+void split_permute(const float2* in, uint16_t* out, int64_t batch, const PermTile& t, int kbits,
+                   hipStream_t s) {
+  if (batch < 1 || batch > 65535) throw std::runtime_error("split_permute: bad batch");
+  // a thread's 4 consecutive write indices must be the 4 lowest k of one row
+  if (kbits < 2 || t.tile_bits < 2 || t.tile_out[0] != 0 || t.tile_out[1] != 1)
+    throw std::runtime_error("split_permute: K must be >= 4 and the tile must hold the 2 lowest bits");
+  const int64_t tiles = int64_t(1) << t.nrest;
+  hipLaunchKernelGGL(split_permute_kernel, dim3((unsigned)tiles, (unsigned)batch), dim3(256), 0,
+                     s, in, out, t);
+  check_launch("split_permute");
+}
+
+// Complex product on bf16 MFMA from the compact split layout.  WM x WN wavefronts per
+// workgroup (8 for the 256x128 complex tile: two per SIMD hide each other's barrier and LDS
+// latency, and the larger tile halves the bytes loaded per MFMA), each owning a 64x64 complex
+// block = 2x2 sub-tiles of v_mfma_f32_32x32x16_bf16 with separate real and imaginary
+// accumulators.  One instruction step covers 8 complex k: lanes 0-31 hold
+// k-group g, lanes 32-63 group g+1, each lane's 8 bf16 being [re(4 k), im(4 k)] of one part:
+//   Cr += Ah.Brh + Ah.Brl + Al.Brh,  Brh = [Br_h, -Bi_h]
+//   Ci += Ah.Bih + Ah.Bil + Al.Bih,  Bih = [Bi_h,  Br_h]
+// (Brh / Bih are built from one 16-byte LDS read by a sign flip / a half swap).  k-tiles of
+// 16 complex are staged in LDS (rows of 128 bytes padded to 144), double buffered; the next
+struct PermBits {
+  int8_t p[kPermMaxBits];
+};
+
+__global__ void scatter_add_perm_kernel(const float2* __restrict__ in, int nbits, PermBits pb,
+                                        double2* __restrict__ out, const int64_t* __restrict__ off,
+                                        int64_t add) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n = int64_t(1) << nbits;
+  if (e >= n) return;
+  const int b = blockIdx.y;
+  int64_t o = 0;
+  for (int j = 0; j < nbits; ++j) o |= ((e >> pb.p[j]) & 1) << j;
+  const float2 v = in[(int64_t)b * n + e];
+  double2* dst = out + add + (off ? off[b] : 0) + o;
+  atomicAdd(&dst->x, (double)v.x);
+  atomicAdd(&dst->y, (double)v.y);
+}
+
+void scatter_add_perm(const float2* in, int nbits, const int8_t* perm, int batch, double2* out,
+                      const int64_t* off, int64_t add, hipStream_t s) {
+  if (nbits > kPermMaxBits) throw std::runtime_error("scatter_add_perm: too many bits");
+  PermBits pb{};
+  for (int j = 0; j < nbits; ++j) pb.p[j] = perm[j];
+  const int64_t n = int64_t(1) << nbits;
+  hipLaunchKernelGGL(scatter_add_perm_kernel, dim3((unsigned)((n + 255) / 256), (unsigned)batch),
+                     dim3(256), 0, s, in, nbits, pb, out, off, add);
+  check_launch("scatter_add_perm");
+}
+}  // namespace dev
+}  // namespace qflex
