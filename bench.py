@@ -3,9 +3,9 @@
 Workload: 7x7 grid, depth 1+32+1 (bond dimension 16 on every link), the quadrant plan with
 2 cut bonds (256 slices, all summed: fidelity 1), a 6-qubit open batch (64 amplitudes per
 bit-string).  One step = one contraction call over the next `--bitstrings` bit-strings of a
-seeded set of 1024, every slice included.  Both precisions are measured: split-bf16 (the
-headline `value`) and complex64 (reported alongside), each with its error against the FP64
-oracle on sampled slices.
+seeded set of 1024, every slice included.  Three precisions are measured: split-bf16 (the
+headline `value`), split-fp16 and complex64 (reported alongside), each with its error against
+the FP64 oracle on sampled slices.
 
 Prints one JSON line: amplitudes/s (whole job), sustained TFLOP/s of the plan (8 real flops
 per complex multiply-add), the roofline of the dominant kernel measured with HIP events around
@@ -24,14 +24,19 @@ sys.path.insert(0, ROOT)
 
 # MI355X published peaks: dense MFMA fp32 / bf16, fp32 vector without packed math, HBM3E
 PEAK = {"mfma_fp32": (157.3, "TFLOP/s"), "mfma_bf16": (2500.0, "TFLOP/s"),
+        "mfma_fp16": (2500.0, "TFLOP/s"),
         "alu": (78.6, "TFLOP/s"), "hbm": (8000.0, "GB/s")}
-SPLIT_TOL = 2e-4
 C64_TOL = 1e-5
+# stated bounds of the 2^(n/2)-scaled amplitude error (max over the batch)
+TOL = {"split_bf16": 2e-4, "split_fp16": 4 * C64_TOL, "c64": C64_TOL}
+DTYPE = {"split_bf16": "bf16x3", "split_fp16": "fp16x3", "c64": "c64"}
 
 
 def kernel_bound(name):
     if name.startswith("gemm_split_bf16"):
         return "mfma", PEAK["mfma_bf16"]
+    if name.startswith("gemm_split_fp16"):
+        return "mfma", PEAK["mfma_fp16"]
     if name.startswith("gemm_mfma"):
         return "mfma", PEAK["mfma_fp32"]
     if name.startswith("gemm_simt"):
@@ -101,7 +106,8 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--bitstrings", type=int, default=4, help="bit-strings per step")
-    ap.add_argument("--precision", default="both", choices=["both", "c64", "split_bf16"])
+    ap.add_argument("--precision", default="all",
+                    choices=["all", "c64", "split_bf16", "split_fp16"])
     ap.add_argument("--cpu-slices", type=int, default=3, help="oracle sample size (slices)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -121,7 +127,7 @@ def main():
     open_q = R.grid_ids((rows, cols), [(5, 0), (5, 1), (5, 2), (6, 0), (6, 1), (6, 2)])
     all_bits = R.bitstrings(rows * cols, 1024, 2500, open_q)
     plan = plan_describe(circ, open_qubits=open_q)
-    precs = ["split_bf16", "c64"] if args.precision == "both" else [args.precision]
+    precs = ["split_bf16", "split_fp16", "c64"] if args.precision == "all" else [args.precision]
     results, grids = {}, {}
     for p in precs:
         grids[p], results[p] = run_precision(p, circ, open_q, all_bits, args)
@@ -131,7 +137,7 @@ def main():
         "metric": "amplitudes/s", "value": r["value"], "unit": "amplitudes/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "bf16x3" if head == "split_bf16" else "c64", "data": "synthetic",
+        "dtype": DTYPE[head], "data": "synthetic",
         "config": {"workload": "7x7 RQC depth 1+32+1 (bond dim 16), quadrant plan with 2 cuts "
                                "(256 slices, fidelity 1), 6-qubit open batch (64 amplitudes "
                                "per bit-string), %d bit-strings per step" % args.bitstrings,
@@ -145,8 +151,9 @@ def main():
         "precisions": {p: {k: v for k, v in results[p].items() if k != "kernels"}
                        for p in precs},
     }
-    if len(precs) == 2:
-        res["speedup_split_bf16_vs_c64"] = results["split_bf16"]["value"] / results["c64"]["value"]
+    for p in precs:
+        if p != "c64" and "c64" in results:
+            res["speedup_%s_vs_c64" % p] = results[p]["value"] / results["c64"]["value"]
     if not args.no_cpu_baseline:
         res.update(cpu_baseline(circ, grids, all_bits[:1], open_q, args.cpu_slices, rows, cols))
     print(json.dumps(res), flush=True)
@@ -176,7 +183,7 @@ def cpu_baseline(circ, grids, bits, open_q, n_slices, rows, cols):
         gpu = g.contract_amplitudes(bits, slice_ids=ids).cpu().numpy()
         err = metrics.amp_errors(gpu, ref, rows * cols)
         parity[p] = {"max_rel_err": err["max"], "median_rel_err": err["median"],
-                     "l2_rel_err": err["l2"], "tol": SPLIT_TOL if p == "split_bf16" else C64_TOL}
+                     "l2_rel_err": err["l2"], "tol": TOL[p]}
     per_slice = dt / len(ids)
     rate = 64.0 / (per_slice * S)
     return {"cpu_baseline": {"value": rate, "unit": "amplitudes/s",

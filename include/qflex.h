@@ -61,7 +61,7 @@ typedef enum {
 typedef enum {
   QFLEX_PREC_C64 = 0,        /* complex64 operands, FP32 MFMA, FP32 accumulation */
   QFLEX_PREC_SPLIT_BF16 = 1, /* complex64 operands split into hi+lo bf16, FP32 accumulation */
-  QFLEX_PREC_SPLIT_FP16 = 2  /* hi + scaled lo fp16 parts, FP32 accumulation */
+  QFLEX_PREC_SPLIT_FP16 = 2  /* hi+lo fp16 parts of the operand times a power-of-two scale */
 } qflex_precision;
 
 /* Gate kinds (matrices as in the paper's Methods A; fSim as in the comment below). */

@@ -34,15 +34,23 @@ qflex_status qflex_permute_c64(const void* in, void* out, int32_t nbits, const i
 qflex_status qflex_gemm_c64(const void* A, const void* B, void* C, int64_t M, int64_t N,
                             int64_t K, int32_t ta, int32_t tb, int64_t batch, void* stream);
 
-/* The same product in split precision (QFLEX_PREC_SPLIT_BF16): each complex64 operand is
- * split into hi + lo bf16 parts, the three products hi*hi + hi*lo + lo*hi of each real part
- * run on bf16 MFMA with FP32 accumulation (lo*lo is dropped), giving about 16 significant bits
- * per operand instead of 24.  M, N, K must be powers of two with M >= 128, N >= 64, K >= 16.
- * workspace: device memory of at least qflex_gemm_split_workspace(M, N, K, batch) bytes that
- * the call uses for the split operands (it allocates nothing itself). */
+/* The same product in split precision: each real part x of a complex64 operand is split into
+ * two 16-bit parts, hi = round(x) and lo = round(x - hi); the three products hi*hi + hi*lo +
+ * lo*hi run on 16-bit MFMA with FP32 accumulation (lo*lo is dropped).
+ *   precision = QFLEX_PREC_SPLIT_BF16: bf16 parts, about 16 significant bits per operand.
+ *   precision = QFLEX_PREC_SPLIT_FP16: fp16 parts of the operand times 2^k, k chosen from the
+ *     operand's largest magnitude m (over the whole batch) so that m 2^k is in [2^14, 2^15);
+ *     about 22 significant bits for values within 2^-17 of m, fewer below; the result is
+ *     scaled back by 2^-(kA+kB).
+ * (Split-precision products are not in the paper, which multiplies in complex64.)
+ * M, N, K must be powers of two, multiples of 64 (M, N) and 16 (K); A and B 16-byte aligned.
+ * workspace: device memory, 16-byte aligned, of at least qflex_gemm_split_workspace(M, N, K,
+ * batch) bytes, used for the split operands and the two scale slots (the call allocates
+ * nothing itself; calls sharing one workspace must be ordered on one stream). */
 qflex_status qflex_gemm_split_c64(const void* A, const void* B, void* C, int64_t M, int64_t N,
                                   int64_t K, int32_t ta, int32_t tb, int64_t batch,
-                                  void* workspace, int64_t workspace_bytes, void* stream);
+                                  int32_t precision, void* workspace, int64_t workspace_bytes,
+                                  void* stream);
 int64_t qflex_gemm_split_workspace(int64_t M, int64_t N, int64_t K, int64_t batch);
 
 /* Kernel variant qflex_gemm_c64 uses for a shape: 0 SIMT, 1 MFMA 64x64, 2 MFMA 128x128. */

@@ -96,7 +96,7 @@ def lib():
     L.qflex_grid_free.restype = None
     L.qflex_last_error.restype = C.c_char_p
     L.qflex_gemm_split_c64.argtypes = [P, P, P, C.c_int64, C.c_int64, C.c_int64, C.c_int32,
-                                       C.c_int32, C.c_int64, P, C.c_int64, P]
+                                       C.c_int32, C.c_int64, C.c_int32, P, C.c_int64, P]
     L.qflex_gemm_split_workspace.argtypes = [C.c_int64] * 4
     L.qflex_gemm_split_workspace.restype = C.c_int64
     for name in EXPORTS[:-4]:

@@ -36,6 +36,7 @@ void release(qflex_grid* g) {
   if (g->grid) (void)hipFree(g->grid);
   if (g->bidx) (void)hipFree(g->bidx);
   if (g->grid_split) (void)hipFree(g->grid_split);
+  if (g->amax) (void)hipFree(g->amax);
   g->split_scratch.release();
   for (qflex::DevBuf* b : {&g->gq, &g->gpieces, &g->gmats, &g->gpos, &g->grad_arena, &g->tbar,
                            &g->pbar, &g->gbar, &g->amps_dev, &g->xeb})
@@ -79,8 +80,6 @@ qflex_status qflex_build_grid(const qflex_circuit* circuits, int32_t n_circuits,
         cs.plan = qflex::make_plan(cs.model, *opt);
         g->circ.push_back(std::move(cs));
       }
-      if (opt->precision == QFLEX_PREC_SPLIT_FP16)
-        qflex::fail(QFLEX_E_UNSUPPORTED, "split fp16 products are not built in");
       int dev = 0;
       hipError_t e = hipGetDevice(&dev);
       if (e != hipSuccess) qflex::fail(QFLEX_E_DEVICE, std::string("no HIP device: ") + hipGetErrorString(e));
@@ -242,16 +241,24 @@ qflex_status qflex_gemm_c64(const void* A, const void* B, void* C, int64_t M, in
   });
 }
 
+// split workspace: two fp16 scale slots (padded), then the split A and B operands
+constexpr int64_t kSplitSlotBytes = 256;
+
 int64_t qflex_gemm_split_workspace(int64_t M, int64_t N, int64_t K, int64_t batch) {
   if (M < 1 || N < 1 || K < 1 || batch < 1) return 0;
-  return (int64_t)sizeof(uint16_t) * 4 * batch * (M * K + N * K);
+  return kSplitSlotBytes + (int64_t)sizeof(uint16_t) * 4 * batch * (M * K + N * K);
 }
 
 qflex_status qflex_gemm_split_c64(const void* A, const void* B, void* C, int64_t M, int64_t N,
                                   int64_t K, int32_t ta, int32_t tb, int64_t batch,
-                                  void* workspace, int64_t workspace_bytes, void* stream) {
+                                  int32_t precision, void* workspace, int64_t workspace_bytes,
+                                  void* stream) {
   return guarded([&] {
     if (!A || !B || !C || !workspace) qflex::fail(QFLEX_E_INVALID, "NULL argument");
+    if (precision != QFLEX_PREC_SPLIT_BF16 && precision != QFLEX_PREC_SPLIT_FP16)
+      qflex::fail(QFLEX_E_INVALID, "precision must be QFLEX_PREC_SPLIT_BF16 or QFLEX_PREC_SPLIT_FP16");
+    if ((reinterpret_cast<uintptr_t>(A) | reinterpret_cast<uintptr_t>(B)) & 15)
+      qflex::fail(QFLEX_E_INVALID, "A and B must be 16-byte aligned");
     auto log2i = [](int64_t v) {
       int b = 0;
       while ((int64_t(1) << b) < v) ++b;
@@ -278,14 +285,24 @@ qflex_status qflex_gemm_split_c64(const void* A, const void* B, void* C, int64_t
     for (int j = 0; j < nb + kb; ++j) pbv[j] = j;
     if (ta) pa = transpose(kb, mb);   // stored [K][M] -> [M][K]
     if (!tb) pbv = transpose(kb, nb); // stored [K][N] -> [N][K]
-    auto* sa = static_cast<uint16_t*>(workspace);
+    auto* slots = static_cast<uint64_t*>(workspace);
+    auto* sa = reinterpret_cast<uint16_t*>(static_cast<char*>(workspace) + kSplitSlotBytes);
     auto* sb = sa + 4 * batch * M * K;
     const hipStream_t st = static_cast<hipStream_t>(stream);
+    const bool f16 = precision == QFLEX_PREC_SPLIT_FP16;
+    if (f16) {  // the caller's workspace holds anything: clear the slots, then tag 1
+      qflex::dev::fill_zero(reinterpret_cast<double*>(slots), 2, st);
+      qflex::dev::absmax(static_cast<const float2*>(A), batch * M * K, slots, 1, st);
+      qflex::dev::absmax(static_cast<const float2*>(B), batch * N * K, slots + 1, 1, st);
+    }
     qflex::dev::split_permute(static_cast<const float2*>(A), sa, batch,
-                              qflex::dev::make_perm_tile(mb + kb, pa.data()), kb, st);
+                              qflex::dev::make_perm_tile(mb + kb, pa.data()), kb,
+                              f16 ? slots : nullptr, st);
     qflex::dev::split_permute(static_cast<const float2*>(B), sb, batch,
-                              qflex::dev::make_perm_tile(nb + kb, pbv.data()), kb, st);
+                              qflex::dev::make_perm_tile(nb + kb, pbv.data()), kb,
+                              f16 ? slots + 1 : nullptr, st);
     qflex::dev::GemmSplit g;
+    if (f16) g.a_amax = slots, g.b_amax = slots + 1;
     g.A = sa;
     g.B = sb;
     g.C = static_cast<float2*>(C);

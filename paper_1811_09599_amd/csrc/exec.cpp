@@ -212,20 +212,35 @@ void build_grid_device(qflex_grid* g, hipStream_t s) {
       if (st.scratch_y >= 0) cs.py[i] = dev::make_perm_tile(st.py.nbits, st.py.perm.data());
     }
   }
-  if (g->precision == QFLEX_PREC_SPLIT_BF16) prepare_split(g, s);
+  if (g->precision == QFLEX_PREC_SPLIT_BF16 || g->precision == QFLEX_PREC_SPLIT_FP16)
+    prepare_split(g, s);
 }
 
-// Split-precision set-up: choose the steps that run as bf16 products, pre-split the qubit
+// Tag for the next absmax() into the fp16 scale slots: tags grow, so a slot never needs
+// clearing; when they would wrap, the two step slots are cleared and the tags start again (the
+// qubit slots are written once, at build, and only read after that).
+static uint32_t next_amax_tag(qflex_grid* g, hipStream_t s) {
+  if (g->amax_tag == UINT32_MAX) {
+    dev::fill_zero(reinterpret_cast<double*>(g->amax), 2, s);
+    g->amax_tag = 0;
+  }
+  return ++g->amax_tag;
+}
+
+// Split-precision set-up: choose the steps that run as 16-bit products, pre-split the qubit
 // tensors they read (A layout for a row operand, B layout for a column operand; the fixed
 // leading bits stay leading so that bit-string and cut offsets only scale), and build the
 // permute+split descriptors of intermediate operands.
 void prepare_split(qflex_grid* g, hipStream_t s) {
+  const bool f16 = g->precision == QFLEX_PREC_SPLIT_FP16;
   int64_t total = 0;
+  int64_t n_slots = 2;
   struct Job {
     int64_t src, dst;
     int nfixed, nbits, kbits;
     bool role_b;
     PermDesc pd;
+    int64_t slot;
   };
   std::vector<Job> jobs;
   for (auto& cs : g->circ) {
@@ -235,6 +250,7 @@ void prepare_split(qflex_grid* g, hipStream_t s) {
     cs.sx.assign(ns, dev::PermTile{});
     cs.sy.assign(ns, dev::PermTile{});
     cs.qsplit_offset.assign(cs.model.n, -1);
+    cs.qamax_slot.assign(cs.model.n, -1);
     cs.split_a_elems = cs.split_b_elems = 0;
     for (size_t i = 0; i < ns; ++i) {
       const Step& st = P.steps[i];
@@ -251,7 +267,8 @@ void prepare_split(qflex_grid* g, hipStream_t s) {
         if (o.qubit) {
           const QubitLayout& L = P.qubits[o.id];
           Job j{cs.grid_offset + cs.qubit_offset[o.id], total, L.n_fixed, L.free_bits(), st.kb,
-                side == 1, pd};
+                side == 1, pd, f16 ? n_slots : -1};
+          if (f16) cs.qamax_slot[o.id] = n_slots++;
           cs.qsplit_offset[o.id] = total;
           total += ((int64_t(4) << L.storage.size()) + 63) & ~int64_t(63);
           jobs.push_back(j);
@@ -264,12 +281,22 @@ void prepare_split(qflex_grid* g, hipStream_t s) {
       }
     }
   }
+  if (f16) {
+    QHIP(hipMalloc(&g->amax, sizeof(uint64_t) * n_slots));
+    g->n_amax = n_slots;
+    g->amax_tag = 0;
+    dev::fill_zero(reinterpret_cast<double*>(g->amax), n_slots, s);
+  }
   if (total == 0) return;
   QHIP(hipMalloc(&g->grid_split, sizeof(uint16_t) * total));
   for (const Job& j : jobs) {
     const dev::PermTile t = dev::make_perm_tile(j.nbits, j.pd.perm.data());
+    const int64_t n = int64_t(1) << (j.nfixed + j.nbits);
+    uint64_t* slot = j.slot >= 0 ? g->amax + j.slot : nullptr;
+    // one scale per qubit tensor, over every value of its fixed (bit-string / cut) indexes
+    if (slot) dev::absmax(g->grid + j.src, n, slot, next_amax_tag(g, s), s);
     dev::split_permute(g->grid + j.src, g->grid_split + j.dst, int64_t(1) << j.nfixed, t,
-                       j.kbits, s);
+                       j.kbits, slot, s);
   }
   QHIP(hipStreamSynchronize(s));
 }
@@ -453,13 +480,21 @@ void contract(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets, dou
             dev::GemmSplit gs;
             const int64_t M = int64_t(1) << stp.mb, N = int64_t(1) << stp.nb;
             const int64_t K = int64_t(1) << stp.kb;
+            const bool f16 = g->amax != nullptr;
             if (stp.x.qubit) {
               gs.A = g->grid_split + cs.qsplit_offset[stp.x.id];
               gs.a_add = x.add;
               gs.a_off = x.off;
+              if (f16) gs.a_amax = g->amax + cs.qamax_slot[stp.x.id];
             } else {
+              if (f16) {
+                gs.a_amax = g->amax;
+                g->prof.begin("absmax", 0, 8.0 * M * K * nb, s);
+                dev::absmax(x.base, M * K * nb, g->amax, next_amax_tag(g, s), s);
+                g->prof.end(s);
+              }
               g->prof.begin("split_permute", 0, 16.0 * M * K * nb, s);
-              dev::split_permute(x.base, sa, nb, cs.sx[k], stp.kb, s);
+              dev::split_permute(x.base, sa, nb, cs.sx[k], stp.kb, gs.a_amax, s);
               g->prof.end(s);
               st.permute_bytes += 16.0 * M * K * nb;
               ++st.n_permute;
@@ -470,9 +505,16 @@ void contract(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets, dou
               gs.B = g->grid_split + cs.qsplit_offset[stp.y.id];
               gs.b_add = y.add;
               gs.b_off = y.off;
+              if (f16) gs.b_amax = g->amax + cs.qamax_slot[stp.y.id];
             } else {
+              if (f16) {
+                gs.b_amax = g->amax + 1;
+                g->prof.begin("absmax", 0, 8.0 * N * K * nb, s);
+                dev::absmax(y.base, N * K * nb, g->amax + 1, next_amax_tag(g, s), s);
+                g->prof.end(s);
+              }
               g->prof.begin("split_permute", 0, 16.0 * N * K * nb, s);
-              dev::split_permute(y.base, sb, nb, cs.sy[k], stp.kb, s);
+              dev::split_permute(y.base, sb, nb, cs.sy[k], stp.kb, gs.b_amax, s);
               g->prof.end(s);
               st.permute_bytes += 16.0 * N * K * nb;
               ++st.n_permute;
@@ -486,7 +528,7 @@ void contract(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets, dou
             gs.N = N;
             gs.K = K;
             gs.batch = nb;
-            // the kernel's own arithmetic: 3 bf16 products per real product, 24*M*N*K flops
+            // the kernel's own arithmetic: 3 16-bit products per real product, 24*M*N*K flops
             g->prof.begin(dev::gemm_split_name(gs), 3.0 * stp.flops() * nb,
                           8.0 * nb * (double)(M * K + N * K + M * N), s);
             dev::gemm_split(gs, s);

@@ -1,23 +1,45 @@
 // Split-precision complex products on 16-bit MFMA.
 #include "kernel_util.h"
 
+#include <type_traits>
+
 namespace qflex {
 namespace dev {
 
-// tile's global loads are issued before the current tile's MFMAs.
+// Complex product on 16-bit MFMA from the compact split layout.  WM x WN wavefronts per
+// workgroup (8 for the 256x128 complex tile: two per SIMD hide each other's barrier and LDS
+// latency, and the larger tile halves the bytes loaded per MFMA), each owning a 64x64 complex
+// block = 2x2 sub-tiles of v_mfma_f32_32x32x16_{bf16,f16} with separate real and imaginary
+// accumulators.  One instruction step covers 8 complex k: lanes 0-31 hold
+// k-group g, lanes 32-63 group g+1, each lane's 8 values being [re(4 k), im(4 k)] of one part:
+//   Cr += Ah.Brh + Ah.Brl + Al.Brh,  Brh = [Br_h, -Bi_h]
+//   Ci += Ah.Bih + Ah.Bil + Al.Bih,  Bih = [Bi_h,  Br_h]
+// (Brh / Bih are built from one 16-byte LDS read by a sign flip / a half swap; both formats
+// keep the sign in bit 15).  k-tiles of 16 complex are staged in LDS (rows of 128 bytes padded
+// to 144), double buffered; the next tile's global loads are issued before the current tile's
+// MFMAs.  fp16 operands carry power-of-two scales, undone on the FP32 results.
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 
-__device__ inline bf16x8 as_bf16x8(uint4 v) {
-  bf16x8 r;
+template <typename V>
+__device__ inline V as_vec(uint4 v) {
+  V r;
   __builtin_memcpy(&r, &v, 16);
   return r;
 }
+__device__ inline floatx16 mfma16(bf16x8 a, bf16x8 b, floatx16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
+__device__ inline floatx16 mfma16(f16x8 a, f16x8 b, floatx16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+}
 
-template <int BM, int BN, int WM, int WN>
+template <int BM, int BN, int WM, int WN, bool F16>
 __global__ void __launch_bounds__(64 * WM * WN) gemm_split_kernel(const GemmSplit g) {
+  using V = typename std::conditional<F16, f16x8, bf16x8>::type;
   constexpr int NT = 64 * WM * WN;       // threads: WM x WN wavefronts
   constexpr int BK = 16;                 // complex k per tile
-  constexpr int ROW = BK * 4;            // bf16 per row per tile (128 bytes)
+  constexpr int ROW = BK * 4;            // 16-bit values per row per tile (128 bytes)
   constexpr int LDR = ROW + 8;           // padded row (144 bytes)
   constexpr int WTM = BM / WM, WTN = BN / WN;  // wavefront tile (complex)
   constexpr int TMI = WTM / 32, TNI = WTN / 32;
@@ -37,7 +59,7 @@ __global__ void __launch_bounds__(64 * WM * WN) gemm_split_kernel(const GemmSpli
   const int64_t m0 = tm * BM, n0 = tn * BN;
 
   uint4 ra[AV], rb[BV];
-  auto gload = [&](int64_t k0) {  // k0 in bf16 units along the row
+  auto gload = [&](int64_t k0) {  // k0 in 16-bit units along the row
 #pragma unroll
     for (int v = 0; v < AV; ++v) {
       const int e = tid + v * NT, row = e >> 3, ch = e & 7;
@@ -79,23 +101,23 @@ __global__ void __launch_bounds__(64 * WM * WN) gemm_split_kernel(const GemmSpli
     const uint16_t* bs = Bs[buf];
 #pragma unroll
     for (int s2 = 0; s2 < BK / 8; ++s2) {
-      const int col = 16 * (2 * s2 + h);  // this lane's 4-k group, in bf16
-      bf16x8 ah[TMI], al[TMI], brh[TNI], brl[TNI], bih[TNI], bil[TNI];
+      const int col = 16 * (2 * s2 + h);  // this lane's 4-k group, in 16-bit units
+      V ah[TMI], al[TMI], brh[TNI], brl[TNI], bih[TNI], bil[TNI];
 #pragma unroll
       for (int i = 0; i < TMI; ++i) {
         const uint16_t* p = &as[(wm * WTM + i * 32 + r) * LDR + col];
-        ah[i] = as_bf16x8(*reinterpret_cast<const uint4*>(p));
-        al[i] = as_bf16x8(*reinterpret_cast<const uint4*>(p + 8));
+        ah[i] = as_vec<V>(*reinterpret_cast<const uint4*>(p));
+        al[i] = as_vec<V>(*reinterpret_cast<const uint4*>(p + 8));
       }
 #pragma unroll
       for (int j = 0; j < TNI; ++j) {
         const uint16_t* p = &bs[(wn * WTN + j * 32 + r) * LDR + col];
         const uint4 vh = *reinterpret_cast<const uint4*>(p);
         const uint4 vl = *reinterpret_cast<const uint4*>(p + 8);
-        brh[j] = as_bf16x8(make_uint4(vh.x, vh.y, vh.z ^ 0x80008000u, vh.w ^ 0x80008000u));
-        brl[j] = as_bf16x8(make_uint4(vl.x, vl.y, vl.z ^ 0x80008000u, vl.w ^ 0x80008000u));
-        bih[j] = as_bf16x8(make_uint4(vh.z, vh.w, vh.x, vh.y));
-        bil[j] = as_bf16x8(make_uint4(vl.z, vl.w, vl.x, vl.y));
+        brh[j] = as_vec<V>(make_uint4(vh.x, vh.y, vh.z ^ 0x80008000u, vh.w ^ 0x80008000u));
+        brl[j] = as_vec<V>(make_uint4(vl.x, vl.y, vl.z ^ 0x80008000u, vl.w ^ 0x80008000u));
+        bih[j] = as_vec<V>(make_uint4(vh.z, vh.w, vh.x, vh.y));
+        bil[j] = as_vec<V>(make_uint4(vl.z, vl.w, vl.x, vl.y));
       }
       // term by term over all sub-tiles, so that consecutive MFMAs never feed the same
       // accumulator (each chain has 2*TMI*TNI-1 independent instructions between its links)
@@ -103,27 +125,29 @@ __global__ void __launch_bounds__(64 * WM * WN) gemm_split_kernel(const GemmSpli
       for (int i = 0; i < TMI; ++i)
 #pragma unroll
         for (int j = 0; j < TNI; ++j) {
-          cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], brh[j], cr[i][j], 0, 0, 0);
-          ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bih[j], ci[i][j], 0, 0, 0);
+          cr[i][j] = mfma16(ah[i], brh[j], cr[i][j]);
+          ci[i][j] = mfma16(ah[i], bih[j], ci[i][j]);
         }
 #pragma unroll
       for (int i = 0; i < TMI; ++i)
 #pragma unroll
         for (int j = 0; j < TNI; ++j) {
-          cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], brl[j], cr[i][j], 0, 0, 0);
-          ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bil[j], ci[i][j], 0, 0, 0);
+          cr[i][j] = mfma16(ah[i], brl[j], cr[i][j]);
+          ci[i][j] = mfma16(ah[i], bil[j], ci[i][j]);
         }
 #pragma unroll
       for (int i = 0; i < TMI; ++i)
 #pragma unroll
         for (int j = 0; j < TNI; ++j) {
-          cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], brh[j], cr[i][j], 0, 0, 0);
-          ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], bih[j], ci[i][j], 0, 0, 0);
+          cr[i][j] = mfma16(al[i], brh[j], cr[i][j]);
+          ci[i][j] = mfma16(al[i], bih[j], ci[i][j]);
         }
     }
     if (kt + 1 < nk) sstore(buf ^ 1);
     __syncthreads();
   }
+  float ua = 1.f, ub = 1.f;
+  if constexpr (F16) ua = fp16_unscale(*g.a_amax), ub = fp16_unscale(*g.b_amax);
 #pragma unroll
   for (int i = 0; i < TMI; ++i)
 #pragma unroll
@@ -132,7 +156,9 @@ __global__ void __launch_bounds__(64 * WM * WN) gemm_split_kernel(const GemmSpli
       for (int v = 0; v < 16; ++v) {
         const int row = wm * WTM + i * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
         const int col = wn * WTN + j * 32 + r;
-        C[(m0 + row) * g.N + n0 + col] = make_float2(cr[i][j][v], ci[i][j][v]);
+        float re = cr[i][j][v], im = ci[i][j][v];
+        if constexpr (F16) re = re * ua * ub, im = im * ua * ub;
+        C[(m0 + row) * g.N + n0 + col] = make_float2(re, im);
       }
 }
 
@@ -141,25 +167,35 @@ bool gemm_split_ok(int64_t M, int64_t N, int64_t K) {
 }
 
 const char* gemm_split_name(const GemmSplit& g) {
-  if (g.M % 256 == 0 && g.N % 128 == 0) return "gemm_split_bf16_256x128";
-  if (g.M % 128 == 0 && g.N % 128 == 0) return "gemm_split_bf16_128x128";
-  return "gemm_split_bf16_64x64";
+  const bool f16 = g.a_amax != nullptr;
+  if (g.M % 256 == 0 && g.N % 128 == 0) return f16 ? "gemm_split_fp16_256x128" : "gemm_split_bf16_256x128";
+  if (g.M % 128 == 0 && g.N % 128 == 0) return f16 ? "gemm_split_fp16_128x128" : "gemm_split_bf16_128x128";
+  return f16 ? "gemm_split_fp16_64x64" : "gemm_split_bf16_64x64";
+}
+
+template <bool F16>
+static void gemm_split_t(const GemmSplit& g, hipStream_t s) {
+  if (g.M % 256 == 0 && g.N % 128 == 0) {
+    dim3 grid((unsigned)((g.M / 256) * (g.N / 128)), (unsigned)g.batch);
+    hipLaunchKernelGGL((gemm_split_kernel<256, 128, 4, 2, F16>), grid, dim3(512), 0, s, g);
+  } else if (g.M % 128 == 0 && g.N % 128 == 0) {
+    dim3 grid((unsigned)((g.M / 128) * (g.N / 128)), (unsigned)g.batch);
+    hipLaunchKernelGGL((gemm_split_kernel<128, 128, 2, 2, F16>), grid, dim3(256), 0, s, g);
+  } else {
+    dim3 grid((unsigned)((g.M / 64) * (g.N / 64)), (unsigned)g.batch);
+    hipLaunchKernelGGL((gemm_split_kernel<64, 64, 2, 2, F16>), grid, dim3(256), 0, s, g);
+  }
 }
 
 void gemm_split(const GemmSplit& g, hipStream_t s) {
   if (!gemm_split_ok(g.M, g.N, g.K)) throw std::runtime_error("gemm_split: unsupported shape");
   if (g.batch < 1 || g.batch > 65535) throw std::runtime_error("gemm_split: bad batch");
-  if (g.M % 256 == 0 && g.N % 128 == 0) {
-    dim3 grid((unsigned)((g.M / 256) * (g.N / 128)), (unsigned)g.batch);
-    hipLaunchKernelGGL((gemm_split_kernel<256, 128, 4, 2>), grid, dim3(512), 0, s, g);
-  } else if (g.M % 128 == 0 && g.N % 128 == 0) {
-    dim3 grid((unsigned)((g.M / 128) * (g.N / 128)), (unsigned)g.batch);
-    hipLaunchKernelGGL((gemm_split_kernel<128, 128, 2, 2>), grid, dim3(256), 0, s, g);
-  } else {
-    dim3 grid((unsigned)((g.M / 64) * (g.N / 64)), (unsigned)g.batch);
-    hipLaunchKernelGGL((gemm_split_kernel<64, 64, 2, 2>), grid, dim3(256), 0, s, g);
-  }
+  if ((g.a_amax == nullptr) != (g.b_amax == nullptr))
+    throw std::runtime_error("gemm_split: both operands must use the same format");
+  if (g.a_amax) gemm_split_t<true>(g, s);
+  else gemm_split_t<false>(g, s);
   check_launch("gemm_split");
 }
+
 }  // namespace dev
 }  // namespace qflex

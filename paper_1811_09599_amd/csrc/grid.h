@@ -26,10 +26,11 @@ struct CircuitState {
   int64_t bidx_offset = 0;           // offset of its batch-index table in the device table
   std::vector<dev::PermTile> px, py; // per step (valid when the step permutes x / y)
   // split-precision products
-  std::vector<char> split;           // per step: runs as a split bf16 product
+  std::vector<char> split;           // per step: runs as a split (16-bit) product
   std::vector<dev::PermTile> sx, sy; // per step: node operand -> split operand layout
-  std::vector<int64_t> qsplit_offset;// per qubit: bf16 offset in grid_split, -1 if none
-  int64_t split_a_elems = 0, split_b_elems = 0;  // scratch per bit-string (bf16 values)
+  std::vector<int64_t> qsplit_offset;// per qubit: offset in grid_split (16-bit values), -1 if none
+  std::vector<int64_t> qamax_slot;   // per qubit: fp16 scale slot in amax, -1 if none
+  int64_t split_a_elems = 0, split_b_elems = 0;  // scratch per bit-string (16-bit values)
 };
 
 // Device buffer that only grows; freed with the grid.
@@ -81,7 +82,12 @@ struct qflex_grid {
   float2* grid = nullptr;                // all qubit tensors
   int64_t grid_elems = 0;
   uint32_t* bidx = nullptr;              // batch-index tables of all circuits
-  uint16_t* grid_split = nullptr;        // qubit tensors pre-split for bf16 products
+  uint16_t* grid_split = nullptr;        // qubit tensors pre-split for 16-bit products
+  // fp16 split scales: absmax slots [0] = row operand, [1] = column operand of the current
+  // step, then one per pre-split qubit tensor; amax_tag = the last tag used on them
+  uint64_t* amax = nullptr;
+  int64_t n_amax = 0;
+  uint32_t amax_tag = 0;
   // time-collapse descriptors, kept for the adjoint of the grid build
   qflex::DevBuf gq, gpieces, gmats, gpos;
   int64_t n_mats = 0;

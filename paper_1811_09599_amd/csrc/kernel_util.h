@@ -27,6 +27,22 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
+// ---- fp16 split operands: power-of-two scale from the largest magnitude (low 32 bits of the
+// slot absmax() fills).  The scaled maximum lies in [2^14, 2^15): hi parts stay below the
+// fp16 maximum (65504) and lo parts stay normal down to 2^-17 of it.
+__device__ inline float pow2f(int k) {  // 2^k for -126 <= k <= 127
+  return __uint_as_float((uint32_t)(127 + k) << 23);
+}
+__device__ inline int fp16_scale_exp(uint64_t slot) {
+  const uint32_t bits = (uint32_t)slot;
+  const int e = (int)((bits >> 23) & 0xff);  // biased exponent: max in [2^(e-127), 2^(e-126))
+  if (e == 0 || e == 0xff) return 0;  // zero or subnormal maximum, inf or NaN: no scaling
+  const int k = 14 - (e - 127);
+  return k < -100 ? -100 : (k > 100 ? 100 : k);
+}
+__device__ inline float fp16_scale(uint64_t slot) { return pow2f(fp16_scale_exp(slot)); }
+__device__ inline float fp16_unscale(uint64_t slot) { return pow2f(-fp16_scale_exp(slot)); }
+
 // ---- binary index tiles (see permute.hip)
 __device__ inline int lds_pad(int i) { return i + (i >> 5); }
 

@@ -66,25 +66,38 @@ void gemm(const Gemm& g, hipStream_t s);
 
 // ---------------------------------------------------------------- split-precision products
 // A complex product C = A B runs with both operands stored "K-major" ([rows][K]) in a compact
-// split layout: each complex value x = xr + i xi is split per part into hi = bf16(x) and
-// lo = bf16(x - hi), and every group of 4 consecutive k of a row is stored as 16 bf16
+// split layout: each real part x of a complex value is split into two 16-bit values,
+// hi = round(x) and lo = round(x - hi), and every group of 4 consecutive k of a row is stored
+// as 16 of them
 //   [rh(k0..k3), ih(k0..k3), rl(k0..k3), il(k0..k3)]            (32 bytes, 8 per complex)
-// The product accumulates hi*hi + hi*lo + lo*hi of every real part in FP32 on bf16 MFMA
-// (lo*lo is dropped): about 16 significant bits per operand instead of 24.
-// Permute (as permute()) into [rows][K] order, K the low kbits bits, and split.
+// The product accumulates hi*hi + hi*lo + lo*hi of every real part in FP32 on 16-bit MFMA
+// (lo*lo is dropped).  Two formats:
+//  - bf16: about 16 significant bits per operand (8 + 8) over FP32's whole range;
+//  - fp16: the operand is first multiplied by 2^k, chosen from its largest magnitude m so that
+//    m 2^k lies in [2^14, 2^15); about 22 bits (11 + 11) for every value within 2^-17 of m,
+//    fewer below (lo parts turn subnormal), and the product is multiplied back by 2^-(kA+kB).
+// Permute (as permute()) into [rows][K] order, K the low kbits bits, and split.  amax = NULL
+// selects bf16; otherwise fp16, with the scale taken from the slot absmax() filled.
 void split_permute(const float2* in, uint16_t* out, int64_t batch, const PermTile& t, int kbits,
-                   hipStream_t s);
+                   const uint64_t* amax, hipStream_t s);
+// Record max(|re|, |im|) over n complex values into *slot as (tag << 32) | float bits, by a
+// 64-bit atomic maximum: the slot needs no clearing as long as every call on it uses a larger
+// tag than the calls before (tag >= 1; in must be 16-byte aligned).
+void absmax(const float2* in, int64_t n, uint64_t* slot, uint32_t tag, hipStream_t s);
 
 struct GemmSplit {
-  const uint16_t* A = nullptr;  // [M][K] split, row stride 4K bf16
+  const uint16_t* A = nullptr;  // [M][K] split, row stride 4K 16-bit values
   const uint16_t* B = nullptr;  // [N][K] split
   float2* C = nullptr;          // [M][N] complex64
-  const int64_t* a_off = nullptr;  // per-batch offsets in complex elements (x4 bf16)
+  const int64_t* a_off = nullptr;  // per-batch offsets in complex elements (x4 16-bit values)
   const int64_t* b_off = nullptr;
   int64_t a_bs = 0, b_bs = 0, c_bs = 0;  // batch strides: complex elements
   int64_t a_add = 0, b_add = 0;          // complex elements
   int64_t M = 0, N = 0, K = 0;
   int batch = 1;
+  // fp16 operands: the absmax() slots their scales came from (both NULL: bf16 operands)
+  const uint64_t* a_amax = nullptr;
+  const uint64_t* b_amax = nullptr;
 };
 bool gemm_split_ok(int64_t M, int64_t N, int64_t K);  // shape fits the tiled kernel
 void gemm_split(const GemmSplit& g, hipStream_t s);

@@ -90,7 +90,7 @@ void permute(const float2* in, float2* out, int64_t batch, const PermTile& t, hi
 }
 
 // =============================================================================================
-// Split-precision complex products on bf16 MFMA (see kernels.h for the operand layouts).
+// Split layouts of the 16-bit products (see kernels.h for the layout and the two formats).
 // =============================================================================================
 __device__ inline uint16_t bf16_rne(float x) {
   uint32_t u = __float_as_uint(x);
@@ -99,12 +99,29 @@ __device__ inline uint16_t bf16_rne(float x) {
 }
 __device__ inline float bf16_to_f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
+// x = hi + lo with hi, lo in the 16-bit format (x already scaled for fp16)
+template <bool F16>
+__device__ inline void split16(float x, uint16_t& hi, uint16_t& lo) {
+  if constexpr (F16) {
+    const _Float16 h = (_Float16)x;  // round to nearest even
+    const _Float16 l = (_Float16)(x - (float)h);  // the difference is exact in FP32
+    hi = __builtin_bit_cast(uint16_t, h);
+    lo = __builtin_bit_cast(uint16_t, l);
+  } else {
+    hi = bf16_rne(x);
+    lo = bf16_rne(x - bf16_to_f(hi));
+  }
+}
+
 // One thread per group of 4 consecutive k of a row: the tile's write order starts with the
 // lowest output bits, so a group is 4 consecutive write indices and is stored as two 16-byte
-// vectors.
+// vectors.  For fp16, every value is first multiplied by the operand's power-of-two scale,
+// derived from the largest magnitude that absmax() recorded in *amax.
+template <bool F16>
 __global__ void __launch_bounds__(256) split_permute_kernel(const float2* __restrict__ in,
                                                             uint16_t* __restrict__ out,
-                                                            const PermTile t) {
+                                                            const PermTile t,
+                                                            const uint64_t* __restrict__ amax) {
   __shared__ float2 tile[(1 << kPermMaxTile) + (1 << kPermMaxTile) / 32];
   const int64_t n_el = int64_t(1) << t.nbits;
   in += (int64_t)blockIdx.y * n_el;
@@ -121,9 +138,11 @@ __global__ void __launch_bounds__(256) split_permute_kernel(const float2* __rest
     for (int k = 0; k < nk; ++k)
       tile[lds_pad(tid + (k << 8))] = in[in_lo + deposit<8, kPermMaxTile>(k, t.tile_in, tb)];
   }
+  float scale = 1.f;
+  if constexpr (F16) scale = fp16_scale(*amax);
   __syncthreads();
   // group q holds write indices 4q..4q+3 (write bits 0 and 1 are the two lowest k bits);
-  // q = tid + 256*k2, k2 < 1 for tiles of up to 1024 elements
+  // a tile of up to 1024 elements has at most 256 groups
   const int ngroups = tsize >> 2;
   if (tid < ngroups) {
     const int q = tid;
@@ -141,50 +160,75 @@ __global__ void __launch_bounds__(256) split_permute_kernel(const float2* __rest
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int i = ig | ((u & 1) << t.j2i[0]) | (((u >> 1) & 1) << t.j2i[1]);
-      const float2 v = tile[lds_pad(i)];
-      const uint16_t rh = bf16_rne(v.x), ih = bf16_rne(v.y);
-      h[u] = rh;
-      h[4 + u] = ih;
-      h[8 + u] = bf16_rne(v.x - bf16_to_f(rh));
-      h[12 + u] = bf16_rne(v.y - bf16_to_f(ih));
+      float2 v = tile[lds_pad(i)];
+      if constexpr (F16) v = make_float2(v.x * scale, v.y * scale);
+      split16<F16>(v.x, h[u], h[8 + u]);
+      split16<F16>(v.y, h[4 + u], h[12 + u]);
     }
-    uint4 lo, hi;
-    lo.x = h[0] | ((uint32_t)h[1] << 16);
-    lo.y = h[2] | ((uint32_t)h[3] << 16);
-    lo.z = h[4] | ((uint32_t)h[5] << 16);
-    lo.w = h[6] | ((uint32_t)h[7] << 16);
-    hi.x = h[8] | ((uint32_t)h[9] << 16);
-    hi.y = h[10] | ((uint32_t)h[11] << 16);
-    hi.z = h[12] | ((uint32_t)h[13] << 16);
-    hi.w = h[14] | ((uint32_t)h[15] << 16);
+    uint4 v0, v1;  // [rh, ih] and [rl, il] of the 4 k
+    v0.x = h[0] | ((uint32_t)h[1] << 16);
+    v0.y = h[2] | ((uint32_t)h[3] << 16);
+    v0.z = h[4] | ((uint32_t)h[5] << 16);
+    v0.w = h[6] | ((uint32_t)h[7] << 16);
+    v1.x = h[8] | ((uint32_t)h[9] << 16);
+    v1.y = h[10] | ((uint32_t)h[11] << 16);
+    v1.z = h[12] | ((uint32_t)h[13] << 16);
+    v1.w = h[14] | ((uint32_t)h[15] << 16);
     uint4* o = reinterpret_cast<uint4*>(out + 4 * e0);  // e0 is a multiple of 4
-    o[0] = lo;
-    o[1] = hi;
+    o[0] = v0;
+    o[1] = v1;
   }
 }
 
 void split_permute(const float2* in, uint16_t* out, int64_t batch, const PermTile& t, int kbits,
-                   hipStream_t s) {
+                   const uint64_t* amax, hipStream_t s) {
   if (batch < 1 || batch > 65535) throw std::runtime_error("split_permute: bad batch");
   // a thread's 4 consecutive write indices must be the 4 lowest k of one row
   if (kbits < 2 || t.tile_bits < 2 || t.tile_out[0] != 0 || t.tile_out[1] != 1)
     throw std::runtime_error("split_permute: K must be >= 4 and the tile must hold the 2 lowest bits");
   const int64_t tiles = int64_t(1) << t.nrest;
-  hipLaunchKernelGGL(split_permute_kernel, dim3((unsigned)tiles, (unsigned)batch), dim3(256), 0,
-                     s, in, out, t);
+  if (amax)
+    hipLaunchKernelGGL(split_permute_kernel<true>, dim3((unsigned)tiles, (unsigned)batch),
+                       dim3(256), 0, s, in, out, t, amax);
+  else
+    hipLaunchKernelGGL(split_permute_kernel<false>, dim3((unsigned)tiles, (unsigned)batch),
+                       dim3(256), 0, s, in, out, t, amax);
   check_launch("split_permute");
 }
 
-// Complex product on bf16 MFMA from the compact split layout.  WM x WN wavefronts per
-// workgroup (8 for the 256x128 complex tile: two per SIMD hide each other's barrier and LDS
-// latency, and the larger tile halves the bytes loaded per MFMA), each owning a 64x64 complex
-// block = 2x2 sub-tiles of v_mfma_f32_32x32x16_bf16 with separate real and imaginary
-// accumulators.  One instruction step covers 8 complex k: lanes 0-31 hold
-// k-group g, lanes 32-63 group g+1, each lane's 8 bf16 being [re(4 k), im(4 k)] of one part:
-//   Cr += Ah.Brh + Ah.Brl + Al.Brh,  Brh = [Br_h, -Bi_h]
-//   Ci += Ah.Bih + Ah.Bil + Al.Bih,  Bih = [Bi_h,  Br_h]
-// (Brh / Bih are built from one 16-byte LDS read by a sign flip / a half swap).  k-tiles of
-// 16 complex are staged in LDS (rows of 128 bytes padded to 144), double buffered; the next
+// Largest magnitude of the real and imaginary parts of n complex values, recorded as
+// (tag << 32 | float bits) by a 64-bit atomic maximum: non-negative floats order like their
+// bit patterns, and a larger tag replaces whatever an earlier call left in the slot.
+__global__ void __launch_bounds__(256) absmax_kernel(const float4* __restrict__ in, int64_t n4,
+                                                     const float2* __restrict__ tail,
+                                                     uint64_t* __restrict__ slot, uint64_t tag) {
+  float m = 0.f;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += stride) {
+    const float4 v = in[i];
+    m = fmaxf(m, fmaxf(fmaxf(fabsf(v.x), fabsf(v.y)), fmaxf(fabsf(v.z), fabsf(v.w))));
+  }
+  if (tail && blockIdx.x == 0 && threadIdx.x == 0) m = fmaxf(m, fmaxf(fabsf(tail->x), fabsf(tail->y)));
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+  if ((threadIdx.x & 63) == 0)
+    atomicMax(reinterpret_cast<unsigned long long*>(slot),
+              (unsigned long long)(tag | __float_as_uint(m)));
+}
+
+void absmax(const float2* in, int64_t n, uint64_t* slot, uint32_t tag, hipStream_t s) {
+  if (n < 1) throw std::runtime_error("absmax: empty input");
+  if (tag == 0) throw std::runtime_error("absmax: tag must be non-zero");
+  if (reinterpret_cast<uintptr_t>(in) % 16) throw std::runtime_error("absmax: misaligned input");
+  const int64_t n4 = n / 2;
+  const float2* tail = (n & 1) ? in + (n - 1) : nullptr;
+  const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((n4 + 255) / 256, 2048));
+  hipLaunchKernelGGL(absmax_kernel, dim3((unsigned)blocks), dim3(256), 0, s,
+                     reinterpret_cast<const float4*>(in), n4, tail, slot,
+                     (uint64_t)tag << 32);
+  check_launch("absmax");
+}
+
 struct PermBits {
   int8_t p[kPermMaxBits];
 };

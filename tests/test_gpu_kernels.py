@@ -136,39 +136,82 @@ SPLIT_SHAPES = [(128, 64, 16, 1), (256, 128, 64, 2), (512, 256, 256, 1), (128, 5
                 (1024, 1024, 512, 1), (2048, 64, 4096, 1)]
 
 
-@pytest.mark.parametrize("M,N,K,batch", SPLIT_SHAPES)
-@pytest.mark.parametrize("ta,tb", [(0, 0), (1, 1), (0, 1)])
-def test_split_bf16_gemm_error_bound(M, N, K, batch, ta, tb):
-    """bf16x3 (hi*hi + hi*lo + lo*hi per real part): each operand keeps ~16 significant bits,
-    so the product's relative L2 error is ~1e-5 on random data (measured bound: 3e-5)."""
+def _split_gemm(a, b, M, N, K, ta, tb, batch, prec):
     torch = _torch()
-    _say("split gemm", M, N, K, batch, ta, tb)
-    rng = np.random.default_rng(M + 3 * N + 7 * K + batch + 11 * ta + 13 * tb)
-    sa = (batch, K, M) if ta else (batch, M, K)
-    sb = (batch, N, K) if tb else (batch, K, N)
-    a = (rng.standard_normal(sa) + 1j * rng.standard_normal(sa)).astype(np.complex64)
-    b = (rng.standard_normal(sb) + 1j * rng.standard_normal(sb)).astype(np.complex64)
     A = torch.from_numpy(a).cuda()
     B = torch.from_numpy(b).cuda()
     Cm = torch.empty((batch, M, N), dtype=torch.complex64, device="cuda")
     L = F.lib()
     ws_bytes = L.qflex_gemm_split_workspace(M, N, K, batch)
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
-    assert L.qflex_gemm_split_c64(C.c_void_p(A.data_ptr()), C.c_void_p(B.data_ptr()),
-                                  C.c_void_p(Cm.data_ptr()), M, N, K, ta, tb, batch,
-                                  C.c_void_p(ws.data_ptr()), ws_bytes - 1, None) == F.E_INVALID
-    F.check(L.qflex_gemm_split_c64(C.c_void_p(A.data_ptr()), C.c_void_p(B.data_ptr()),
-                                   C.c_void_p(Cm.data_ptr()), M, N, K, ta, tb, batch,
-                                   C.c_void_p(ws.data_ptr()), ws_bytes, None))
+    args = (C.c_void_p(A.data_ptr()), C.c_void_p(B.data_ptr()), C.c_void_p(Cm.data_ptr()),
+            M, N, K, ta, tb, batch, F.PREC[prec], C.c_void_p(ws.data_ptr()))
+    assert L.qflex_gemm_split_c64(*args, ws_bytes - 1, None) == F.E_INVALID
+    F.check(L.qflex_gemm_split_c64(*args, ws_bytes, None))
     torch.cuda.synchronize()
-    got = Cm.cpu().numpy()
+    return Cm.cpu().numpy()
+
+
+def _ref(a, b, ta, tb):
     A64 = a.astype(np.complex128)
     B64 = b.astype(np.complex128)
     if ta:
         A64 = np.transpose(A64, (0, 2, 1))
     if tb:
         B64 = np.transpose(B64, (0, 2, 1))
-    want = A64 @ B64
+    return A64 @ B64
+
+
+# bf16x3 keeps ~16 significant bits per operand: relative L2 error ~1e-5 on random data
+# (measured bound 3e-5).  fp16x3 keeps ~22 bits per operand, so the FP32 accumulation
+# dominates, as in the complex64 product (bound 3e-6).
+SPLIT_BOUND = {"split_bf16": 3e-5, "split_fp16": 3e-6}
+
+
+@pytest.mark.parametrize("prec", ["split_bf16", "split_fp16"])
+@pytest.mark.parametrize("M,N,K,batch", SPLIT_SHAPES)
+@pytest.mark.parametrize("ta,tb", [(0, 0), (1, 1), (0, 1)])
+def test_split_gemm_error_bound(M, N, K, batch, ta, tb, prec):
+    """hi*hi + hi*lo + lo*hi per real part against the FP64 product of the same operands."""
+    _say("split gemm", prec, M, N, K, batch, ta, tb)
+    rng = np.random.default_rng(M + 3 * N + 7 * K + batch + 11 * ta + 13 * tb)
+    sa = (batch, K, M) if ta else (batch, M, K)
+    sb = (batch, N, K) if tb else (batch, K, N)
+    a = (rng.standard_normal(sa) + 1j * rng.standard_normal(sa)).astype(np.complex64)
+    b = (rng.standard_normal(sb) + 1j * rng.standard_normal(sb)).astype(np.complex64)
+    got = _split_gemm(a, b, M, N, K, ta, tb, batch, prec)
+    want = _ref(a, b, ta, tb)
     rel = np.linalg.norm(got - want) / np.linalg.norm(want)
     _say("  rel_l2", rel)
-    assert rel < 3e-5, rel
+    assert rel < SPLIT_BOUND[prec], rel
+
+
+@pytest.mark.parametrize("prec", ["split_bf16", "split_fp16"])
+def test_split_gemm_power_of_two_scale_invariance(prec):
+    """Both formats split a scaled copy exactly like the original (bf16 shares FP32's exponent
+    range; fp16 takes a power-of-two scale per operand), so scaling A by 2^-70 and B by 2^50
+    scales the product by exactly 2^-20, bit for bit, far outside fp16's own range."""
+    M, N, K, batch = 256, 128, 256, 2
+    rng = np.random.default_rng(77)
+    a = (rng.standard_normal((batch, M, K)) + 1j * rng.standard_normal((batch, M, K))).astype(np.complex64)
+    b = (rng.standard_normal((batch, K, N)) + 1j * rng.standard_normal((batch, K, N))).astype(np.complex64)
+    c1 = _split_gemm(a, b, M, N, K, 0, 0, batch, prec)
+    c2 = _split_gemm((a * np.float32(2.0 ** -70)).astype(np.complex64),
+                     (b * np.float32(2.0 ** 50)).astype(np.complex64), M, N, K, 0, 0, batch, prec)
+    assert np.array_equal(c2, (c1 * np.float32(2.0 ** -20)).astype(np.complex64))
+
+
+def test_split_fp16_rows_of_mixed_magnitude():
+    """Rows of A spread over 2^-16 .. 1 (inside the window where fp16 lo parts stay normal):
+    every output row keeps the fp16x3 accuracy relative to its own size."""
+    M, N, K = 256, 128, 512
+    rng = np.random.default_rng(5)
+    a = rng.standard_normal((1, M, K)) + 1j * rng.standard_normal((1, M, K))
+    a *= 2.0 ** -rng.integers(0, 17, size=(1, M, 1))
+    a = a.astype(np.complex64)
+    b = (rng.standard_normal((1, K, N)) + 1j * rng.standard_normal((1, K, N))).astype(np.complex64)
+    got = _split_gemm(a, b, M, N, K, 0, 0, 1, "split_fp16")
+    want = _ref(a, b, 0, 0)
+    row_err = np.linalg.norm(got - want, axis=2) / np.linalg.norm(want, axis=2)
+    _say("  worst row", row_err.max())
+    assert row_err.max() < 1e-5

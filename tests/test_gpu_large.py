@@ -30,7 +30,16 @@ def _say(*a):
 SPLIT_TOL_D32 = 1.5e-3
 
 
-@pytest.mark.parametrize("precision,tol", [("c64", 1e-5), ("split_bf16", SPLIT_TOL_D32)])
+# Split-fp16 keeps ~22 bits only for values within 2^-17 of each operand's largest magnitude
+# (fp16 has 5 exponent bits).  With identity couplings the network is a product state whose
+# tensors span far more than that (products of 49 single-qubit amplitudes), so this pin is
+# its worst case: measured 1.3e-3, bound 3e-3.  Random circuits spread their amplitudes
+# (Porter-Thomas) and stay at the complex64 level (see the next test).
+SPLIT_FP16_TOL_PRODUCT_STATE = 3e-3
+
+
+@pytest.mark.parametrize("precision,tol", [("c64", 1e-5), ("split_bf16", SPLIT_TOL_D32),
+                                           ("split_fp16", SPLIT_FP16_TOL_PRODUCT_STATE)])
 def test_d32_identity_coupled_slice_matches_closed_form(precision, tol):
     _need_gpu()
     _say("7x7 1+40+1 identity couplings, one slice,", precision)
@@ -59,19 +68,22 @@ def test_d32_identity_coupled_slice_matches_closed_form(precision, tol):
     g.close()
 
 
-def test_d32_rqc_split_bf16_agrees_with_c64_on_a_slice():
+def test_d32_rqc_split_agrees_with_c64_on_a_slice():
     _need_gpu()
     _say("7x7 1+40+1 RQC, split vs c64 on one slice")
     c = R.grid_rqc(7, 7, 40, 3000)
     bits = R.bitstrings(49, 1, 3500, OPEN7)
     res = {}
-    for p in ("c64", "split_bf16"):
+    for p in ("c64", "split_bf16", "split_fp16"):
         g = build_grid(c, open_qubits=OPEN7, precision=p)
         res[p] = g.contract_amplitudes(bits, slice_ids=[300]).cpu().numpy()
         g.close()
     e = metrics.amp_errors(res["split_bf16"], res["c64"], 49)
-    _say("  split vs c64", e)
+    _say("  split-bf16 vs c64", e)
     assert e["max"] < SPLIT_TOL_D32
+    e = metrics.amp_errors(res["split_fp16"], res["c64"], 49)
+    _say("  split-fp16 vs c64", e)
+    assert e["max"] < 4e-5
 
 
 def test_7x7_fidelity_subset_matches_oracle():

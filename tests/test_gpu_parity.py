@@ -208,37 +208,42 @@ def test_cfg2_7x7_depth32_sampled_slices_vs_oracle():
     _check(a, ref, 49)
 
 
-# ------------------------------------------------------------------- split-bf16 precision
-SPLIT_TOL = 2e-4  # stated bound for the split-bf16 path (bf16x3 products, FP32 accumulation)
+# ------------------------------------------------------------------- split precisions
+# Stated bounds: split-bf16 keeps ~16 of an operand's 24 bits (bf16x3 products, FP32
+# accumulation); split-fp16 keeps ~22 (inside its scale window), so its bound is 4x the
+# complex64 bound.
+SPLIT_TOL = {"split_bf16": 2e-4, "split_fp16": 4 * TOL}
 
 
-def test_split_bf16_quadrant_5x4_depth32_vs_state_vector():
+@pytest.mark.parametrize("prec", ["split_bf16", "split_fp16"])
+def test_split_quadrant_5x4_depth32_vs_state_vector(prec):
     _need_gpu()
-    _say("split bf16 5x4 1+32+1 quadrant")
+    _say(prec, "5x4 1+32+1 quadrant")
     c = R.grid_rqc(5, 4, 32, 5432)
     op = [19, 18, 15]
     bits = R.bitstrings(20, 6, 7, op)
-    g = build_grid(c, plan="quadrant", open_qubits=op, precision="split_bf16")
+    g = build_grid(c, plan="quadrant", open_qubits=op, precision=prec)
     g.set_profiling(True)
     a = g.contract_amplitudes(bits).cpu().numpy()
     prof = g.profile_read()
-    assert any(k.startswith("gemm_split_bf16") for k in prof), prof
-    e = _check(a, E1.amplitudes(c, bits, op), 20, SPLIT_TOL)
+    assert any(k.startswith("gemm_" + prec) for k in prof), prof
+    e = _check(a, E1.amplitudes(c, bits, op), 20, SPLIT_TOL[prec])
     _say("  split error", e)
     ref_c64 = build_grid(c, plan="quadrant", open_qubits=op).contract_amplitudes(bits)
     _say("  c64 error", metrics.amp_errors(ref_c64.cpu().numpy(), E1.amplitudes(c, bits, op), 20))
 
 
-def test_split_bf16_7x7_depth32_sampled_slices_vs_oracle():
+@pytest.mark.parametrize("prec", ["split_bf16", "split_fp16"])
+def test_split_7x7_depth32_sampled_slices_vs_oracle(prec):
     _need_gpu()
-    _say("split bf16 7x7 1+32+1 per-slice parity")
+    _say(prec, "7x7 1+32+1 per-slice parity")
     c = R.grid_rqc(7, 7, 32, 2001)
     op = R.grid_ids((7, 7), [(5, 0), (5, 1), (5, 2), (6, 0), (6, 1), (6, 2)])
     bits = R.bitstrings(49, 1, 2500, op)
-    g = build_grid(c, open_qubits=op, precision="split_bf16")
+    g = build_grid(c, open_qubits=op, precision=prec)
     ids = [37, 200]
     a = g.contract_amplitudes(bits, slice_ids=ids).cpu().numpy()
     ref = E2.amplitudes(c, bits, op, cuts=g.plan_cuts(), slice_ids=ids,
                         order=E2.quadrant_order(7, 7))
-    e = _check(a, ref, 49, SPLIT_TOL)
+    e = _check(a, ref, 49, SPLIT_TOL[prec])
     _say("  split error", e)

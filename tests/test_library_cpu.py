@@ -161,3 +161,22 @@ def test_gemm_variant_choice():
     assert L.qflex_gemm_variant(64, 64, 16) == 1
     assert L.qflex_gemm_variant(64, 8, 256) == 0
     assert L.qflex_gemm_variant(1 << 20, 256, 8) == 0
+
+
+def test_split_gemm_argument_checks_run_before_any_launch():
+    """Host-side validation of the kernel-level split product (no device memory is touched:
+    the pointers are never dereferenced when a check fails)."""
+    L = F.lib()
+    fake = C.c_void_p(1 << 20)  # 16-byte aligned, never dereferenced
+    ws = L.qflex_gemm_split_workspace(256, 128, 64, 1)
+    assert ws >= 2 * 4 * (256 * 64 + 128 * 64)
+
+    def call(M=256, N=128, K=64, prec=F.PREC["split_fp16"], ws_bytes=ws, A=fake):
+        return L.qflex_gemm_split_c64(A, fake, fake, M, N, K, 0, 0, 1, prec, fake, ws_bytes, None)
+
+    assert call(prec=F.PREC["c64"]) == F.E_INVALID
+    assert call(prec=7) == F.E_INVALID
+    assert call(ws_bytes=ws - 1) == F.E_INVALID
+    assert call(M=96) == F.E_INVALID      # not a power of two
+    assert call(K=8) == F.E_INVALID       # below the kernel's k-tile
+    assert call(A=C.c_void_p((1 << 20) + 8)) == F.E_INVALID  # misaligned operand
