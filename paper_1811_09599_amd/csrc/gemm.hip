@@ -36,17 +36,17 @@ __global__ void __launch_bounds__(256) gemm_mfma_kernel(const Gemm g) {
   float2* __restrict__ C = g.C + b * g.c_bs;
   const int64_t m0 = tm * BM, n0 = tn * BN;
 
-  float4 ra[AV], rb[BV];
+  f32x4 ra[AV], rb[BV];
   auto gload = [&](int64_t k0) {
 #pragma unroll
     for (int v = 0; v < AV; ++v) {
       const int e = tid + v * 256;
       if (!TA) {
         const int row = e >> 3, kp = e & 7;
-        ra[v] = *reinterpret_cast<const float4*>(A + (m0 + row) * g.lda + k0 + 2 * kp);
+        ra[v] = *reinterpret_cast<const f32x4*>(A + (m0 + row) * g.lda + k0 + 2 * kp);
       } else {
         const int kr = e / (BM / 2), mp = e % (BM / 2);
-        ra[v] = *reinterpret_cast<const float4*>(A + (k0 + kr) * g.lda + m0 + 2 * mp);
+        ra[v] = *reinterpret_cast<const f32x4*>(A + (k0 + kr) * g.lda + m0 + 2 * mp);
       }
     }
 #pragma unroll
@@ -54,10 +54,10 @@ __global__ void __launch_bounds__(256) gemm_mfma_kernel(const Gemm g) {
       const int e = tid + v * 256;
       if (!TB) {
         const int kr = e / (BN / 2), np = e % (BN / 2);
-        rb[v] = *reinterpret_cast<const float4*>(B + (k0 + kr) * g.ldb + n0 + 2 * np);
+        rb[v] = *reinterpret_cast<const f32x4*>(B + (k0 + kr) * g.ldb + n0 + 2 * np);
       } else {
         const int row = e >> 3, kp = e & 7;
-        rb[v] = *reinterpret_cast<const float4*>(B + (n0 + row) * g.ldb + k0 + 2 * kp);
+        rb[v] = *reinterpret_cast<const f32x4*>(B + (n0 + row) * g.ldb + k0 + 2 * kp);
       }
     }
   };
@@ -67,7 +67,7 @@ __global__ void __launch_bounds__(256) gemm_mfma_kernel(const Gemm g) {
       const int e = tid + v * 256;
       if (!TA) {
         const int row = e >> 3, kp = e & 7;
-        *reinterpret_cast<float4*>(&As[buf][row * LDK + 2 * kp]) = ra[v];
+        *reinterpret_cast<f32x4*>(&As[buf][row * LDK + 2 * kp]) = ra[v];
       } else {
         const int kr = e / (BM / 2), mp = e % (BM / 2);
         As[buf][(2 * mp) * LDK + kr] = make_float2(ra[v].x, ra[v].y);
@@ -83,7 +83,7 @@ __global__ void __launch_bounds__(256) gemm_mfma_kernel(const Gemm g) {
         Bs[buf][(2 * np + 1) * LDK + kr] = make_float2(rb[v].z, rb[v].w);
       } else {
         const int row = e >> 3, kp = e & 7;
-        *reinterpret_cast<float4*>(&Bs[buf][row * LDK + 2 * kp]) = rb[v];
+        *reinterpret_cast<f32x4*>(&Bs[buf][row * LDK + 2 * kp]) = rb[v];
       }
     }
   };
@@ -107,14 +107,14 @@ __global__ void __launch_bounds__(256) gemm_mfma_kernel(const Gemm g) {
     const float2* bs = Bs[buf];
 #pragma unroll
     for (int s2 = 0; s2 < 4; ++s2) {
-      float4 af[TMI], bf[TNI];
+      f32x4 af[TMI], bf[TNI];
 #pragma unroll
       for (int i = 0; i < TMI; ++i)
-        af[i] = *reinterpret_cast<const float4*>(
+        af[i] = *reinterpret_cast<const f32x4*>(
             &as[(wm * (BM / 2) + i * 32 + r) * LDK + h * 8 + 2 * s2]);
 #pragma unroll
       for (int j = 0; j < TNI; ++j)
-        bf[j] = *reinterpret_cast<const float4*>(
+        bf[j] = *reinterpret_cast<const f32x4*>(
             &bs[(wn * (BN / 2) + j * 32 + r) * LDK + h * 8 + 2 * s2]);
       // the two terms of each part are issued in separate passes over the sub-tiles, so that
       // consecutive MFMAs never feed the same accumulator

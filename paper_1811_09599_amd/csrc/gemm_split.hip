@@ -22,10 +22,8 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 
 template <typename V>
-__device__ inline V as_vec(uint4 v) {
-  V r;
-  __builtin_memcpy(&r, &v, 16);
-  return r;
+__device__ inline V as_vec(u32x4 v) {
+  return __builtin_bit_cast(V, v);
 }
 __device__ inline floatx16 mfma16(bf16x8 a, bf16x8 b, floatx16 c) {
   return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
@@ -43,7 +41,7 @@ __global__ void __launch_bounds__(64 * WM * WN) gemm_split_kernel(const GemmSpli
   constexpr int LDR = ROW + 8;           // padded row (144 bytes)
   constexpr int WTM = BM / WM, WTN = BN / WN;  // wavefront tile (complex)
   constexpr int TMI = WTM / 32, TNI = WTN / 32;
-  constexpr int AV = BM * ROW / 8 / NT, BV = BN * ROW / 8 / NT;  // uint4 loads per thread
+  constexpr int AV = BM * ROW / 8 / NT, BV = BN * ROW / 8 / NT;  // 16-byte loads per thread
   __shared__ __attribute__((aligned(16))) uint16_t As[2][BM * LDR];
   __shared__ __attribute__((aligned(16))) uint16_t Bs[2][BN * LDR];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -58,29 +56,29 @@ __global__ void __launch_bounds__(64 * WM * WN) gemm_split_kernel(const GemmSpli
   const int64_t lda = 4 * g.K, ldb = 4 * g.K;
   const int64_t m0 = tm * BM, n0 = tn * BN;
 
-  uint4 ra[AV], rb[BV];
+  u32x4 ra[AV], rb[BV];
   auto gload = [&](int64_t k0) {  // k0 in 16-bit units along the row
 #pragma unroll
     for (int v = 0; v < AV; ++v) {
       const int e = tid + v * NT, row = e >> 3, ch = e & 7;
-      ra[v] = *reinterpret_cast<const uint4*>(A + (m0 + row) * lda + k0 + 8 * ch);
+      ra[v] = *reinterpret_cast<const u32x4*>(A + (m0 + row) * lda + k0 + 8 * ch);
     }
 #pragma unroll
     for (int v = 0; v < BV; ++v) {
       const int e = tid + v * NT, row = e >> 3, ch = e & 7;
-      rb[v] = *reinterpret_cast<const uint4*>(B + (n0 + row) * ldb + k0 + 8 * ch);
+      rb[v] = *reinterpret_cast<const u32x4*>(B + (n0 + row) * ldb + k0 + 8 * ch);
     }
   };
   auto sstore = [&](int buf) {
 #pragma unroll
     for (int v = 0; v < AV; ++v) {
       const int e = tid + v * NT, row = e >> 3, ch = e & 7;
-      *reinterpret_cast<uint4*>(&As[buf][row * LDR + 8 * ch]) = ra[v];
+      *reinterpret_cast<u32x4*>(&As[buf][row * LDR + 8 * ch]) = ra[v];
     }
 #pragma unroll
     for (int v = 0; v < BV; ++v) {
       const int e = tid + v * NT, row = e >> 3, ch = e & 7;
-      *reinterpret_cast<uint4*>(&Bs[buf][row * LDR + 8 * ch]) = rb[v];
+      *reinterpret_cast<u32x4*>(&Bs[buf][row * LDR + 8 * ch]) = rb[v];
     }
   };
   floatx16 cr[TMI][TNI], ci[TMI][TNI];
@@ -106,18 +104,19 @@ __global__ void __launch_bounds__(64 * WM * WN) gemm_split_kernel(const GemmSpli
 #pragma unroll
       for (int i = 0; i < TMI; ++i) {
         const uint16_t* p = &as[(wm * WTM + i * 32 + r) * LDR + col];
-        ah[i] = as_vec<V>(*reinterpret_cast<const uint4*>(p));
-        al[i] = as_vec<V>(*reinterpret_cast<const uint4*>(p + 8));
+        ah[i] = as_vec<V>(*reinterpret_cast<const u32x4*>(p));
+        al[i] = as_vec<V>(*reinterpret_cast<const u32x4*>(p + 8));
       }
 #pragma unroll
       for (int j = 0; j < TNI; ++j) {
         const uint16_t* p = &bs[(wn * WTN + j * 32 + r) * LDR + col];
-        const uint4 vh = *reinterpret_cast<const uint4*>(p);
-        const uint4 vl = *reinterpret_cast<const uint4*>(p + 8);
-        brh[j] = as_vec<V>(make_uint4(vh.x, vh.y, vh.z ^ 0x80008000u, vh.w ^ 0x80008000u));
-        brl[j] = as_vec<V>(make_uint4(vl.x, vl.y, vl.z ^ 0x80008000u, vl.w ^ 0x80008000u));
-        bih[j] = as_vec<V>(make_uint4(vh.z, vh.w, vh.x, vh.y));
-        bil[j] = as_vec<V>(make_uint4(vl.z, vl.w, vl.x, vl.y));
+        const u32x4 vh = *reinterpret_cast<const u32x4*>(p);
+        const u32x4 vl = *reinterpret_cast<const u32x4*>(p + 8);
+        const u32x4 sgn = {0u, 0u, 0x80008000u, 0x80008000u};
+        brh[j] = as_vec<V>(vh ^ sgn);
+        brl[j] = as_vec<V>(vl ^ sgn);
+        bih[j] = as_vec<V>(vh.zwxy);
+        bil[j] = as_vec<V>(vl.zwxy);
       }
       // term by term over all sub-tiles, so that consecutive MFMAs never feed the same
       // accumulator (each chain has 2*TMI*TNI-1 independent instructions between its links)

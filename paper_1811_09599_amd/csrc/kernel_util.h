@@ -15,6 +15,11 @@ inline void check_launch(const char* what) {
 }
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
+// Register staging uses native vector types: HIP's float4 / uint4 are structs whose copies
+// lower to memcpy calls, which keep staging arrays in memory (scratch or LDS) instead of
+// registers and expose every global load's latency.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 __device__ inline double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
