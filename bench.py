@@ -110,6 +110,8 @@ def main():
                     choices=["all", "c64", "split_bf16", "split_fp16"])
     ap.add_argument("--cpu-slices", type=int, default=3, help="oracle sample size (slices)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="first copy 1 GiB device to device (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -122,6 +124,15 @@ def main():
     from paper_1811_09599_amd import plan_describe
 
     torch.cuda.set_device(0)
+    if args.copy_probe:
+        # a plain copy of known size: reads 1 GiB and writes 1 GiB; under rocprofv3 --pmc its
+        # FETCH_SIZE / WRITE_SIZE give the scale of those counters on this device
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     rows = cols = 7
     circ = R.grid_rqc(rows, cols, 32, 2000)
     open_q = R.grid_ids((rows, cols), [(5, 0), (5, 1), (5, 2), (6, 0), (6, 1), (6, 2)])

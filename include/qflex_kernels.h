@@ -30,9 +30,16 @@ qflex_status qflex_permute_c64(const void* in, void* out, int32_t nbits, const i
 /* Batched complex64 matrix product C[b] = op(A[b]) op(B[b]) with FP32 accumulation (device).
  * A[b] is stored [M][K] (ta = 0) or [K][M] (ta = 1), B[b] is [K][N] (tb = 0) or [N][K]
  * (tb = 1), C[b] is [M][N]; all row-major and densely packed, batch b at offset b*size.
- * M, N, K >= 1, 1 <= batch <= 65535.  C must not overlap A or B. */
+ * M, N, K >= 1, 1 <= batch <= 65535.  C must not overlap A or B.
+ * workspace (optional, device, NULL allowed): when it holds at least
+ * qflex_gemm_c64_workspace(M, N, K, batch) bytes and that is non-zero, a product with few
+ * output tiles and a long K is split along K; the partial products land in the workspace and
+ * are summed into C in a fixed order (same result on every run).  Otherwise, or with
+ * workspace = NULL, the product runs unsplit.  The call allocates nothing itself. */
 qflex_status qflex_gemm_c64(const void* A, const void* B, void* C, int64_t M, int64_t N,
-                            int64_t K, int32_t ta, int32_t tb, int64_t batch, void* stream);
+                            int64_t K, int32_t ta, int32_t tb, int64_t batch, void* workspace,
+                            int64_t workspace_bytes, void* stream);
+int64_t qflex_gemm_c64_workspace(int64_t M, int64_t N, int64_t K, int64_t batch);
 
 /* The same product in split precision: each real part x of a complex64 operand is split into
  * two 16-bit parts, hi = round(x) and lo = round(x - hi); the three products hi*hi + hi*lo +

@@ -46,6 +46,7 @@ EXPORTS = ("qflex_build_grid", "qflex_num_slices", "qflex_plan_cuts", "qflex_pla
            "qflex_set_profiling",
            "qflex_profile_read", "qflex_permute_c64", "qflex_gemm_split_c64",
            "qflex_gemm_c64", "qflex_select_slices", "qflex_gemm_split_workspace",
+           "qflex_gemm_c64_workspace",
            "qflex_gemm_variant", "qflex_grid_free",
            "qflex_last_error")
 
@@ -87,7 +88,9 @@ def lib():
     L.qflex_profile_read.argtypes = [P, C.POINTER(KernelStat), C.c_int32, C.POINTER(C.c_int32)]
     L.qflex_permute_c64.argtypes = [P, P, C.c_int32, C.POINTER(C.c_int32), C.c_int64, P]
     L.qflex_gemm_c64.argtypes = [P, P, P, C.c_int64, C.c_int64, C.c_int64, C.c_int32, C.c_int32,
-                                 C.c_int64, P]
+                                 C.c_int64, P, C.c_int64, P]
+    L.qflex_gemm_c64_workspace.argtypes = [C.c_int64] * 4
+    L.qflex_gemm_c64_workspace.restype = C.c_int64
     L.qflex_gemm_variant.argtypes = [C.c_int64, C.c_int64, C.c_int64]
     L.qflex_gemm_variant.restype = C.c_int32
     L.qflex_select_slices.argtypes = [C.c_int64, C.c_double, C.c_uint64, C.POINTER(C.c_int64),

@@ -39,7 +39,7 @@ void release(qflex_grid* g) {
   if (g->amax) (void)hipFree(g->amax);
   g->split_scratch.release();
   for (qflex::DevBuf* b : {&g->gq, &g->gpieces, &g->gmats, &g->gpos, &g->grad_arena, &g->tbar,
-                           &g->pbar, &g->gbar, &g->amps_dev, &g->xeb})
+                           &g->pbar, &g->gbar, &g->amps_dev, &g->xeb, &g->splitk_ws})
     b->release();
   g->arena.release();
   g->amps64.release();
@@ -211,29 +211,46 @@ qflex_status qflex_permute_c64(const void* in, void* out, int32_t nbits, const i
   });
 }
 
+static qflex::dev::Gemm dense_gemm(int64_t M, int64_t N, int64_t K, int32_t ta, int32_t tb,
+                                   int64_t batch) {
+  qflex::dev::Gemm g;
+  g.M = M;
+  g.N = N;
+  g.K = K;
+  g.ta = ta;
+  g.tb = tb;
+  g.lda = ta ? M : K;
+  g.ldb = tb ? K : N;
+  g.ldc = N;
+  g.a_bs = M * K;
+  g.b_bs = K * N;
+  g.c_bs = M * N;
+  g.batch = (int)batch;
+  return g;
+}
+
+int64_t qflex_gemm_c64_workspace(int64_t M, int64_t N, int64_t K, int64_t batch) {
+  if (M < 1 || N < 1 || K < 1 || batch < 1 || batch > 65535) return 0;
+  return (int64_t)sizeof(float) * 2 * qflex::dev::gemm_splitk_elems(dense_gemm(M, N, K, 0, 0, batch));
+}
+
 qflex_status qflex_gemm_c64(const void* A, const void* B, void* C, int64_t M, int64_t N,
-                            int64_t K, int32_t ta, int32_t tb, int64_t batch, void* stream) {
+                            int64_t K, int32_t ta, int32_t tb, int64_t batch, void* workspace,
+                            int64_t workspace_bytes, void* stream) {
   return guarded([&] {
     if (!A || !B || !C) qflex::fail(QFLEX_E_INVALID, "NULL argument");
+    if (workspace_bytes < 0) qflex::fail(QFLEX_E_INVALID, "negative workspace size");
     if (M < 1 || N < 1 || K < 1) qflex::fail(QFLEX_E_INVALID, "M, N, K must be >= 1");
     if (batch < 1 || batch > 65535) qflex::fail(QFLEX_E_INVALID, "batch must be in [1, 65535]");
     if ((ta != 0 && ta != 1) || (tb != 0 && tb != 1)) qflex::fail(QFLEX_E_INVALID, "ta/tb must be 0 or 1");
-    qflex::dev::Gemm g;
+    qflex::dev::Gemm g = dense_gemm(M, N, K, ta, tb, batch);
     g.A = static_cast<const float2*>(A);
     g.B = static_cast<const float2*>(B);
     g.C = static_cast<float2*>(C);
-    g.M = M;
-    g.N = N;
-    g.K = K;
-    g.ta = ta;
-    g.tb = tb;
-    g.lda = ta ? M : K;
-    g.ldb = tb ? K : N;
-    g.ldc = N;
-    g.a_bs = M * K;
-    g.b_bs = K * N;
-    g.c_bs = M * N;
-    g.batch = (int)batch;
+    if (workspace) {
+      g.ws = static_cast<float2*>(workspace);
+      g.ws_elems = workspace_bytes / (int64_t)sizeof(float2);
+    }
     if (qflex::dev::gemm_variant(g) > 0 &&
         ((reinterpret_cast<uintptr_t>(A) | reinterpret_cast<uintptr_t>(B)) & 15))
       qflex::fail(QFLEX_E_INVALID, "A and B must be 16-byte aligned");

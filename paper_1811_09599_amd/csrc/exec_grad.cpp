@@ -141,6 +141,27 @@ void contract_grad(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets
     B = std::min<int64_t>(std::min<int64_t>(B, nbs), 1024);
     g->grad_arena.reserve(sizeof(float2) * (size_t)(top * B));
     float2* ar = static_cast<float2*>(g->grad_arena.p);
+    // split-K workspace for the products of this circuit (forward, Xbar and Ybar shapes) at
+    // the batch sizes it runs: full batches and the last, partial one
+    int64_t ws_need = 0;
+    for (int64_t nbv : {B, nbs % B}) {
+      if (nbv <= 0) continue;
+      for (const Step& stp : P.steps) {
+        const int64_t M = int64_t(1) << stp.mb, K = int64_t(1) << stp.kb,
+                      N = int64_t(1) << stp.nb;
+        const int64_t shapes[3][3] = {{M, N, K}, {M, K, N}, {K, N, M}};  // (rows, cols, depth)
+        for (const auto& sh : shapes) {
+          dev::Gemm q;
+          q.M = sh[0];
+          q.N = sh[1];
+          q.K = sh[2];
+          q.batch = (int)nbv;
+          ws_need = std::max(ws_need, dev::gemm_splitk_elems(q));
+        }
+      }
+    }
+    if (ws_need) g->splitk_ws.reserve(sizeof(float2) * (size_t)ws_need);
+    float2* splitk_ws = ws_need ? static_cast<float2*>(g->splitk_ws.p) : nullptr;
     // permutations routing each product cotangent back to its operand's storage order
     std::vector<dev::PermTile> rx(P.steps.size()), ry(P.steps.size());
     std::vector<PermDesc> dx(P.steps.size()), dy(P.steps.size());
@@ -231,6 +252,8 @@ void contract_grad(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets
           gm.ldb = stp.tb ? gm.K : gm.N;
           gm.ldc = gm.N;
           gm.batch = nb;
+          gm.ws = splitk_ws;
+          gm.ws_elems = ws_need;
           dev::gemm(gm, s);
           st.flops += stp.flops() * nb;
           ++st.n_gemm;
@@ -277,6 +300,8 @@ void contract_grad(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets
           g1.c_bs = M * K;
           g1.ldc = K;
           g1.batch = nb;
+          g1.ws = splitk_ws;
+          g1.ws_elems = ws_need;
           dev::gemm(g1, s);
           dev::Gemm g2;  // Ybar = X'^T Zbar
           g2.A = x.base;
@@ -295,6 +320,8 @@ void contract_grad(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets
           g2.c_bs = K * N;
           g2.ldc = N;
           g2.batch = nb;
+          g2.ws = splitk_ws;
+          g2.ws_elems = ws_need;
           dev::gemm(g2, s);
           st.flops += 2.0 * stp.flops() * nb;
           st.n_gemm += 2;

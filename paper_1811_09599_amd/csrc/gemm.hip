@@ -30,10 +30,13 @@ __global__ void __launch_bounds__(256) gemm_mfma_kernel(const Gemm g) {
   const int h = lane >> 5, r = lane & 31;
   const int64_t tiles_n = g.N / BN;
   const int64_t tm = (int64_t)blockIdx.x / tiles_n, tn = (int64_t)blockIdx.x % tiles_n;
-  const int b = blockIdx.y;
-  const float2* __restrict__ A = g.A + g.a_add + (g.a_off ? g.a_off[b] : b * g.a_bs);
-  const float2* __restrict__ B = g.B + g.b_add + (g.b_off ? g.b_off[b] : b * g.b_bs);
-  float2* __restrict__ C = g.C + b * g.c_bs;
+  const int b = blockIdx.y, z = blockIdx.z;
+  const float2* __restrict__ A = g.A + g.a_add + (g.a_off ? g.a_off[b] : b * g.a_bs) + z * g.a_ks;
+  const float2* __restrict__ B = g.B + g.b_add + (g.b_off ? g.b_off[b] : b * g.b_bs) + z * g.b_ks;
+  // split K: chunk z's partial product goes to the workspace, densely packed
+  float2* __restrict__ C = g.split > 1 ? g.ws + ((int64_t)z * g.batch + b) * g.M * g.N
+                                       : g.C + b * g.c_bs;
+  const int64_t ldc = g.split > 1 ? g.N : g.ldc;
   const int64_t m0 = tm * BM, n0 = tn * BN;
 
   f32x4 ra[AV], rb[BV];
@@ -153,7 +156,7 @@ __global__ void __launch_bounds__(256) gemm_mfma_kernel(const Gemm g) {
       for (int v = 0; v < 16; ++v) {
         const int row = wm * (BM / 2) + i * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
         const int col = wn * (BN / 2) + j * 32 + r;
-        C[(m0 + row) * g.ldc + n0 + col] = make_float2(cr[i][j][v], ci[i][j][v]);
+        C[(m0 + row) * ldc + n0 + col] = make_float2(cr[i][j][v], ci[i][j][v]);
       }
 }
 
@@ -168,10 +171,11 @@ __global__ void __launch_bounds__(256) gemm_simt_kernel(const Gemm g) {
   const int tid = threadIdx.x;
   const int64_t tiles_n = (g.N + BN - 1) / BN;
   const int64_t m0 = (int64_t)(blockIdx.x / tiles_n) * BM, n0 = (int64_t)(blockIdx.x % tiles_n) * BN;
-  const int b = blockIdx.y;
-  const float2* A = g.A + g.a_add + (g.a_off ? g.a_off[b] : b * g.a_bs);
-  const float2* B = g.B + g.b_add + (g.b_off ? g.b_off[b] : b * g.b_bs);
-  float2* C = g.C + b * g.c_bs;
+  const int b = blockIdx.y, z = blockIdx.z;
+  const float2* A = g.A + g.a_add + (g.a_off ? g.a_off[b] : b * g.a_bs) + z * g.a_ks;
+  const float2* B = g.B + g.b_add + (g.b_off ? g.b_off[b] : b * g.b_bs) + z * g.b_ks;
+  float2* C = g.split > 1 ? g.ws + ((int64_t)z * g.batch + b) * g.M * g.N : g.C + b * g.c_bs;
+  const int64_t ldc = g.split > 1 ? g.N : g.ldc;
   const int tm = tid / BN, tn = tid % BN;
   float accr = 0.f, acci = 0.f;
   for (int64_t k0 = 0; k0 < g.K; k0 += BK) {
@@ -205,7 +209,7 @@ __global__ void __launch_bounds__(256) gemm_simt_kernel(const Gemm g) {
     __syncthreads();
   }
   const int64_t m = m0 + tm, n = n0 + tn;
-  if (m < g.M && n < g.N) C[m * g.ldc + n] = make_float2(accr, acci);
+  if (m < g.M && n < g.N) C[m * ldc + n] = make_float2(accr, acci);
 }
 
 int gemm_variant(const Gemm& g) {
@@ -223,20 +227,66 @@ const char* gemm_name(const Gemm& g) {
   return names[gemm_variant(g)][(g.ta ? 2 : 0) + (g.tb ? 1 : 0)];
 }
 
+// Output tiles of the kernel gemm() picks (one workgroup each, per batch element).
+static int64_t gemm_tiles(const Gemm& g) {
+  switch (gemm_variant(g)) {
+    case 2: return (g.M / 128) * (g.N / 128);
+    case 1: return (g.M / 64) * (g.N / 64);
+    default: {
+      const int bn = g.N >= 16 && g.M >= 16 ? 16 : g.N >= 8 ? 8 : g.N >= 4 ? 4 : g.N >= 2 ? 2 : 1;
+      const int bm = 256 / bn;
+      return ((g.M + bm - 1) / bm) * ((g.N + bn - 1) / bn);
+    }
+  }
+}
+
+// Split K when fewer than ~2048 workgroups would run and every chunk keeps >= 256 k values
+// (chunks are a power of two dividing K, so every K tile of 16 stays whole).
+int gemm_splitk(const Gemm& g) {
+  constexpr int64_t kTarget = 2048, kMinChunk = 256, kMaxSplit = 64;
+  const int64_t wgs = gemm_tiles(g) * g.batch;
+  if (wgs >= kTarget / 2 || g.K < 2 * kMinChunk || (g.K & (g.K - 1))) return 1;
+  int split = 1;
+  while (split < kMaxSplit && wgs * split < kTarget && g.K / (2 * split) >= kMinChunk) split *= 2;
+  return split;
+}
+
+int64_t gemm_splitk_elems(const Gemm& g) {
+  const int split = gemm_splitk(g);
+  return split > 1 ? (int64_t)split * g.batch * g.M * g.N : 0;
+}
+
+// C[b] = sum over chunks z of ws[z][b] (in chunk order), written with C's row stride
+__global__ void splitk_reduce_kernel(const float2* __restrict__ ws, int split, int batch,
+                                     int64_t M, int64_t N, float2* __restrict__ C, int64_t ldc,
+                                     int64_t c_bs) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t mn = M * N;
+  if (e >= mn) return;
+  const int b = blockIdx.y;
+  float re = 0.f, im = 0.f;
+  for (int z = 0; z < split; ++z) {
+    const float2 v = ws[((int64_t)z * batch + b) * mn + e];
+    re += v.x;
+    im += v.y;
+  }
+  C[b * c_bs + (e / N) * ldc + e % N] = make_float2(re, im);
+}
+
 template <bool TA, bool TB>
 static void gemm_t(const Gemm& g, hipStream_t s) {
-  if (g.batch < 1 || g.batch > 65535) throw std::runtime_error("gemm: bad batch");
   const int v = gemm_variant(g);
+  const unsigned z = (unsigned)g.split;
   if (v == 2) {
-    dim3 grid((unsigned)((g.M / 128) * (g.N / 128)), (unsigned)g.batch);
+    dim3 grid((unsigned)((g.M / 128) * (g.N / 128)), (unsigned)g.batch, z);
     hipLaunchKernelGGL((gemm_mfma_kernel<TA, TB, 128, 128>), grid, dim3(256), 0, s, g);
   } else if (v == 1) {
-    dim3 grid((unsigned)((g.M / 64) * (g.N / 64)), (unsigned)g.batch);
+    dim3 grid((unsigned)((g.M / 64) * (g.N / 64)), (unsigned)g.batch, z);
     hipLaunchKernelGGL((gemm_mfma_kernel<TA, TB, 64, 64>), grid, dim3(256), 0, s, g);
   } else {
     auto launch = [&](auto kern, int bm, int bn) {
       const int64_t tiles = ((g.M + bm - 1) / bm) * ((g.N + bn - 1) / bn);
-      hipLaunchKernelGGL(kern, dim3((unsigned)tiles, (unsigned)g.batch), dim3(256), 0, s, g);
+      hipLaunchKernelGGL(kern, dim3((unsigned)tiles, (unsigned)g.batch, z), dim3(256), 0, s, g);
     };
     if (g.N >= 16 && g.M >= 16) launch(gemm_simt_kernel<16, 16, TA, TB>, 16, 16);
     else if (g.N >= 8) launch(gemm_simt_kernel<32, 8, TA, TB>, 32, 8);
@@ -247,13 +297,33 @@ static void gemm_t(const Gemm& g, hipStream_t s) {
   check_launch("gemm");
 }
 
-void gemm(const Gemm& g, hipStream_t s) {
+void gemm(const Gemm& g0, hipStream_t s) {
+  if (g0.batch < 1 || g0.batch > 65535) throw std::runtime_error("gemm: bad batch");
+  Gemm g = g0;
+  g.split = 1;
+  g.a_ks = g.b_ks = 0;
+  if (g0.ws) {
+    const int split = gemm_splitk(g0);
+    if (split > 1 && (int64_t)split * g0.batch * g0.M * g0.N <= g0.ws_elems) {
+      const int64_t chunk = g0.K / split;
+      g.split = split;
+      g.K = chunk;
+      g.a_ks = g0.ta ? chunk * g0.lda : chunk;
+      g.b_ks = g0.tb ? chunk : chunk * g0.ldb;
+    }
+  }
   if (g.ta) {
     if (g.tb) gemm_t<true, true>(g, s);
     else gemm_t<true, false>(g, s);
   } else {
     if (g.tb) gemm_t<false, true>(g, s);
     else gemm_t<false, false>(g, s);
+  }
+  if (g.split > 1) {
+    dim3 grid((unsigned)((g.M * g.N + 255) / 256), (unsigned)g.batch);
+    hipLaunchKernelGGL(splitk_reduce_kernel, grid, dim3(256), 0, s, g.ws, g.split, g.batch, g.M,
+                       g.N, g0.C, g0.ldc, g0.c_bs);
+    check_launch("splitk_reduce");
   }
 }
 }  // namespace dev

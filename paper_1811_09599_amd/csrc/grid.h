@@ -94,6 +94,7 @@ struct qflex_grid {
   int max_pieces = 0;                    // longest qubit time line
   // gradient buffers
   qflex::DevBuf grad_arena, tbar, pbar, gbar, amps_dev, xeb;
+  qflex::DevBuf splitk_ws;               // partial products of split-K complex64 products
   qflex::DevBuf split_scratch;           // split operands of intermediates
   qflex::DevBuf arena;                   // intermediates
   qflex::DevBuf amps64;                  // FP64 amplitude accumulator

@@ -58,10 +58,22 @@ struct Gemm {
   int ta = 0, tb = 0;
   int batch = 1;
   int64_t a_add = 0, b_add = 0;  // extra element offset added to every batch element
+  // Split-K workspace (optional): when the product has too few output tiles to fill the GPU
+  // and a long K, gemm() splits K into chunks whose partial products go to ws
+  // ([chunks][batch][M][N]) and are then summed into C in a fixed order.  ws = NULL or too
+  // small: no split.
+  float2* ws = nullptr;
+  int64_t ws_elems = 0;
+  // set by gemm() for the kernels: number of K chunks and the operand offset of one chunk
+  int split = 1;
+  int64_t a_ks = 0, b_ks = 0;
 };
 // which kernel gemm() would pick: 0 = SIMT, 1 = MFMA 64x64 tile, 2 = MFMA 128x128 tile
 int gemm_variant(const Gemm& g);
 const char* gemm_name(const Gemm& g);  // kernel name used by the profiler
+// K chunks gemm() would use with an unlimited workspace, and the workspace that needs
+int gemm_splitk(const Gemm& g);
+int64_t gemm_splitk_elems(const Gemm& g);
 void gemm(const Gemm& g, hipStream_t s);
 
 // ---------------------------------------------------------------- split-precision products

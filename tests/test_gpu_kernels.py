@@ -91,13 +91,20 @@ def test_permute_rejects_bad_arguments():
     assert st == F.E_INVALID
 
 
-def _gemm(a, b, M, N, K, ta, tb, batch):
+def _gemm(a, b, M, N, K, ta, tb, batch, splitk=False):
     torch = _torch()
     A = torch.from_numpy(a).cuda()
     B = torch.from_numpy(b).cuda()
     Cm = torch.empty((batch, M, N), dtype=torch.complex64, device="cuda")
-    F.check(F.lib().qflex_gemm_c64(C.c_void_p(A.data_ptr()), C.c_void_p(B.data_ptr()),
-                                   C.c_void_p(Cm.data_ptr()), M, N, K, ta, tb, batch, None))
+    L = F.lib()
+    ws, ws_bytes = None, 0
+    if splitk:
+        ws_bytes = L.qflex_gemm_c64_workspace(M, N, K, batch)
+        assert ws_bytes > 0, "shape would not be split"
+        ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+    F.check(L.qflex_gemm_c64(C.c_void_p(A.data_ptr()), C.c_void_p(B.data_ptr()),
+                             C.c_void_p(Cm.data_ptr()), M, N, K, ta, tb, batch,
+                             C.c_void_p(ws.data_ptr()) if splitk else None, ws_bytes, None))
     torch.cuda.synchronize()
     return Cm.cpu().numpy()
 
@@ -130,6 +137,31 @@ def test_gemm_matches_fp64(M, N, K, batch, ta, tb):
     assert rel < 2e-6, rel
     rms = np.sqrt(np.mean(np.abs(want) ** 2))
     assert np.max(np.abs(got - want)) < 2e-5 * rms * max(1.0, np.sqrt(K / 64))
+
+
+# Reduction-shaped products (few output tiles, long K: the shapes of a gradient's operand
+# cotangents) split along K into a workspace and summed in a fixed order.
+SPLITK_SHAPES = [(16, 16, 1 << 16, 4, 1, 0), (4, 16, 1 << 14, 3, 1, 0), (256, 256, 8192, 1, 1, 0),
+                 (64, 64, 4096, 2, 0, 0), (16, 8, 1 << 15, 2, 0, 1), (1, 1, 1 << 12, 1, 1, 1)]
+
+
+@pytest.mark.parametrize("M,N,K,batch,ta,tb", SPLITK_SHAPES)
+def test_gemm_split_k_matches_fp64_and_is_deterministic(M, N, K, batch, ta, tb):
+    _say("split-K gemm", M, N, K, batch, ta, tb)
+    rng = np.random.default_rng(M + 5 * N + K + batch)
+    sa = (batch, K, M) if ta else (batch, M, K)
+    sb = (batch, N, K) if tb else (batch, K, N)
+    a = (rng.standard_normal(sa) + 1j * rng.standard_normal(sa)).astype(np.complex64)
+    b = (rng.standard_normal(sb) + 1j * rng.standard_normal(sb)).astype(np.complex64)
+    got = _gemm(a, b, M, N, K, ta, tb, batch, splitk=True)
+    again = _gemm(a, b, M, N, K, ta, tb, batch, splitk=True)
+    assert np.array_equal(got, again)
+    A = np.transpose(a, (0, 2, 1)) if ta else a
+    B = np.transpose(b, (0, 2, 1)) if tb else b
+    want = A.astype(np.complex128) @ B.astype(np.complex128)
+    rel = np.linalg.norm(got - want) / np.linalg.norm(want)
+    _say("  rel", rel)
+    assert rel < 2e-6, rel
 
 
 SPLIT_SHAPES = [(128, 64, 16, 1), (256, 128, 64, 2), (512, 256, 256, 1), (128, 512, 1024, 1),

@@ -180,3 +180,15 @@ def test_split_gemm_argument_checks_run_before_any_launch():
     assert call(M=96) == F.E_INVALID      # not a power of two
     assert call(K=8) == F.E_INVALID       # below the kernel's k-tile
     assert call(A=C.c_void_p((1 << 20) + 8)) == F.E_INVALID  # misaligned operand
+
+
+def test_split_k_workspace_only_for_reduction_shapes():
+    """qflex_gemm_c64_workspace is non-zero only when a product has few output tiles and a long
+    K (host-only arithmetic)."""
+    L = F.lib()
+    assert L.qflex_gemm_c64_workspace(16, 16, 1 << 16, 4) > 0
+    assert L.qflex_gemm_c64_workspace(4096, 4096, 4096, 1) == 0   # enough tiles
+    assert L.qflex_gemm_c64_workspace(16, 16, 256, 1) == 0        # K too short to split
+    # the workspace holds chunks x batch x M x N complex64 values
+    ws = L.qflex_gemm_c64_workspace(16, 16, 1 << 16, 4)
+    assert ws % (8 * 4 * 16 * 16) == 0
