@@ -212,18 +212,116 @@ __global__ void __launch_bounds__(256) gemm_simt_kernel(const Gemm g) {
   if (m < g.M && n < g.N) C[m * ldc + n] = make_float2(accr, acci);
 }
 
+// Tall-skinny products (M >= 256 rows, N <= 32 columns): one output row per thread, its
+// N <= NB complex accumulators in registers.  A k-tile of 16 values of 256 rows is staged in
+// LDS as [k][row] (so each thread reads its own row without bank conflicts) and B's k-tile
+// as [k][NB] (every lane reads the same B values: LDS broadcast).  Such products move far more
+// bytes than they compute (HBM-bound), so the loads are 16-byte vectors along the
+// contiguous dimension of A, and the next tile's loads are issued before this tile's math.
+template <int NB, bool TA, bool TB>
+__global__ void __launch_bounds__(256) gemm_rows_kernel(const Gemm g) {
+  constexpr int BM = 256, BK = 16;
+  constexpr int AV = BM * BK / 2 / 256;  // 16-byte (2 complex) loads of A per thread per tile
+  __shared__ __attribute__((aligned(16))) float2 As[2][BK][BM + 2];
+  __shared__ __attribute__((aligned(16))) float2 Bs[2][BK][NB];
+  const int tid = threadIdx.x;
+  const int b = blockIdx.y, z = blockIdx.z;
+  const int64_t m0 = (int64_t)blockIdx.x * BM;
+  const float2* __restrict__ A = g.A + g.a_add + (g.a_off ? g.a_off[b] : b * g.a_bs) + z * g.a_ks;
+  const float2* __restrict__ B = g.B + g.b_add + (g.b_off ? g.b_off[b] : b * g.b_bs) + z * g.b_ks;
+  float2* __restrict__ C = g.split > 1 ? g.ws + ((int64_t)z * g.batch + b) * g.M * g.N
+                                       : g.C + b * g.c_bs;
+  const int64_t ldc = g.split > 1 ? g.N : g.ldc;
+  const int N = (int)g.N;
+  f32x4 ra[AV];
+  float2 rb[(BK * NB + 255) / 256];
+  auto gload = [&](int64_t k0) {
+#pragma unroll
+    for (int v = 0; v < AV; ++v) {
+      const int e = tid + v * 256;
+      if (!TA) {  // [M][K]: 8 vectors of 2 k per row
+        const int row = e >> 3, kp = e & 7;
+        ra[v] = *reinterpret_cast<const f32x4*>(A + (m0 + row) * g.lda + k0 + 2 * kp);
+      } else {    // [K][M]: 128 vectors of 2 rows per k
+        const int kr = e >> 7, mp = e & 127;
+        ra[v] = *reinterpret_cast<const f32x4*>(A + (k0 + kr) * g.lda + m0 + 2 * mp);
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < (BK * NB + 255) / 256; ++v) {
+      const int e = tid + v * 256;
+      const int kr = e / NB, n = e % NB;
+      float2 x = make_float2(0.f, 0.f);
+      if (e < BK * NB && n < N) x = TB ? B[(int64_t)n * g.ldb + k0 + kr] : B[(k0 + kr) * g.ldb + n];
+      rb[v] = x;
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int v = 0; v < AV; ++v) {
+      const int e = tid + v * 256;
+      if (!TA) {
+        const int row = e >> 3, kp = e & 7;
+        As[buf][2 * kp][row] = make_float2(ra[v].x, ra[v].y);
+        As[buf][2 * kp + 1][row] = make_float2(ra[v].z, ra[v].w);
+      } else {
+        const int kr = e >> 7, mp = e & 127;
+        *reinterpret_cast<f32x4*>(&As[buf][kr][2 * mp]) = ra[v];
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < (BK * NB + 255) / 256; ++v) {
+      const int e = tid + v * 256;
+      if (e < BK * NB) Bs[buf][e / NB][e % NB] = rb[v];
+    }
+  };
+  float accr[NB], acci[NB];
+#pragma unroll
+  for (int n = 0; n < NB; ++n) accr[n] = acci[n] = 0.f;
+  const int nk = (int)(g.K / BK);
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < nk) gload((int64_t)(kt + 1) * BK);
+    // partial unrolling: a full one would hoist all BK x NB values of B into registers
+#pragma unroll 2
+    for (int kk = 0; kk < BK; ++kk) {
+      const float2 a = As[buf][kk][tid];
+#pragma unroll
+      for (int n = 0; n < NB; ++n) {
+        const float2 w = Bs[buf][kk][n];
+        accr[n] = fmaf(a.x, w.x, accr[n]);
+        accr[n] = fmaf(-a.y, w.y, accr[n]);
+        acci[n] = fmaf(a.x, w.y, acci[n]);
+        acci[n] = fmaf(a.y, w.x, acci[n]);
+      }
+    }
+    if (kt + 1 < nk) sstore(buf ^ 1);
+    __syncthreads();
+  }
+  const int64_t row = m0 + tid;
+  float2* c = C + row * ldc;
+#pragma unroll
+  for (int n = 0; n < NB; ++n)
+    if (n < N) c[n] = make_float2(accr[n], acci[n]);
+}
+
 int gemm_variant(const Gemm& g) {
   if (g.K % 16 == 0 && g.M % 128 == 0 && g.N % 128 == 0) return 2;
   if (g.K % 16 == 0 && g.M % 64 == 0 && g.N % 64 == 0) return 1;
+  if (g.K % 16 == 0 && g.M % 256 == 0 && g.N <= 32) return 3;
   return 0;
 }
 
 const char* gemm_name(const Gemm& g) {
-  static const char* names[3][4] = {
+  static const char* names[4][4] = {
       {"gemm_simt_nn", "gemm_simt_nt", "gemm_simt_tn", "gemm_simt_tt"},
       {"gemm_mfma_64x64_nn", "gemm_mfma_64x64_nt", "gemm_mfma_64x64_tn", "gemm_mfma_64x64_tt"},
       {"gemm_mfma_128x128_nn", "gemm_mfma_128x128_nt", "gemm_mfma_128x128_tn",
-       "gemm_mfma_128x128_tt"}};
+       "gemm_mfma_128x128_tt"},
+      {"gemm_rows_nn", "gemm_rows_nt", "gemm_rows_tn", "gemm_rows_tt"}};
   return names[gemm_variant(g)][(g.ta ? 2 : 0) + (g.tb ? 1 : 0)];
 }
 
@@ -232,6 +330,7 @@ static int64_t gemm_tiles(const Gemm& g) {
   switch (gemm_variant(g)) {
     case 2: return (g.M / 128) * (g.N / 128);
     case 1: return (g.M / 64) * (g.N / 64);
+    case 3: return g.M / 256;
     default: {
       const int bn = g.N >= 16 && g.M >= 16 ? 16 : g.N >= 8 ? 8 : g.N >= 4 ? 4 : g.N >= 2 ? 2 : 1;
       const int bm = 256 / bn;
@@ -283,6 +382,14 @@ static void gemm_t(const Gemm& g, hipStream_t s) {
   } else if (v == 1) {
     dim3 grid((unsigned)((g.M / 64) * (g.N / 64)), (unsigned)g.batch, z);
     hipLaunchKernelGGL((gemm_mfma_kernel<TA, TB, 64, 64>), grid, dim3(256), 0, s, g);
+  } else if (v == 3) {
+    dim3 grid((unsigned)(g.M / 256), (unsigned)g.batch, z);
+    if (g.N > 16) hipLaunchKernelGGL((gemm_rows_kernel<32, TA, TB>), grid, dim3(256), 0, s, g);
+    else if (g.N > 8) hipLaunchKernelGGL((gemm_rows_kernel<16, TA, TB>), grid, dim3(256), 0, s, g);
+    else if (g.N > 4) hipLaunchKernelGGL((gemm_rows_kernel<8, TA, TB>), grid, dim3(256), 0, s, g);
+    else if (g.N > 2) hipLaunchKernelGGL((gemm_rows_kernel<4, TA, TB>), grid, dim3(256), 0, s, g);
+    else if (g.N > 1) hipLaunchKernelGGL((gemm_rows_kernel<2, TA, TB>), grid, dim3(256), 0, s, g);
+    else hipLaunchKernelGGL((gemm_rows_kernel<1, TA, TB>), grid, dim3(256), 0, s, g);
   } else {
     auto launch = [&](auto kern, int bm, int bn) {
       const int64_t tiles = ((g.M + bm - 1) / bm) * ((g.N + bn - 1) / bn);

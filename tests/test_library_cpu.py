@@ -161,6 +161,8 @@ def test_gemm_variant_choice():
     assert L.qflex_gemm_variant(64, 64, 16) == 1
     assert L.qflex_gemm_variant(64, 8, 256) == 0
     assert L.qflex_gemm_variant(1 << 20, 256, 8) == 0
+    assert L.qflex_gemm_variant(1 << 16, 16, 256) == 3
+    assert L.qflex_gemm_variant(1 << 16, 4, 16) == 3
 
 
 def test_split_gemm_argument_checks_run_before_any_launch():
