@@ -338,9 +338,11 @@ struct View {
 
 }  // namespace
 
-void contract(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets, double fidelity,
-              uint64_t seed, const int64_t* slice_ids, const int64_t* slice_offsets,
-              double* amps, bool amps_on_device, hipStream_t s) {
+std::vector<std::vector<int64_t>> prepare_call(qflex_grid* g, const uint8_t* bits,
+                                               const int64_t* bs_offsets, double fidelity,
+                                               uint64_t seed, const int64_t* slice_ids,
+                                               const int64_t* slice_offsets, const void* amps,
+                                               hipStream_t s) {
   const int nc = (int)g->circ.size();
   // ---- validation (host only)
   if (!bs_offsets) fail(QFLEX_E_INVALID, "NULL argument");
@@ -371,7 +373,6 @@ void contract(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets, dou
     }
   }
   QHIP(hipGetLastError());
-  qflex_stats st{};
   // ---- per-bit-string output offsets of every closed qubit tensor, all circuits
   std::vector<int64_t> offs_base(nc + 1, 0);
   for (int c = 0; c < nc; ++c)
@@ -395,6 +396,19 @@ void contract(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets, dou
   QHIP(hipMemcpyAsync(g->offs.p, oh, offs_bytes, hipMemcpyHostToDevice, s));
   if (!g->offs_done) QHIP(hipEventCreateWithFlags(&g->offs_done, hipEventDisableTiming));
   QHIP(hipEventRecord(g->offs_done, s));
+  return sel;
+}
+
+void contract(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets, double fidelity,
+              uint64_t seed, const int64_t* slice_ids, const int64_t* slice_offsets,
+              double* amps, bool amps_on_device, hipStream_t s) {
+  const int nc = (int)g->circ.size();
+  const std::vector<std::vector<int64_t>> sel =
+      prepare_call(g, bits, bs_offsets, fidelity, seed, slice_ids, slice_offsets, amps, s);
+  qflex_stats st{};
+  std::vector<int64_t> offs_base(nc + 1, 0);
+  for (int c = 0; c < nc; ++c)
+    offs_base[c + 1] = offs_base[c] + (bs_offsets[c + 1] - bs_offsets[c]) * g->circ[c].model.n;
   const int64_t* offs_dev = static_cast<const int64_t*>(g->offs.p);
 
   size_t free_b = 0, total_b = 0;

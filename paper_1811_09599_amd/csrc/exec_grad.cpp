@@ -57,12 +57,25 @@ void contract_grad(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets
   const int64_t namp = int64_t(1) << no;
   const int64_t total_bs = bs_offsets[nc];
   const int64_t total_amp = total_bs * namp;
-  // ---- forward amplitudes (validates the call and uploads the output-bit offsets)
+  // ---- host checks, slice selection and output-offset upload
   g->amps_dev.reserve(sizeof(double2) * std::max<int64_t>(total_amp, 1));
-  contract(g, bits, bs_offsets, fidelity, seed, slice_ids, slice_offsets,
-           static_cast<double*>(g->amps_dev.p), true, s);
-  const qflex_stats fwd = g->last;
-  const double2* amps = static_cast<const double2*>(g->amps_dev.p);
+  double2* amps = static_cast<double2*>(g->amps_dev.p);
+  const std::vector<std::vector<int64_t>> sel =
+      prepare_call(g, bits, bs_offsets, fidelity, seed, slice_ids, slice_offsets, amps, s);
+  // With one slice per circuit, the forward pass that keeps the intermediates for the reverse
+  // sweep already yields the amplitudes (and, batch by batch, the linear-XEB cotangent), so no
+  // separate amplitude pass runs.  Otherwise every slice's cotangent needs the full sum first.
+  bool fused = true;
+  for (int c = 0; c < nc; ++c)
+    fused = fused && sel[c].size() == 1 && !g->circ[c].plan.result.qubit;
+  qflex_stats fwd{};
+  if (fused) {
+    dev::fill_zero(reinterpret_cast<double*>(amps), 2 * total_amp, s);
+  } else {
+    contract(g, bits, bs_offsets, fidelity, seed, slice_ids, slice_offsets,
+             reinterpret_cast<double*>(amps), true, s);
+    fwd = g->last;
+  }
   // ---- cotangent of the amplitudes, kept as dL/d(conj psi)
   g->gbar.reserve(sizeof(double2) * std::max<int64_t>(total_amp, 1));
   double2* gbar = static_cast<double2*>(g->gbar.p);
@@ -83,8 +96,9 @@ void contract_grad(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets
       const int64_t m = (bs_offsets[c + 1] - bs_offsets[c]) * namp;
       if (m == 0) continue;
       scale[c] = std::ldexp(1.0, g->circ[c].model.n) / (double)m;  // linear XEB 2^n/m
-      dev::xeb_cotangent(amps + bs_offsets[c] * namp, m, scale[c], gbar + bs_offsets[c] * namp,
-                         xeb_sum + c, s);
+      if (!fused)
+        dev::xeb_cotangent(amps + bs_offsets[c] * namp, m, scale[c],
+                           gbar + bs_offsets[c] * namp, xeb_sum + c, s);
     }
   }
   // ---- FP64 cotangents of the qubit tensors and of the piece matrices
@@ -107,13 +121,7 @@ void contract_grad(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets
     const Plan& P = cs.plan;
     const int64_t nbs = bs_offsets[c + 1] - bs_offsets[c];
     if (nbs == 0) continue;
-    std::vector<int64_t> slices;
-    if (slice_ids) {
-      slices.assign(slice_ids + slice_offsets[c], slice_ids + slice_offsets[c + 1]);
-      std::sort(slices.begin(), slices.end());
-    } else {
-      slices = select_slices(P.num_slices(), fidelity, seed);
-    }
+    const std::vector<int64_t>& slices = sel[c];
     // ---- memory: every node keeps its value and its cotangent; two product scratches
     const size_t nn = P.nodes.size();
     std::vector<int64_t> voff(nn), coff(nn);
@@ -257,6 +265,15 @@ void contract_grad(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets
           dev::gemm(gm, s);
           st.flops += stp.flops() * nb;
           ++st.n_gemm;
+        }
+        if (fused) {  // this batch's amplitudes (its only slice), then its XEB cotangent
+          const Node& rn = P.nodes[P.result.id];
+          double2* ab = amps + (bs_offsets[c] + b0) * namp;
+          dev::accumulate(ar + voff[P.result.id] * B, nullptr, rn.elems(), 0, namp,
+                          g->bidx + cs.bidx_offset, ab, namp, nb, s);
+          if (!cot)
+            dev::xeb_cotangent(ab, nb * namp, scale[c], gbar + (bs_offsets[c] + b0) * namp,
+                               xeb_sum + c, s);
         }
         // seed: cotangent of the result = conj(gbar) of this batch's amplitudes
         const double2* gb = gbar + (bs_offsets[c] + b0) * namp;

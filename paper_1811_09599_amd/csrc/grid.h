@@ -107,6 +107,13 @@ struct qflex_grid {
 
 namespace qflex {
 void build_grid_device(qflex_grid* g, hipStream_t s);
+// Host checks of a contract call, the slices each circuit sums, and the upload of the
+// per-bit-string output offsets (g->offs); everything contract() does before its launches.
+std::vector<std::vector<int64_t>> prepare_call(qflex_grid* g, const uint8_t* bits,
+                                               const int64_t* bs_offsets, double fidelity,
+                                               uint64_t seed, const int64_t* slice_ids,
+                                               const int64_t* slice_offsets, const void* amps,
+                                               hipStream_t s);
 void contract(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets, double fidelity,
               uint64_t seed, const int64_t* slice_ids, const int64_t* slice_offsets,
               double* amps, bool amps_on_device, hipStream_t s);

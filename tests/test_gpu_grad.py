@@ -86,15 +86,18 @@ def test_uneven_circuits_in_one_call():
         assert abs(res["loss"][i] - f_ref) < 1e-4 * max(1.0, abs(f_ref)), i
 
 
-def test_gradient_with_open_batch_and_fidelity_subset():
+@pytest.mark.parametrize("one_slice", [False, True])
+def test_gradient_with_open_batch_and_fidelity_subset(one_slice):
+    """Several slices (amplitudes first, then one reverse sweep per slice) and a single slice
+    (the forward pass of the reverse sweep also yields the amplitudes)."""
     _need_gpu()
-    _say("open batch + fidelity subset grad")
+    _say("open batch + fidelity subset grad, one slice:", one_slice)
     c = R.grid_rqc(4, 4, 12, 909, two_qubit="fsim", jitter_sd=0.02, jitter_seed=12)
     op = [15, 14]
     bits = R.bitstrings(16, 6, 2, op)
     g = build_grid(c, plan="quadrant", open_qubits=op)
     S = g.num_slices()
-    ids = [0, 5, S // 2, S - 1]
+    ids = [5] if one_slice else [0, 5, S // 2, S - 1]
     rng = np.random.default_rng(3)
     cot = rng.standard_normal((6, 4)) + 1j * rng.standard_normal((6, 4))
     res = g.contract_grad(bits, cotangent=cot, slice_ids=ids)
@@ -102,6 +105,8 @@ def test_gradient_with_open_batch_and_fidelity_subset():
     ref = E2.amplitude_gate_grads(c, bits, cot, op, cuts, ids)
     got = res["grad_params"][0][_fsim_rows(c)]
     assert metrics.rel_l2(got, ref) < GTOL
+    amp_ref = E2.amplitudes(c, bits, op, cuts=cuts, slice_ids=ids)
+    assert metrics.amp_errors(res["amps"], amp_ref, 16)["max"] < 1e-5
 
 
 def test_6x6_gradient_vs_autograd_oracle():
