@@ -9,7 +9,10 @@ the FP64 oracle on sampled slices.
 
 Prints one JSON line: amplitudes/s (whole job), sustained TFLOP/s of the plan (8 real flops
 per complex multiply-add), the roofline of the dominant kernel measured with HIP events around
-its launches in the timed region, and the CPU oracle timed on a bounded sample.
+its launches in the timed region, and the CPU oracle timed on a bounded sample.  A second
+workload, reported under "gradient", times the adjoint contraction: 96 jittered-fSim circuits
+on 4x4 to 6x6 grids (depth 1+12+1), linear XEB over 128 bit-strings each, amplitudes and
+gradients of every fSim angle in one call.
 
     python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--bitstrings 4]
 """
@@ -110,6 +113,7 @@ def main():
                     choices=["all", "c64", "split_bf16", "split_fp16"])
     ap.add_argument("--cpu-slices", type=int, default=3, help="oracle sample size (slices)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-gradient", action="store_true", help="skip the gradient workload")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first copy 1 GiB device to device (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -165,9 +169,65 @@ def main():
     for p in precs:
         if p != "c64" and "c64" in results:
             res["speedup_%s_vs_c64" % p] = results[p]["value"] / results["c64"]["value"]
+    if not args.no_gradient:
+        res["gradient"] = run_gradient(args)
     if not args.no_cpu_baseline:
         res.update(cpu_baseline(circ, grids, all_bits[:1], open_q, args.cpu_slices, rows, cols))
     print(json.dumps(res), flush=True)
+
+
+def run_gradient(args):
+    """Linear-XEB gradients of a batch of 96 fSim circuits (one contract_grad call = one step),
+    with the FP64 state-vector adjoint of the first 4x4 circuit as the parity check."""
+    import numpy as np
+    import torch
+
+    import rqc_inputs as R
+    from oracle import metrics
+    from oracle import statevector as E1
+    from paper_1811_09599_amd import build_grid
+
+    circs = R.fsim_batch(96, depth=12, sizes=(4, 5, 6), seed=5000, jitter_seed0=5900)
+    bits = [R.bitstrings(c["n_qubits"], 128, 5500 + i) for i, c in enumerate(circs)]
+    t0 = time.time()
+    grid = build_grid(circs)
+    torch.cuda.synchronize()
+    build_s = time.time() - t0
+    steps = max(1, min(args.steps, 2))
+    for _ in range(max(args.warmup, 0)):
+        grid.contract_grad(bits)
+    torch.cuda.synchronize()
+    grid.set_profiling(True)
+    t0 = time.perf_counter()
+    flops = 0.0
+    for _ in range(steps):
+        res = grid.contract_grad(bits)
+        flops += grid.last_stats()["flops"]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = grid.profile_read()
+    grid.set_profiling(False)
+    dom, roof = roofline(prof)
+    top = sorted(prof.items(), key=lambda kv: -kv[1]["ms"])[:6]
+    kernels = {k: {"launches": v["launches"], "ms": round(v["ms"], 3),
+                   "tflops": round(v["flops"] / max(v["ms"], 1e-9) / 1e9, 3),
+                   "gbps": round(v["bytes"] / max(v["ms"], 1e-9) / 1e6, 1)} for k, v in top}
+    i4 = next(i for i, c in enumerate(circs) if c["n_qubits"] == 16)
+    fsim = [j for j, gt in enumerate(circs[i4]["gates"]) if gt["kind"] == "fsim"]
+    f_ref, g_ref = E1.linear_xeb_grad(circs[i4], bits[i4])
+    sizes = np.bincount([c["n_qubits"] for c in circs])
+    return {"workload": "96 fSim circuits, grids 4x4..6x6 (rows, cols from {4,5,6}), depth "
+                        "1+12+1, theta = pi/2 + N(0, 0.02), phi = pi/6 + N(0, 0.02), linear "
+                        "XEB over 128 bit-strings each; amplitudes and d/d(theta, phi) of every "
+                        "fSim gate in one call per step",
+            "metric": "circuits/s", "value": len(circs) * steps / dt, "unit": "circuits/s",
+            "steps": steps, "ms_per_step": 1e3 * dt / steps,
+            "qubits_histogram": {str(n): int(k) for n, k in enumerate(sizes) if k},
+            "tflops": flops / dt / 1e12, "dominant_kernel": dom, "roofline": roof,
+            "kernels": kernels, "grid_build_s": build_s,
+            "parity": {"circuit": i4, "oracle": "state-vector adjoint (FP64)",
+                       "grad_rel_l2": metrics.rel_l2(res["grad_params"][i4][fsim], g_ref),
+                       "loss_abs_err": abs(float(res["loss"][i4]) - f_ref), "tol": 1e-3}}
 
 
 def cpu_baseline(circ, grids, bits, open_q, n_slices, rows, cols):

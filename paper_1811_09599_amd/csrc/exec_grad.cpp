@@ -214,9 +214,14 @@ void contract_grad(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets
           const int64_t* off =
               L.out_shift >= 0 ? offs_dev + offs_base[c] + (int64_t)o.id * nbs + b0 : nullptr;
           std::vector<int8_t> p8(d.perm.begin(), d.perm.end());
+          g->prof.begin("scatter_add_perm", 0,
+                        24.0 * (double)(int64_t(1) << d.nbits) * nb, s);
           dev::scatter_add_perm(src, d.nbits, p8.data(), nb, tgrid, off, add, s);
+          g->prof.end(s);
         } else {
+          g->prof.begin("permute", 0, 16.0 * (double)(int64_t(1) << d.nbits) * nb, s);
           dev::permute(src, ar + coff[o.id] * B, nb, t, s);
+          g->prof.end(s);
           ++st.n_permute;
         }
       };
@@ -232,12 +237,18 @@ void contract_grad(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets
           GView x = view(stp.x), y = view(stp.y);
           if (stp.scratch_x >= 0) {
             float2* dst = ar + voff[stp.scratch_x] * B;
+            g->prof.begin("permute", 0,
+                          16.0 * (double)P.nodes[stp.scratch_x].elems() * nb, s);
             dev::permute(x.base, dst, nb, cs.px[k], s);
+            g->prof.end(s);
             x = nodev(stp.scratch_x);
           }
           if (stp.scratch_y >= 0) {
             float2* dst = ar + voff[stp.scratch_y] * B;
+            g->prof.begin("permute", 0,
+                          16.0 * (double)P.nodes[stp.scratch_y].elems() * nb, s);
             dev::permute(y.base, dst, nb, cs.py[k], s);
+            g->prof.end(s);
             y = nodev(stp.scratch_y);
           }
           dev::Gemm gm;
@@ -262,7 +273,10 @@ void contract_grad(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets
           gm.batch = nb;
           gm.ws = splitk_ws;
           gm.ws_elems = ws_need;
+          g->prof.begin(dev::gemm_name(gm), stp.flops() * nb,
+                        8.0 * nb * (double)(gm.M * gm.K + gm.K * gm.N + gm.M * gm.N), s);
           dev::gemm(gm, s);
+          g->prof.end(s);
           st.flops += stp.flops() * nb;
           ++st.n_gemm;
         }
@@ -319,7 +333,10 @@ void contract_grad(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets
           g1.batch = nb;
           g1.ws = splitk_ws;
           g1.ws_elems = ws_need;
+          g->prof.begin(dev::gemm_name(g1), stp.flops() * nb,
+                        8.0 * nb * (double)(g1.M * g1.K + g1.K * g1.N + g1.M * g1.N), s);
           dev::gemm(g1, s);
+          g->prof.end(s);
           dev::Gemm g2;  // Ybar = X'^T Zbar
           g2.A = x.base;
           g2.a_off = x.off;
@@ -339,7 +356,10 @@ void contract_grad(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets
           g2.batch = nb;
           g2.ws = splitk_ws;
           g2.ws_elems = ws_need;
+          g->prof.begin(dev::gemm_name(g2), stp.flops() * nb,
+                        8.0 * nb * (double)(g2.M * g2.K + g2.K * g2.N + g2.M * g2.N), s);
           dev::gemm(g2, s);
+          g->prof.end(s);
           st.flops += 2.0 * stp.flops() * nb;
           st.n_gemm += 2;
           route(stp.x, xbar, dx[kk], rx[kk]);
@@ -348,10 +368,12 @@ void contract_grad(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets
       }
     }
     // reverse the time collapse of this circuit's qubits
+    g->prof.begin("grid_adjoint", 0, 0, s);
     dev::grid_adjoint(static_cast<const dev::GridQubit*>(g->gq.p) + cs.qdesc_base, cs.model.n,
                       cs.max_nlb, static_cast<const dev::GridPiece*>(g->gpieces.p),
                       static_cast<const double2*>(g->gmats.p),
                       static_cast<const int32_t*>(g->gpos.p), tbar, pbar, s);
+    g->prof.end(s);
   }
   // ---- host: piece cotangents -> gate entries -> angles (FP64)
   std::vector<double2> hp(4 * std::max<int64_t>(g->n_mats, 1));
