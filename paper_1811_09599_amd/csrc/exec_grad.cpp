@@ -439,6 +439,7 @@ void contract_grad(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets
     QHIPG(hipMemcpyAsync(amps_out, amps, sizeof(double2) * total_amp,
                          out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
   QHIPG(hipStreamSynchronize(s));
+  if (g->prof.on) g->prof.resolve();
   g->last = st;
 }
 
