@@ -77,10 +77,14 @@ typedef enum {
 } qflex_gate_kind;
 
 typedef enum {
-  QFLEX_PLAN_AUTO = 0,     /* SWEEP if it fits max_tensor_elems, else QUADRANT */
+  QFLEX_PLAN_AUTO = 0,     /* SWEEP if it fits max_tensor_elems, else QUADRANT on a full
+                              rectangular grid, else CUT_SWEEP */
   QFLEX_PLAN_SWEEP = 1,    /* absorb every qubit into one tensor, no cuts */
-  QFLEX_PLAN_QUADRANT = 2  /* four regions A|B over C|D, one cut between B and D in the last
+  QFLEX_PLAN_QUADRANT = 2, /* four regions A|B over C|D, one cut between B and D in the last
                               column and one between C and D in the last row (SI A) */
+  QFLEX_PLAN_CUT_SWEEP = 3 /* any layout: one sweep in the qubit order with the narrowest
+                              frontier, cutting links (most over-limit frontiers first) until
+                              every intermediate fits max_tensor_elems (Methods B.1 cutting) */
 } qflex_plan_kind;
 
 typedef struct {

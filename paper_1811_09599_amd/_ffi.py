@@ -11,7 +11,7 @@ OK, E_INVALID, E_PLAN, E_NOMEM, E_DEVICE, E_UNSUPPORTED = range(6)
 STATUS_NAMES = {0: "QFLEX_OK", 1: "QFLEX_E_INVALID", 2: "QFLEX_E_PLAN", 3: "QFLEX_E_NOMEM",
                 4: "QFLEX_E_DEVICE", 5: "QFLEX_E_UNSUPPORTED"}
 PREC = {"c64": 0, "split_bf16": 1, "split_fp16": 2}
-PLAN = {"auto": 0, "sweep": 1, "quadrant": 2}
+PLAN = {"auto": 0, "sweep": 1, "quadrant": 2, "cut_sweep": 3}
 KIND = {"h": 0, "x12": 1, "y12": 2, "t": 3, "cz": 4, "fsim": 5, "mat1": 6, "mat2": 7}
 
 

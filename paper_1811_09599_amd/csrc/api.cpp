@@ -54,7 +54,7 @@ void check_options(const qflex_options& o) {
   if (o.precision != QFLEX_PREC_C64 && o.precision != QFLEX_PREC_SPLIT_BF16 &&
       o.precision != QFLEX_PREC_SPLIT_FP16)
     qflex::fail(QFLEX_E_INVALID, "unknown precision");
-  if (o.plan_kind < QFLEX_PLAN_AUTO || o.plan_kind > QFLEX_PLAN_QUADRANT)
+  if (o.plan_kind < QFLEX_PLAN_AUTO || o.plan_kind > QFLEX_PLAN_CUT_SWEEP)
     qflex::fail(QFLEX_E_INVALID, "unknown plan_kind");
   if (o.bitstring_batch < 0) qflex::fail(QFLEX_E_INVALID, "bitstring_batch < 0");
 }

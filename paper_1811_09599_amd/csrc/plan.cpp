@@ -119,6 +119,94 @@ struct Planner {
   }
   int rmin_ = 0, cmin_ = 0;
 
+  // ---------------------------------------------------------------- sweeps with cuts
+  // Labels in the running tensor after each qubit of `ord` is absorbed (cut links excluded).
+  std::vector<std::set<int>> frontiers(const std::vector<int>& ord) const {
+    std::vector<std::set<int>> out;
+    std::set<int> cur;
+    for (int q : ord) {
+      for (int x : free_labels(q))
+        if (!cur.erase(x)) cur.insert(x);
+      out.push_back(cur);
+    }
+    return out;
+  }
+
+  // Of the line orders over the layout's coordinates (by x, by y, and along both diagonals),
+  // the one whose widest frontier is narrowest, then whose frontiers are smallest in total.
+  std::vector<int> narrowest_sweep() const {
+    std::vector<int> best;
+    std::pair<int, double> best_key{1 << 30, 0.0};
+    for (int kind = 0; kind < 4; ++kind) {
+      std::vector<int> o(m.n);
+      for (int q = 0; q < m.n; ++q) o[q] = q;
+      auto key = [&](int q) {
+        const int x = m.xy[q].first, y = m.xy[q].second;
+        switch (kind) {
+          case 0: return std::make_pair(x, y);
+          case 1: return std::make_pair(y, x);
+          case 2: return std::make_pair(x - y, x + y);
+          default: return std::make_pair(x + y, x - y);
+        }
+      };
+      std::stable_sort(o.begin(), o.end(), [&](int a, int b) { return key(a) < key(b); });
+      int mx = 0;
+      double sum = 0;
+      for (const auto& f : frontiers(o)) {
+        mx = std::max(mx, (int)f.size());
+        sum += std::ldexp(1.0, (int)f.size());
+      }
+      const std::pair<int, double> k{mx, sum};
+      if (best.empty() || k < best_key) best_key = k, best = o;
+    }
+    return best;
+  }
+
+  // Cut links until every frontier of the sweep fits limit_bits: each round cuts the link
+  // present in the most frontiers that are still too wide (ties: the lower link id).
+  void choose_cuts_sweep(const std::vector<int>& ord) {
+    for (;;) {
+      const auto fr = frontiers(ord);
+      std::map<int, int> votes;  // link -> over-limit frontiers holding it
+      for (const auto& f : fr) {
+        if ((int)f.size() <= limit_bits) continue;
+        std::set<int> links;
+        for (int lab : f)
+          if (lab < P.total_link_bits)
+            links.insert(int(std::upper_bound(P.link_base.begin(), P.link_base.end(), lab) -
+                             P.link_base.begin()) - 1);
+        for (int l : links) ++votes[l];
+      }
+      if (votes.empty()) break;
+      if (P.cuts.size() >= 31) fail(QFLEX_E_PLAN, "more than 31 cut links needed");
+      int best = -1, bv = 0;
+      for (auto& kv : votes)
+        if (kv.second > bv) best = kv.first, bv = kv.second;
+      int total_bits = 0;
+      for (int b : P.cut_bits) total_bits += b;
+      if (total_bits + m.links[best].bits > 40)
+        fail(QFLEX_E_PLAN, "cutting this circuit down to max_tensor_elems needs over 2^40 slices");
+      cut_of_link[best] = (int)P.cuts.size();
+      P.cuts.push_back(best);
+      P.cut_bits.push_back(m.links[best].bits);
+    }
+    // slice radix: the cut the sweep meets first varies slowest, so that everything
+    // absorbed before a cut's first qubit is reused across the faster cuts' values
+    std::vector<int> pos(m.n);
+    for (size_t i = 0; i < ord.size(); ++i) pos[ord[i]] = (int)i;
+    std::vector<int> cuts = P.cuts;
+    std::stable_sort(cuts.begin(), cuts.end(), [&](int a, int b) {
+      return std::min(pos[m.links[a].lo], pos[m.links[a].hi]) <
+             std::min(pos[m.links[b].lo], pos[m.links[b].hi]);
+    });
+    P.cuts = cuts;
+    P.cut_bits.clear();
+    for (size_t c = 0; c < cuts.size(); ++c) {
+      cut_of_link[cuts[c]] = (int)c;
+      P.cut_bits.push_back(m.links[cuts[c]].bits);
+    }
+  }
+
   // ---------------------------------------------------------------- ordering
   // Order in which to absorb `qs` into a running tensor with labels `acc` (may be empty).
   std::vector<int> order(const std::vector<int>& acc_labels, uint32_t acc_deps,
@@ -603,49 +691,38 @@ struct Planner {
     cut_of_link.assign(m.links.size(), -1);
     int kind = opt.plan_kind;
     if (kind == QFLEX_PLAN_AUTO) {
-      try {
-        qflex_options o2 = opt;
-        o2.plan_kind = QFLEX_PLAN_SWEEP;
-        Planner t2(m, o2);
-        t2.run();
-        kind = QFLEX_PLAN_SWEEP;
-      } catch (const Error& e) {
-        if (e.status != QFLEX_E_PLAN) throw;
-        kind = QFLEX_PLAN_QUADRANT;
+      kind = QFLEX_PLAN_CUT_SWEEP;
+      for (int k : {QFLEX_PLAN_SWEEP, QFLEX_PLAN_QUADRANT}) {
+        try {
+          qflex_options o2 = opt;
+          o2.plan_kind = k;
+          Planner t2(m, o2);
+          t2.run();
+          kind = k;
+          break;
+        } catch (const Error& e) {
+          if (e.status != QFLEX_E_PLAN) throw;
+        }
       }
     }
     P.kind = kind;
     std::vector<std::pair<bool, std::vector<int>>> segs;
     bool exact = false;
     if (kind == QFLEX_PLAN_SWEEP) {
-      // row- or column-major, whichever keeps the frontier narrower; exact order search
-      // for small circuits
+      // exact order search for small circuits, else the narrowest of the line orders
       std::vector<int> ids(m.n);
       for (int q = 0; q < m.n; ++q) ids[q] = q;
       if (m.n <= 20) {
         segs.push_back({false, ids});
       } else {
-        int best_bits = 1 << 30;
-        std::vector<int> best;
-        for (int major = 0; major < 2; ++major) {
-          std::vector<int> o = ids;
-          std::stable_sort(o.begin(), o.end(), [&](int a, int b) {
-            auto pa = m.xy[a], pb = m.xy[b];
-            if (major) std::swap(pa.first, pa.second), std::swap(pb.first, pb.second);
-            return pa < pb;
-          });
-          std::set<int> cur;
-          int mx = 0;
-          for (int q : o) {
-            for (int x : free_labels(q))
-              if (!cur.erase(x)) cur.insert(x);
-            mx = std::max(mx, (int)cur.size());
-          }
-          if (mx < best_bits) best_bits = mx, best = o;
-        }
-        segs.push_back({false, best});
+        segs.push_back({false, narrowest_sweep()});
         exact = true;
       }
+    } else if (kind == QFLEX_PLAN_CUT_SWEEP) {
+      const std::vector<int> ord = narrowest_sweep();
+      choose_cuts_sweep(ord);
+      segs.push_back({false, ord});
+      exact = true;
     } else if (kind == QFLEX_PLAN_QUADRANT) {
       int rs, cs, I, J;
       choose_cuts_quadrant(rs, cs, I, J);
@@ -715,7 +792,10 @@ Plan make_plan(const Model& m, const qflex_options& opt) {
 std::string Plan::describe(const Model& m) const {
   std::ostringstream o;
   o.precision(17);
-  o << "{\"kind\":\"" << (kind == QFLEX_PLAN_SWEEP ? "sweep" : "quadrant") << "\",\"cuts\":[";
+  const char* kname = kind == QFLEX_PLAN_SWEEP      ? "sweep"
+                      : kind == QFLEX_PLAN_QUADRANT ? "quadrant"
+                                                    : "cut_sweep";
+  o << "{\"kind\":\"" << kname << "\",\"cuts\":[";
   for (size_t i = 0; i < cuts.size(); ++i)
     o << (i ? "," : "") << "[" << m.links[cuts[i]].lo << "," << m.links[cuts[i]].hi << ","
       << cut_bits[i] << "]";

@@ -99,3 +99,47 @@ def test_7x7_fidelity_subset_matches_oracle():
                         order=E2.quadrant_order(7, 7))
     e = metrics.amp_errors(a, ref, 49)
     assert e["max"] < 1e-5, e
+
+
+# ------------------------------------------------------------------- 70-qubit diamond
+DIAMOND_TOL = {"c64": 1e-5, "split_bf16": SPLIT_TOL_D32}
+
+
+@pytest.mark.parametrize("precision", ["c64", "split_bf16"])
+def test_diamond70_identity_coupled_slice_matches_closed_form(precision):
+    """The 70-qubit diamond at depth 1+24+1 (bond 8 on every link) is swept with a cut link
+    and 2^30-element intermediates; with identity couplings each slice has a closed form."""
+    _need_gpu()
+    _say("diamond 70 1+24+1 identity couplings, one slice,", precision)
+    c = R.replace_two_qubit(R.diamond_rqc(24, 4001), "fsim", 0.0, 0.0)
+    for seed in range(4500, 4600):
+        bits = R.bitstrings(70, 1, seed)
+        if np.abs(E1.identity_coupled_path_amplitudes(c, bits)).max() > 0:
+            break
+    g = build_grid(c, precision=precision)
+    cuts = g.plan_cuts()
+    assert len(cuts) >= 1 and g.num_slices() >= 8
+    norms = [np.abs(E1.identity_coupled_path_amplitudes(c, bits, (), cuts, s)).max()
+             for s in range(g.num_slices())]
+    sid = int(np.argmax(norms))
+    a = g.contract_amplitudes(bits, slice_ids=[sid]).cpu().numpy()
+    ref = E1.identity_coupled_path_amplitudes(c, bits, (), cuts, sid)
+    e = metrics.amp_errors(a, ref, 70)
+    _say("  error", e)
+    assert e["max"] < DIAMOND_TOL[precision]
+    g.close()
+
+
+def test_diamond70_rqc_split_bf16_agrees_with_c64_on_a_slice():
+    _need_gpu()
+    _say("diamond 70 RQC, split vs c64 on one slice")
+    c = R.diamond_rqc(24, 4001)
+    bits = R.bitstrings(70, 2, 4700)
+    res = {}
+    for p in ("c64", "split_bf16"):
+        g = build_grid(c, precision=p)
+        res[p] = g.contract_amplitudes(bits, slice_ids=[3]).cpu().numpy()
+        g.close()
+    e = metrics.amp_errors(res["split_bf16"], res["c64"], 70)
+    _say("  split vs c64", e)
+    assert e["max"] < SPLIT_TOL_D32

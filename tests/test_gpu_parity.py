@@ -208,6 +208,39 @@ def test_cfg2_7x7_depth32_sampled_slices_vs_oracle():
     _check(a, ref, 49)
 
 
+# ------------------------------------------------------------------- cut sweeps
+@pytest.mark.parametrize("layout", ["grid4x5", "diamond15"])
+def test_cut_sweep_all_slices_vs_state_vector(layout):
+    """Links cut until every intermediate fits a small cap: the sum over all slices is the
+    amplitude (slicing is exact), on a grid and on a corner of the diamond lattice."""
+    _need_gpu()
+    _say("cut sweep", layout)
+    if layout == "grid4x5":
+        c, cap, op = R.grid_rqc(4, 5, 16, 4242), 1 << 8, [19, 18]
+    else:
+        c, cap, op = R.rqc([p for p in R.diamond_layout() if p[0] <= 3], 16, 77), 1 << 7, [0, 1]
+    n = c["n_qubits"]
+    bits = R.bitstrings(n, 3, 91, op)
+    g = build_grid(c, plan="cut_sweep", max_tensor_elems=cap, open_qubits=op)
+    assert g.num_slices() >= 64
+    a = g.contract_amplitudes(bits).cpu().numpy()
+    e = _check(a, E1.amplitudes(c, bits, op), n)
+    _say("  error", e, "slices", g.num_slices())
+
+
+def test_cut_sweep_single_slices_match_oracle_paths():
+    _need_gpu()
+    c = R.grid_rqc(4, 5, 16, 4343)
+    op = [19, 18]
+    bits = R.bitstrings(20, 2, 92, op)
+    g = build_grid(c, plan="cut_sweep", max_tensor_elems=1 << 8, open_qubits=op)
+    S = g.num_slices()
+    ids = [0, 17, S - 1]
+    a = g.contract_amplitudes(bits, slice_ids=ids).cpu().numpy()
+    ref = E2.amplitudes(c, bits, op, cuts=g.plan_cuts(), slice_ids=ids)
+    _check(a, ref, 20)
+
+
 # ------------------------------------------------------------------- split precisions
 # Stated bounds: split-bf16 keeps ~16 of an operand's 24 bits (bf16x3 products, FP32
 # accumulation); split-fp16 keeps ~22 (inside its scale window), so its bound is 4x the

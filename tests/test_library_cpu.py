@@ -194,3 +194,29 @@ def test_split_k_workspace_only_for_reduction_shapes():
     # the workspace holds chunks x batch x M x N complex64 values
     ws = L.qflex_gemm_c64_workspace(16, 16, 1 << 16, 4)
     assert ws % (8 * 4 * 16 * 16) == 0
+
+
+def test_cut_sweep_plan_fits_the_70_qubit_diamond():
+    """The diamond (no full rectangle, so no quadrant plan) is swept with cut links: every
+    intermediate fits 2^30 elements and the slices number 2^(cut bits)."""
+    c = R.diamond_rqc(24, 4001)
+    d = plan_describe(c)
+    assert d["kind"] == "cut_sweep"
+    assert d["max_bits"] <= 30 and len(d["cuts"]) >= 1
+    xy = c["xy"]
+    for q0, q1, bits in d["cuts"]:
+        assert abs(xy[q0][0] - xy[q1][0]) + abs(xy[q0][1] - xy[q1][1]) == 1
+        assert bits == 3  # three CZ gates per link at depth 24, one bit each
+    assert d["num_slices"] == 2 ** sum(b for _, _, b in d["cuts"])
+    # without cuts the same sweep would need a 2^33-element frontier
+    with pytest.raises(F.QflexError):
+        plan_describe(c, plan="sweep")
+
+
+def test_cut_sweep_cuts_until_the_cap():
+    c = R.grid_rqc(4, 5, 16, 4242)
+    for cap_bits in (8, 6):
+        d = plan_describe(c, plan="cut_sweep", max_tensor_elems=1 << cap_bits)
+        assert d["kind"] == "cut_sweep"
+        assert d["max_bits"] <= cap_bits and d["cuts"]
+    assert not plan_describe(c, plan="cut_sweep", max_tensor_elems=1 << 10)["cuts"]  # fits
