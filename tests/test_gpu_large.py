@@ -105,6 +105,19 @@ def test_7x7_fidelity_subset_matches_oracle():
 DIAMOND_TOL = {"c64": 1e-5, "split_bf16": SPLIT_TOL_D32}
 
 
+def _likely_product_state_bitstring(c):
+    """A random bit-string has an astronomically small amplitude in a 70-qubit product state
+    (1e-29 here), far below what any FP32 contraction resolves; take instead each qubit's more
+    likely value (amplitude >= 2^-35), qubit by qubit from the closed form with that qubit
+    left open."""
+    n = c["n_qubits"]
+    bits = np.zeros((1, n), dtype=np.uint8)
+    for q in range(n):
+        pair = E1.identity_coupled_path_amplitudes(c, bits, (q,))[0]
+        bits[0, q] = int(abs(pair[1]) > abs(pair[0]))
+    return bits
+
+
 @pytest.mark.parametrize("precision", ["c64", "split_bf16"])
 def test_diamond70_identity_coupled_slice_matches_closed_form(precision):
     """The 70-qubit diamond at depth 1+24+1 (bond 8 on every link) is swept with a cut link
@@ -112,10 +125,7 @@ def test_diamond70_identity_coupled_slice_matches_closed_form(precision):
     _need_gpu()
     _say("diamond 70 1+24+1 identity couplings, one slice,", precision)
     c = R.replace_two_qubit(R.diamond_rqc(24, 4001), "fsim", 0.0, 0.0)
-    for seed in range(4500, 4600):
-        bits = R.bitstrings(70, 1, seed)
-        if np.abs(E1.identity_coupled_path_amplitudes(c, bits)).max() > 0:
-            break
+    bits = _likely_product_state_bitstring(c)
     g = build_grid(c, precision=precision)
     cuts = g.plan_cuts()
     assert len(cuts) >= 1 and g.num_slices() >= 8
