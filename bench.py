@@ -114,6 +114,7 @@ def main():
     ap.add_argument("--cpu-slices", type=int, default=3, help="oracle sample size (slices)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-gradient", action="store_true", help="skip the gradient workload")
+    ap.add_argument("--no-diamond", action="store_true", help="skip the diamond workload")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first copy 1 GiB device to device (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -171,9 +172,70 @@ def main():
             res["speedup_%s_vs_c64" % p] = results[p]["value"] / results["c64"]["value"]
     if not args.no_gradient:
         res["gradient"] = run_gradient(args)
+    if not args.no_diamond:
+        res["diamond"] = run_diamond(args)
     if not args.no_cpu_baseline:
         res.update(cpu_baseline(circ, grids, all_bits[:1], open_q, args.cpu_slices, rows, cols))
     print(json.dumps(res), flush=True)
+
+
+def run_diamond(args):
+    """70-qubit diamond lattice, depth 1+24+1 (bond 8), cut sweep with 2^30-element
+    intermediates, one amplitude per bit-string at fidelity 1/8 (one of the 8 slices, seeded),
+    split-bf16 products; checked against complex64 on the same call."""
+    import numpy as np
+    import torch
+
+    import rqc_inputs as R
+    from oracle import metrics
+    from paper_1811_09599_amd import build_grid
+
+    circ = R.diamond_rqc(24, 4001)
+    bits = R.bitstrings(70, 64, 4500)
+    B = 4  # bit-strings per step
+    t0 = time.time()
+    grid = build_grid(circ, precision="split_bf16")
+    torch.cuda.synchronize()
+    build_s = time.time() - t0
+    S = grid.num_slices()
+    fid = 1.0 / S
+    for i in range(max(args.warmup, 0)):
+        grid.contract_amplitudes(bits[:B], fidelity=fid, seed=4700)
+    torch.cuda.synchronize()
+    grid.set_profiling(True)
+    t0 = time.perf_counter()
+    flops = 0.0
+    steps = max(1, args.steps)
+    for i in range(steps):
+        lo = (i * B) % len(bits)
+        grid.contract_amplitudes(bits[lo:lo + B], fidelity=fid, seed=4700)
+        flops += grid.last_stats()["flops"]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = grid.profile_read()
+    grid.set_profiling(False)
+    dom, roof = roofline(prof)
+    top = sorted(prof.items(), key=lambda kv: -kv[1]["ms"])[:5]
+    kernels = {k: {"launches": v["launches"], "ms": round(v["ms"], 3),
+                   "tflops": round(v["flops"] / max(v["ms"], 1e-9) / 1e9, 3),
+                   "gbps": round(v["bytes"] / max(v["ms"], 1e-9) / 1e6, 1)} for k, v in top}
+    a = grid.contract_amplitudes(bits[:B], fidelity=fid, seed=4700).cpu().numpy()
+    grid.close()
+    ref = build_grid(circ).contract_amplitudes(bits[:B], fidelity=fid, seed=4700).cpu().numpy()
+    err = metrics.amp_errors(a, ref, 70)
+    return {"workload": "70-qubit diamond lattice, depth 1+24+1 (bond 8), cut sweep (%d cut "
+                        "link, %d slices), fidelity 1/%d, one amplitude per bit-string, %d "
+                        "bit-strings per step, split-bf16" % (len(grid_cuts(circ)), S, S, B),
+            "metric": "amplitudes/s", "value": B * steps / dt, "unit": "amplitudes/s",
+            "steps": steps, "ms_per_step": 1e3 * dt / steps, "tflops": flops / dt / 1e12,
+            "dominant_kernel": dom, "roofline": roof, "kernels": kernels,
+            "grid_build_s": build_s,
+            "split_bf16_vs_c64": {"max_rel_err": err["max"], "median_rel_err": err["median"]}}
+
+
+def grid_cuts(circ):
+    from paper_1811_09599_amd import plan_describe
+    return plan_describe(circ)["cuts"]
 
 
 def run_gradient(args):
