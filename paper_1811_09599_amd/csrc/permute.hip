@@ -204,8 +204,18 @@ __global__ void __launch_bounds__(256) absmax_kernel(const float4* __restrict__ 
                                                      uint64_t* __restrict__ slot, uint64_t tag) {
   float m = 0.f;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += stride) {
-    const float4 v = in[i];
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  // four independent loads in flight per thread
+  for (; i + 3 * stride < n4; i += 4 * stride) {
+    f32x4 v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = *reinterpret_cast<const f32x4*>(in + i + u * stride);
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      m = fmaxf(m, fmaxf(fmaxf(fabsf(v[u].x), fabsf(v[u].y)), fmaxf(fabsf(v[u].z), fabsf(v[u].w))));
+  }
+  for (; i < n4; i += stride) {
+    const f32x4 v = *reinterpret_cast<const f32x4*>(in + i);
     m = fmaxf(m, fmaxf(fmaxf(fabsf(v.x), fabsf(v.y)), fmaxf(fabsf(v.z), fabsf(v.w))));
   }
   if (tail && blockIdx.x == 0 && threadIdx.x == 0) m = fmaxf(m, fmaxf(fabsf(tail->x), fabsf(tail->y)));
@@ -222,7 +232,7 @@ void absmax(const float2* in, int64_t n, uint64_t* slot, uint32_t tag, hipStream
   if (reinterpret_cast<uintptr_t>(in) % 16) throw std::runtime_error("absmax: misaligned input");
   const int64_t n4 = n / 2;
   const float2* tail = (n & 1) ? in + (n - 1) : nullptr;
-  const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((n4 + 255) / 256, 2048));
+  const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((n4 + 1023) / 1024, 4096));
   hipLaunchKernelGGL(absmax_kernel, dim3((unsigned)blocks), dim3(256), 0, s,
                      reinterpret_cast<const float4*>(in), n4, tail, slot,
                      (uint64_t)tag << 32);
