@@ -61,7 +61,8 @@ qflex_status qflex_gemm_split_c64(const void* A, const void* B, void* C, int64_t
 int64_t qflex_gemm_split_workspace(int64_t M, int64_t N, int64_t K, int64_t batch);
 
 /* Kernel variant qflex_gemm_c64 uses for a shape: 0 SIMT, 1 MFMA 64x64, 2 MFMA 128x128,
- * 3 tall-skinny rows kernel (M a multiple of 256, N <= 32, K a multiple of 16). */
+ * 3 tall-skinny rows kernel (M a multiple of 256 and at least 32768, N <= 32, K a multiple
+ * of 16). */
 int32_t qflex_gemm_variant(int64_t M, int64_t N, int64_t K);
 
 /* The slice subset that qflex_contract_amplitudes sums for a fidelity (host only): writes up to

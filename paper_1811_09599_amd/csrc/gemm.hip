@@ -301,17 +301,40 @@ __global__ void __launch_bounds__(256) gemm_rows_kernel(const Gemm g) {
     if (kt + 1 < nk) sstore(buf ^ 1);
     __syncthreads();
   }
-  const int64_t row = m0 + tid;
-  float2* c = C + row * ldc;
+  if (ldc == N && N == NB && NB >= 2) {
+    // the workgroup's 256 output rows are one contiguous block of 256*NB values: stage it in
+    // LDS (the A buffers are free after the last barrier) and write it with 16-byte stores
+    float2* stage = &As[0][0][0];  // 256*NB <= 2*16*258 values
 #pragma unroll
-  for (int n = 0; n < NB; ++n)
-    if (n < N) c[n] = make_float2(accr[n], acci[n]);
+    for (int n = 0; n < NB; ++n) stage[tid * NB + ((n + tid) % NB)] = make_float2(accr[n], acci[n]);
+    __syncthreads();
+    f32x4* out = reinterpret_cast<f32x4*>(C + m0 * ldc);
+#pragma unroll
+    for (int v = 0; v < NB / 2; ++v) {
+      const int e = tid + v * 256;          // pair of values 2e, 2e+1
+      const int r0 = (2 * e) / NB, c0 = (2 * e) % NB;  // c0 even, c0 + 1 < NB
+      const float2 p0 = stage[r0 * NB + ((c0 + r0) % NB)];
+      const float2 p1 = stage[r0 * NB + ((c0 + 1 + r0) % NB)];
+      f32x4 w;
+      w.x = p0.x;
+      w.y = p0.y;
+      w.z = p1.x;
+      w.w = p1.y;
+      out[e] = w;
+    }
+  } else {
+    float2* c = C + (m0 + tid) * ldc;
+#pragma unroll
+    for (int n = 0; n < NB; ++n)
+      if (n < N) c[n] = make_float2(accr[n], acci[n]);
+  }
 }
 
 int gemm_variant(const Gemm& g) {
   if (g.K % 16 == 0 && g.M % 128 == 0 && g.N % 128 == 0) return 2;
   if (g.K % 16 == 0 && g.M % 64 == 0 && g.N % 64 == 0) return 1;
-  if (g.K % 16 == 0 && g.M % 256 == 0 && g.N <= 32) return 3;
+  // rows kernel: one workgroup per 256 rows, so only when that fills half the chip or more
+  if (g.K % 16 == 0 && g.M % 256 == 0 && g.N <= 32 && (g.M / 256) * g.batch >= 128) return 3;
   return 0;
 }
 

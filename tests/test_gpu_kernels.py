@@ -112,9 +112,10 @@ def _gemm(a, b, M, N, K, ta, tb, batch, splitk=False):
 SHAPES = [(1, 1, 1, 1), (3, 5, 7, 2), (64, 64, 16, 1), (64, 64, 64, 3), (128, 128, 32, 1),
           (256, 128, 48, 2), (128, 256, 1024, 1), (1024, 256, 256, 1), (4096, 16, 256, 1),
           (16, 4096, 256, 1), (1 << 14, 1, 256, 2), (64, 2, 8, 5), (512, 512, 4096, 1),
-          # tall-skinny rows kernel: M a multiple of 256, N <= 32, K a multiple of 16
-          (1 << 16, 4, 256, 2), (2048, 32, 64, 3), (1 << 16, 8, 16, 1), (512, 2, 4096, 1),
-          (768, 24, 32, 2)]
+          # tall-skinny rows kernel: M a multiple of 256, N <= 32, K a multiple of 16, and at
+          # least 256 row blocks over the batch
+          (1 << 16, 4, 256, 2), (1 << 16, 32, 64, 1), (1 << 16, 8, 16, 1), (1 << 15, 2, 64, 2),
+          (3 << 15, 24, 32, 1), (1 << 16, 1, 16, 1), (1 << 16, 16, 32, 1)]
 
 
 @pytest.mark.parametrize("M,N,K,batch", SHAPES)

@@ -163,6 +163,7 @@ def test_gemm_variant_choice():
     assert L.qflex_gemm_variant(1 << 20, 256, 8) == 0
     assert L.qflex_gemm_variant(1 << 16, 16, 256) == 3
     assert L.qflex_gemm_variant(1 << 16, 4, 16) == 3
+    assert L.qflex_gemm_variant(1 << 14, 16, 256) == 0  # 64 row blocks: SIMT tiles instead
 
 
 def test_split_gemm_argument_checks_run_before_any_launch():
