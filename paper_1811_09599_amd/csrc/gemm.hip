@@ -330,21 +330,145 @@ __global__ void __launch_bounds__(256) gemm_rows_kernel(const Gemm g) {
   }
 }
 
+// Reduction-shaped products (M <= 32 rows, 4 <= N columns, a long K): C = op(A) B with B
+// stored [K][N], as in the cotangent of a product's right operand.  Each thread owns one
+// column n of a 256-column tile (NT = min(N, 256) columns, 256 / NT k-subgroups), streams
+// B[k][n] from HBM (coalesced along n) and keeps the column's M complex sums in registers;
+// A's k-tile ([BK][M], BK = max(16, subgroups)) is broadcast from LDS.  Subgroups are summed
+// through LDS at the end.
+template <int MB, bool TA>
+__global__ void __launch_bounds__(256) gemm_reduce_kernel(const Gemm g) {
+  constexpr int BKMAX = 64;
+  __shared__ float2 As[BKMAX][MB];
+  __shared__ float2 red[256];
+  const int tid = threadIdx.x;
+  const int b = blockIdx.y, z = blockIdx.z;
+  const int NT = g.N < 256 ? (int)g.N : 256;
+  const int nsub = 256 / NT;
+  const int BK = nsub > 16 ? nsub : 16;
+  const int col_in = tid % NT, sub = tid / NT;
+  const int64_t n0 = (int64_t)blockIdx.x * NT;
+  const int M = (int)g.M;
+  const float2* __restrict__ A = g.A + g.a_add + (g.a_off ? g.a_off[b] : b * g.a_bs) + z * g.a_ks;
+  const float2* __restrict__ B = g.B + g.b_add + (g.b_off ? g.b_off[b] : b * g.b_bs) + z * g.b_ks;
+  float2* __restrict__ C = g.split > 1 ? g.ws + ((int64_t)z * g.batch + b) * g.M * g.N
+                                       : g.C + b * g.c_bs;
+  const int64_t ldc = g.split > 1 ? g.N : g.ldc;
+  float accr[MB], acci[MB];
+#pragma unroll
+  for (int m = 0; m < MB; ++m) accr[m] = acci[m] = 0.f;
+  for (int64_t k0 = 0; k0 < g.K; k0 += BK) {
+    for (int e = tid; e < BK * MB; e += 256) {
+      const int kk = e / MB, m = e % MB;
+      float2 v = make_float2(0.f, 0.f);
+      if (m < M) v = TA ? A[(k0 + kk) * g.lda + m] : A[(int64_t)m * g.lda + k0 + kk];
+      As[kk][m] = v;
+    }
+    __syncthreads();
+    for (int kk = sub; kk < BK; kk += nsub) {
+      const float2 w = B[(k0 + kk) * g.ldb + n0 + col_in];
+#pragma unroll
+      for (int m = 0; m < MB; ++m) {
+        const float2 a = As[kk][m];
+        accr[m] = fmaf(a.x, w.x, accr[m]);
+        accr[m] = fmaf(-a.y, w.y, accr[m]);
+        acci[m] = fmaf(a.x, w.y, acci[m]);
+        acci[m] = fmaf(a.y, w.x, acci[m]);
+      }
+    }
+    __syncthreads();
+  }
+  // sum the subgroups' partial columns, one row at a time
+#pragma unroll
+  for (int m = 0; m < MB; ++m) {
+    if (m >= M) break;
+    if (nsub == 1) {
+      C[m * ldc + n0 + col_in] = make_float2(accr[m], acci[m]);
+      continue;
+    }
+    red[tid] = make_float2(accr[m], acci[m]);
+    __syncthreads();
+    if (sub == 0) {
+      float2 t = red[col_in];
+      for (int j = 1; j < nsub; ++j) {
+        const float2 u = red[j * NT + col_in];
+        t.x += u.x;
+        t.y += u.y;
+      }
+      C[m * ldc + n0 + col_in] = t;
+    }
+    __syncthreads();
+  }
+}
+
+// Products with a short K (K < 16) and N >= 32 columns, which write far more than they read:
+// each thread owns one output column of a 256-column tile and a set of rows, keeps its
+// column of B (K values) in registers, and reads each row of A from LDS (broadcast); the
+// stores are coalesced along the row.
+template <int KB, bool TA, bool TB>
+__global__ void __launch_bounds__(256) gemm_smallk_kernel(const Gemm g) {
+  constexpr int BM = 64;
+  __shared__ float2 As[BM][KB];
+  const int tid = threadIdx.x;
+  const int b = blockIdx.y;
+  const int NT = g.N < 256 ? (int)g.N : 256;
+  const int64_t tiles_n = g.N / NT;
+  const int64_t m0 = (int64_t)(blockIdx.x / tiles_n) * BM;
+  const int64_t n0 = (int64_t)(blockIdx.x % tiles_n) * NT;
+  const int col_in = tid % NT, rsub = tid / NT, nrs = 256 / NT;
+  const int K = (int)g.K;
+  const float2* __restrict__ A = g.A + g.a_add + (g.a_off ? g.a_off[b] : b * g.a_bs);
+  const float2* __restrict__ B = g.B + g.b_add + (g.b_off ? g.b_off[b] : b * g.b_bs);
+  float2* __restrict__ C = g.C + b * g.c_bs;
+  float2 w[KB];
+#pragma unroll
+  for (int k = 0; k < KB; ++k)
+    w[k] = k < K ? (TB ? B[(n0 + col_in) * g.ldb + k] : B[(int64_t)k * g.ldb + n0 + col_in])
+                 : make_float2(0.f, 0.f);
+  for (int e = tid; e < BM * KB; e += 256) {
+    const int r = e / KB, k = e % KB;
+    float2 v = make_float2(0.f, 0.f);
+    if (m0 + r < g.M && k < K) v = TA ? A[(int64_t)k * g.lda + m0 + r] : A[(m0 + r) * g.lda + k];
+    As[r][k] = v;
+  }
+  __syncthreads();
+  for (int r = rsub; r < BM; r += nrs) {
+    if (m0 + r >= g.M) break;
+    float re = 0.f, im = 0.f;
+#pragma unroll
+    for (int k = 0; k < KB; ++k) {
+      const float2 a = As[r][k];
+      re = fmaf(a.x, w[k].x, re);
+      re = fmaf(-a.y, w[k].y, re);
+      im = fmaf(a.x, w[k].y, im);
+      im = fmaf(a.y, w[k].x, im);
+    }
+    C[(m0 + r) * g.ldc + n0 + col_in] = make_float2(re, im);
+  }
+}
+
+static bool pow2_or_256(int64_t n) { return n <= 256 ? (n & (n - 1)) == 0 : n % 256 == 0; }
+
 int gemm_variant(const Gemm& g) {
   if (g.K % 16 == 0 && g.M % 128 == 0 && g.N % 128 == 0) return 2;
   if (g.K % 16 == 0 && g.M % 64 == 0 && g.N % 64 == 0) return 1;
   // rows kernel: one workgroup per 256 rows, so only when that fills half the chip or more
   if (g.K % 16 == 0 && g.M % 256 == 0 && g.N <= 32 && (g.M / 256) * g.batch >= 128) return 3;
+  if (!g.tb && g.M <= 32 && g.N >= 4 && pow2_or_256(g.N) && g.K >= 256 && g.K % 64 == 0)
+    return 4;  // reduction-shaped
+  if (g.K < 16 && (g.K & (g.K - 1)) == 0 && g.N >= 32 && pow2_or_256(g.N)) return 5;  // short K
   return 0;
 }
 
 const char* gemm_name(const Gemm& g) {
-  static const char* names[4][4] = {
+  static const char* names[6][4] = {
       {"gemm_simt_nn", "gemm_simt_nt", "gemm_simt_tn", "gemm_simt_tt"},
       {"gemm_mfma_64x64_nn", "gemm_mfma_64x64_nt", "gemm_mfma_64x64_tn", "gemm_mfma_64x64_tt"},
       {"gemm_mfma_128x128_nn", "gemm_mfma_128x128_nt", "gemm_mfma_128x128_tn",
        "gemm_mfma_128x128_tt"},
-      {"gemm_rows_nn", "gemm_rows_nt", "gemm_rows_tn", "gemm_rows_tt"}};
+      {"gemm_rows_nn", "gemm_rows_nt", "gemm_rows_tn", "gemm_rows_tt"},
+      {"gemm_reduce_nn", "gemm_reduce_nt", "gemm_reduce_tn", "gemm_reduce_tt"},
+      {"gemm_smallk_nn", "gemm_smallk_nt", "gemm_smallk_tn", "gemm_smallk_tt"}};
   return names[gemm_variant(g)][(g.ta ? 2 : 0) + (g.tb ? 1 : 0)];
 }
 
@@ -354,6 +478,8 @@ static int64_t gemm_tiles(const Gemm& g) {
     case 2: return (g.M / 128) * (g.N / 128);
     case 1: return (g.M / 64) * (g.N / 64);
     case 3: return g.M / 256;
+    case 4: return g.N / std::min<int64_t>(g.N, 256);
+    case 5: return ((g.M + 63) / 64) * (g.N / std::min<int64_t>(g.N, 256));
     default: {
       const int bn = g.N >= 16 && g.M >= 16 ? 16 : g.N >= 8 ? 8 : g.N >= 4 ? 4 : g.N >= 2 ? 2 : 1;
       const int bm = 256 / bn;
@@ -413,6 +539,21 @@ static void gemm_t(const Gemm& g, hipStream_t s) {
     else if (g.N > 2) hipLaunchKernelGGL((gemm_rows_kernel<4, TA, TB>), grid, dim3(256), 0, s, g);
     else if (g.N > 1) hipLaunchKernelGGL((gemm_rows_kernel<2, TA, TB>), grid, dim3(256), 0, s, g);
     else hipLaunchKernelGGL((gemm_rows_kernel<1, TA, TB>), grid, dim3(256), 0, s, g);
+  } else if (v == 4) {
+    dim3 grid((unsigned)(g.N / std::min<int64_t>(g.N, 256)), (unsigned)g.batch, z);
+    if (g.M > 16) hipLaunchKernelGGL((gemm_reduce_kernel<32, TA>), grid, dim3(256), 0, s, g);
+    else if (g.M > 8) hipLaunchKernelGGL((gemm_reduce_kernel<16, TA>), grid, dim3(256), 0, s, g);
+    else if (g.M > 4) hipLaunchKernelGGL((gemm_reduce_kernel<8, TA>), grid, dim3(256), 0, s, g);
+    else if (g.M > 2) hipLaunchKernelGGL((gemm_reduce_kernel<4, TA>), grid, dim3(256), 0, s, g);
+    else if (g.M > 1) hipLaunchKernelGGL((gemm_reduce_kernel<2, TA>), grid, dim3(256), 0, s, g);
+    else hipLaunchKernelGGL((gemm_reduce_kernel<1, TA>), grid, dim3(256), 0, s, g);
+  } else if (v == 5) {
+    dim3 grid((unsigned)(((g.M + 63) / 64) * (g.N / std::min<int64_t>(g.N, 256))),
+              (unsigned)g.batch);
+    if (g.K > 4) hipLaunchKernelGGL((gemm_smallk_kernel<8, TA, TB>), grid, dim3(256), 0, s, g);
+    else if (g.K > 2) hipLaunchKernelGGL((gemm_smallk_kernel<4, TA, TB>), grid, dim3(256), 0, s, g);
+    else if (g.K > 1) hipLaunchKernelGGL((gemm_smallk_kernel<2, TA, TB>), grid, dim3(256), 0, s, g);
+    else hipLaunchKernelGGL((gemm_smallk_kernel<1, TA, TB>), grid, dim3(256), 0, s, g);
   } else {
     auto launch = [&](auto kern, int bm, int bn) {
       const int64_t tiles = ((g.M + bm - 1) / bm) * ((g.N + bn - 1) / bn);

@@ -115,7 +115,11 @@ SHAPES = [(1, 1, 1, 1), (3, 5, 7, 2), (64, 64, 16, 1), (64, 64, 64, 3), (128, 12
           # tall-skinny rows kernel: M a multiple of 256, N <= 32, K a multiple of 16, and at
           # least 256 row blocks over the batch
           (1 << 16, 4, 256, 2), (1 << 16, 32, 64, 1), (1 << 16, 8, 16, 1), (1 << 15, 2, 64, 2),
-          (3 << 15, 24, 32, 1), (1 << 16, 1, 16, 1), (1 << 16, 16, 32, 1)]
+          (3 << 15, 24, 32, 1), (1 << 16, 1, 16, 1), (1 << 16, 16, 32, 1),
+          # reduction-shaped kernel (M <= 32, N >= 4, K >= 256; B stored [K][N])
+          (16, 256, 1024, 2), (4, 64, 4096, 1), (32, 512, 512, 1), (1, 4, 256, 3), (3, 8, 320, 1),
+          # short-K kernel (K < 16, N >= 32)
+          (1000, 64, 4, 2), (4096, 256, 8, 1), (100, 512, 2, 3), (64, 32, 1, 1)]
 
 
 @pytest.mark.parametrize("M,N,K,batch", SHAPES)

@@ -160,10 +160,12 @@ def test_gemm_variant_choice():
     assert L.qflex_gemm_variant(4096, 4096, 4096) == 2
     assert L.qflex_gemm_variant(64, 64, 16) == 1
     assert L.qflex_gemm_variant(64, 8, 256) == 0
-    assert L.qflex_gemm_variant(1 << 20, 256, 8) == 0
+    assert L.qflex_gemm_variant(1 << 20, 256, 8) == 5   # short K
     assert L.qflex_gemm_variant(1 << 16, 16, 256) == 3
     assert L.qflex_gemm_variant(1 << 16, 4, 16) == 3
     assert L.qflex_gemm_variant(1 << 14, 16, 256) == 0  # 64 row blocks: SIMT tiles instead
+    assert L.qflex_gemm_variant(16, 256, 1 << 16) == 4  # reduction-shaped
+    assert L.qflex_gemm_variant(1 << 16, 256, 4) == 5   # short K
 
 
 def test_split_gemm_argument_checks_run_before_any_launch():
