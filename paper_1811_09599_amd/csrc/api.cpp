@@ -312,14 +312,23 @@ qflex_status qflex_gemm_split_c64(const void* A, const void* B, void* C, int64_t
       qflex::dev::absmax(static_cast<const float2*>(A), batch * M * K, slots, 1, st);
       qflex::dev::absmax(static_cast<const float2*>(B), batch * N * K, slots + 1, 1, st);
     }
-    qflex::dev::split_permute(static_cast<const float2*>(A), sa, batch,
-                              qflex::dev::make_perm_tile(mb + kb, pa.data()), kb,
-                              f16 ? slots : nullptr, st);
+    // A stored [M][K] is read by the product itself (identity gather), else permuted and split
+    if (ta)
+      qflex::dev::split_permute(static_cast<const float2*>(A), sa, batch,
+                                qflex::dev::make_perm_tile(mb + kb, pa.data()), kb,
+                                f16 ? slots : nullptr, st);
     qflex::dev::split_permute(static_cast<const float2*>(B), sb, batch,
                               qflex::dev::make_perm_tile(nb + kb, pbv.data()), kb,
                               f16 ? slots + 1 : nullptr, st);
     qflex::dev::GemmSplit g;
     if (f16) g.a_amax = slots, g.b_amax = slots + 1;
+    if (!ta) {
+      g.Ac = static_cast<const float2*>(A);
+      g.ga.nm = mb;
+      g.ga.nk = kb - 4;
+      for (int i = 0; i < mb; ++i) g.ga.mpos[i] = (int8_t)(kb + i);
+      for (int j = 0; j < kb - 4; ++j) g.ga.kpos[j] = (int8_t)(4 + j);
+    }
     g.A = sa;
     g.B = sb;
     g.C = static_cast<float2*>(C);

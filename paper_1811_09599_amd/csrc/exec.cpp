@@ -249,6 +249,8 @@ void prepare_split(qflex_grid* g, hipStream_t s) {
     cs.split.assign(ns, 0);
     cs.sx.assign(ns, dev::PermTile{});
     cs.sy.assign(ns, dev::PermTile{});
+    cs.gather_x.assign(ns, 0);
+    cs.gx.assign(ns, dev::SplitGather{});
     cs.qsplit_offset.assign(cs.model.n, -1);
     cs.qamax_slot.assign(cs.model.n, -1);
     cs.split_a_elems = cs.split_b_elems = 0;
@@ -257,8 +259,38 @@ void prepare_split(qflex_grid* g, hipStream_t s) {
       const int64_t M = int64_t(1) << st.mb, N = int64_t(1) << st.nb, K = int64_t(1) << st.kb;
       if (!dev::gemm_split_ok(M, N, K)) continue;
       cs.split[i] = 1;
-      const std::vector<int> xa = [&] { auto v = st.mlab; v.insert(v.end(), st.klab.begin(), st.klab.end()); return v; }();
-      const std::vector<int> yb = [&] { auto v = st.nlab; v.insert(v.end(), st.klab.begin(), st.klab.end()); return v; }();
+      // The order of the contracted labels is this step's own choice: when the 4 lowest
+      // storage labels of an intermediate x are contracted ones, put them last, in storage
+      // order, and let the product read x straight from its complex64 storage (no
+      // permutation or split pass over x).
+      std::vector<int> klab = st.klab;
+      bool gather = false;
+      if (!st.x.qubit && st.kb >= 4 && st.x_in.size() >= 4) {
+        const std::vector<int> low(st.x_in.end() - 4, st.x_in.end());
+        std::vector<int> rest;
+        int found = 0;
+        for (int l : st.klab)
+          if (std::find(low.begin(), low.end(), l) != low.end()) ++found;
+          else rest.push_back(l);
+        if (found == 4) {
+          klab = rest;
+          klab.insert(klab.end(), low.begin(), low.end());
+          gather = true;
+        }
+      }
+      const std::vector<int> xa = [&] { auto v = st.mlab; v.insert(v.end(), klab.begin(), klab.end()); return v; }();
+      const std::vector<int> yb = [&] { auto v = st.nlab; v.insert(v.end(), klab.begin(), klab.end()); return v; }();
+      if (gather) {
+        const PermDesc pd = make_perm_desc(st.x_in, xa);
+        dev::SplitGather& ga = cs.gx[i];
+        ga.nm = st.mb;
+        ga.nk = st.kb - 4;
+        bool ok = st.mb + st.kb <= dev::kGatherMaxBits;
+        for (int j = 0; j < 4 && ok; ++j) ok = pd.perm[j] == j;
+        for (int j = 0; ok && j < ga.nk; ++j) ga.kpos[j] = (int8_t)pd.perm[4 + j];
+        for (int j = 0; ok && j < ga.nm; ++j) ga.mpos[j] = (int8_t)pd.perm[st.kb + j];
+        cs.gather_x[i] = ok;
+      }
       for (int side = 0; side < 2; ++side) {
         const Operand& o = side ? st.y : st.x;
         const std::vector<int>& in = side ? st.y_in : st.x_in;
@@ -272,7 +304,7 @@ void prepare_split(qflex_grid* g, hipStream_t s) {
           cs.qsplit_offset[o.id] = total;
           total += ((int64_t(4) << L.storage.size()) + 63) & ~int64_t(63);
           jobs.push_back(j);
-        } else {
+        } else if (!(side == 0 && cs.gather_x[i])) {
           (side ? cs.sy[i] : cs.sx[i]) = dev::make_perm_tile(pd.nbits, pd.perm.data());
           const int64_t e = int64_t(4) << P.nodes[o.id].labels.size();
           if (side) cs.split_b_elems = std::max(cs.split_b_elems, e);
@@ -500,6 +532,16 @@ void contract(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets, dou
               gs.a_add = x.add;
               gs.a_off = x.off;
               if (f16) gs.a_amax = g->amax + cs.qamax_slot[stp.x.id];
+            } else if (cs.gather_x[k]) {
+              if (f16) {
+                gs.a_amax = g->amax;
+                g->prof.begin("absmax", 0, 8.0 * M * K * nb, s);
+                dev::absmax(x.base, M * K * nb, g->amax, next_amax_tag(g, s), s);
+                g->prof.end(s);
+              }
+              gs.Ac = x.base;
+              gs.a_bs = x.bs;
+              gs.ga = cs.gx[k];
             } else {
               if (f16) {
                 gs.a_amax = g->amax;

@@ -32,7 +32,10 @@ __device__ inline floatx16 mfma16(f16x8 a, f16x8 b, floatx16 c) {
   return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
 }
 
-template <int BM, int BN, int WM, int WN, bool F16>
+// GA: A comes from complex64 storage through the gather descriptor (one permutation and one
+// split pass over A fewer): each thread loads whole groups of 4 consecutive k (32 bytes) of
+// two rows, and splits them into the compact layout while storing the tile to LDS.
+template <int BM, int BN, int WM, int WN, bool F16, bool GA>
 __global__ void __launch_bounds__(64 * WM * WN) gemm_split_kernel(const GemmSplit g) {
   using V = typename std::conditional<F16, f16x8, bf16x8>::type;
   constexpr int NT = 64 * WM * WN;       // threads: WM x WN wavefronts
@@ -57,11 +60,40 @@ __global__ void __launch_bounds__(64 * WM * WN) gemm_split_kernel(const GemmSpli
   const int64_t m0 = tm * BM, n0 = tn * BN;
 
   u32x4 ra[AV], rb[BV];
-  auto gload = [&](int64_t k0) {  // k0 in 16-bit units along the row
+  // gathered A: AG groups of 4 k per thread per tile, rows fixed for the whole k loop
+  constexpr int AG = BM * (BK / 4) / NT;
+  f32x4 rc[GA ? AG : 1][2];
+  int64_t frow[GA ? AG : 1];
+  const float2* __restrict__ Ac =
+      GA ? g.Ac + g.a_add + (g.a_off ? g.a_off[b] : b * g.a_bs) : nullptr;
+  float ascale = 1.f;
+  if constexpr (GA) {
 #pragma unroll
-    for (int v = 0; v < AV; ++v) {
-      const int e = tid + v * NT, row = e >> 3, ch = e & 7;
-      ra[v] = *reinterpret_cast<const u32x4*>(A + (m0 + row) * lda + k0 + 8 * ch);
+    for (int u = 0; u < AG; ++u) {
+      const int64_t m = m0 + ((tid + u * NT) >> 2);
+      int64_t f = 0;
+      for (int i = 0; i < g.ga.nm; ++i) f |= ((m >> i) & 1) << g.ga.mpos[i];
+      frow[u] = f;
+    }
+    if constexpr (F16) ascale = fp16_scale(*g.a_amax);
+  }
+  auto gload = [&](int64_t k0) {  // k0 in 16-bit units along the row
+    if constexpr (GA) {
+      const int64_t kt = k0 / ROW;
+      int64_t gk = 0;
+      for (int j = 0; j < g.ga.nk; ++j) gk |= ((kt >> j) & 1) << g.ga.kpos[j];
+#pragma unroll
+      for (int u = 0; u < AG; ++u) {
+        const float2* p = Ac + frow[u] + gk + 4 * ((tid + u * NT) & 3);
+        rc[u][0] = *reinterpret_cast<const f32x4*>(p);
+        rc[u][1] = *reinterpret_cast<const f32x4*>(p + 2);
+      }
+    } else {
+#pragma unroll
+      for (int v = 0; v < AV; ++v) {
+        const int e = tid + v * NT, row = e >> 3, ch = e & 7;
+        ra[v] = *reinterpret_cast<const u32x4*>(A + (m0 + row) * lda + k0 + 8 * ch);
+      }
     }
 #pragma unroll
     for (int v = 0; v < BV; ++v) {
@@ -70,10 +102,27 @@ __global__ void __launch_bounds__(64 * WM * WN) gemm_split_kernel(const GemmSpli
     }
   };
   auto sstore = [&](int buf) {
+    if constexpr (GA) {
 #pragma unroll
-    for (int v = 0; v < AV; ++v) {
-      const int e = tid + v * NT, row = e >> 3, ch = e & 7;
-      *reinterpret_cast<u32x4*>(&As[buf][row * LDR + 8 * ch]) = ra[v];
+      for (int u = 0; u < AG; ++u) {
+        const int e = tid + u * NT, row = e >> 2, grp = e & 3;
+        // 4 complex (re, im pairs) -> [rh(4) ih(4)] and [rl(4) il(4)]
+        const f32x4 p0 = rc[u][0] * ascale, p1 = rc[u][1] * ascale;
+        uint32_t h0, h1, h2, h3, l0, l1, l2, l3;
+        split16x2<F16>(p0.x, p0.z, h0, l0);
+        split16x2<F16>(p1.x, p1.z, h1, l1);
+        split16x2<F16>(p0.y, p0.w, h2, l2);
+        split16x2<F16>(p1.y, p1.w, h3, l3);
+        const u32x4 hi = {h0, h1, h2, h3}, lo = {l0, l1, l2, l3};
+        *reinterpret_cast<u32x4*>(&As[buf][row * LDR + 16 * grp]) = hi;
+        *reinterpret_cast<u32x4*>(&As[buf][row * LDR + 16 * grp + 8]) = lo;
+      }
+    } else {
+#pragma unroll
+      for (int v = 0; v < AV; ++v) {
+        const int e = tid + v * NT, row = e >> 3, ch = e & 7;
+        *reinterpret_cast<u32x4*>(&As[buf][row * LDR + 8 * ch]) = ra[v];
+      }
     }
 #pragma unroll
     for (int v = 0; v < BV; ++v) {
@@ -166,23 +215,28 @@ bool gemm_split_ok(int64_t M, int64_t N, int64_t K) {
 }
 
 const char* gemm_split_name(const GemmSplit& g) {
-  const bool f16 = g.a_amax != nullptr;
-  if (g.M % 256 == 0 && g.N % 128 == 0) return f16 ? "gemm_split_fp16_256x128" : "gemm_split_bf16_256x128";
-  if (g.M % 128 == 0 && g.N % 128 == 0) return f16 ? "gemm_split_fp16_128x128" : "gemm_split_bf16_128x128";
-  return f16 ? "gemm_split_fp16_64x64" : "gemm_split_bf16_64x64";
+  static const char* names[2][2][3] = {
+      {{"gemm_split_bf16_256x128", "gemm_split_bf16_128x128", "gemm_split_bf16_64x64"},
+       {"gemm_split_fp16_256x128", "gemm_split_fp16_128x128", "gemm_split_fp16_64x64"}},
+      {{"gemm_split_bf16_gather_256x128", "gemm_split_bf16_gather_128x128",
+        "gemm_split_bf16_gather_64x64"},
+       {"gemm_split_fp16_gather_256x128", "gemm_split_fp16_gather_128x128",
+        "gemm_split_fp16_gather_64x64"}}};
+  const int t = g.M % 256 == 0 && g.N % 128 == 0 ? 0 : g.M % 128 == 0 && g.N % 128 == 0 ? 1 : 2;
+  return names[g.Ac != nullptr][g.a_amax != nullptr][t];
 }
 
-template <bool F16>
+template <bool F16, bool GA>
 static void gemm_split_t(const GemmSplit& g, hipStream_t s) {
   if (g.M % 256 == 0 && g.N % 128 == 0) {
     dim3 grid((unsigned)((g.M / 256) * (g.N / 128)), (unsigned)g.batch);
-    hipLaunchKernelGGL((gemm_split_kernel<256, 128, 4, 2, F16>), grid, dim3(512), 0, s, g);
+    hipLaunchKernelGGL((gemm_split_kernel<256, 128, 4, 2, F16, GA>), grid, dim3(512), 0, s, g);
   } else if (g.M % 128 == 0 && g.N % 128 == 0) {
     dim3 grid((unsigned)((g.M / 128) * (g.N / 128)), (unsigned)g.batch);
-    hipLaunchKernelGGL((gemm_split_kernel<128, 128, 2, 2, F16>), grid, dim3(256), 0, s, g);
+    hipLaunchKernelGGL((gemm_split_kernel<128, 128, 2, 2, F16, GA>), grid, dim3(256), 0, s, g);
   } else {
     dim3 grid((unsigned)((g.M / 64) * (g.N / 64)), (unsigned)g.batch);
-    hipLaunchKernelGGL((gemm_split_kernel<64, 64, 2, 2, F16>), grid, dim3(256), 0, s, g);
+    hipLaunchKernelGGL((gemm_split_kernel<64, 64, 2, 2, F16, GA>), grid, dim3(256), 0, s, g);
   }
 }
 
@@ -191,8 +245,17 @@ void gemm_split(const GemmSplit& g, hipStream_t s) {
   if (g.batch < 1 || g.batch > 65535) throw std::runtime_error("gemm_split: bad batch");
   if ((g.a_amax == nullptr) != (g.b_amax == nullptr))
     throw std::runtime_error("gemm_split: both operands must use the same format");
-  if (g.a_amax) gemm_split_t<true>(g, s);
-  else gemm_split_t<false>(g, s);
+  if (g.Ac) {
+    // the gathered k groups need the 4 lowest k bits in the 4 lowest storage bits
+    if (g.ga.nm + g.ga.nk + 4 > kGatherMaxBits || (int64_t(1) << g.ga.nm) != g.M ||
+        (int64_t(16) << g.ga.nk) != g.K)
+      throw std::runtime_error("gemm_split: gather descriptor does not match the shape");
+    if (g.a_amax) gemm_split_t<true, true>(g, s);
+    else gemm_split_t<false, true>(g, s);
+  } else {
+    if (g.a_amax) gemm_split_t<true, false>(g, s);
+    else gemm_split_t<false, false>(g, s);
+  }
   check_launch("gemm_split");
 }
 

@@ -28,6 +28,8 @@ struct CircuitState {
   // split-precision products
   std::vector<char> split;           // per step: runs as a split (16-bit) product
   std::vector<dev::PermTile> sx, sy; // per step: node operand -> split operand layout
+  std::vector<char> gather_x;        // per step: x read from complex64 storage by the product
+  std::vector<dev::SplitGather> gx;  // per step: its gather descriptor
   std::vector<int64_t> qsplit_offset;// per qubit: offset in grid_split (16-bit values), -1 if none
   std::vector<int64_t> qamax_slot;   // per qubit: fp16 scale slot in amax, -1 if none
   int64_t split_a_elems = 0, split_b_elems = 0;  // scratch per bit-string (16-bit values)

@@ -48,6 +48,30 @@ __device__ inline int fp16_scale_exp(uint64_t slot) {
 __device__ inline float fp16_scale(uint64_t slot) { return pow2f(fp16_scale_exp(slot)); }
 __device__ inline float fp16_unscale(uint64_t slot) { return pow2f(-fp16_scale_exp(slot)); }
 
+// ---- hi + lo split of FP32 values into 16-bit parts (bf16 or fp16)
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+
+// (a, b) = hi + lo per value, both rounded to nearest even, packed two per 32-bit word (a in
+// the low half); the differences are exact in FP32.  gfx950 converts a pair in one
+// instruction (v_cvt_pk_bf16_f32 / v_cvt_pk_f16_f32).
+template <bool F16>
+__device__ inline void split16x2(float a, float b, uint32_t& hi, uint32_t& lo) {
+  const f32x2 x = {a, b};
+  if constexpr (F16) {
+    const f16x2 h = __builtin_convertvector(x, f16x2);
+    const f16x2 l = __builtin_convertvector(x - __builtin_convertvector(h, f32x2), f16x2);
+    hi = __builtin_bit_cast(uint32_t, h);
+    lo = __builtin_bit_cast(uint32_t, l);
+  } else {
+    const bf16x2 h = __builtin_convertvector(x, bf16x2);
+    const bf16x2 l = __builtin_convertvector(x - __builtin_convertvector(h, f32x2), bf16x2);
+    hi = __builtin_bit_cast(uint32_t, h);
+    lo = __builtin_bit_cast(uint32_t, l);
+  }
+}
+
 // ---- binary index tiles (see permute.hip)
 __device__ inline int lds_pad(int i) { return i + (i >> 5); }
 

@@ -97,6 +97,16 @@ void split_permute(const float2* in, uint16_t* out, int64_t batch, const PermTil
 // tag than the calls before (tag >= 1; in must be 16-byte aligned).
 void absmax(const float2* in, int64_t n, uint64_t* slot, uint32_t tag, hipStream_t s);
 
+// Storage positions of the bits of a product operand's row index m and of k >> 4, for an
+// operand read straight from complex64 storage whose 4 lowest storage bits are k's 4 lowest
+// bits: element (m, k) sits at f(m) + (k & 15) + g(k >> 4).
+constexpr int kGatherMaxBits = 40;
+struct SplitGather {
+  int32_t nm = 0, nk = 0;
+  int8_t mpos[kGatherMaxBits] = {};
+  int8_t kpos[kGatherMaxBits] = {};
+};
+
 struct GemmSplit {
   const uint16_t* A = nullptr;  // [M][K] split, row stride 4K 16-bit values
   const uint16_t* B = nullptr;  // [N][K] split
@@ -110,6 +120,10 @@ struct GemmSplit {
   // fp16 operands: the absmax() slots their scales came from (both NULL: bf16 operands)
   const uint64_t* a_amax = nullptr;
   const uint64_t* b_amax = nullptr;
+  // A read from complex64 storage through ga and split while staging (then A is unused and
+  // a_off / a_bs / a_add count complex64 elements of Ac); NULL: A is pre-split
+  const float2* Ac = nullptr;
+  SplitGather ga;
 };
 bool gemm_split_ok(int64_t M, int64_t N, int64_t K);  // shape fits the tiled kernel
 void gemm_split(const GemmSplit& g, hipStream_t s);

@@ -92,27 +92,6 @@ void permute(const float2* in, float2* out, int64_t batch, const PermTile& t, hi
 // =============================================================================================
 // Split layouts of the 16-bit products (see kernels.h for the layout and the two formats).
 // =============================================================================================
-__device__ inline uint16_t bf16_rne(float x) {
-  uint32_t u = __float_as_uint(x);
-  u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even (finite inputs)
-  return (uint16_t)(u >> 16);
-}
-__device__ inline float bf16_to_f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
-
-// x = hi + lo with hi, lo in the 16-bit format (x already scaled for fp16)
-template <bool F16>
-__device__ inline void split16(float x, uint16_t& hi, uint16_t& lo) {
-  if constexpr (F16) {
-    const _Float16 h = (_Float16)x;  // round to nearest even
-    const _Float16 l = (_Float16)(x - (float)h);  // the difference is exact in FP32
-    hi = __builtin_bit_cast(uint16_t, h);
-    lo = __builtin_bit_cast(uint16_t, l);
-  } else {
-    hi = bf16_rne(x);
-    lo = bf16_rne(x - bf16_to_f(hi));
-  }
-}
-
 // One thread per group of 4 consecutive k of a row: the tile's write order starts with the
 // lowest output bits, so a group is 4 consecutive write indices and is stored as two 16-byte
 // vectors.  For fp16, every value is first multiplied by the operand's power-of-two scale,
@@ -156,24 +135,19 @@ __global__ void __launch_bounds__(256) split_permute_kernel(const float2* __rest
         ig |= bit << t.j2i[b];
         e0 |= (int64_t)bit << t.tile_out[b];
       }
-    uint16_t h[16];
+    float re[4], im[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int i = ig | ((u & 1) << t.j2i[0]) | (((u >> 1) & 1) << t.j2i[1]);
-      float2 v = tile[lds_pad(i)];
-      if constexpr (F16) v = make_float2(v.x * scale, v.y * scale);
-      split16<F16>(v.x, h[u], h[8 + u]);
-      split16<F16>(v.y, h[4 + u], h[12 + u]);
+      const float2 v = tile[lds_pad(i)];
+      re[u] = v.x * scale;
+      im[u] = v.y * scale;
     }
     uint4 v0, v1;  // [rh, ih] and [rl, il] of the 4 k
-    v0.x = h[0] | ((uint32_t)h[1] << 16);
-    v0.y = h[2] | ((uint32_t)h[3] << 16);
-    v0.z = h[4] | ((uint32_t)h[5] << 16);
-    v0.w = h[6] | ((uint32_t)h[7] << 16);
-    v1.x = h[8] | ((uint32_t)h[9] << 16);
-    v1.y = h[10] | ((uint32_t)h[11] << 16);
-    v1.z = h[12] | ((uint32_t)h[13] << 16);
-    v1.w = h[14] | ((uint32_t)h[15] << 16);
+    split16x2<F16>(re[0], re[1], v0.x, v1.x);
+    split16x2<F16>(re[2], re[3], v0.y, v1.y);
+    split16x2<F16>(im[0], im[1], v0.z, v1.z);
+    split16x2<F16>(im[2], im[3], v0.w, v1.w);
     uint4* o = reinterpret_cast<uint4*>(out + 4 * e0);  // e0 is a multiple of 4
     o[0] = v0;
     o[1] = v1;
