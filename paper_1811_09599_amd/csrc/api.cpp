@@ -325,9 +325,9 @@ qflex_status qflex_gemm_split_c64(const void* A, const void* B, void* C, int64_t
     if (!ta) {
       g.Ac = static_cast<const float2*>(A);
       g.ga.nm = mb;
-      g.ga.nk = kb - 4;
+      g.ga.nk = kb - 2;
       for (int i = 0; i < mb; ++i) g.ga.mpos[i] = (int8_t)(kb + i);
-      for (int j = 0; j < kb - 4; ++j) g.ga.kpos[j] = (int8_t)(4 + j);
+      for (int j = 0; j < kb - 2; ++j) g.ga.kpos[j] = (int8_t)(2 + j);
     }
     g.A = sa;
     g.B = sb;

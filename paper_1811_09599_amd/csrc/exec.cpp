@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstring>
 #include <numeric>
+#include <set>
 
 #include "grid.h"
 
@@ -259,22 +260,18 @@ void prepare_split(qflex_grid* g, hipStream_t s) {
       const int64_t M = int64_t(1) << st.mb, N = int64_t(1) << st.nb, K = int64_t(1) << st.kb;
       if (!dev::gemm_split_ok(M, N, K)) continue;
       cs.split[i] = 1;
-      // The order of the contracted labels is this step's own choice: when the 4 lowest
-      // storage labels of an intermediate x are contracted ones, put them last, in storage
-      // order, and let the product read x straight from its complex64 storage (no
-      // permutation or split pass over x).
+      // The order of the contracted labels is this step's own choice.  For an intermediate
+      // x, order them as x stores them: when x's 2 lowest storage labels are contracted ones,
+      // every group of 4 consecutive k is then 32 contiguous bytes of x, and the product reads
+      // x straight from its complex64 storage (no permutation or split pass over x).
       std::vector<int> klab = st.klab;
       bool gather = false;
-      if (!st.x.qubit && st.kb >= 4 && st.x_in.size() >= 4) {
-        const std::vector<int> low(st.x_in.end() - 4, st.x_in.end());
-        std::vector<int> rest;
-        int found = 0;
-        for (int l : st.klab)
-          if (std::find(low.begin(), low.end(), l) != low.end()) ++found;
-          else rest.push_back(l);
-        if (found == 4) {
-          klab = rest;
-          klab.insert(klab.end(), low.begin(), low.end());
+      if (!st.x.qubit && st.kb >= 4 && st.x_in.size() >= 2) {
+        const std::set<int> K(st.klab.begin(), st.klab.end());
+        if (K.count(st.x_in.end()[-1]) && K.count(st.x_in.end()[-2])) {
+          klab.clear();
+          for (int l : st.x_in)
+            if (K.count(l)) klab.push_back(l);
           gather = true;
         }
       }
@@ -284,10 +281,10 @@ void prepare_split(qflex_grid* g, hipStream_t s) {
         const PermDesc pd = make_perm_desc(st.x_in, xa);
         dev::SplitGather& ga = cs.gx[i];
         ga.nm = st.mb;
-        ga.nk = st.kb - 4;
+        ga.nk = st.kb - 2;
         bool ok = st.mb + st.kb <= dev::kGatherMaxBits;
-        for (int j = 0; j < 4 && ok; ++j) ok = pd.perm[j] == j;
-        for (int j = 0; ok && j < ga.nk; ++j) ga.kpos[j] = (int8_t)pd.perm[4 + j];
+        for (int j = 0; j < 2 && ok; ++j) ok = pd.perm[j] == j;
+        for (int j = 0; ok && j < ga.nk; ++j) ga.kpos[j] = (int8_t)pd.perm[2 + j];
         for (int j = 0; ok && j < ga.nm; ++j) ga.mpos[j] = (int8_t)pd.perm[st.kb + j];
         cs.gather_x[i] = ok;
       }

@@ -33,8 +33,8 @@ __device__ inline floatx16 mfma16(f16x8 a, f16x8 b, floatx16 c) {
 }
 
 // GA: A comes from complex64 storage through the gather descriptor (one permutation and one
-// split pass over A fewer): each thread loads whole groups of 4 consecutive k (32 bytes) of
-// two rows, and splits them into the compact layout while storing the tile to LDS.
+// split pass over A fewer): each thread loads whole groups of 4 consecutive k (32 contiguous
+// bytes) of its rows, and splits them into the compact layout while storing the tile to LDS.
 template <int BM, int BN, int WM, int WN, bool F16, bool GA>
 __global__ void __launch_bounds__(64 * WM * WN) gemm_split_kernel(const GemmSplit g) {
   using V = typename std::conditional<F16, f16x8, bf16x8>::type;
@@ -63,7 +63,7 @@ __global__ void __launch_bounds__(64 * WM * WN) gemm_split_kernel(const GemmSpli
   // gathered A: AG groups of 4 k per thread per tile, rows fixed for the whole k loop
   constexpr int AG = BM * (BK / 4) / NT;
   f32x4 rc[GA ? AG : 1][2];
-  int64_t frow[GA ? AG : 1];
+  int64_t frow[GA ? AG : 1];  // row offset plus the offset of the thread's k group
   const float2* __restrict__ Ac =
       GA ? g.Ac + g.a_add + (g.a_off ? g.a_off[b] : b * g.a_bs) : nullptr;
   float ascale = 1.f;
@@ -71,7 +71,8 @@ __global__ void __launch_bounds__(64 * WM * WN) gemm_split_kernel(const GemmSpli
 #pragma unroll
     for (int u = 0; u < AG; ++u) {
       const int64_t m = m0 + ((tid + u * NT) >> 2);
-      int64_t f = 0;
+      const int grp = (tid + u * NT) & 3;  // k bits 2 and 3 within the tile
+      int64_t f = (int64_t)(grp & 1) << g.ga.kpos[0] | (int64_t)(grp >> 1) << g.ga.kpos[1];
       for (int i = 0; i < g.ga.nm; ++i) f |= ((m >> i) & 1) << g.ga.mpos[i];
       frow[u] = f;
     }
@@ -80,11 +81,11 @@ __global__ void __launch_bounds__(64 * WM * WN) gemm_split_kernel(const GemmSpli
   auto gload = [&](int64_t k0) {  // k0 in 16-bit units along the row
     if constexpr (GA) {
       const int64_t kt = k0 / ROW;
-      int64_t gk = 0;
-      for (int j = 0; j < g.ga.nk; ++j) gk |= ((kt >> j) & 1) << g.ga.kpos[j];
+      int64_t gk = 0;  // k bits 4.. of the tile
+      for (int j = 2; j < g.ga.nk; ++j) gk |= ((kt >> (j - 2)) & 1) << g.ga.kpos[j];
 #pragma unroll
       for (int u = 0; u < AG; ++u) {
-        const float2* p = Ac + frow[u] + gk + 4 * ((tid + u * NT) & 3);
+        const float2* p = Ac + frow[u] + gk;
         rc[u][0] = *reinterpret_cast<const f32x4*>(p);
         rc[u][1] = *reinterpret_cast<const f32x4*>(p + 2);
       }
@@ -246,9 +247,9 @@ void gemm_split(const GemmSplit& g, hipStream_t s) {
   if ((g.a_amax == nullptr) != (g.b_amax == nullptr))
     throw std::runtime_error("gemm_split: both operands must use the same format");
   if (g.Ac) {
-    // the gathered k groups need the 4 lowest k bits in the 4 lowest storage bits
-    if (g.ga.nm + g.ga.nk + 4 > kGatherMaxBits || (int64_t(1) << g.ga.nm) != g.M ||
-        (int64_t(16) << g.ga.nk) != g.K)
+    // the gathered k groups need the 2 lowest k bits in the 2 lowest storage bits
+    if (g.ga.nm + g.ga.nk + 2 > kGatherMaxBits || g.ga.nk < 2 || (int64_t(1) << g.ga.nm) != g.M ||
+        (int64_t(4) << g.ga.nk) != g.K)
       throw std::runtime_error("gemm_split: gather descriptor does not match the shape");
     if (g.a_amax) gemm_split_t<true, true>(g, s);
     else gemm_split_t<false, true>(g, s);

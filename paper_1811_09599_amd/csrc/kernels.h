@@ -97,9 +97,10 @@ void split_permute(const float2* in, uint16_t* out, int64_t batch, const PermTil
 // tag than the calls before (tag >= 1; in must be 16-byte aligned).
 void absmax(const float2* in, int64_t n, uint64_t* slot, uint32_t tag, hipStream_t s);
 
-// Storage positions of the bits of a product operand's row index m and of k >> 4, for an
-// operand read straight from complex64 storage whose 4 lowest storage bits are k's 4 lowest
-// bits: element (m, k) sits at f(m) + (k & 15) + g(k >> 4).
+// Storage positions of the bits of a product operand's row index m and of k >> 2, for an
+// operand read straight from complex64 storage whose 2 lowest storage bits are k's 2 lowest
+// bits: element (m, k) sits at f(m) + (k & 3) + g(k >> 2), so every group of 4 consecutive k
+// is 32 contiguous bytes.
 constexpr int kGatherMaxBits = 40;
 struct SplitGather {
   int32_t nm = 0, nk = 0;
