@@ -38,6 +38,7 @@ void release(qflex_grid* g) {
   if (g->grid_split) (void)hipFree(g->grid_split);
   if (g->amax) (void)hipFree(g->amax);
   g->split_scratch.release();
+  g->split_cache.release();
   for (qflex::DevBuf* b : {&g->gq, &g->gpieces, &g->gmats, &g->gpos, &g->grad_arena, &g->tbar,
                            &g->pbar, &g->gbar, &g->amps_dev, &g->xeb, &g->splitk_ws})
     b->release();

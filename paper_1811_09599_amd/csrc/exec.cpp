@@ -252,6 +252,9 @@ void prepare_split(qflex_grid* g, hipStream_t s) {
     cs.sy.assign(ns, dev::PermTile{});
     cs.gather_x.assign(ns, 0);
     cs.gx.assign(ns, dev::SplitGather{});
+    cs.xcache_offset.assign(ns, -1);
+    cs.xcache_slot.assign(ns, -1);
+    cs.xcache_elems = 0;
     cs.qsplit_offset.assign(cs.model.n, -1);
     cs.qamax_slot.assign(cs.model.n, -1);
     cs.split_a_elems = cs.split_b_elems = 0;
@@ -266,7 +269,15 @@ void prepare_split(qflex_grid* g, hipStream_t s) {
       // x straight from its complex64 storage (no permutation or split pass over x).
       std::vector<int> klab = st.klab;
       bool gather = false;
-      if (!st.x.qubit && st.kb >= 4 && st.x_in.size() >= 2) {
+      // an intermediate x that outlives this step's slices (it depends on fewer cuts) is split
+      // once per recomputation into a cache instead of being gathered every time
+      const bool cached = !st.x.qubit && P.nodes[st.x.id].deps != st.deps;
+      if (cached) {
+        cs.xcache_offset[i] = cs.xcache_elems;
+        cs.xcache_elems += ((int64_t(4) << P.nodes[st.x.id].labels.size()) + 63) & ~int64_t(63);
+        if (f16) cs.xcache_slot[i] = n_slots++;
+      }
+      if (!cached && !st.x.qubit && st.kb >= 4 && st.x_in.size() >= 2) {
         const std::set<int> K(st.klab.begin(), st.klab.end());
         if (K.count(st.x_in.end()[-1]) && K.count(st.x_in.end()[-2])) {
           klab.clear();
@@ -301,6 +312,8 @@ void prepare_split(qflex_grid* g, hipStream_t s) {
           cs.qsplit_offset[o.id] = total;
           total += ((int64_t(4) << L.storage.size()) + 63) & ~int64_t(63);
           jobs.push_back(j);
+        } else if (side == 0 && cached) {
+          cs.sx[i] = dev::make_perm_tile(pd.nbits, pd.perm.data());
         } else if (!(side == 0 && cs.gather_x[i])) {
           (side ? cs.sy[i] : cs.sx[i]) = dev::make_perm_tile(pd.nbits, pd.perm.data());
           const int64_t e = int64_t(4) << P.nodes[o.id].labels.size();
@@ -470,6 +483,11 @@ void contract(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets, dou
                                           (size_t)(g->circ[c].split_a_elems +
                                                    g->circ[c].split_b_elems));
   if (split_need) g->split_scratch.reserve(split_need);
+  size_t cache_need = 0;
+  for (int c = 0; c < nc; ++c)
+    cache_need = std::max(cache_need, sizeof(uint16_t) * (size_t)batch[c] *
+                                          (size_t)g->circ[c].xcache_elems);
+  if (cache_need) g->split_cache.reserve(cache_need);
   g->amps64.reserve(sizeof(double2) * std::max<int64_t>(amp_total, 1));
   float2* arena = static_cast<float2*>(g->arena.p);
   double2* acc_all = static_cast<double2*>(g->amps64.p);
@@ -529,6 +547,24 @@ void contract(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets, dou
               gs.a_add = x.add;
               gs.a_off = x.off;
               if (f16) gs.a_amax = g->amax + cs.qamax_slot[stp.x.id];
+            } else if (cs.xcache_offset[k] >= 0) {
+              uint16_t* xc = static_cast<uint16_t*>(g->split_cache.p) + B * cs.xcache_offset[k];
+              if (f16) gs.a_amax = g->amax + cs.xcache_slot[k];
+              if (si == 0 || (P.nodes[stp.x.id].deps & changed)) {  // x was just recomputed
+                if (f16) {
+                  g->prof.begin("absmax", 0, 8.0 * M * K * nb, s);
+                  dev::absmax(x.base, M * K * nb, g->amax + cs.xcache_slot[k],
+                              next_amax_tag(g, s), s);
+                  g->prof.end(s);
+                }
+                g->prof.begin("split_permute", 0, 16.0 * M * K * nb, s);
+                dev::split_permute(x.base, xc, nb, cs.sx[k], stp.kb, gs.a_amax, s);
+                g->prof.end(s);
+                st.permute_bytes += 16.0 * M * K * nb;
+                ++st.n_permute;
+              }
+              gs.A = xc;
+              gs.a_bs = M * K;
             } else if (cs.gather_x[k]) {
               if (f16) {
                 gs.a_amax = g->amax;

@@ -30,6 +30,11 @@ struct CircuitState {
   std::vector<dev::PermTile> sx, sy; // per step: node operand -> split operand layout
   std::vector<char> gather_x;        // per step: x read from complex64 storage by the product
   std::vector<dev::SplitGather> gx;  // per step: its gather descriptor
+  // per step: x is an intermediate reused across slices, kept split in split_cache (offset in
+  // 16-bit values per bit-string, -1 if not) and re-split only when it is recomputed
+  std::vector<int64_t> xcache_offset;
+  std::vector<int64_t> xcache_slot;  // its fp16 scale slot
+  int64_t xcache_elems = 0;          // 16-bit values per bit-string
   std::vector<int64_t> qsplit_offset;// per qubit: offset in grid_split (16-bit values), -1 if none
   std::vector<int64_t> qamax_slot;   // per qubit: fp16 scale slot in amax, -1 if none
   int64_t split_a_elems = 0, split_b_elems = 0;  // scratch per bit-string (16-bit values)
@@ -98,6 +103,7 @@ struct qflex_grid {
   qflex::DevBuf grad_arena, tbar, pbar, gbar, amps_dev, xeb;
   qflex::DevBuf splitk_ws;               // partial products of split-K complex64 products
   qflex::DevBuf split_scratch;           // split operands of intermediates
+  qflex::DevBuf split_cache;             // split copies of intermediates reused across slices
   qflex::DevBuf arena;                   // intermediates
   qflex::DevBuf amps64;                  // FP64 amplitude accumulator
   qflex::DevBuf offs;                    // per-bit-string output offsets of the qubit tensors
