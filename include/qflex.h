@@ -110,7 +110,15 @@ typedef struct {
   const int32_t* open_qubits;/* qubits whose output bit stays open (may be NULL) */
   int32_t n_open;            /* 0 .. 16; the same ids are used for every circuit */
   int32_t bitstring_batch;   /* most bit-strings contracted together (0 = automatic) */
+  int32_t slice_mode;        /* subset summed at fidelity f < 1 (Methods C.1), k = f * S:
+                                QFLEX_SLICES_RANDOM: k ids of a SplitMix64-driven Fisher-Yates
+                                shuffle of [0, S), sorted;
+                                QFLEX_SLICES_BLOCK: k must divide S; the k consecutive ids from
+                                a seeded multiple of k (the leading cuts fixed, the trailing
+                                ones all summed: intermediates reused across the block) */
 } qflex_options;
+
+typedef enum { QFLEX_SLICES_RANDOM = 0, QFLEX_SLICES_BLOCK = 1 } qflex_slice_mode;
 
 typedef struct qflex_grid qflex_grid;
 

@@ -68,10 +68,11 @@ int64_t qflex_gemm_split_workspace(int64_t M, int64_t N, int64_t K, int64_t batc
 int32_t qflex_gemm_variant(int64_t M, int64_t N, int64_t K);
 
 /* The slice subset that qflex_contract_amplitudes sums for a fidelity (host only): writes up to
- * max_ids ascending ids into ids and their count into *n.  QFLEX_E_INVALID if fidelity is
- * outside (0, 1], QFLEX_E_PLAN if fidelity*total is not an integer >= 1. */
-qflex_status qflex_select_slices(int64_t total, double fidelity, uint64_t seed, int64_t* ids,
-                                 int64_t max_ids, int64_t* n);
+ * max_ids ascending ids into ids and their count into *n.  mode: qflex_slice_mode.
+ * QFLEX_E_INVALID if fidelity is outside (0, 1] or mode is unknown, QFLEX_E_PLAN if
+ * fidelity*total is not an integer >= 1 (or, in block mode, does not divide total). */
+qflex_status qflex_select_slices(int64_t total, double fidelity, uint64_t seed, int32_t mode,
+                                 int64_t* ids, int64_t max_ids, int64_t* n);
 
 #ifdef __cplusplus
 }

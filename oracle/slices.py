@@ -7,6 +7,11 @@ subset from a seed: k = f * S must be an integer >= 1; shuffle [0, S) with Fishe
 (Steele, Lea and Flood, "Fast splittable pseudorandom number generators", OOPSLA 2014:
 state += 0x9E3779B97F4A7C15; z = state; z = (z ^ z>>30) * 0xBF58476D1CE4E5B9;
 z = (z ^ z>>27) * 0x94D049BB133111EB; return z ^ z>>31), keep the first k entries, sorted.
+
+Block mode (a reuse-friendly variant of the same fraction): k must divide S; the subset is
+the k consecutive ids [j k, (j + 1) k) with j = next() mod (S / k) from SplitMix64(seed).
+Slice ids are mixed radix over the cuts, first cut most significant, so with S and k powers
+of two a block fixes the leading cuts' values and runs over all values of the trailing ones.
 """
 from __future__ import annotations
 
@@ -41,3 +46,11 @@ def select(total: int, fidelity: float, seed: int) -> list[int]:
         j = g.next() % (i + 1)
         a[i], a[j] = a[j], a[i]
     return sorted(a[:k])
+
+
+def select_block(total: int, fidelity: float, seed: int) -> list[int]:
+    k = count_for_fidelity(total, fidelity)
+    if total % k:
+        raise ValueError("block slice subsets need fidelity * slices to divide the slices")
+    j = SplitMix64(seed).next() % (total // k)
+    return list(range(j * k, (j + 1) * k))

@@ -12,6 +12,7 @@ STATUS_NAMES = {0: "QFLEX_OK", 1: "QFLEX_E_INVALID", 2: "QFLEX_E_PLAN", 3: "QFLE
                 4: "QFLEX_E_DEVICE", 5: "QFLEX_E_UNSUPPORTED"}
 PREC = {"c64": 0, "split_bf16": 1, "split_fp16": 2}
 PLAN = {"auto": 0, "sweep": 1, "quadrant": 2, "cut_sweep": 3}
+SLICES = {"random": 0, "block": 1}
 KIND = {"h": 0, "x12": 1, "y12": 2, "t": 3, "cz": 4, "fsim": 5, "mat1": 6, "mat2": 7}
 
 
@@ -28,7 +29,8 @@ class Circuit(C.Structure):
 class Options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("plan_kind", C.c_int32),
                 ("max_tensor_elems", C.c_int64), ("open_qubits", C.POINTER(C.c_int32)),
-                ("n_open", C.c_int32), ("bitstring_batch", C.c_int32)]
+                ("n_open", C.c_int32), ("bitstring_batch", C.c_int32),
+                ("slice_mode", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -93,8 +95,8 @@ def lib():
     L.qflex_gemm_c64_workspace.restype = C.c_int64
     L.qflex_gemm_variant.argtypes = [C.c_int64, C.c_int64, C.c_int64]
     L.qflex_gemm_variant.restype = C.c_int32
-    L.qflex_select_slices.argtypes = [C.c_int64, C.c_double, C.c_uint64, C.POINTER(C.c_int64),
-                                      C.c_int64, C.POINTER(C.c_int64)]
+    L.qflex_select_slices.argtypes = [C.c_int64, C.c_double, C.c_uint64, C.c_int32,
+                                      C.POINTER(C.c_int64), C.c_int64, C.POINTER(C.c_int64)]
     L.qflex_grid_free.argtypes = [P]
     L.qflex_grid_free.restype = None
     L.qflex_last_error.restype = C.c_char_p

@@ -58,6 +58,8 @@ void check_options(const qflex_options& o) {
   if (o.plan_kind < QFLEX_PLAN_AUTO || o.plan_kind > QFLEX_PLAN_CUT_SWEEP)
     qflex::fail(QFLEX_E_INVALID, "unknown plan_kind");
   if (o.bitstring_batch < 0) qflex::fail(QFLEX_E_INVALID, "bitstring_batch < 0");
+  if (o.slice_mode != QFLEX_SLICES_RANDOM && o.slice_mode != QFLEX_SLICES_BLOCK)
+    qflex::fail(QFLEX_E_INVALID, "unknown slice_mode");
 }
 
 }  // namespace
@@ -75,6 +77,7 @@ qflex_status qflex_build_grid(const qflex_circuit* circuits, int32_t n_circuits,
     try {
       g->precision = opt->precision;
       g->bitstring_batch = opt->bitstring_batch;
+      g->slice_mode = opt->slice_mode;
       for (int c = 0; c < n_circuits; ++c) {
         qflex::CircuitState cs;
         cs.model = qflex::build_model(circuits[c]);
@@ -352,12 +355,12 @@ int32_t qflex_gemm_variant(int64_t M, int64_t N, int64_t K) {
   return qflex::dev::gemm_variant(g);
 }
 
-qflex_status qflex_select_slices(int64_t total, double fidelity, uint64_t seed, int64_t* ids,
-                                 int64_t max_ids, int64_t* n) {
+qflex_status qflex_select_slices(int64_t total, double fidelity, uint64_t seed, int32_t mode,
+                                 int64_t* ids, int64_t max_ids, int64_t* n) {
   return guarded([&] {
     if (!n || (max_ids > 0 && !ids)) qflex::fail(QFLEX_E_INVALID, "NULL argument");
     if (total < 1 || total > (int64_t(1) << 32)) qflex::fail(QFLEX_E_INVALID, "total out of range");
-    const auto v = qflex::select_slices(total, fidelity, seed);
+    const auto v = qflex::select_slices(total, fidelity, seed, mode);
     *n = (int64_t)v.size();
     for (int64_t i = 0; i < (int64_t)v.size() && i < max_ids; ++i) ids[i] = v[i];
   });

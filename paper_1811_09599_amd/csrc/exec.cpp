@@ -344,14 +344,14 @@ void prepare_split(qflex_grid* g, hipStream_t s) {
 }
 
 // ------------------------------------------------------------------------------ slices
-std::vector<int64_t> select_slices(int64_t total, double fidelity, uint64_t seed) {
+std::vector<int64_t> select_slices(int64_t total, double fidelity, uint64_t seed, int mode) {
   if (!(fidelity > 0.0 && fidelity <= 1.0)) fail(QFLEX_E_INVALID, "fidelity must be in (0, 1]");
+  if (mode != QFLEX_SLICES_RANDOM && mode != QFLEX_SLICES_BLOCK)
+    fail(QFLEX_E_INVALID, "unknown slice_mode");
   const double k = fidelity * (double)total;
   const double kr = std::round(k);
   if (std::fabs(k - kr) > 1e-9 * std::max(1.0, k) || kr < 1)
     fail(QFLEX_E_PLAN, "fidelity * slices must be an integer >= 1");
-  std::vector<int64_t> a(total);
-  std::iota(a.begin(), a.end(), 0);
   uint64_t state = seed;
   auto next = [&]() {  // SplitMix64
     state += 0x9E3779B97F4A7C15ull;
@@ -360,6 +360,16 @@ std::vector<int64_t> select_slices(int64_t total, double fidelity, uint64_t seed
     z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
     return z ^ (z >> 31);
   };
+  if (mode == QFLEX_SLICES_BLOCK) {  // k consecutive ids from a seeded multiple of k
+    const int64_t kk = (int64_t)kr;
+    if (total % kk) fail(QFLEX_E_PLAN, "block slice subsets need fidelity * slices to divide them");
+    const int64_t j = (int64_t)(next() % (uint64_t)(total / kk));
+    std::vector<int64_t> b(kk);
+    std::iota(b.begin(), b.end(), j * kk);
+    return b;
+  }
+  std::vector<int64_t> a(total);
+  std::iota(a.begin(), a.end(), 0);
   for (int64_t i = total - 1; i > 0; --i) {
     const int64_t j = (int64_t)(next() % (uint64_t)(i + 1));
     std::swap(a[i], a[j]);
@@ -411,7 +421,7 @@ std::vector<std::vector<int64_t>> prepare_call(qflex_grid* g, const uint8_t* bit
         if (i && sel[c][i] == sel[c][i - 1]) fail(QFLEX_E_INVALID, "slice id repeated");
       }
     } else {
-      sel[c] = select_slices(S, fidelity, seed);
+      sel[c] = select_slices(S, fidelity, seed, g->slice_mode);
     }
   }
   QHIP(hipGetLastError());

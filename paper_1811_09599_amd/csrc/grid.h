@@ -85,6 +85,7 @@ struct qflex_grid {
   int device = 0;
   int precision = QFLEX_PREC_C64;
   int bitstring_batch = 0;
+  int slice_mode = QFLEX_SLICES_RANDOM;
   std::vector<qflex::CircuitState> circ;
   float2* grid = nullptr;                // all qubit tensors
   int64_t grid_elems = 0;
@@ -125,7 +126,7 @@ std::vector<std::vector<int64_t>> prepare_call(qflex_grid* g, const uint8_t* bit
 void contract(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets, double fidelity,
               uint64_t seed, const int64_t* slice_ids, const int64_t* slice_offsets,
               double* amps, bool amps_on_device, hipStream_t s);
-std::vector<int64_t> select_slices(int64_t total, double fidelity, uint64_t seed);
+std::vector<int64_t> select_slices(int64_t total, double fidelity, uint64_t seed, int mode);
 void contract_grad(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets,
                    double fidelity, uint64_t seed, const int64_t* slice_ids,
                    const int64_t* slice_offsets, const double* cot, int32_t cot_on_device,

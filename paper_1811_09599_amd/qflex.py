@@ -45,7 +45,7 @@ class _CircuitPack:
 
 
 def _options(precision="c64", plan="auto", max_tensor_elems=0, open_qubits=(),
-             bitstring_batch=0):
+             bitstring_batch=0, slice_mode="random"):
     o = F.Options()
     o.precision = F.PREC[precision]
     o.plan_kind = F.PLAN[plan]
@@ -54,6 +54,7 @@ def _options(precision="c64", plan="auto", max_tensor_elems=0, open_qubits=(),
     o.open_qubits = C.cast(op, C.POINTER(C.c_int32))
     o.n_open = len(open_qubits)
     o.bitstring_batch = int(bitstring_batch)
+    o.slice_mode = F.SLICES[slice_mode]
     return o, op
 
 
@@ -85,7 +86,7 @@ class Grid:
     """qflex_grid handle (device-resident time-collapsed tensors of a batch of circuits)."""
 
     def __init__(self, circuits, precision="c64", plan="auto", max_tensor_elems=0,
-                 open_qubits=(), bitstring_batch=0, stream=None):
+                 open_qubits=(), bitstring_batch=0, slice_mode="random", stream=None):
         L = F.lib()
         if isinstance(circuits, dict):
             circuits = [circuits]
@@ -93,7 +94,8 @@ class Grid:
         self.n_open = len(open_qubits)
         self.open_qubits = list(open_qubits)
         pack = _CircuitPack(self.circuits)
-        o, keep = _options(precision, plan, max_tensor_elems, open_qubits, bitstring_batch)
+        o, keep = _options(precision, plan, max_tensor_elems, open_qubits, bitstring_batch,
+                           slice_mode)
         h = C.c_void_p()
         F.check(L.qflex_build_grid(pack.arr, len(self.circuits), C.byref(o), _stream(stream),
                                    C.byref(h)))

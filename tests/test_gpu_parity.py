@@ -106,16 +106,17 @@ def test_quadrant_single_slices_match_oracle_paths():
         _check(a, ref, 20)
 
 
-def test_low_fidelity_subset_matches_oracle_subset():
+@pytest.mark.parametrize("mode", ["random", "block"])
+def test_low_fidelity_subset_matches_oracle_subset(mode):
     _need_gpu()
-    _say("fidelity 1/4 on 4x4 depth 24")
+    _say("fidelity 1/4 on 4x4 depth 24,", mode)
     c = R.grid_rqc(4, 4, 24, 55)
     bits = R.bitstrings(16, 6, 2)
-    g = build_grid(c, plan="quadrant")
+    g = build_grid(c, plan="quadrant", slice_mode=mode)
     S = g.num_slices()
     f, seed = 0.25, 2700
     a = g.contract_amplitudes(bits, fidelity=f, seed=seed).cpu().numpy()[:, 0]
-    ids = OS.select(S, f, seed)
+    ids = OS.select(S, f, seed) if mode == "random" else OS.select_block(S, f, seed)
     assert g.last_stats()["n_slices"] == len(ids)
     ref = E2.amplitudes(c, bits, cuts=g.plan_cuts(), slice_ids=ids)
     _check(a, ref, 16)

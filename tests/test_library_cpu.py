@@ -142,7 +142,7 @@ def test_slice_subset_matches_oracle(total, f, seed):
     k = int(round(total * f))
     ids = (C.c_int64 * k)()
     n = C.c_int64()
-    F.check(L.qflex_select_slices(total, f, seed, ids, k, C.byref(n)))
+    F.check(L.qflex_select_slices(total, f, seed, 0, ids, k, C.byref(n)))
     assert n.value == k
     assert list(ids) == OS.select(total, f, seed)
 
@@ -150,9 +150,27 @@ def test_slice_subset_matches_oracle(total, f, seed):
 def test_slice_subset_rejects_bad_fidelity():
     L = F.lib()
     n = C.c_int64()
-    assert L.qflex_select_slices(10, 0.25, 1, None, 0, C.byref(n)) == F.E_PLAN
-    assert L.qflex_select_slices(10, 0.0, 1, None, 0, C.byref(n)) == F.E_INVALID
-    assert L.qflex_select_slices(10, 1.5, 1, None, 0, C.byref(n)) == F.E_INVALID
+    assert L.qflex_select_slices(10, 0.25, 1, 0, None, 0, C.byref(n)) == F.E_PLAN
+    assert L.qflex_select_slices(10, 0.0, 1, 0, None, 0, C.byref(n)) == F.E_INVALID
+    assert L.qflex_select_slices(10, 1.5, 1, 0, None, 0, C.byref(n)) == F.E_INVALID
+    assert L.qflex_select_slices(10, 0.5, 1, 2, None, 0, C.byref(n)) == F.E_INVALID  # mode
+    assert L.qflex_select_slices(12, 0.25, 1, 1, None, 0, C.byref(n)) == F.OK
+    assert L.qflex_select_slices(12, 5 / 12, 1, 1, None, 0, C.byref(n)) == F.E_PLAN  # 5 !| 12
+
+
+@pytest.mark.parametrize("total,f,seed", [(1024, 1 / 64, 2700), (256, 1.0, 1), (96, 0.25, 7),
+                                          (4096, 1 / 256, 4700), (256, 1 / 16, 11)])
+def test_block_slice_subset_matches_oracle(total, f, seed):
+    """Block mode: k consecutive ids from a seeded multiple of k (both sides from SplitMix64)."""
+    L = F.lib()
+    k = int(round(total * f))
+    ids = (C.c_int64 * k)()
+    n = C.c_int64()
+    F.check(L.qflex_select_slices(total, f, seed, 1, ids, k, C.byref(n)))
+    assert n.value == k
+    got = list(ids)
+    assert got == OS.select_block(total, f, seed)
+    assert got == list(range(got[0], got[0] + k)) and got[0] % k == 0
 
 
 def test_gemm_variant_choice():

@@ -293,6 +293,19 @@ def test_splitmix64_reference_outputs():
     assert [g.next() for _ in range(5)] == want
 
 
+def test_block_slice_selection_uses_the_first_splitmix64_output():
+    """Block mode: the block index is the first SplitMix64 output (pinned by the published
+    reference values) modulo the number of blocks; the block is k aligned consecutive ids."""
+    first = int([l for l in open(os.path.join(GOLD, "splitmix64_seed1234567.txt"))
+                 if l.strip() and not l.startswith("#")][0])
+    for total, f in ((1024, 1 / 64), (256, 1 / 4), (96, 0.25), (8, 1.0)):
+        k = int(round(total * f))
+        j = first % (total // k)
+        assert slices.select_block(total, f, 1234567) == list(range(j * k, (j + 1) * k))
+    with pytest.raises(ValueError):
+        slices.select_block(12, 5 / 12, 1)
+
+
 def test_slice_selection_properties():
     s = slices.select(1024, 1 / 64, 700)
     assert len(s) == 16 and s == sorted(s) and len(set(s)) == 16 and 0 <= s[0] and s[-1] < 1024
