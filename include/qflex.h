@@ -116,6 +116,9 @@ typedef struct {
                                 QFLEX_SLICES_BLOCK: k must divide S; the k consecutive ids from
                                 a seeded multiple of k (the leading cuts fixed, the trailing
                                 ones all summed: intermediates reused across the block) */
+  int32_t graph;             /* 1: qflex_contract_amplitudes captures its launches in one HIP
+                                graph and replays it for later calls with the same shapes and
+                                slices (bit-strings may differ); 0: launches every call */
 } qflex_options;
 
 typedef enum { QFLEX_SLICES_RANDOM = 0, QFLEX_SLICES_BLOCK = 1 } qflex_slice_mode;

@@ -37,6 +37,10 @@ void release(qflex_grid* g) {
   if (g->bidx) (void)hipFree(g->bidx);
   if (g->grid_split) (void)hipFree(g->grid_split);
   if (g->amax) (void)hipFree(g->amax);
+  if (g->graph_exec) (void)hipGraphExecDestroy(g->graph_exec);
+  if (g->graph_in) (void)hipEventDestroy(g->graph_in);
+  if (g->graph_out) (void)hipEventDestroy(g->graph_out);
+  if (g->graph_stream) (void)hipStreamDestroy(g->graph_stream);
   g->split_scratch.release();
   g->split_cache.release();
   for (qflex::DevBuf* b : {&g->gq, &g->gpieces, &g->gmats, &g->gpos, &g->grad_arena, &g->tbar,
@@ -60,6 +64,7 @@ void check_options(const qflex_options& o) {
   if (o.bitstring_batch < 0) qflex::fail(QFLEX_E_INVALID, "bitstring_batch < 0");
   if (o.slice_mode != QFLEX_SLICES_RANDOM && o.slice_mode != QFLEX_SLICES_BLOCK)
     qflex::fail(QFLEX_E_INVALID, "unknown slice_mode");
+  if (o.graph != 0 && o.graph != 1) qflex::fail(QFLEX_E_INVALID, "graph must be 0 or 1");
 }
 
 }  // namespace
@@ -78,6 +83,7 @@ qflex_status qflex_build_grid(const qflex_circuit* circuits, int32_t n_circuits,
       g->precision = opt->precision;
       g->bitstring_batch = opt->bitstring_batch;
       g->slice_mode = opt->slice_mode;
+      g->graph_mode = opt->graph != 0;
       for (int c = 0; c < n_circuits; ++c) {
         qflex::CircuitState cs;
         cs.model = qflex::build_model(circuits[c]);

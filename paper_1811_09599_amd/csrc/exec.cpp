@@ -453,7 +453,8 @@ std::vector<std::vector<int64_t>> prepare_call(qflex_grid* g, const uint8_t* bit
 
 void contract(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets, double fidelity,
               uint64_t seed, const int64_t* slice_ids, const int64_t* slice_offsets,
-              double* amps, bool amps_on_device, hipStream_t s) {
+              double* amps, bool amps_on_device, hipStream_t s_user) {
+  hipStream_t s = s_user;
   const int nc = (int)g->circ.size();
   const std::vector<std::vector<int64_t>> sel =
       prepare_call(g, bits, bs_offsets, fidelity, seed, slice_ids, slice_offsets, amps, s);
@@ -501,6 +502,78 @@ void contract(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets, dou
   g->amps64.reserve(sizeof(double2) * std::max<int64_t>(amp_total, 1));
   float2* arena = static_cast<float2*>(g->arena.p);
   double2* acc_all = static_cast<double2*>(g->amps64.p);
+  // ---- graph mode: every launch below depends only on the call's shape (bit-strings per
+  // circuit, their batching, the slices) and on buffer addresses, so an identical call replays
+  // the graph captured the first time; the bit-strings themselves travel in g->offs
+  std::string key;
+  bool capturing = false;
+  const bool prof_was_on = g->prof.on;
+  if (g->graph_mode) {
+    // the launches go to the grid's own stream, ordered after the caller's earlier work
+    if (!g->graph_stream) {
+      QHIP(hipStreamCreateWithFlags(&g->graph_stream, hipStreamNonBlocking));
+      QHIP(hipEventCreateWithFlags(&g->graph_in, hipEventDisableTiming));
+      QHIP(hipEventCreateWithFlags(&g->graph_out, hipEventDisableTiming));
+    }
+    QHIP(hipEventRecord(g->graph_in, s_user));
+    QHIP(hipStreamWaitEvent(g->graph_stream, g->graph_in, 0));
+    s = g->graph_stream;
+    key.reserve(256);
+    for (const void* p : {g->arena.p, g->split_scratch.p, g->split_cache.p, g->amps64.p,
+                          g->offs.p, g->splitk_ws.p})
+      key += std::to_string(reinterpret_cast<uintptr_t>(p)) + ",";
+    for (int c = 0; c < nc; ++c) {
+      key += "|" + std::to_string(bs_offsets[c + 1] - bs_offsets[c]) + ":" +
+             std::to_string(batch[c]) + ":";
+      for (int64_t id : sel[c]) key += std::to_string(id) + ",";
+    }
+    if (g->graph_exec && key == g->graph_key) {
+      QHIP(hipGraphLaunch(g->graph_exec, s));
+      st = g->graph_stats;
+    } else {
+      if (g->graph_exec) {
+        QHIP(hipGraphExecDestroy(g->graph_exec));
+        g->graph_exec = nullptr;
+        g->graph_key.clear();
+      }
+      g->prof.on = false;  // no event records inside a graph
+      QHIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+      capturing = true;
+    }
+  }
+  auto end_capture = [&](bool launch) {
+    hipGraph_t gr = nullptr;
+    const hipError_t e = hipStreamEndCapture(s, &gr);
+    capturing = false;
+    g->prof.on = prof_was_on;
+    if (e != hipSuccess || !gr) {
+      if (gr) (void)hipGraphDestroy(gr);
+      if (launch) fail(QFLEX_E_DEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+      return;
+    }
+    if (!launch) {
+      (void)hipGraphDestroy(gr);
+      return;
+    }
+    hipGraphExec_t ex = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(gr);
+    if (ei != hipSuccess) fail(QFLEX_E_DEVICE, std::string("graph instantiate: ") + hipGetErrorString(ei));
+    g->graph_exec = ex;
+    g->graph_key = key;
+    QHIP(hipGraphLaunch(ex, s));
+  };
+  const bool replayed = g->graph_mode && !capturing;
+  try {
+  if (!replayed) {
+  if (g->graph_mode && g->amax) {
+    // fp16 scale slots rewritten by every call start from zero in each replay (the tags of
+    // their atomic maxima are fixed in the graph)
+    dev::fill_zero(reinterpret_cast<double*>(g->amax), 2, s);
+    for (const CircuitState& cs : g->circ)
+      for (int64_t sl : cs.xcache_slot)
+        if (sl >= 0) dev::fill_zero(reinterpret_cast<double*>(g->amax + sl), 1, s);
+  }
   dev::fill_zero(reinterpret_cast<double*>(acc_all), 2 * amp_total, s);
   for (int c = 0; c < nc; ++c) {
     CircuitState& cs = g->circ[c];
@@ -693,6 +766,20 @@ void contract(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets, dou
     }
     st.n_slices += (int64_t)slices.size();
     st.n_bitstrings += nbs;
+  }
+  }  // !replayed
+  if (capturing) {
+    g->graph_stats = st;
+    end_capture(true);
+  }
+  } catch (...) {
+    if (capturing) end_capture(false);
+    throw;
+  }
+  if (g->graph_mode) {  // the caller's later work waits for the graph
+    QHIP(hipEventRecord(g->graph_out, s));
+    QHIP(hipStreamWaitEvent(s_user, g->graph_out, 0));
+    s = s_user;
   }
   if (amp_total > 0) {
     QHIP(hipMemcpyAsync(amps, acc_all, sizeof(double2) * amp_total,

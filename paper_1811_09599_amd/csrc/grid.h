@@ -86,6 +86,13 @@ struct qflex_grid {
   int precision = QFLEX_PREC_C64;
   int bitstring_batch = 0;
   int slice_mode = QFLEX_SLICES_RANDOM;
+  // graph mode: the captured launches of the last call and the call shape they belong to
+  bool graph_mode = false;
+  hipGraphExec_t graph_exec = nullptr;
+  hipStream_t graph_stream = nullptr;    // captures and replays (the null stream cannot capture)
+  hipEvent_t graph_in = nullptr, graph_out = nullptr;
+  std::string graph_key;
+  qflex_stats graph_stats{};
   std::vector<qflex::CircuitState> circ;
   float2* grid = nullptr;                // all qubit tensors
   int64_t grid_elems = 0;

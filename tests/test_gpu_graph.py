@@ -1,0 +1,64 @@
+"""GPU: graph mode (qflex_options.graph = 1).  A contract call captures its launches in a HIP
+graph and later calls with the same shape replay it; every replay must equal the eager
+launches bit for bit, with unrelated eager GPU work and synchronisations between replays."""
+import numpy as np
+import pytest
+
+import rqc_inputs as R
+from oracle import statevector as E1
+from oracle import metrics
+from paper_1811_09599_amd import build_grid
+
+pytestmark = pytest.mark.gpu
+
+
+def _need_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+@pytest.mark.parametrize("precision", ["c64", "split_bf16", "split_fp16"])
+def test_graph_replays_equal_eager_launches(precision):
+    _need_gpu()
+    import torch
+    _say("graph replay,", precision)
+    c = R.grid_rqc(5, 4, 24, 5151)
+    op = [19, 18, 15]
+    g_eager = build_grid(c, plan="quadrant", open_qubits=op, precision=precision)
+    g_graph = build_grid(c, plan="quadrant", open_qubits=op, precision=precision, graph=True)
+    x = torch.randn(512, 512, device="cuda")
+    shapes = [4, 4, 4, 6, 4, 4]  # a new shape re-captures; returning to 4 re-captures again
+    for i, nb in enumerate(shapes):
+        bits = R.bitstrings(20, nb, 600 + i, op)
+        want = g_eager.contract_amplitudes(bits, fidelity=0.5, seed=31).cpu().numpy()
+        got = g_graph.contract_amplitudes(bits, fidelity=0.5, seed=31).cpu().numpy()
+        assert np.array_equal(got, want), (i, nb)
+        assert g_graph.last_stats()["flops"] == g_eager.last_stats()["flops"]
+        y = x @ x  # unrelated eager work between replays
+        torch.cuda.synchronize()
+        assert torch.isfinite(y).all()
+    # and the replayed amplitudes are right
+    bits = R.bitstrings(20, 4, 700, op)
+    a = g_graph.contract_amplitudes(bits).cpu().numpy()
+    tol = {"c64": 1e-5, "split_bf16": 2e-4, "split_fp16": 4e-5}[precision]
+    assert metrics.amp_errors(a, E1.amplitudes(c, bits, op), 20)["max"] < tol
+    g_eager.close()
+    g_graph.close()
+
+
+def test_graph_mode_with_many_circuits():
+    _need_gpu()
+    _say("graph replay, 12 uneven fSim circuits")
+    cs = R.fsim_batch(12, depth=12, sizes=(3, 4), seed=9100, jitter_seed0=9200)
+    ge = build_grid(cs)
+    gg = build_grid(cs, graph=True)
+    for rep in range(3):
+        bits = [R.bitstrings(c["n_qubits"], 16, 9300 + 31 * rep + i) for i, c in enumerate(cs)]
+        want = ge.contract_amplitudes(bits).cpu().numpy()
+        got = gg.contract_amplitudes(bits).cpu().numpy()
+        assert np.array_equal(got, want), rep

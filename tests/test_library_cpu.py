@@ -88,6 +88,19 @@ def test_invalid_options_rejected():
     assert _status_describe(big, open_qubits=list(range(17)))[0] == F.E_INVALID
 
 
+def test_invalid_mode_fields_rejected():
+    """slice_mode and graph are checked with the other options, before any device work."""
+    c = R.grid_rqc(3, 3, 8, 1)
+    L = F.lib()
+    pack = _CircuitPack([c])
+    for field, bad in (("slice_mode", 2), ("slice_mode", -1), ("graph", 2)):
+        o, keep = _options()
+        setattr(o, field, bad)
+        h = C.c_void_p()
+        assert L.qflex_build_grid(pack.arr, 1, C.byref(o), None, C.byref(h)) == F.E_INVALID, field
+        assert not h.value
+
+
 def test_plan_that_cannot_fit_is_reported():
     c = R.grid_rqc(4, 4, 16, 1)
     st, msg = _status_describe(c, plan="sweep", max_tensor_elems=64)
