@@ -119,6 +119,11 @@ typedef struct {
   int32_t graph;             /* 1: qflex_contract_amplitudes captures its launches in one HIP
                                 graph and replays it for later calls with the same shapes and
                                 slices (bit-strings may differ); 0: launches every call */
+  int32_t autotune;          /* 1: the first call that runs a contraction step times every
+                                kernel variant that fits it (product tiles, kernel family, and
+                                for split products gathered vs permuted row operands) on that
+                                call's operands and keeps the fastest for the grid's lifetime;
+                                results do not depend on the choice beyond rounding order */
 } qflex_options;
 
 typedef enum { QFLEX_SLICES_RANDOM = 0, QFLEX_SLICES_BLOCK = 1 } qflex_slice_mode;

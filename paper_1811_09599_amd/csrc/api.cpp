@@ -39,6 +39,8 @@ void release(qflex_grid* g) {
   if (g->amax) (void)hipFree(g->amax);
   if (g->graph_exec) (void)hipGraphExecDestroy(g->graph_exec);
   if (g->graph_in) (void)hipEventDestroy(g->graph_in);
+  for (hipEvent_t e : g->tune_ev)
+    if (e) (void)hipEventDestroy(e);
   if (g->graph_out) (void)hipEventDestroy(g->graph_out);
   if (g->graph_stream) (void)hipStreamDestroy(g->graph_stream);
   g->split_scratch.release();
@@ -65,6 +67,7 @@ void check_options(const qflex_options& o) {
   if (o.slice_mode != QFLEX_SLICES_RANDOM && o.slice_mode != QFLEX_SLICES_BLOCK)
     qflex::fail(QFLEX_E_INVALID, "unknown slice_mode");
   if (o.graph != 0 && o.graph != 1) qflex::fail(QFLEX_E_INVALID, "graph must be 0 or 1");
+  if (o.autotune != 0 && o.autotune != 1) qflex::fail(QFLEX_E_INVALID, "autotune must be 0 or 1");
 }
 
 }  // namespace
@@ -84,6 +87,7 @@ qflex_status qflex_build_grid(const qflex_circuit* circuits, int32_t n_circuits,
       g->bitstring_batch = opt->bitstring_batch;
       g->slice_mode = opt->slice_mode;
       g->graph_mode = opt->graph != 0;
+      g->autotune = opt->autotune != 0;
       for (int c = 0; c < n_circuits; ++c) {
         qflex::CircuitState cs;
         cs.model = qflex::build_model(circuits[c]);

@@ -102,6 +102,7 @@ void Profiler::release() {
 void prepare_split(qflex_grid* g, hipStream_t s);
 
 void build_grid_device(qflex_grid* g, hipStream_t s) {
+  for (CircuitState& cs : g->circ) cs.tuned.assign(cs.plan.steps.size(), -1);
   std::vector<dev::GridPiece> pieces;
   std::vector<double2> mats;
   std::vector<int32_t> pos;
@@ -314,7 +315,7 @@ void prepare_split(qflex_grid* g, hipStream_t s) {
           jobs.push_back(j);
         } else if (side == 0 && cached) {
           cs.sx[i] = dev::make_perm_tile(pd.nbits, pd.perm.data());
-        } else if (!(side == 0 && cs.gather_x[i])) {
+        } else {  // also for a gathered x: the autotuner may prefer permuting it
           (side ? cs.sy[i] : cs.sx[i]) = dev::make_perm_tile(pd.nbits, pd.perm.data());
           const int64_t e = int64_t(4) << P.nodes[o.id].labels.size();
           if (side) cs.split_b_elems = std::max(cs.split_b_elems, e);
@@ -502,6 +503,28 @@ void contract(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets, dou
   g->amps64.reserve(sizeof(double2) * std::max<int64_t>(amp_total, 1));
   float2* arena = static_cast<float2*>(g->arena.p);
   double2* acc_all = static_cast<double2*>(g->amps64.p);
+  // ---- autotuning: the wall time of one run of `launch` (after one warm-up run), profiling off
+  auto time_launches = [&](auto&& launch) -> float {
+    if (!g->tune_ev[0]) {
+      QHIP(hipEventCreate(&g->tune_ev[0]));
+      QHIP(hipEventCreate(&g->tune_ev[1]));
+    }
+    const bool on = g->prof.on;
+    g->prof.on = false;
+    launch();
+    QHIP(hipEventRecord(g->tune_ev[0], s));
+    launch();
+    QHIP(hipEventRecord(g->tune_ev[1], s));
+    QHIP(hipEventSynchronize(g->tune_ev[1]));
+    g->prof.on = on;
+    float ms = 0;
+    QHIP(hipEventElapsedTime(&ms, g->tune_ev[0], g->tune_ev[1]));
+    return ms;
+  };
+  bool tuning_pending = false;
+  if (g->autotune)
+    for (const CircuitState& cs : g->circ)
+      for (int v : cs.tuned) tuning_pending = tuning_pending || v < 0;
   // ---- graph mode: every launch below depends only on the call's shape (bit-strings per
   // circuit, their batching, the slices) and on buffer addresses, so an identical call replays
   // the graph captured the first time; the bit-strings themselves travel in g->offs
@@ -530,6 +553,8 @@ void contract(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets, dou
     if (g->graph_exec && key == g->graph_key) {
       QHIP(hipGraphLaunch(g->graph_exec, s));
       st = g->graph_stats;
+    } else if (tuning_pending) {
+      // autotuning synchronises: this call runs eagerly, a later identical one is captured
     } else {
       if (g->graph_exec) {
         QHIP(hipGraphExecDestroy(g->graph_exec));
@@ -563,7 +588,7 @@ void contract(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets, dou
     g->graph_key = key;
     QHIP(hipGraphLaunch(ex, s));
   };
-  const bool replayed = g->graph_mode && !capturing;
+  const bool replayed = g->graph_mode && !capturing && !tuning_pending;
   try {
   if (!replayed) {
   if (g->graph_mode && g->amax) {
@@ -618,12 +643,16 @@ void contract(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets, dou
           const Step& stp = P.steps[k];
           if (si > 0 && !(stp.deps & changed)) continue;
           View x = view(stp.x), y = view(stp.y);
-          if (!cs.split.empty() && cs.split[k]) {
+          const bool is_split = !cs.split.empty() && cs.split[k];
+          const int64_t M = int64_t(1) << stp.mb, N = int64_t(1) << stp.nb;
+          const int64_t K = int64_t(1) << stp.kb;
+          // one split product: gather = read x straight from complex64 storage (when the
+          // plan allows it), tile = output tile (-1: shape rule); `final` runs count in stats
+          auto run_split = [&](bool gather, int tile, bool final) {
             uint16_t* sa = static_cast<uint16_t*>(g->split_scratch.p);
             uint16_t* sb = sa + B * cs.split_a_elems;
             dev::GemmSplit gs;
-            const int64_t M = int64_t(1) << stp.mb, N = int64_t(1) << stp.nb;
-            const int64_t K = int64_t(1) << stp.kb;
+            gs.tile = tile;
             const bool f16 = g->amax != nullptr;
             if (stp.x.qubit) {
               gs.A = g->grid_split + cs.qsplit_offset[stp.x.id];
@@ -643,21 +672,10 @@ void contract(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets, dou
                 g->prof.begin("split_permute", 0, 16.0 * M * K * nb, s);
                 dev::split_permute(x.base, xc, nb, cs.sx[k], stp.kb, gs.a_amax, s);
                 g->prof.end(s);
-                st.permute_bytes += 16.0 * M * K * nb;
-                ++st.n_permute;
+                if (final) st.permute_bytes += 16.0 * M * K * nb, ++st.n_permute;
               }
               gs.A = xc;
               gs.a_bs = M * K;
-            } else if (cs.gather_x[k]) {
-              if (f16) {
-                gs.a_amax = g->amax;
-                g->prof.begin("absmax", 0, 8.0 * M * K * nb, s);
-                dev::absmax(x.base, M * K * nb, g->amax, next_amax_tag(g, s), s);
-                g->prof.end(s);
-              }
-              gs.Ac = x.base;
-              gs.a_bs = x.bs;
-              gs.ga = cs.gx[k];
             } else {
               if (f16) {
                 gs.a_amax = g->amax;
@@ -665,13 +683,18 @@ void contract(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets, dou
                 dev::absmax(x.base, M * K * nb, g->amax, next_amax_tag(g, s), s);
                 g->prof.end(s);
               }
-              g->prof.begin("split_permute", 0, 16.0 * M * K * nb, s);
-              dev::split_permute(x.base, sa, nb, cs.sx[k], stp.kb, gs.a_amax, s);
-              g->prof.end(s);
-              st.permute_bytes += 16.0 * M * K * nb;
-              ++st.n_permute;
-              gs.A = sa;
-              gs.a_bs = M * K;
+              if (gather) {
+                gs.Ac = x.base;
+                gs.a_bs = x.bs;
+                gs.ga = cs.gx[k];
+              } else {
+                g->prof.begin("split_permute", 0, 16.0 * M * K * nb, s);
+                dev::split_permute(x.base, sa, nb, cs.sx[k], stp.kb, gs.a_amax, s);
+                g->prof.end(s);
+                if (final) st.permute_bytes += 16.0 * M * K * nb, ++st.n_permute;
+                gs.A = sa;
+                gs.a_bs = M * K;
+              }
             }
             if (stp.y.qubit) {
               gs.B = g->grid_split + cs.qsplit_offset[stp.y.id];
@@ -688,8 +711,7 @@ void contract(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets, dou
               g->prof.begin("split_permute", 0, 16.0 * N * K * nb, s);
               dev::split_permute(y.base, sb, nb, cs.sy[k], stp.kb, gs.b_amax, s);
               g->prof.end(s);
-              st.permute_bytes += 16.0 * N * K * nb;
-              ++st.n_permute;
+              if (final) st.permute_bytes += 16.0 * N * K * nb, ++st.n_permute;
               gs.B = sb;
               gs.b_bs = N * K;
             }
@@ -705,8 +727,26 @@ void contract(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets, dou
                           8.0 * nb * (double)(M * K + N * K + M * N), s);
             dev::gemm_split(gs, s);
             g->prof.end(s);
-            st.flops += stp.flops() * nb;
-            ++st.n_gemm;
+            if (final) st.flops += stp.flops() * nb, ++st.n_gemm;
+          };
+          if (is_split) {
+            int choice = cs.tuned[k];
+            if (choice < 0 && g->autotune) {
+              // time every fitting (tile, gather) pair once on this call's operands
+              dev::GemmSplit shape;
+              shape.M = M;
+              shape.N = N;
+              float best = 0;
+              for (int gth = 0; gth < (cs.gather_x[k] ? 2 : 1); ++gth)
+                for (int t = 0; t < 3; ++t) {
+                  if (!dev::gemm_split_tile_fits(shape, t)) continue;
+                  const float ms = time_launches([&] { run_split(gth == 1, t, false); });
+                  if (choice < 0 || ms < best) choice = 2 * t + gth, best = ms;
+                }
+              cs.tuned[k] = choice;
+            }
+            if (choice >= 0) run_split(choice & 1, choice >> 1, true);
+            else run_split(cs.gather_x[k] != 0, -1, true);
             continue;
           }
           if (stp.scratch_x >= 0) {
@@ -741,15 +781,27 @@ void contract(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets, dou
           const Node& out = P.nodes[stp.out];
           gm.C = arena + out.offset * B;
           gm.c_bs = out.elems();
-          gm.M = int64_t(1) << stp.mb;
-          gm.K = int64_t(1) << stp.kb;
-          gm.N = int64_t(1) << stp.nb;
+          gm.M = M;
+          gm.K = K;
+          gm.N = N;
           gm.ta = stp.ta;
           gm.tb = stp.tb;
           gm.lda = stp.ta ? gm.M : gm.K;
           gm.ldb = stp.tb ? gm.K : gm.N;
           gm.ldc = gm.N;
           gm.batch = nb;
+          gm.force_variant = cs.tuned[k];
+          if (gm.force_variant < 0 && g->autotune) {  // time every fitting kernel variant once
+            float best = 0;
+            for (int v = 0; v < 6; ++v) {
+              if (!dev::gemm_variant_fits(gm, v)) continue;
+              dev::Gemm t = gm;
+              t.force_variant = v;
+              const float ms = time_launches([&] { dev::gemm(t, s); });
+              if (gm.force_variant < 0 || ms < best) gm.force_variant = v, best = ms;
+            }
+            cs.tuned[k] = gm.force_variant;
+          }
           g->prof.begin(dev::gemm_name(gm), stp.flops() * nb,
                         8.0 * nb * (double)(gm.M * gm.K + gm.K * gm.N + gm.M * gm.N), s);
           dev::gemm(gm, s);

@@ -449,14 +449,26 @@ __global__ void __launch_bounds__(256) gemm_smallk_kernel(const Gemm g) {
 
 static bool pow2_or_256(int64_t n) { return n <= 256 ? (n & (n - 1)) == 0 : n % 256 == 0; }
 
+bool gemm_variant_fits(const Gemm& g, int v) {
+  switch (v) {
+    case 0: return true;
+    case 1: return g.K % 16 == 0 && g.M % 64 == 0 && g.N % 64 == 0;
+    case 2: return g.K % 16 == 0 && g.M % 128 == 0 && g.N % 128 == 0;
+    case 3: return g.K % 16 == 0 && g.M % 256 == 0 && g.N <= 32;
+    case 4: return !g.tb && g.M <= 32 && g.N >= 4 && pow2_or_256(g.N) && g.K >= 256 && g.K % 64 == 0;
+    case 5: return g.K < 16 && (g.K & (g.K - 1)) == 0 && g.N >= 32 && pow2_or_256(g.N);
+    default: return false;
+  }
+}
+
 int gemm_variant(const Gemm& g) {
-  if (g.K % 16 == 0 && g.M % 128 == 0 && g.N % 128 == 0) return 2;
-  if (g.K % 16 == 0 && g.M % 64 == 0 && g.N % 64 == 0) return 1;
+  if (g.force_variant >= 0 && gemm_variant_fits(g, g.force_variant)) return g.force_variant;
+  if (gemm_variant_fits(g, 2)) return 2;
+  if (gemm_variant_fits(g, 1)) return 1;
   // rows kernel: one workgroup per 256 rows, so only when that fills half the chip or more
-  if (g.K % 16 == 0 && g.M % 256 == 0 && g.N <= 32 && (g.M / 256) * g.batch >= 128) return 3;
-  if (!g.tb && g.M <= 32 && g.N >= 4 && pow2_or_256(g.N) && g.K >= 256 && g.K % 64 == 0)
-    return 4;  // reduction-shaped
-  if (g.K < 16 && (g.K & (g.K - 1)) == 0 && g.N >= 32 && pow2_or_256(g.N)) return 5;  // short K
+  if (gemm_variant_fits(g, 3) && (g.M / 256) * g.batch >= 128) return 3;
+  if (gemm_variant_fits(g, 4)) return 4;  // reduction-shaped
+  if (gemm_variant_fits(g, 5)) return 5;  // short K
   return 0;
 }
 

@@ -215,6 +215,20 @@ bool gemm_split_ok(int64_t M, int64_t N, int64_t K) {
   return M > 0 && N > 0 && K > 0 && M % 64 == 0 && N % 64 == 0 && K % 16 == 0;
 }
 
+bool gemm_split_tile_fits(const GemmSplit& g, int tile) {
+  switch (tile) {
+    case 0: return g.M % 256 == 0 && g.N % 128 == 0;
+    case 1: return g.M % 128 == 0 && g.N % 128 == 0;
+    case 2: return g.M % 64 == 0 && g.N % 64 == 0;
+    default: return false;
+  }
+}
+
+static int split_tile(const GemmSplit& g) {
+  if (g.tile >= 0 && gemm_split_tile_fits(g, g.tile)) return g.tile;
+  return gemm_split_tile_fits(g, 0) ? 0 : gemm_split_tile_fits(g, 1) ? 1 : 2;
+}
+
 const char* gemm_split_name(const GemmSplit& g) {
   static const char* names[2][2][3] = {
       {{"gemm_split_bf16_256x128", "gemm_split_bf16_128x128", "gemm_split_bf16_64x64"},
@@ -223,16 +237,16 @@ const char* gemm_split_name(const GemmSplit& g) {
         "gemm_split_bf16_gather_64x64"},
        {"gemm_split_fp16_gather_256x128", "gemm_split_fp16_gather_128x128",
         "gemm_split_fp16_gather_64x64"}}};
-  const int t = g.M % 256 == 0 && g.N % 128 == 0 ? 0 : g.M % 128 == 0 && g.N % 128 == 0 ? 1 : 2;
-  return names[g.Ac != nullptr][g.a_amax != nullptr][t];
+  return names[g.Ac != nullptr][g.a_amax != nullptr][split_tile(g)];
 }
 
 template <bool F16, bool GA>
 static void gemm_split_t(const GemmSplit& g, hipStream_t s) {
-  if (g.M % 256 == 0 && g.N % 128 == 0) {
+  const int tile = split_tile(g);
+  if (tile == 0) {
     dim3 grid((unsigned)((g.M / 256) * (g.N / 128)), (unsigned)g.batch);
     hipLaunchKernelGGL((gemm_split_kernel<256, 128, 4, 2, F16, GA>), grid, dim3(512), 0, s, g);
-  } else if (g.M % 128 == 0 && g.N % 128 == 0) {
+  } else if (tile == 1) {
     dim3 grid((unsigned)((g.M / 128) * (g.N / 128)), (unsigned)g.batch);
     hipLaunchKernelGGL((gemm_split_kernel<128, 128, 2, 2, F16, GA>), grid, dim3(256), 0, s, g);
   } else {

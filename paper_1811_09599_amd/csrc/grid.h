@@ -35,6 +35,9 @@ struct CircuitState {
   std::vector<int64_t> xcache_offset;
   std::vector<int64_t> xcache_slot;  // its fp16 scale slot
   int64_t xcache_elems = 0;          // 16-bit values per bit-string
+  // per step: the autotuner's choice (-1 untuned): split steps 2*tile + gather, complex64
+  // steps the kernel variant
+  std::vector<int> tuned;
   std::vector<int64_t> qsplit_offset;// per qubit: offset in grid_split (16-bit values), -1 if none
   std::vector<int64_t> qamax_slot;   // per qubit: fp16 scale slot in amax, -1 if none
   int64_t split_a_elems = 0, split_b_elems = 0;  // scratch per bit-string (16-bit values)
@@ -88,6 +91,8 @@ struct qflex_grid {
   int slice_mode = QFLEX_SLICES_RANDOM;
   // graph mode: the captured launches of the last call and the call shape they belong to
   bool graph_mode = false;
+  bool autotune = false;                 // time kernel variants per step on first use
+  hipEvent_t tune_ev[2] = {nullptr, nullptr};
   hipGraphExec_t graph_exec = nullptr;
   hipStream_t graph_stream = nullptr;    // captures and replays (the null stream cannot capture)
   hipEvent_t graph_in = nullptr, graph_out = nullptr;

@@ -67,9 +67,14 @@ struct Gemm {
   // set by gemm() for the kernels: number of K chunks and the operand offset of one chunk
   int split = 1;
   int64_t a_ks = 0, b_ks = 0;
+  // kernel variant chosen by an autotuner (-1: the shape rule of gemm_variant); ignored when
+  // the shape does not fit that variant
+  int force_variant = -1;
 };
-// which kernel gemm() would pick: 0 = SIMT, 1 = MFMA 64x64 tile, 2 = MFMA 128x128 tile
+// which kernel gemm() would pick: 0 = SIMT, 1 = MFMA 64x64 tile, 2 = MFMA 128x128 tile,
+// 3 = rows, 4 = reduction-shaped, 5 = short K
 int gemm_variant(const Gemm& g);
+bool gemm_variant_fits(const Gemm& g, int v);  // the shape meets variant v's requirements
 const char* gemm_name(const Gemm& g);  // kernel name used by the profiler
 // K chunks gemm() would use with an unlimited workspace, and the workspace that needs
 int gemm_splitk(const Gemm& g);
@@ -125,8 +130,12 @@ struct GemmSplit {
   // a_off / a_bs / a_add count complex64 elements of Ac); NULL: A is pre-split
   const float2* Ac = nullptr;
   SplitGather ga;
+  // output tile chosen by an autotuner: 0 = 256x128, 1 = 128x128, 2 = 64x64 (-1 or a tile the
+  // shape does not fit: the largest that fits)
+  int tile = -1;
 };
 bool gemm_split_ok(int64_t M, int64_t N, int64_t K);  // shape fits the tiled kernel
+bool gemm_split_tile_fits(const GemmSplit& g, int tile);
 void gemm_split(const GemmSplit& g, hipStream_t s);
 const char* gemm_split_name(const GemmSplit& g);
 

@@ -45,7 +45,7 @@ class _CircuitPack:
 
 
 def _options(precision="c64", plan="auto", max_tensor_elems=0, open_qubits=(),
-             bitstring_batch=0, slice_mode="random", graph=False):
+             bitstring_batch=0, slice_mode="random", graph=False, autotune=False):
     o = F.Options()
     o.precision = F.PREC[precision]
     o.plan_kind = F.PLAN[plan]
@@ -56,6 +56,7 @@ def _options(precision="c64", plan="auto", max_tensor_elems=0, open_qubits=(),
     o.bitstring_batch = int(bitstring_batch)
     o.slice_mode = F.SLICES[slice_mode]
     o.graph = 1 if graph else 0
+    o.autotune = 1 if autotune else 0
     return o, op
 
 
@@ -88,7 +89,7 @@ class Grid:
 
     def __init__(self, circuits, precision="c64", plan="auto", max_tensor_elems=0,
                  open_qubits=(), bitstring_batch=0, slice_mode="random", graph=False,
-                 stream=None):
+                 autotune=False, stream=None):
         L = F.lib()
         if isinstance(circuits, dict):
             circuits = [circuits]
@@ -97,7 +98,7 @@ class Grid:
         self.open_qubits = list(open_qubits)
         pack = _CircuitPack(self.circuits)
         o, keep = _options(precision, plan, max_tensor_elems, open_qubits, bitstring_batch,
-                           slice_mode, graph)
+                           slice_mode, graph, autotune)
         h = C.c_void_p()
         F.check(L.qflex_build_grid(pack.arr, len(self.circuits), C.byref(o), _stream(stream),
                                    C.byref(h)))

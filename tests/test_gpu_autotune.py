@@ -1,0 +1,61 @@
+"""GPU: autotuned grids (qflex_options.autotune = 1).  Every kernel variant the tuner may pick
+computes the same products, so tuned results must match the FP64 oracle to the same bounds;
+a tuned grid in graph mode tunes on its first call, captures on the next and replays after."""
+import numpy as np
+import pytest
+
+import rqc_inputs as R
+from oracle import metrics
+from oracle import statevector as E1
+from oracle import tn as E2
+from paper_1811_09599_amd import build_grid
+
+pytestmark = pytest.mark.gpu
+TOL = {"c64": 1e-5, "split_bf16": 2e-4, "split_fp16": 4e-5}
+
+
+def _need_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+@pytest.mark.parametrize("precision", ["c64", "split_bf16", "split_fp16"])
+def test_autotuned_quadrant_matches_state_vector(precision):
+    _need_gpu()
+    _say("autotune 5x4 quadrant,", precision)
+    c = R.grid_rqc(5, 4, 32, 5432)
+    op = [19, 18, 15]
+    g = build_grid(c, plan="quadrant", open_qubits=op, precision=precision, autotune=True)
+    ref_g = build_grid(c, plan="quadrant", open_qubits=op, precision=precision)
+    for i in range(2):  # the first call tunes, the second runs the choices
+        bits = R.bitstrings(20, 5, 40 + i, op)
+        a = g.contract_amplitudes(bits).cpu().numpy()
+        e = metrics.amp_errors(a, E1.amplitudes(c, bits, op), 20)
+        _say("  call", i, e)
+        assert e["max"] < TOL[precision]
+        flops = g.last_stats()["flops"]
+        ref_g.contract_amplitudes(bits)
+        assert flops == ref_g.last_stats()["flops"]  # same plan, whatever the kernels
+
+
+def test_autotuned_7x7_slices_match_oracle_and_graph_replays():
+    _need_gpu()
+    _say("autotune 7x7 1+32+1 split-bf16, graph mode")
+    c = R.grid_rqc(7, 7, 32, 2001)
+    op = R.grid_ids((7, 7), [(5, 0), (5, 1), (5, 2), (6, 0), (6, 1), (6, 2)])
+    g = build_grid(c, open_qubits=op, precision="split_bf16", autotune=True, graph=True)
+    ids = [37, 200]
+    outs = []
+    for i in range(3):  # tune (eager), capture, replay
+        bits = R.bitstrings(49, 1, 2500, op)
+        outs.append(g.contract_amplitudes(bits, slice_ids=ids).cpu().numpy())
+    ref = E2.amplitudes(c, R.bitstrings(49, 1, 2500, op), op, cuts=g.plan_cuts(), slice_ids=ids,
+                        order=E2.quadrant_order(7, 7))
+    for o in outs:
+        assert metrics.amp_errors(o, ref, 49)["max"] < TOL["split_bf16"]
+    assert np.array_equal(outs[1], outs[2])

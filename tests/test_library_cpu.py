@@ -93,7 +93,7 @@ def test_invalid_mode_fields_rejected():
     c = R.grid_rqc(3, 3, 8, 1)
     L = F.lib()
     pack = _CircuitPack([c])
-    for field, bad in (("slice_mode", 2), ("slice_mode", -1), ("graph", 2)):
+    for field, bad in (("slice_mode", 2), ("slice_mode", -1), ("graph", 2), ("autotune", 3)):
         o, keep = _options()
         setattr(o, field, bad)
         h = C.c_void_p()
