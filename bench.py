@@ -67,7 +67,8 @@ def run_precision(precision, circ, open_q, all_bits, args):
     from paper_1811_09599_amd import build_grid
 
     t0 = time.time()
-    grid = build_grid(circ, open_qubits=open_q, precision=precision)
+    grid = build_grid(circ, open_qubits=open_q, precision=precision,
+                      autotune=not args.no_autotune)
     torch.cuda.synchronize()
     build_s = time.time() - t0
     B = args.bitstrings
@@ -115,6 +116,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-gradient", action="store_true", help="skip the gradient workload")
     ap.add_argument("--no-diamond", action="store_true", help="skip the diamond workload")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="kernel choice by shape rules only (default: the library's autotuner "
+                         "times the variants of every step during the warm-up call)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first copy 1 GiB device to device (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -194,7 +198,7 @@ def run_diamond(args):
     bits = R.bitstrings(70, 64, 4500)
     B = 4  # bit-strings per step
     t0 = time.time()
-    grid = build_grid(circ, precision="split_bf16")
+    grid = build_grid(circ, precision="split_bf16", autotune=not args.no_autotune)
     torch.cuda.synchronize()
     build_s = time.time() - t0
     S = grid.num_slices()
