@@ -37,6 +37,7 @@ void release(qflex_grid* g) {
   if (g->bidx) (void)hipFree(g->bidx);
   if (g->grid_split) (void)hipFree(g->grid_split);
   if (g->amax) (void)hipFree(g->amax);
+  if (g->node_amax) (void)hipFree(g->node_amax);
   if (g->graph_exec) (void)hipGraphExecDestroy(g->graph_exec);
   if (g->graph_in) (void)hipEventDestroy(g->graph_in);
   for (hipEvent_t e : g->tune_ev)

@@ -218,12 +218,16 @@ void build_grid_device(qflex_grid* g, hipStream_t s) {
     prepare_split(g, s);
 }
 
-// Tag for the next absmax() into the fp16 scale slots: tags grow, so a slot never needs
-// clearing; when they would wrap, the two step slots are cleared and the tags start again (the
-// qubit slots are written once, at build, and only read after that).
+// Tag for the next absmax() (or product maximum) into the fp16 scale slots: tags grow, so a
+// slot never needs clearing; when they would wrap, every slot that calls rewrite is cleared
+// and the tags start again (the qubit slots are written once, at build, and only read after).
 static uint32_t next_amax_tag(qflex_grid* g, hipStream_t s) {
-  if (g->amax_tag == UINT32_MAX) {
+  if (g->amax_tag == UINT32_MAX) {  // clear every slot that calls rewrite
     dev::fill_zero(reinterpret_cast<double*>(g->amax), 2, s);
+    for (const CircuitState& cs : g->circ)
+      for (int64_t sl : cs.xcache_slot)
+        if (sl >= 0) dev::fill_zero(reinterpret_cast<double*>(g->amax + sl), 1, s);
+    if (g->node_amax) dev::fill_zero(reinterpret_cast<double*>(g->node_amax), g->n_node_amax, s);
     g->amax_tag = 0;
   }
   return ++g->amax_tag;
@@ -237,6 +241,7 @@ void prepare_split(qflex_grid* g, hipStream_t s) {
   const bool f16 = g->precision == QFLEX_PREC_SPLIT_FP16;
   int64_t total = 0;
   int64_t n_slots = 2;
+  int64_t n_node_slots = 0;
   struct Job {
     int64_t src, dst;
     int nfixed, nbits, kbits;
@@ -256,6 +261,7 @@ void prepare_split(qflex_grid* g, hipStream_t s) {
     cs.xcache_offset.assign(ns, -1);
     cs.xcache_slot.assign(ns, -1);
     cs.xcache_elems = 0;
+    cs.node_slot.assign(P.nodes.size(), -1);
     cs.qsplit_offset.assign(cs.model.n, -1);
     cs.qamax_slot.assign(cs.model.n, -1);
     cs.split_a_elems = cs.split_b_elems = 0;
@@ -264,6 +270,7 @@ void prepare_split(qflex_grid* g, hipStream_t s) {
       const int64_t M = int64_t(1) << st.mb, N = int64_t(1) << st.nb, K = int64_t(1) << st.kb;
       if (!dev::gemm_split_ok(M, N, K)) continue;
       cs.split[i] = 1;
+      if (f16) cs.node_slot[st.out] = n_node_slots++;
       // The order of the contracted labels is this step's own choice.  For an intermediate
       // x, order them as x stores them: when x's 2 lowest storage labels are contracted ones,
       // every group of 4 consecutive k is then 32 contiguous bytes of x, and the product reads
@@ -329,6 +336,11 @@ void prepare_split(qflex_grid* g, hipStream_t s) {
     g->n_amax = n_slots;
     g->amax_tag = 0;
     dev::fill_zero(reinterpret_cast<double*>(g->amax), n_slots, s);
+    if (n_node_slots) {
+      QHIP(hipMalloc(&g->node_amax, sizeof(uint64_t) * n_node_slots));
+      g->n_node_amax = n_node_slots;
+      dev::fill_zero(reinterpret_cast<double*>(g->node_amax), n_node_slots, s);
+    }
   }
   if (total == 0) return;
   QHIP(hipMalloc(&g->grid_split, sizeof(uint16_t) * total));
@@ -598,6 +610,7 @@ void contract(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets, dou
     for (const CircuitState& cs : g->circ)
       for (int64_t sl : cs.xcache_slot)
         if (sl >= 0) dev::fill_zero(reinterpret_cast<double*>(g->amax + sl), 1, s);
+    if (g->node_amax) dev::fill_zero(reinterpret_cast<double*>(g->node_amax), g->n_node_amax, s);
   }
   dev::fill_zero(reinterpret_cast<double*>(acc_all), 2 * amp_total, s);
   for (int c = 0; c < nc; ++c) {
@@ -654,6 +667,13 @@ void contract(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets, dou
             dev::GemmSplit gs;
             gs.tile = tile;
             const bool f16 = g->amax != nullptr;
+            // fp16 scales of intermediates that a split product produced (and measured)
+            auto node_slot = [&](const Operand& o) -> uint64_t* {
+              if (!f16 || o.qubit || cs.node_slot[o.id] < 0) return nullptr;
+              return g->node_amax + cs.node_slot[o.id];
+            };
+            uint64_t* const xslot = node_slot(stp.x);
+            uint64_t* const yslot = node_slot(stp.y);
             if (stp.x.qubit) {
               gs.A = g->grid_split + cs.qsplit_offset[stp.x.id];
               gs.a_add = x.add;
@@ -661,9 +681,9 @@ void contract(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets, dou
               if (f16) gs.a_amax = g->amax + cs.qamax_slot[stp.x.id];
             } else if (cs.xcache_offset[k] >= 0) {
               uint16_t* xc = static_cast<uint16_t*>(g->split_cache.p) + B * cs.xcache_offset[k];
-              if (f16) gs.a_amax = g->amax + cs.xcache_slot[k];
+              if (f16) gs.a_amax = xslot ? xslot : g->amax + cs.xcache_slot[k];
               if (si == 0 || (P.nodes[stp.x.id].deps & changed)) {  // x was just recomputed
-                if (f16) {
+                if (f16 && !xslot) {
                   g->prof.begin("absmax", 0, 8.0 * M * K * nb, s);
                   dev::absmax(x.base, M * K * nb, g->amax + cs.xcache_slot[k],
                               next_amax_tag(g, s), s);
@@ -677,7 +697,9 @@ void contract(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets, dou
               gs.A = xc;
               gs.a_bs = M * K;
             } else {
-              if (f16) {
+              if (f16 && xslot) {
+                gs.a_amax = xslot;
+              } else if (f16) {
                 gs.a_amax = g->amax;
                 g->prof.begin("absmax", 0, 8.0 * M * K * nb, s);
                 dev::absmax(x.base, M * K * nb, g->amax, next_amax_tag(g, s), s);
@@ -702,7 +724,9 @@ void contract(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets, dou
               gs.b_off = y.off;
               if (f16) gs.b_amax = g->amax + cs.qamax_slot[stp.y.id];
             } else {
-              if (f16) {
+              if (f16 && yslot) {
+                gs.b_amax = yslot;
+              } else if (f16) {
                 gs.b_amax = g->amax + 1;
                 g->prof.begin("absmax", 0, 8.0 * N * K * nb, s);
                 dev::absmax(y.base, N * K * nb, g->amax + 1, next_amax_tag(g, s), s);
@@ -722,6 +746,10 @@ void contract(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets, dou
             gs.N = N;
             gs.K = K;
             gs.batch = nb;
+            if (f16 && cs.node_slot[stp.out] >= 0) {
+              gs.c_amax = g->node_amax + cs.node_slot[stp.out];
+              gs.c_tag = next_amax_tag(g, s);
+            }
             // the kernel's own arithmetic: 3 16-bit products per real product, 24*M*N*K flops
             g->prof.begin(dev::gemm_split_name(gs), 3.0 * stp.flops() * nb,
                           8.0 * nb * (double)(M * K + N * K + M * N), s);

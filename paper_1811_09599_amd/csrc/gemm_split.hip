@@ -195,7 +195,7 @@ __global__ void __launch_bounds__(64 * WM * WN) gemm_split_kernel(const GemmSpli
     if (kt + 1 < nk) sstore(buf ^ 1);
     __syncthreads();
   }
-  float ua = 1.f, ub = 1.f;
+  float ua = 1.f, ub = 1.f, cmax = 0.f;
   if constexpr (F16) ua = fp16_unscale(*g.a_amax), ub = fp16_unscale(*g.b_amax);
 #pragma unroll
   for (int i = 0; i < TMI; ++i)
@@ -208,7 +208,18 @@ __global__ void __launch_bounds__(64 * WM * WN) gemm_split_kernel(const GemmSpli
         float re = cr[i][j][v], im = ci[i][j][v];
         if constexpr (F16) re = re * ua * ub, im = im * ua * ub;
         C[(m0 + row) * g.N + n0 + col] = make_float2(re, im);
+        if constexpr (F16) cmax = fmaxf(cmax, fmaxf(fabsf(re), fabsf(im)));
       }
+  if constexpr (F16) {
+    // the product's largest magnitude, for the fp16 scale of whoever consumes it next
+    if (g.c_amax) {
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) cmax = fmaxf(cmax, __shfl_xor(cmax, o, 64));
+      if (lane == 0)
+        atomicMax(reinterpret_cast<unsigned long long*>(g.c_amax),
+                  (unsigned long long)(g.c_tag << 32 | __float_as_uint(cmax)));
+    }
+  }
 }
 
 bool gemm_split_ok(int64_t M, int64_t N, int64_t K) {

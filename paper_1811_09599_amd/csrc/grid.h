@@ -34,6 +34,9 @@ struct CircuitState {
   // 16-bit values per bit-string, -1 if not) and re-split only when it is recomputed
   std::vector<int64_t> xcache_offset;
   std::vector<int64_t> xcache_slot;  // its fp16 scale slot
+  // fp16: per node, its slot in node_amax when a split product produces it (the product
+  // records its largest magnitude, so consumers need no absmax pass), else -1
+  std::vector<int64_t> node_slot;
   int64_t xcache_elems = 0;          // 16-bit values per bit-string
   // per step: the autotuner's choice (-1 untuned): split steps 2*tile + gather, complex64
   // steps the kernel variant
@@ -107,6 +110,8 @@ struct qflex_grid {
   // step, then one per pre-split qubit tensor; amax_tag = the last tag used on them
   uint64_t* amax = nullptr;
   int64_t n_amax = 0;
+  uint64_t* node_amax = nullptr;         // node slots (see CircuitState::node_slot)
+  int64_t n_node_amax = 0;
   uint32_t amax_tag = 0;
   // time-collapse descriptors, kept for the adjoint of the grid build
   qflex::DevBuf gq, gpieces, gmats, gpos;

@@ -133,6 +133,10 @@ struct GemmSplit {
   // output tile chosen by an autotuner: 0 = 256x128, 1 = 128x128, 2 = 64x64 (-1 or a tile the
   // shape does not fit: the largest that fits)
   int tile = -1;
+  // fp16 products: record the largest |re|, |im| of C into *c_amax as absmax() would, with
+  // tag c_tag (NULL: not recorded)
+  uint64_t* c_amax = nullptr;
+  uint64_t c_tag = 0;
 };
 bool gemm_split_ok(int64_t M, int64_t N, int64_t K);  // shape fits the tiled kernel
 bool gemm_split_tile_fits(const GemmSplit& g, int tile);
