@@ -256,7 +256,7 @@ def run_gradient(args):
     circs = R.fsim_batch(96, depth=12, sizes=(4, 5, 6), seed=5000, jitter_seed0=5900)
     bits = [R.bitstrings(c["n_qubits"], 128, 5500 + i) for i, c in enumerate(circs)]
     t0 = time.time()
-    grid = build_grid(circs)
+    grid = build_grid(circs, autotune=not args.no_autotune)
     torch.cuda.synchronize()
     build_s = time.time() - t0
     steps = max(1, min(args.steps, 2))

@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <numeric>
 #include <set>
 
@@ -102,7 +103,10 @@ void Profiler::release() {
 void prepare_split(qflex_grid* g, hipStream_t s);
 
 void build_grid_device(qflex_grid* g, hipStream_t s) {
-  for (CircuitState& cs : g->circ) cs.tuned.assign(cs.plan.steps.size(), -1);
+  for (CircuitState& cs : g->circ) {
+    cs.tuned.assign(cs.plan.steps.size(), -1);
+    cs.tuned_grad.assign(3 * cs.plan.steps.size(), -1);
+  }
   std::vector<dev::GridPiece> pieces;
   std::vector<double2> mats;
   std::vector<int32_t> pos;
@@ -356,6 +360,38 @@ void prepare_split(qflex_grid* g, hipStream_t s) {
   QHIP(hipStreamSynchronize(s));
 }
 
+// ------------------------------------------------------------------------------ autotuning
+float time_launches(qflex_grid* g, hipStream_t s, const std::function<void()>& launch) {
+  if (!g->tune_ev[0]) {
+    QHIP(hipEventCreate(&g->tune_ev[0]));
+    QHIP(hipEventCreate(&g->tune_ev[1]));
+  }
+  const bool on = g->prof.on;
+  g->prof.on = false;
+  launch();  // warm-up
+  QHIP(hipEventRecord(g->tune_ev[0], s));
+  launch();
+  QHIP(hipEventRecord(g->tune_ev[1], s));
+  QHIP(hipEventSynchronize(g->tune_ev[1]));
+  g->prof.on = on;
+  float ms = 0;
+  QHIP(hipEventElapsedTime(&ms, g->tune_ev[0], g->tune_ev[1]));
+  return ms;
+}
+
+int tune_gemm(qflex_grid* g, hipStream_t s, const dev::Gemm& gm) {
+  int best_v = -1;
+  float best = 0;
+  for (int v = 0; v < 6; ++v) {
+    if (!dev::gemm_variant_fits(gm, v)) continue;
+    dev::Gemm t = gm;
+    t.force_variant = v;
+    const float ms = time_launches(g, s, [&] { dev::gemm(t, s); });
+    if (best_v < 0 || ms < best) best_v = v, best = ms;
+  }
+  return best_v;
+}
+
 // ------------------------------------------------------------------------------ slices
 std::vector<int64_t> select_slices(int64_t total, double fidelity, uint64_t seed, int mode) {
   if (!(fidelity > 0.0 && fidelity <= 1.0)) fail(QFLEX_E_INVALID, "fidelity must be in (0, 1]");
@@ -515,23 +551,8 @@ void contract(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets, dou
   g->amps64.reserve(sizeof(double2) * std::max<int64_t>(amp_total, 1));
   float2* arena = static_cast<float2*>(g->arena.p);
   double2* acc_all = static_cast<double2*>(g->amps64.p);
-  // ---- autotuning: the wall time of one run of `launch` (after one warm-up run), profiling off
-  auto time_launches = [&](auto&& launch) -> float {
-    if (!g->tune_ev[0]) {
-      QHIP(hipEventCreate(&g->tune_ev[0]));
-      QHIP(hipEventCreate(&g->tune_ev[1]));
-    }
-    const bool on = g->prof.on;
-    g->prof.on = false;
-    launch();
-    QHIP(hipEventRecord(g->tune_ev[0], s));
-    launch();
-    QHIP(hipEventRecord(g->tune_ev[1], s));
-    QHIP(hipEventSynchronize(g->tune_ev[1]));
-    g->prof.on = on;
-    float ms = 0;
-    QHIP(hipEventElapsedTime(&ms, g->tune_ev[0], g->tune_ev[1]));
-    return ms;
+  auto time_launches = [&](const std::function<void()>& launch) {
+    return qflex::time_launches(g, s, launch);
   };
   bool tuning_pending = false;
   if (g->autotune)
@@ -819,17 +840,8 @@ void contract(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets, dou
           gm.ldc = gm.N;
           gm.batch = nb;
           gm.force_variant = cs.tuned[k];
-          if (gm.force_variant < 0 && g->autotune) {  // time every fitting kernel variant once
-            float best = 0;
-            for (int v = 0; v < 6; ++v) {
-              if (!dev::gemm_variant_fits(gm, v)) continue;
-              dev::Gemm t = gm;
-              t.force_variant = v;
-              const float ms = time_launches([&] { dev::gemm(t, s); });
-              if (gm.force_variant < 0 || ms < best) gm.force_variant = v, best = ms;
-            }
-            cs.tuned[k] = gm.force_variant;
-          }
+          if (gm.force_variant < 0 && g->autotune)  // time every fitting kernel variant once
+            gm.force_variant = cs.tuned[k] = tune_gemm(g, s, gm);
           g->prof.begin(dev::gemm_name(gm), stp.flops() * nb,
                         8.0 * nb * (double)(gm.M * gm.K + gm.K * gm.N + gm.M * gm.N), s);
           dev::gemm(gm, s);

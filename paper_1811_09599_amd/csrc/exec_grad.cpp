@@ -273,6 +273,9 @@ void contract_grad(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets
           gm.batch = nb;
           gm.ws = splitk_ws;
           gm.ws_elems = ws_need;
+          gm.force_variant = cs.tuned_grad[3 * k + 0];
+          if (gm.force_variant < 0 && g->autotune)
+            gm.force_variant = cs.tuned_grad[3 * k + 0] = tune_gemm(g, s, gm);
           g->prof.begin(dev::gemm_name(gm), stp.flops() * nb,
                         8.0 * nb * (double)(gm.M * gm.K + gm.K * gm.N + gm.M * gm.N), s);
           dev::gemm(gm, s);
@@ -333,6 +336,9 @@ void contract_grad(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets
           g1.batch = nb;
           g1.ws = splitk_ws;
           g1.ws_elems = ws_need;
+          g1.force_variant = cs.tuned_grad[3 * kk + 1];
+          if (g1.force_variant < 0 && g->autotune)
+            g1.force_variant = cs.tuned_grad[3 * kk + 1] = tune_gemm(g, s, g1);
           g->prof.begin(dev::gemm_name(g1), stp.flops() * nb,
                         8.0 * nb * (double)(g1.M * g1.K + g1.K * g1.N + g1.M * g1.N), s);
           dev::gemm(g1, s);
@@ -356,6 +362,9 @@ void contract_grad(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets
           g2.batch = nb;
           g2.ws = splitk_ws;
           g2.ws_elems = ws_need;
+          g2.force_variant = cs.tuned_grad[3 * kk + 2];
+          if (g2.force_variant < 0 && g->autotune)
+            g2.force_variant = cs.tuned_grad[3 * kk + 2] = tune_gemm(g, s, g2);
           g->prof.begin(dev::gemm_name(g2), stp.flops() * nb,
                         8.0 * nb * (double)(g2.M * g2.K + g2.K * g2.N + g2.M * g2.N), s);
           dev::gemm(g2, s);

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <functional>
 #include <map>
 #include <string>
 #include <vector>
@@ -39,8 +40,9 @@ struct CircuitState {
   std::vector<int64_t> node_slot;
   int64_t xcache_elems = 0;          // 16-bit values per bit-string
   // per step: the autotuner's choice (-1 untuned): split steps 2*tile + gather, complex64
-  // steps the kernel variant
+  // steps the kernel variant; and for the adjoint, per step its forward, Xbar and Ybar products
   std::vector<int> tuned;
+  std::vector<int> tuned_grad;
   std::vector<int64_t> qsplit_offset;// per qubit: offset in grid_split (16-bit values), -1 if none
   std::vector<int64_t> qamax_slot;   // per qubit: fp16 scale slot in amax, -1 if none
   int64_t split_a_elems = 0, split_b_elems = 0;  // scratch per bit-string (16-bit values)
@@ -140,6 +142,10 @@ std::vector<std::vector<int64_t>> prepare_call(qflex_grid* g, const uint8_t* bit
                                                uint64_t seed, const int64_t* slice_ids,
                                                const int64_t* slice_offsets, const void* amps,
                                                hipStream_t s);
+// Autotuning: wall time of one run of `launch` after a warm-up run (profiling off; the stream
+// is synchronised), and the fastest kernel variant of a complex64 product.
+float time_launches(qflex_grid* g, hipStream_t s, const std::function<void()>& launch);
+int tune_gemm(qflex_grid* g, hipStream_t s, const dev::Gemm& gm);
 void contract(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets, double fidelity,
               uint64_t seed, const int64_t* slice_ids, const int64_t* slice_offsets,
               double* amps, bool amps_on_device, hipStream_t s);

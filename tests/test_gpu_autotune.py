@@ -59,3 +59,18 @@ def test_autotuned_7x7_slices_match_oracle_and_graph_replays():
     for o in outs:
         assert metrics.amp_errors(o, ref, 49)["max"] < TOL["split_bf16"]
     assert np.array_equal(outs[1], outs[2])
+
+
+def test_autotuned_gradients_match_state_vector_adjoint():
+    _need_gpu()
+    _say("autotune gradients, 6 fSim circuits")
+    cs = R.fsim_batch(6, depth=12, sizes=(3, 4), seed=8800, jitter_seed0=8900)
+    bits = [R.bitstrings(c["n_qubits"], 24, 8950 + i) for i, c in enumerate(cs)]
+    g = build_grid(cs, autotune=True)
+    for rep in range(2):  # tune, then use the choices
+        res = g.contract_grad(bits)
+        for i, c in enumerate(cs):
+            f_ref, g_ref = E1.linear_xeb_grad(c, bits[i])
+            rows = [j for j, gt in enumerate(c["gates"]) if gt["kind"] == "fsim"]
+            assert metrics.rel_l2(res["grad_params"][i][rows], g_ref) < 1e-3, (rep, i)
+            assert abs(res["loss"][i] - f_ref) < 1e-4 * max(1.0, abs(f_ref)), (rep, i)
