@@ -21,6 +21,21 @@ namespace dev {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 
+// f(v) of a bit map given as runs (see SplitGather); the n <= kGatherRuns run words sit in
+// the kernel arguments at fixed offsets, so they are read once, by scalar loads
+__device__ inline int64_t deposit_runs(int64_t v, const int32_t (&runs)[kGatherRuns], int n) {
+  int64_t f = 0;
+#pragma unroll
+  for (int r = 0; r < kGatherRuns; ++r) {
+    if (r < n) {
+      const int32_t w = runs[r];
+      const int s = w & 0xff, len = (w >> 8) & 0xff, d = (w >> 16) & 0xff;
+      f |= ((v >> s) & ((int64_t(1) << len) - 1)) << d;
+    }
+  }
+  return f;
+}
+
 template <typename V>
 __device__ inline V as_vec(u32x4 v) {
   return __builtin_bit_cast(V, v);
@@ -73,7 +88,11 @@ __global__ void __launch_bounds__(64 * WM * WN) gemm_split_kernel(const GemmSpli
       const int64_t m = m0 + ((tid + u * NT) >> 2);
       const int grp = (tid + u * NT) & 3;  // k bits 2 and 3 within the tile
       int64_t f = (int64_t)(grp & 1) << g.ga.kpos[0] | (int64_t)(grp >> 1) << g.ga.kpos[1];
-      for (int i = 0; i < g.ga.nm; ++i) f |= ((m >> i) & 1) << g.ga.mpos[i];
+      if (g.ga.nmr <= kGatherRuns) {
+        f |= deposit_runs(m, g.ga.mrun, g.ga.nmr);
+      } else {
+        for (int i = 0; i < g.ga.nm; ++i) f |= ((m >> i) & 1) << g.ga.mpos[i];
+      }
       frow[u] = f;
     }
     if constexpr (F16) ascale = fp16_scale(*g.a_amax);
@@ -82,7 +101,11 @@ __global__ void __launch_bounds__(64 * WM * WN) gemm_split_kernel(const GemmSpli
     if constexpr (GA) {
       const int64_t kt = k0 / ROW;
       int64_t gk = 0;  // k bits 4.. of the tile
-      for (int j = 2; j < g.ga.nk; ++j) gk |= ((kt >> (j - 2)) & 1) << g.ga.kpos[j];
+      if (g.ga.nkr <= kGatherRuns) {
+        gk = deposit_runs(kt, g.ga.krun, g.ga.nkr);
+      } else {
+        for (int j = 2; j < g.ga.nk; ++j) gk |= ((kt >> (j - 2)) & 1) << g.ga.kpos[j];
+      }
 #pragma unroll
       for (int u = 0; u < AG; ++u) {
         const float2* p = Ac + frow[u] + gk;
@@ -266,7 +289,22 @@ static void gemm_split_t(const GemmSplit& g, hipStream_t s) {
   }
 }
 
-void gemm_split(const GemmSplit& g, hipStream_t s) {
+// Bits first .. n-1 of a map as runs of consecutive positions; bit i of the source is bit
+// (i - first) of the index the kernel deposits.  Returns kGatherRuns + 1 if they do not fit.
+static int32_t gather_runs(const int8_t* pos, int first, int n, int32_t* runs) {
+  int32_t nr = 0;
+  for (int i = first; i < n;) {
+    int len = 1;
+    while (i + len < n && pos[i + len] == pos[i] + len) ++len;
+    if (nr == kGatherRuns) return kGatherRuns + 1;
+    runs[nr++] = (i - first) | len << 8 | (int32_t)pos[i] << 16;
+    i += len;
+  }
+  return nr;
+}
+
+void gemm_split(const GemmSplit& g_in, hipStream_t s) {
+  GemmSplit g = g_in;
   if (!gemm_split_ok(g.M, g.N, g.K)) throw std::runtime_error("gemm_split: unsupported shape");
   if (g.batch < 1 || g.batch > 65535) throw std::runtime_error("gemm_split: bad batch");
   if ((g.a_amax == nullptr) != (g.b_amax == nullptr))
@@ -276,6 +314,8 @@ void gemm_split(const GemmSplit& g, hipStream_t s) {
     if (g.ga.nm + g.ga.nk + 2 > kGatherMaxBits || g.ga.nk < 2 || (int64_t(1) << g.ga.nm) != g.M ||
         (int64_t(4) << g.ga.nk) != g.K)
       throw std::runtime_error("gemm_split: gather descriptor does not match the shape");
+    g.ga.nmr = gather_runs(g.ga.mpos, 0, g.ga.nm, g.ga.mrun);
+    g.ga.nkr = gather_runs(g.ga.kpos, 2, g.ga.nk, g.ga.krun);
     if (g.a_amax) gemm_split_t<true, true>(g, s);
     else gemm_split_t<false, true>(g, s);
   } else {

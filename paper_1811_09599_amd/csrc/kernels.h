@@ -107,10 +107,17 @@ void absmax(const float2* in, int64_t n, uint64_t* slot, uint32_t tag, hipStream
 // bits: element (m, k) sits at f(m) + (k & 3) + g(k >> 2), so every group of 4 consecutive k
 // is 32 contiguous bytes.
 constexpr int kGatherMaxBits = 40;
+constexpr int kGatherRuns = 8;
 struct SplitGather {
   int32_t nm = 0, nk = 0;
   int8_t mpos[kGatherMaxBits] = {};
   int8_t kpos[kGatherMaxBits] = {};
+  // Filled by gemm_split from mpos / kpos: the same maps as runs of consecutive bits (bits
+  // s .. s+len-1 of m, or of the k-tile index, land at storage positions d .. d+len-1), packed
+  // as s | len << 8 | d << 16.  More than kGatherRuns runs: the kernel walks the bits instead.
+  int32_t nmr = 0, nkr = 0;
+  int32_t mrun[kGatherRuns] = {};
+  int32_t krun[kGatherRuns] = {};
 };
 
 struct GemmSplit {
