@@ -35,30 +35,78 @@ TOL = {"split_bf16": 2e-4, "split_fp16": 4 * C64_TOL, "c64": C64_TOL}
 DTYPE = {"split_bf16": "bf16x3", "split_fp16": "fp16x3", "c64": "c64"}
 
 
-def kernel_bound(name):
+def flop_peak(name):
+    """The arithmetic peak a kernel's flops are measured against, from its name."""
     if name.startswith("gemm_split_bf16"):
-        return "mfma", PEAK["mfma_bf16"]
+        return "mfma", PEAK["mfma_bf16"][0]
     if name.startswith("gemm_split_fp16"):
-        return "mfma", PEAK["mfma_fp16"]
+        return "mfma", PEAK["mfma_fp16"][0]
     if name.startswith("gemm_mfma"):
-        return "mfma", PEAK["mfma_fp32"]
-    if name.startswith("gemm_simt"):
-        return "alu", PEAK["alu"]
-    return "hbm", PEAK["hbm"]
+        return "mfma", PEAK["mfma_fp32"][0]
+    if name.startswith("gemm_"):  # SIMT, rows, reduce and short-K products: FP32 vector ALU
+        return "alu", PEAK["alu"][0]
+    return None, None
 
 
 def roofline(prof):
+    """Roofline of the kernel with the most time: its algorithmic flops and bytes per launch
+    (recorded by the library with each launch) over its average launch time; the bound is the
+    resource the kernel uses the larger fraction of."""
     name = max(prof, key=lambda k: prof[k]["ms"])
     k = prof[name]
-    bound, (peak, unit) = kernel_bound(name)
-    if bound == "hbm":
-        achieved = k["bytes"] / (k["ms"] * 1e-3) / 1e9
+    sec = k["ms"] * 1e-3
+    gbps = k["bytes"] / sec / 1e9
+    hbm_frac = gbps / PEAK["hbm"][0]
+    kind, fpeak = flop_peak(name)
+    tflops = k["flops"] / sec / 1e12
+    flop_frac = tflops / fpeak if fpeak else 0.0
+    if kind is None or hbm_frac >= flop_frac:
+        bound, achieved, peak, unit = "hbm", gbps, PEAK["hbm"][0], "GB/s"
     else:
-        achieved = k["flops"] / (k["ms"] * 1e-3) / 1e12
+        bound, achieved, peak, unit = kind, tflops, fpeak, "TFLOP/s"
     return name, {"bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": unit,
                   "frac": round(achieved / peak, 4), "traffic": None,
+                  "flop_frac": round(flop_frac, 4), "hbm_frac": round(hbm_frac, 4),
                   "avg_launch_us": round(1e3 * k["ms"] / max(k["launches"], 1), 3),
                   "launches": k["launches"]}
+
+
+def ceilings():
+    """What this device sustains outside the library, measured in the same process: the vendor
+    GEMM (torch.matmul, hipBLASLt) on 8192^3 random bf16 and fp32 operands, and a 1 GiB device
+    to device copy (read + write bytes).  Context for the roofline fractions above."""
+    import torch
+
+    def timed(fn, reps):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) * 1e-3 / reps
+
+    out = {}
+    n = 8192
+    for dt, key in ((torch.bfloat16, "vendor_gemm_bf16_tflops"),
+                    (torch.float32, "vendor_gemm_fp32_tflops")):
+        a = torch.randn(n, n, dtype=dt, device="cuda")
+        b = torch.randn(n, n, dtype=dt, device="cuda")
+        c = torch.empty(n, n, dtype=dt, device="cuda")
+        out[key] = round(2.0 * n ** 3 / timed(lambda: torch.matmul(a, b, out=c), 20) / 1e12, 1)
+        del a, b, c
+    src = torch.randn(1 << 28, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    out["device_copy_gbps"] = round(2.0 * 4 * src.numel() / timed(lambda: dst.copy_(src), 10)
+                                    / 1e9, 1)
+    del src, dst
+    out["note"] = ("hipBLASLt via torch.matmul at 8192^3 on random operands, and a 1 GiB device "
+                   "copy, timed in this run: practical ceilings of this device next to the "
+                   "published peaks")
+    return out
 
 
 def run_precision(precision, circ, open_q, all_bits, args):
@@ -119,6 +167,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true",
                     help="kernel choice by shape rules only (default: the library's autotuner "
                          "times the variants of every step during the warm-up call)")
+    ap.add_argument("--no-ceilings", action="store_true",
+                    help="skip timing the vendor GEMM and a device copy for context")
     ap.add_argument("--copy-probe", action="store_true",
                     help="first copy 1 GiB device to device (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -142,6 +192,8 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    # measured first, on a device that has not been running the workloads yet
+    ceil = None if args.no_ceilings else ceilings()
     rows = cols = 7
     circ = R.grid_rqc(rows, cols, 32, 2000)
     open_q = R.grid_ids((rows, cols), [(5, 0), (5, 1), (5, 2), (6, 0), (6, 1), (6, 2)])
@@ -178,6 +230,8 @@ def main():
         res["gradient"] = run_gradient(args)
     if not args.no_diamond:
         res["diamond"] = run_diamond(args)
+    if ceil:
+        res["ceilings"] = ceil
     if not args.no_cpu_baseline:
         res.update(cpu_baseline(circ, grids, all_bits[:1], open_q, args.cpu_slices, rows, cols))
     print(json.dumps(res), flush=True)

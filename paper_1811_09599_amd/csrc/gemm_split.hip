@@ -50,8 +50,12 @@ __device__ inline floatx16 mfma16(f16x8 a, f16x8 b, floatx16 c) {
 // GA: A comes from complex64 storage through the gather descriptor (one permutation and one
 // split pass over A fewer): each thread loads whole groups of 4 consecutive k (32 contiguous
 // bytes) of its rows, and splits them into the compact layout while storing the tile to LDS.
+//
+// At least two wavefronts per SIMD: left to itself the compiler gives the fp16 128x128 tile
+// 300 registers, which leaves one.
 template <int BM, int BN, int WM, int WN, bool F16, bool GA>
-__global__ void __launch_bounds__(64 * WM * WN) gemm_split_kernel(const GemmSplit g) {
+__global__ void __launch_bounds__(64 * WM * WN) __attribute__((amdgpu_waves_per_eu(2)))
+gemm_split_kernel(const GemmSplit g) {
   using V = typename std::conditional<F16, f16x8, bf16x8>::type;
   constexpr int NT = 64 * WM * WN;       // threads: WM x WN wavefronts
   constexpr int BK = 16;                 // complex k per tile
