@@ -224,6 +224,29 @@ def bitstrings(n_qubits: int, m: int, seed: int, open_qubits=()) -> np.ndarray:
     return bits
 
 
+def sampling_draws(n_batches: int, batch_len: int, n_c: int, seed: int):
+    """Random numbers of the frugal sampler, as inputs: order [n_batches, n_c] int32, each row
+    the first n_c entries of a uniformly random permutation of [0, batch_len) (a random subset
+    without repetition, in random order), and u [n_batches, n_c] float64 uniform in [0, 1);
+    both from PCG64(seed)."""
+    if not 1 <= n_c <= batch_len:
+        raise ValueError("need 1 <= n_c <= batch_len")
+    rng = np.random.Generator(np.random.PCG64(seed))
+    order = np.argsort(rng.random((n_batches, batch_len)), axis=1)[:, :n_c].astype(np.int32)
+    u = rng.random((n_batches, n_c))
+    return np.ascontiguousarray(order), u
+
+
+def porter_thomas_amplitudes(n_batches: int, batch_len: int, n_qubits: int, seed: int):
+    """[n_batches, batch_len] complex128 synthetic amplitudes with Porter-Thomas statistics:
+    independent complex Gaussians of variance 1 / 2^n_qubits (so 2^n |a|^2 ~ Exp(1)), from
+    PCG64(seed)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    sd = math.sqrt(0.5 / 2.0 ** n_qubits)
+    z = rng.standard_normal((n_batches, batch_len, 2)) * sd
+    return z[..., 0] + 1j * z[..., 1]
+
+
 def grid_ids(rows_cols, cells) -> list[int]:
     """Row-major ids of (r, c) cells on a rows x cols grid."""
     _, cols = rows_cols
