@@ -10,8 +10,8 @@ Engines (FP64 throughout):
                        slicing over cut bonds (per-path and partial-path amplitudes);
   E3  ``tn.linear_xeb_grad`` gradient of linear cross-entropy by autograd through E2.
 ``slices`` draws the seeded fraction of paths; ``metrics`` holds the error measures;
-``sampling`` is the fast frugal rejection sampler over open-qubit batches, its error estimate
-and the fraction-of-perfect-amplitudes mix.
+``sampling`` is the fast frugal rejection sampler over open-qubit batches and its error
+estimate.
 Every function is pinned by a test under ``tests/`` against something other than itself
 (closed forms, special cases, the other engine, finite differences, the paper's numbers).
 """

@@ -18,10 +18,6 @@ The same section gives the acceptance probability of a batch under Porter-Thomas
 1 - (1 - 1/M)^N_C, and the sampling error estimate of the next section (Methods, "Sampling
 from a non fully-thermalized Porter-Thomas distribution"): the sum of N p over the computed
 amplitudes with p > M / N, divided by the number of amplitudes computed.
-
-The low-fidelity mode of the Results ("Fraction of perfect fidelity amplitudes") samples the
-state f |psi><psi| + (1 - f) I / N: with probability f an exact sample, else a uniformly
-random bit-string; its coins and uniform bit-strings are inputs too.
 """
 from __future__ import annotations
 
@@ -82,8 +78,3 @@ def porter_thomas_acceptance(m: float, n_c: int) -> float:
 def porter_thomas_tail(m: float) -> float:
     """E[x 1(x > M)] = (M + 1) e^-M for x ~ Exp(1): the error estimate's Porter-Thomas value."""
     return (m + 1.0) * math.exp(-m)
-
-
-def low_fidelity_samples(exact, uniform, coins, fidelity: float) -> list[int]:
-    """Samples of f |psi><psi| + (1 - f) I / N: exact[i] where coins[i] < f, else uniform[i]."""
-    return [int(e) if float(c) < fidelity else int(x) for e, x, c in zip(exact, uniform, coins)]
