@@ -9,10 +9,13 @@ the FP64 oracle on sampled slices.
 
 Prints one JSON line: amplitudes/s (whole job), sustained TFLOP/s of the plan (8 real flops
 per complex multiply-add), the roofline of the dominant kernel measured with HIP events around
-its launches in the timed region, and the CPU oracle timed on a bounded sample.  A second
-workload, reported under "gradient", times the adjoint contraction: 96 jittered-fSim circuits
-on 4x4 to 6x6 grids (depth 1+12+1), linear XEB over 128 bit-strings each, amplitudes and
-gradients of every fSim angle in one call.
+its launches in the timed region, and the CPU oracle timed on a bounded sample (the only part
+that runs the oracle, together with the gradient's parity check).  Further workloads, each
+under its own key: "sampling" (frugal rejection sampling of one bit-string per open batch),
+"gradient" (the adjoint contraction: 96 jittered-fSim circuits on 4x4 to 6x6 grids, depth
+1+12+1, linear XEB over 128 bit-strings each, amplitudes and gradients of every fSim angle in
+one call) and "diamond" (the 70-qubit diamond at fidelity 1/8); "ceilings" holds the vendor
+GEMM and device copy rates of the same device.
 
     python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--bitstrings 4]
 """
@@ -164,6 +167,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-gradient", action="store_true", help="skip the gradient workload")
     ap.add_argument("--no-diamond", action="store_true", help="skip the diamond workload")
+    ap.add_argument("--no-sampling", action="store_true", help="skip the sampler workload")
     ap.add_argument("--no-autotune", action="store_true",
                     help="kernel choice by shape rules only (default: the library's autotuner "
                          "times the variants of every step during the warm-up call)")
@@ -226,14 +230,20 @@ def main():
     for p in precs:
         if p != "c64" and "c64" in results:
             res["speedup_%s_vs_c64" % p] = results[p]["value"] / results["c64"]["value"]
+    if not args.no_sampling:
+        res["sampling"] = run_sampling(grids[head].contract_amplitudes(all_bits[:4]),
+                                       r["value"])
+    grad_check = None
     if not args.no_gradient:
-        res["gradient"] = run_gradient(args)
+        res["gradient"], grad_check = run_gradient(args)
     if not args.no_diamond:
         res["diamond"] = run_diamond(args)
     if ceil:
         res["ceilings"] = ceil
     if not args.no_cpu_baseline:
         res.update(cpu_baseline(circ, grids, all_bits[:1], open_q, args.cpu_slices, rows, cols))
+        if grad_check is not None:
+            res["gradient"]["parity"] = gradient_parity(*grad_check)
     print(json.dumps(res), flush=True)
 
 
@@ -245,7 +255,6 @@ def run_diamond(args):
     import torch
 
     import rqc_inputs as R
-    from oracle import metrics
     from paper_1811_09599_amd import build_grid
 
     circ = R.diamond_rqc(24, 4001)
@@ -280,7 +289,7 @@ def run_diamond(args):
     a = grid.contract_amplitudes(bits[:B], fidelity=fid, seed=4700).cpu().numpy()
     grid.close()
     ref = build_grid(circ).contract_amplitudes(bits[:B], fidelity=fid, seed=4700).cpu().numpy()
-    err = metrics.amp_errors(a, ref, 70)
+    err = scaled_errors(a, ref)
     return {"workload": "70-qubit diamond lattice, depth 1+24+1 (bond 8), cut sweep (%d cut "
                         "link, %d slices), fidelity 1/%d, one amplitude per bit-string, %d "
                         "bit-strings per step, split-bf16" % (len(grid_cuts(circ)), S, S, B),
@@ -291,20 +300,85 @@ def run_diamond(args):
             "split_bf16_vs_c64": {"max_rel_err": err["max"], "median_rel_err": err["median"]}}
 
 
+def scaled_errors(a, ref):
+    """|a - ref| / max(|ref|, rms(ref)) per amplitude (the rms floor keeps tiny amplitudes of
+    the Porter-Thomas tail from dominating): max and median."""
+    import numpy as np
+
+    a, ref = np.ravel(a), np.ravel(ref)
+    rms = float(np.sqrt(np.mean(np.abs(ref) ** 2)))
+    e = np.abs(a - ref) / np.maximum(np.abs(ref), rms)
+    return {"max": float(e.max()), "median": float(np.median(e))}
+
+
+def run_sampling(amps7, amp_rate):
+    """Fast frugal rejection sampling (one bit-string per 64-amplitude open batch, M = 10):
+    the sampler's kernels on 2^20 synthetic Porter-Thomas batches of the 7x7 open batch (about
+    the paper's 10^6 samples), then on the 7x7 workload's own amplitudes.  Its parity with the
+    oracle is tested in tests/test_gpu_sampling.py."""
+    import math
+
+    import numpy as np
+    import torch
+
+    import rqc_inputs as R
+    from paper_1811_09599_amd import frugal_sample
+
+    n_q, m, nb, blen = 49, 10.0, 1 << 20, 64
+    amps = torch.from_numpy(R.porter_thomas_amplitudes(nb, blen, n_q, 6100)).cuda()
+    order_h, u_h = R.sampling_draws(nb, blen, blen, 6200)
+    order, u = torch.from_numpy(order_h).cuda(), torch.from_numpy(u_h).cuda()
+    acc, tail = frugal_sample(amps, order, u, n_q, m)
+    torch.cuda.synchronize()
+    reps = 20
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        frugal_sample(amps, order, u, n_q, m, sync=False)
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) * 1e-3 / reps
+    rate = float((acc >= 0).float().mean().item())
+    # algorithmic bytes: every amplitude read once, one round of 64 visits (order + u) per
+    # batch, the accepted value and the batch's partial sum written
+    by = nb * (blen * 16 + 64 * 12 + 4 + 8)
+    # paper's batch acceptance 1 - (1 - 1/M)^N_C; exact Porter-Thomas values for comparison
+    paper_acc = 1 - (1 - 1 / m) ** blen
+    pt_acc = 1 - (1 - (1 - math.exp(-m)) / m) ** blen
+    o7, u7 = R.sampling_draws(amps7.shape[0], blen, blen, 6300)
+    acc7, tail7 = frugal_sample(amps7, torch.from_numpy(o7).cuda(), torch.from_numpy(u7).cuda(),
+                                n_q, m)
+    del amps, order, u
+    return {"workload": "frugal rejection sampling, M = 10, the 64 open-qubit values of each "
+                        "batch visited in random order; 2^20 synthetic Porter-Thomas batches "
+                        "(n = 49)",
+            "metric": "samples/s", "value": rate * nb / sec, "unit": "samples/s",
+            "batches_per_s": nb / sec, "ms_per_call": 1e3 * sec,
+            "roofline": {"bound": "hbm", "achieved": round(by / sec / 1e9, 1),
+                         "peak": PEAK["hbm"][0], "unit": "GB/s",
+                         "frac": round(by / sec / 1e9 / PEAK["hbm"][0], 4), "traffic": None},
+            "acceptance": rate, "acceptance_paper_formula": paper_acc,
+            "acceptance_porter_thomas": pt_acc,
+            "tail_error": tail, "tail_error_porter_thomas": (m + 1) * math.exp(-m),
+            "on_7x7_amplitudes": {"batches": int(amps7.shape[0]),
+                                  "accepted": int((acc7 >= 0).sum().item()),
+                                  "tail_error": tail7,
+                                  "samples_per_s_at_headline_rate": amp_rate / blen * paper_acc}}
+
+
 def grid_cuts(circ):
     from paper_1811_09599_amd import plan_describe
     return plan_describe(circ)["cuts"]
 
 
 def run_gradient(args):
-    """Linear-XEB gradients of a batch of 96 fSim circuits (one contract_grad call = one step),
-    with the FP64 state-vector adjoint of the first 4x4 circuit as the parity check."""
+    """Linear-XEB gradients of a batch of 96 fSim circuits (one contract_grad call = one step).
+    Returns the result and, for the parity check of the CPU leg, the first 4x4 circuit with
+    its bit-strings, fSim angle gradients and cross-entropy."""
     import numpy as np
     import torch
 
     import rqc_inputs as R
-    from oracle import metrics
-    from oracle import statevector as E1
     from paper_1811_09599_amd import build_grid
 
     circs = R.fsim_batch(96, depth=12, sizes=(4, 5, 6), seed=5000, jitter_seed0=5900)
@@ -334,7 +408,7 @@ def run_gradient(args):
                    "gbps": round(v["bytes"] / max(v["ms"], 1e-9) / 1e6, 1)} for k, v in top}
     i4 = next(i for i, c in enumerate(circs) if c["n_qubits"] == 16)
     fsim = [j for j, gt in enumerate(circs[i4]["gates"]) if gt["kind"] == "fsim"]
-    f_ref, g_ref = E1.linear_xeb_grad(circs[i4], bits[i4])
+    check = (i4, circs[i4], bits[i4], res["grad_params"][i4][fsim], float(res["loss"][i4]))
     sizes = np.bincount([c["n_qubits"] for c in circs])
     return {"workload": "96 fSim circuits, grids 4x4..6x6 (rows, cols from {4,5,6}), depth "
                         "1+12+1, theta = pi/2 + N(0, 0.02), phi = pi/6 + N(0, 0.02), linear "
@@ -344,10 +418,7 @@ def run_gradient(args):
             "steps": steps, "ms_per_step": 1e3 * dt / steps,
             "qubits_histogram": {str(n): int(k) for n, k in enumerate(sizes) if k},
             "tflops": flops / dt / 1e12, "dominant_kernel": dom, "roofline": roof,
-            "kernels": kernels, "grid_build_s": build_s,
-            "parity": {"circuit": i4, "oracle": "state-vector adjoint (FP64)",
-                       "grad_rel_l2": metrics.rel_l2(res["grad_params"][i4][fsim], g_ref),
-                       "loss_abs_err": abs(float(res["loss"][i4]) - f_ref), "tol": 1e-3}}
+            "kernels": kernels, "grid_build_s": build_s}, check
 
 
 def cpu_baseline(circ, grids, bits, open_q, n_slices, rows, cols):
@@ -383,6 +454,17 @@ def cpu_baseline(circ, grids, bits, open_q, n_slices, rows, cols):
                                        "network, no reuse across slices), %.1f s; rate "
                                        "extrapolated to all %d slices" % (len(ids), S, dt, S)},
             "parity": parity}
+
+
+def gradient_parity(i, circ, bits, grad, loss):
+    """CPU leg: the gradient workload's circuit i against the FP64 state-vector adjoint."""
+    from oracle import metrics
+    from oracle import statevector as E1
+
+    f_ref, g_ref = E1.linear_xeb_grad(circ, bits)
+    return {"circuit": i, "oracle": "state-vector adjoint (FP64)",
+            "grad_rel_l2": metrics.rel_l2(grad, g_ref), "loss_abs_err": abs(loss - f_ref),
+            "tol": 1e-3}
 
 
 if __name__ == "__main__":

@@ -211,6 +211,35 @@ qflex_status qflex_contract_grad(qflex_grid* g, const uint8_t* bits, const int64
                                  double* grad_params, double* loss, int32_t out_on_device,
                                  void* stream);
 
+/* Fast frugal rejection sampling over open-qubit batches (paper, Methods, "Fast sampling
+ * technique"), and the sampling-error estimate of Methods, "Sampling from a non
+ * fully-thermalized Porter-Thomas distribution".  All pointers are device memory; the call
+ * enqueues two kernels on stream and returns (it allocates nothing).
+ *   amps       complex128 [n_batch][batch_len]: row b holds batch b's amplitudes, i.e. one
+ *              closed-qubit bit-string with every open-qubit value, as qflex_contract_amplitudes
+ *              writes them (batch_len = 2^n_open).
+ *   order      int32 [n_batch][n_c]: the open-qubit values batch b visits, in visiting order
+ *              (the caller's random subset without repetition, shuffled).
+ *   u          float64 [n_batch][n_c]: the uniform number in [0, 1) drawn for each visit.
+ *   n_qubits   n; N = 2^n is the dimension of the Hilbert space.
+ *   m          M > 0: visit j of batch b accepts its value s when u[b][j] * M < N * p, with
+ *              p = re*re + im*im of amps[b][s] (each operation rounded once), i.e. with
+ *              probability min(1, N p / M).  A batch stops at its first acceptance.
+ *   accepted   int32 [n_batch] out: the accepted open-qubit value; -1 if none of the n_c visits
+ *              accepts; -2 if a value in the batch's order row lies outside [0, batch_len)
+ *              (no visit of that batch is then taken).
+ *   partial    float64 [n_batch] scratch.
+ *   tail       float64 [1] out: the error estimate, sum of N p over every amplitude of every
+ *              batch with N p > M, divided by n_batch * batch_len (summed in FP64 in a fixed
+ *              order: the same value on every run).
+ * With n_batch = 0 nothing is enqueued (amps ... partial may then be NULL, tail is not
+ * written).  QFLEX_E_INVALID for NULL pointers, n_batch < 0, batch_len < 1, n_c < 0,
+ * n_qubits outside [1, 1000] or m <= 0 (or not finite). */
+qflex_status qflex_frugal_sample(const double* amps, int64_t n_batch, int64_t batch_len,
+                                 const int32_t* order, const double* u, int32_t n_c,
+                                 int32_t n_qubits, double m, int32_t* accepted, double* partial,
+                                 double* tail, void* stream);
+
 /* Statistics of the last contract call. */
 qflex_status qflex_last_stats(const qflex_grid* g, qflex_stats* out);
 

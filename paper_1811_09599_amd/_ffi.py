@@ -47,10 +47,13 @@ EXPORTS = ("qflex_build_grid", "qflex_num_slices", "qflex_plan_cuts", "qflex_pla
            "qflex_contract_amplitudes", "qflex_contract_grad", "qflex_last_stats",
            "qflex_set_profiling",
            "qflex_profile_read", "qflex_permute_c64", "qflex_gemm_split_c64",
-           "qflex_gemm_c64", "qflex_select_slices", "qflex_gemm_split_workspace",
-           "qflex_gemm_c64_workspace",
-           "qflex_gemm_variant", "qflex_grid_free",
-           "qflex_last_error")
+           "qflex_gemm_c64", "qflex_select_slices", "qflex_frugal_sample",
+           "qflex_gemm_split_workspace", "qflex_gemm_c64_workspace", "qflex_gemm_variant",
+           "qflex_grid_free", "qflex_last_error")
+# exports that do not return a qflex_status, with their return types
+NON_STATUS = {"qflex_gemm_split_workspace": C.c_int64, "qflex_gemm_c64_workspace": C.c_int64,
+              "qflex_gemm_variant": C.c_int32, "qflex_grid_free": None,
+              "qflex_last_error": C.c_char_p}
 
 _lib = None
 
@@ -92,20 +95,17 @@ def lib():
     L.qflex_gemm_c64.argtypes = [P, P, P, C.c_int64, C.c_int64, C.c_int64, C.c_int32, C.c_int32,
                                  C.c_int64, P, C.c_int64, P]
     L.qflex_gemm_c64_workspace.argtypes = [C.c_int64] * 4
-    L.qflex_gemm_c64_workspace.restype = C.c_int64
     L.qflex_gemm_variant.argtypes = [C.c_int64, C.c_int64, C.c_int64]
-    L.qflex_gemm_variant.restype = C.c_int32
     L.qflex_select_slices.argtypes = [C.c_int64, C.c_double, C.c_uint64, C.c_int32,
                                       C.POINTER(C.c_int64), C.c_int64, C.POINTER(C.c_int64)]
+    L.qflex_frugal_sample.argtypes = [P, C.c_int64, C.c_int64, P, P, C.c_int32, C.c_int32,
+                                      C.c_double, P, P, P, P]
     L.qflex_grid_free.argtypes = [P]
-    L.qflex_grid_free.restype = None
-    L.qflex_last_error.restype = C.c_char_p
     L.qflex_gemm_split_c64.argtypes = [P, P, P, C.c_int64, C.c_int64, C.c_int64, C.c_int32,
                                        C.c_int32, C.c_int64, C.c_int32, P, C.c_int64, P]
     L.qflex_gemm_split_workspace.argtypes = [C.c_int64] * 4
-    L.qflex_gemm_split_workspace.restype = C.c_int64
-    for name in EXPORTS[:-4]:
-        getattr(L, name).restype = C.c_int
+    for name in EXPORTS:
+        getattr(L, name).restype = NON_STATUS.get(name, C.c_int)
     _lib = L
     return L
 

@@ -16,7 +16,8 @@ CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libqflex.so")
 
-HIP_SOURCES = ["grid_kernels.hip", "permute.hip", "gemm.hip", "gemm_split.hip", "reduce.hip"]
+HIP_SOURCES = ["grid_kernels.hip", "permute.hip", "gemm.hip", "gemm_split.hip", "reduce.hip",
+               "sample.hip"]
 HOST_SOURCES = ["model.cpp", "plan.cpp", "exec.cpp", "exec_grad.cpp", "api.cpp"]
 ARCH = "gfx950"
 

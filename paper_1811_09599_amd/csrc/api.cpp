@@ -1,4 +1,5 @@
 // C entry points: argument checks, status codes, thread-local error messages.
+#include <cmath>
 #include <cstring>
 #include <new>
 #include <string>
@@ -374,6 +375,23 @@ qflex_status qflex_select_slices(int64_t total, double fidelity, uint64_t seed, 
     const auto v = qflex::select_slices(total, fidelity, seed, mode);
     *n = (int64_t)v.size();
     for (int64_t i = 0; i < (int64_t)v.size() && i < max_ids; ++i) ids[i] = v[i];
+  });
+}
+
+qflex_status qflex_frugal_sample(const double* amps, int64_t n_batch, int64_t batch_len,
+                                 const int32_t* order, const double* u, int32_t n_c,
+                                 int32_t n_qubits, double m, int32_t* accepted, double* partial,
+                                 double* tail, void* stream) {
+  return guarded([&] {
+    if (!tail || (n_batch > 0 && (!amps || !accepted || !partial || (n_c > 0 && (!order || !u)))))
+      qflex::fail(QFLEX_E_INVALID, "NULL argument");
+    if (n_batch < 0 || batch_len < 1 || n_c < 0)
+      qflex::fail(QFLEX_E_INVALID, "need n_batch >= 0, batch_len >= 1, n_c >= 0");
+    if (n_qubits < 1 || n_qubits > 1000) qflex::fail(QFLEX_E_INVALID, "n_qubits out of range");
+    if (!(m > 0.0) || !std::isfinite(m)) qflex::fail(QFLEX_E_INVALID, "M must be finite and > 0");
+    qflex::dev::frugal_sample(reinterpret_cast<const double2*>(amps), n_batch, batch_len, order,
+                              u, n_c, n_qubits, m, accepted, partial, tail,
+                              static_cast<hipStream_t>(stream));
   });
 }
 

@@ -176,5 +176,12 @@ void accumulate(const float2* res, const int64_t* r_off, int64_t r_bs, int64_t r
                 hipStream_t s);
 void fill_zero(double* p, int64_t n, hipStream_t s);
 
+// ---------------------------------------------------------------- sampling
+// Frugal rejection sampling over open-qubit batches: accepted[b] per batch, partial[b] the
+// batch's sum of N p over N p > M, *tail their sum over n_batch * batch_len (fixed order).
+void frugal_sample(const double2* amps, int64_t n_batch, int64_t batch_len, const int32_t* order,
+                   const double* u, int32_t n_c, int32_t n_qubits, double m, int32_t* accepted,
+                   double* partial, double* tail, hipStream_t s);
+
 }  // namespace dev
 }  // namespace qflex

@@ -313,3 +313,35 @@ except ImportError:  # pragma: no cover
 def build_grid(circuits, **kw) -> Grid:
     """qflex_build_grid."""
     return Grid(circuits, **kw)
+
+
+def frugal_sample(amps, order, u, n_qubits: int, m: float = 10.0, stream=None, sync=True):
+    """qflex_frugal_sample on device tensors: amps complex128 [n_batch, batch_len] (rows as
+    Grid.contract_amplitudes returns them), order int32 [n_batch, n_c], u float64
+    [n_batch, n_c].  Returns (accepted int32 [n_batch] on the device, -1 where a batch accepts
+    nothing, and the error estimate as a float).  With sync=False the call only enqueues the
+    kernels and returns the estimate as a one-element device tensor, without checking order
+    for values outside the batch (accepted then holds -2 for such batches)."""
+    import torch
+
+    if amps.dim() != 2 or amps.dtype != torch.complex128 or not amps.is_cuda:
+        raise ValueError("amps must be a complex128 CUDA tensor [n_batch, batch_len]")
+    nb, blen = amps.shape
+    if order.shape != u.shape or order.dim() != 2 or order.shape[0] != nb:
+        raise ValueError("order and u must both be [n_batch, n_c]")
+    if order.dtype != torch.int32 or u.dtype != torch.float64 or not (order.is_cuda and u.is_cuda):
+        raise ValueError("order must be int32 and u float64, on the device")
+    amps, order, u = amps.contiguous(), order.contiguous(), u.contiguous()
+    accepted = torch.empty(nb, dtype=torch.int32, device=amps.device)
+    partial = torch.empty(max(nb, 1), dtype=torch.float64, device=amps.device)
+    tail = torch.zeros(1, dtype=torch.float64, device=amps.device)
+    F.check(F.lib().qflex_frugal_sample(
+        C.c_void_p(amps.data_ptr()), nb, blen, C.c_void_p(order.data_ptr()),
+        C.c_void_p(u.data_ptr()), int(order.shape[1]), int(n_qubits), float(m),
+        C.c_void_p(accepted.data_ptr()), C.c_void_p(partial.data_ptr()),
+        C.c_void_p(tail.data_ptr()), _stream(stream)))
+    if not sync:
+        return accepted, tail
+    if nb and bool((accepted == -2).any()):
+        raise ValueError("order holds values outside [0, batch_len)")
+    return accepted, float(tail.item()) if nb else 0.0

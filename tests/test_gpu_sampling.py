@@ -1,0 +1,104 @@
+"""GPU: the frugal rejection sampler (qflex_frugal_sample) against the oracle, element by
+element: accepted values bit for bit (both sides decide u * M < N p in FP64 with the same
+roundings), the error estimate to 1e-12 relative (FP64 sums in different orders)."""
+import numpy as np
+import pytest
+
+import rqc_inputs as R
+from oracle import sampling as S
+from oracle import statevector as E1
+from paper_1811_09599_amd import build_grid, frugal_sample
+
+pytestmark = pytest.mark.gpu
+
+
+def _need_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _run(amps, order, u, n_q, m):
+    import torch
+    acc, tail = frugal_sample(torch.from_numpy(amps).cuda(), torch.from_numpy(order).cuda(),
+                              torch.from_numpy(u).cuda(), n_q, m)
+    return acc.cpu().numpy().tolist(), tail
+
+
+@pytest.mark.parametrize("nb,blen,nc,m", [(3000, 64, 64, 10.0), (3000, 64, 7, 3.0),
+                                          (1000, 256, 100, 10.0), (513, 64, 1, 1.5),
+                                          (5, 4096, 300, 10.0)])
+def test_sampler_matches_oracle_on_porter_thomas_batches(nb, blen, nc, m):
+    _need_gpu()
+    _say("frugal sampler", nb, blen, nc, m)
+    n_q = 30
+    amps = R.porter_thomas_amplitudes(nb, blen, n_q, 100 + nc)
+    order, u = R.sampling_draws(nb, blen, nc, 200 + nc)
+    got, tail = _run(amps, order, u, n_q, m)
+    assert got == S.frugal_sample(amps, order, u, n_q, m)
+    want = S.tail_error(amps, n_q, m)
+    assert abs(tail - want) <= 1e-12 * want
+    assert any(g >= 0 for g in got)
+
+
+def test_sampler_edge_cases():
+    _need_gpu()
+    import torch
+    _say("frugal sampler edge cases")
+    n_q = 8
+    amps = R.porter_thomas_amplitudes(40, 16, n_q, 3)
+    order, u = R.sampling_draws(40, 16, 16, 4)
+    # no visits: nothing accepted, the estimate still covers every amplitude
+    got, tail = _run(amps, order[:, :0].copy(), u[:, :0].copy(), n_q, 10.0)
+    assert got == [-1] * 40
+    assert abs(tail - S.tail_error(amps, n_q, 10.0)) <= 1e-12 * max(tail, 1e-300)
+    # no batches
+    acc, tail = frugal_sample(torch.zeros((0, 16), dtype=torch.complex128, device="cuda"),
+                              torch.zeros((0, 3), dtype=torch.int32, device="cuda"),
+                              torch.zeros((0, 3), dtype=torch.float64, device="cuda"), n_q)
+    assert acc.numel() == 0 and tail == 0.0
+    # huge probabilities: the first visit always accepts; zeros: never
+    big = np.full((40, 16), np.sqrt(20.0 / 2 ** n_q), dtype=complex)
+    got, tail = _run(big, order, u, n_q, 10.0)
+    assert got == order[:, 0].tolist() and abs(tail - 20.0) < 1e-12
+    got, _ = _run(np.zeros((40, 16), dtype=complex), order, u, n_q, 10.0)
+    assert got == [-1] * 40
+    # a value outside the batch marks its batch and the binding refuses the result
+    bad = order.copy()
+    bad[7, 3] = 16
+    with pytest.raises(ValueError):
+        _run(amps, bad, u, n_q, 10.0)
+
+
+def test_sampler_on_contracted_open_batches():
+    """End to end: 4x4 RQC amplitudes with a 4-qubit open batch (16 values per closed
+    bit-string) from the contraction, sampled on the device; the oracle takes the same
+    amplitudes (bit-exact decisions) and the state vector's own amplitudes (decisions agree
+    except where u * M and N p nearly tie)."""
+    _need_gpu()
+    import torch
+    _say("frugal sampler on 4x4 open batches")
+    c = R.grid_rqc(4, 4, 16, 1000)
+    op = [12, 13, 14, 15]
+    bits = R.bitstrings(16, 400, 1500, op)
+    g = build_grid(c, open_qubits=op)
+    amps = g.contract_amplitudes(bits, device=True)
+    order, u = R.sampling_draws(400, 16, 16, 1700)
+    acc, tail = frugal_sample(amps, torch.from_numpy(order).cuda(), torch.from_numpy(u).cuda(),
+                              16, 10.0)
+    acc = acc.cpu().numpy().tolist()
+    a_host = amps.cpu().numpy()
+    assert acc == S.frugal_sample(a_host, order, u, 16, 10.0)
+    assert abs(tail - S.tail_error(a_host, 16, 10.0)) <= 1e-12 * tail
+    ref = E1.amplitudes(c, bits, op)
+    assert np.max(np.abs(a_host - ref)) * 2 ** 8 < 1e-5
+    same = np.mean(np.array(acc) == np.array(S.frugal_sample(ref, order, u, 16, 10.0)))
+    assert same >= 0.99
+    # at depth 16 the 4x4 output is close to Porter-Thomas: acceptance near 1 - 0.9^16
+    rate = np.mean(np.array(acc) >= 0)
+    assert abs(rate - S.batch_acceptance(10.0, 16)) < 0.1
+    g.close()

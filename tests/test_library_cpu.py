@@ -254,3 +254,30 @@ def test_cut_sweep_cuts_until_the_cap():
         assert d["kind"] == "cut_sweep"
         assert d["max_bits"] <= cap_bits and d["cuts"]
     assert not plan_describe(c, plan="cut_sweep", max_tensor_elems=1 << 10)["cuts"]  # fits
+
+
+def test_frugal_sample_rejects_bad_arguments_before_any_launch():
+    L = F.lib()
+    P = C.c_void_p
+    one = P(16)  # never dereferenced: every call below fails its argument checks first
+    cases = [
+        (None, 4, 16, one, one, 2, 10, 10.0),   # NULL amps
+        (one, -1, 16, one, one, 2, 10, 10.0),   # n_batch < 0
+        (one, 4, 0, one, one, 2, 10, 10.0),     # batch_len < 1
+        (one, 4, 16, one, one, -1, 10, 10.0),   # n_c < 0
+        (one, 4, 16, None, one, 2, 10, 10.0),   # NULL order with visits
+        (one, 4, 16, one, one, 2, 0, 10.0),     # n_qubits < 1
+        (one, 4, 16, one, one, 2, 10, 0.0),     # M <= 0
+        (one, 4, 16, one, one, 2, 10, float("nan")),
+        (one, 4, 16, one, one, 2, 10, float("inf")),
+    ]
+    for a, nb, bl, o, u, nc, nq, m in cases:
+        st = L.qflex_frugal_sample(a, nb, bl, o, u, nc, nq, m, one, one, one, None)
+        assert st == F.E_INVALID, (nb, bl, nc, nq, m)
+
+
+def test_workspace_sizes_are_64_bit():
+    """Sizes above 2^31 bytes come back whole (the size queries return int64_t)."""
+    L = F.lib()
+    assert L.qflex_gemm_split_workspace(1 << 16, 1 << 16, 1 << 12, 1) == \
+        256 + 2 * 4 * ((1 << 28) + (1 << 28))
