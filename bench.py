@@ -11,7 +11,8 @@ Prints one JSON line: amplitudes/s (whole job), sustained TFLOP/s of the plan (8
 per complex multiply-add), the roofline of the dominant kernel measured with HIP events around
 its launches in the timed region, and the CPU oracle timed on a bounded sample (the only part
 that runs the oracle, together with the gradient's parity check).  Further workloads, each
-under its own key: "sampling" (frugal rejection sampling of one bit-string per open batch),
+under its own key: "fsim_7x7" (the headline workload with fSim couplers at depth 1+16+1),
+"sampling" (frugal rejection sampling of one bit-string per open batch),
 "gradient" (the adjoint contraction: 96 jittered-fSim circuits on 4x4 to 6x6 grids, depth
 1+12+1, linear XEB over 128 bit-strings each, amplitudes and gradients of every fSim angle in
 one call) and "diamond" (the 70-qubit diamond at fidelity 1/8); "ceilings" holds the vendor
@@ -168,6 +169,7 @@ def main():
     ap.add_argument("--no-gradient", action="store_true", help="skip the gradient workload")
     ap.add_argument("--no-diamond", action="store_true", help="skip the diamond workload")
     ap.add_argument("--no-sampling", action="store_true", help="skip the sampler workload")
+    ap.add_argument("--no-fsim", action="store_true", help="skip the 7x7 fSim workload")
     ap.add_argument("--no-autotune", action="store_true",
                     help="kernel choice by shape rules only (default: the library's autotuner "
                          "times the variants of every step during the warm-up call)")
@@ -230,6 +232,19 @@ def main():
     for p in precs:
         if p != "c64" and "c64" in results:
             res["speedup_%s_vs_c64" % p] = results[p]["value"] / results["c64"]["value"]
+    if not args.no_fsim:
+        # fSim couplers at half the depth: the same bond dimensions, plan and flops (1+t/2+1)
+        circ_f = R.grid_rqc(rows, cols, 16, 2002, two_qubit="fsim", jitter_sd=0.02,
+                            jitter_seed=3)
+        g_f, r_f = run_precision(head, circ_f, open_q, all_bits, args)
+        g_f.close()
+        res["fsim_7x7"] = {
+            "workload": "7x7 RQC with fSim(pi/2 + N(0, 0.02), pi/6 + N(0, 0.02)) couplers, depth "
+                        "1+16+1 (bond dim 16, the CZ 1+32+1 plan), %s, other settings as the "
+                        "headline" % head,
+            "metric": "amplitudes/s", "unit": "amplitudes/s",
+            **{k: r_f[k] for k in ("value", "ms_per_step", "tflops", "dominant_kernel",
+                                   "roofline")}}
     if not args.no_sampling:
         res["sampling"] = run_sampling(grids[head].contract_amplitudes(all_bits[:4]),
                                        r["value"])

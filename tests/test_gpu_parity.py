@@ -209,6 +209,27 @@ def test_cfg2_7x7_depth32_sampled_slices_vs_oracle():
     _check(a, ref, 49)
 
 
+@pytest.mark.parametrize("prec", ["c64", "split_bf16"])
+def test_fsim_7x7_depth16_sampled_slices_vs_oracle(prec):
+    """fSim couplers (rank-4 bonds, 2 bond bits per gate): a 1+16+1 fSim circuit has the bond
+    dimensions of a 1+32+1 CZ circuit (16 per link), and its 7x7 contraction runs the same
+    quadrant plan, checked slice by slice against the FP64 contraction."""
+    _need_gpu()
+    _say(prec, "7x7 fSim 1+16+1 per-slice parity")
+    c = R.grid_rqc(7, 7, 16, 2002, two_qubit="fsim", jitter_sd=0.02, jitter_seed=3)
+    op = R.grid_ids((7, 7), [(5, 0), (5, 1), (5, 2), (6, 0), (6, 1), (6, 2)])
+    bits = R.bitstrings(49, 1, 2501, op)
+    g = build_grid(c, open_qubits=op, precision=prec)
+    assert g.num_slices() == 256
+    ids = [11, 190]
+    a = g.contract_amplitudes(bits, slice_ids=ids).cpu().numpy()
+    ref = E2.amplitudes(c, bits, op, cuts=g.plan_cuts(), slice_ids=ids,
+                        order=E2.quadrant_order(7, 7))
+    _say("oracle done")
+    e = _check(a, ref, 49, SPLIT_TOL.get(prec, 1e-5))
+    _say("  error", e)
+
+
 # ------------------------------------------------------------------- cut sweeps
 @pytest.mark.parametrize("layout", ["grid4x5", "diamond15"])
 def test_cut_sweep_all_slices_vs_state_vector(layout):

@@ -281,3 +281,15 @@ def test_workspace_sizes_are_64_bit():
     L = F.lib()
     assert L.qflex_gemm_split_workspace(1 << 16, 1 << 16, 1 << 12, 1) == \
         256 + 2 * 4 * ((1 << 28) + (1 << 28))
+
+
+def test_fsim_half_depth_plans_like_cz_full_depth():
+    """A two-qubit fSim gate has a rank-4 bond decomposition (2 bond bits) where CZ has rank 2,
+    so a 1+t/2+1 fSim circuit collapses to the bond dimensions of a 1+t+1 CZ circuit: on the
+    7x7 grid both get the same quadrant plan, cuts, slices and flops."""
+    op = R.grid_ids((7, 7), [(5, 0), (5, 1), (5, 2), (6, 0), (6, 1), (6, 2)])
+    cz = plan_describe(R.grid_rqc(7, 7, 32, 2001), open_qubits=op)
+    fs = plan_describe(R.grid_rqc(7, 7, 16, 2002, two_qubit="fsim", jitter_sd=0.02,
+                                  jitter_seed=3), open_qubits=op)
+    for key in ("kind", "cuts", "num_slices", "max_bits", "flops_all_slices"):
+        assert cz[key] == fs[key], key
