@@ -107,9 +107,40 @@ def ceilings():
     out["device_copy_gbps"] = round(2.0 * 4 * src.numel() / timed(lambda: dst.copy_(src), 10)
                                     / 1e9, 1)
     del src, dst
-    out["note"] = ("hipBLASLt via torch.matmul at 8192^3 on random operands, and a 1 GiB device "
-                   "copy, timed in this run: practical ceilings of this device next to the "
-                   "published peaks")
+    # the library's split-bf16 product (qflex_gemm_split_c64 with A given transposed, so that
+    # both operands are split by a pass of their own and the product kernel is the pre-split
+    # one the headline's square steps run; the passes are included) on the 7x7 workload's
+    # square shape, on random and then on constant operands: the same launches, differing only
+    # in how many bits the data toggles
+    import ctypes as C
+
+    from paper_1811_09599_amd import _ffi as F
+    L = F.lib()
+    m, b = 4096, 4
+    a = torch.randn(b, m, m, dtype=torch.complex64, device="cuda")
+    bb = torch.randn(b, m, m, dtype=torch.complex64, device="cuda")
+    c = torch.empty_like(a)
+    nws = L.qflex_gemm_split_workspace(m, m, m, b)
+    ws = torch.empty(nws, dtype=torch.uint8, device="cuda")
+    strm = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+    def split_product():
+        F.check(L.qflex_gemm_split_c64(C.c_void_p(a.data_ptr()), C.c_void_p(bb.data_ptr()),
+                                       C.c_void_p(c.data_ptr()), m, m, m, 1, 0, b,
+                                       F.PREC["split_bf16"], C.c_void_p(ws.data_ptr()), nws,
+                                       strm))
+
+    flops = 24.0 * m ** 3 * b  # 3 real products per complex product on 16-bit MFMA
+    out["split_bf16_4096cube_x4_random_tflops"] = round(flops / timed(split_product, 5) / 1e12, 1)
+    a.fill_(complex(0.75, -0.5))
+    bb.fill_(complex(0.25, 0.5))
+    out["split_bf16_4096cube_x4_constant_tflops"] = round(flops / timed(split_product, 5) / 1e12,
+                                                          1)
+    del a, bb, c, ws
+    out["note"] = ("hipBLASLt via torch.matmul at 8192^3 on random operands, a 1 GiB device "
+                   "copy, and this library's split-bf16 product on random vs constant "
+                   "operands, timed in this run: practical ceilings of this device next to the "
+                   "published peaks (the product's MFMA rate depends on the data's power draw)")
     return out
 
 
