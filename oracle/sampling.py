@@ -10,8 +10,8 @@ acceptance (at most one bit-string per batch) or when its N_C values are used up
 
 Random numbers are inputs: ``order[b]`` lists the batch's N_C visited values in visiting
 order (a random subset without repetition, already shuffled), ``u[b][j]`` is the uniform
-number in [0, 1) drawn for the j-th visit.  "Accept with probability a" reads as u < a; with
-a = min(1, N p / M) and u < 1 this is u * M < N * p, the form used here (N * p is exact for
+number in [0, 1) drawn for the j-th visit.  Acceptance with probability a is read as u < a;
+with a = min(1, N p / M) and u < 1 this is u * M < N * p, the form used here (N * p is exact for
 N a power of two, so the decision is one rounding of u * M against an exactly scaled p).
 
 The same section gives the acceptance probability of a batch under Porter-Thomas statistics,
