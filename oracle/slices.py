@@ -1,7 +1,7 @@
 """Seeded choice of a fraction of the paths.  TEST INFRASTRUCTURE (see ``oracle/__init__.py``).
 
 The paper sums a randomly chosen fraction f of the paths to obtain fidelity-f amplitudes
-(Methods C.1).  Reading used for "randomly chosen", so that both sides can draw the same
+(Methods C.1).  Reading used for the random choice, so that both sides can draw the same
 subset from a seed: k = f * S must be an integer >= 1; shuffle [0, S) with Fisher-Yates
 (i from S-1 down to 1, j = next() mod (i + 1), swap a[i], a[j]) driven by SplitMix64
 (Steele, Lea and Flood, "Fast splittable pseudorandom number generators", OOPSLA 2014:
