@@ -209,6 +209,35 @@ def test_cfg2_7x7_depth32_sampled_slices_vs_oracle():
     _check(a, ref, 49)
 
 
+def test_bench_launch_configuration_7x7():
+    """The headline's own configuration: the bench circuit and its first step (4 bit-strings
+    in one call, all 256 slices, autotuned split-bf16 products).  At that size the FP64 oracle
+    affords single slices only, so: (1) two slices of the 4-bit-string call match the oracle;
+    (2) the all-slice call equals the sum of its 256 single-slice calls (a property at any
+    size: the amplitude is the sum of its paths)."""
+    _need_gpu()
+    _say("bench configuration: 7x7 1+32+1, 4 bit-strings, all slices, split-bf16, autotune")
+    c = R.grid_rqc(7, 7, 32, 2000)
+    op = R.grid_ids((7, 7), [(5, 0), (5, 1), (5, 2), (6, 0), (6, 1), (6, 2)])
+    bits = R.bitstrings(49, 1024, 2500, op)[:4]
+    g = build_grid(c, open_qubits=op, precision="split_bf16", autotune=True)
+    full = g.contract_amplitudes(bits).cpu().numpy()  # tunes on this call
+    full = g.contract_amplitudes(bits).cpu().numpy()
+    cuts = g.plan_cuts()
+    order = E2.quadrant_order(7, 7)
+    for sid in (5, 250):
+        one = g.contract_amplitudes(bits, slice_ids=[sid]).cpu().numpy()
+        ref = E2.amplitudes(c, bits[:1], op, cuts=cuts, slice_ids=[sid], order=order)
+        e = _check(one[:1], ref, 49, SPLIT_TOL["split_bf16"])
+        _say("  slice", sid, e)
+    total = np.zeros_like(full)
+    for sid in range(g.num_slices()):
+        total += g.contract_amplitudes(bits, slice_ids=[sid]).cpu().numpy()
+    e = _check(full, total, 49, SPLIT_TOL["split_bf16"])
+    _say("  all slices vs sum of single slices", e)
+    g.close()
+
+
 @pytest.mark.parametrize("prec", ["c64", "split_bf16"])
 def test_fsim_7x7_depth16_sampled_slices_vs_oracle(prec):
     """fSim couplers (rank-4 bonds, 2 bond bits per gate): a 1+16+1 fSim circuit has the bond
