@@ -77,8 +77,12 @@ typedef enum {
 } qflex_gate_kind;
 
 typedef enum {
-  QFLEX_PLAN_AUTO = 0,     /* SWEEP if it fits max_tensor_elems, else QUADRANT on a full
-                              rectangular grid, else CUT_SWEEP */
+  QFLEX_PLAN_AUTO = 0,     /* of SWEEP, QUADRANT (full rectangular grids) and CUT_SWEEP, the
+                              kinds that fit max_tensor_elems, the one with the lowest
+                              estimated time (qflex_plan_describe's cost_estimate_s: per step
+                              and slice, the slowest of its flops at a sustained product rate,
+                              its bytes at a streaming rate and its launches); ties go to the
+                              earlier kind in that list */
   QFLEX_PLAN_SWEEP = 1,    /* absorb every qubit into one tensor, no cuts */
   QFLEX_PLAN_QUADRANT = 2, /* four regions A|B over C|D, one cut between B and D in the last
                               column and one between C and D in the last row (SI A) */

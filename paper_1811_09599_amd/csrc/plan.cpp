@@ -672,6 +672,24 @@ struct Planner {
     (void)ns;
     P.flops_all_slices = 0;
     for (auto& st : P.steps) P.flops_all_slices += st.flops() * mult(st.deps);
+    // sustained rates measured on MI355X: complex64 products on FP32 MFMA tiles (M, N >= 64,
+    // K >= 16), products left to the vector units, a device-to-device stream, and the
+    // smallest time a dependent kernel launch takes
+    constexpr double kTileFlops = 135e12, kVectorFlops = 20e12, kStreamBytes = 5e12,
+                     kLaunch = 5e-6;
+    P.cost_estimate = 0;
+    for (auto& st : P.steps) {
+      const double M = std::ldexp(1.0, st.mb), K = std::ldexp(1.0, st.kb),
+                   N = std::ldexp(1.0, st.nb);
+      const bool tiles = st.mb >= 6 && st.nb >= 6 && st.kb >= 4;
+      double bytes = 8.0 * (M * K + K * N + M * N);
+      if (st.scratch_x >= 0) bytes += 16.0 * M * K;
+      if (st.scratch_y >= 0) bytes += 16.0 * K * N;
+      const int launches = 1 + (st.scratch_x >= 0) + (st.scratch_y >= 0);
+      P.cost_estimate +=
+          mult(st.deps) * std::max({st.flops() / (tiles ? kTileFlops : kVectorFlops),
+                                    bytes / kStreamBytes, launches * kLaunch});
+    }
   }
 
   Plan run() {
@@ -691,19 +709,25 @@ struct Planner {
     cut_of_link.assign(m.links.size(), -1);
     int kind = opt.plan_kind;
     if (kind == QFLEX_PLAN_AUTO) {
-      kind = QFLEX_PLAN_CUT_SWEEP;
-      for (int k : {QFLEX_PLAN_SWEEP, QFLEX_PLAN_QUADRANT}) {
+      // every kind that fits the memory cap, the one with the lowest estimated time (on a tie
+      // the earlier of sweep, quadrant, cut sweep)
+      Plan best;
+      bool found = false;
+      std::string why;
+      for (int k : {QFLEX_PLAN_SWEEP, QFLEX_PLAN_QUADRANT, QFLEX_PLAN_CUT_SWEEP}) {
         try {
           qflex_options o2 = opt;
           o2.plan_kind = k;
           Planner t2(m, o2);
-          t2.run();
-          kind = k;
-          break;
+          Plan c = t2.run();
+          if (!found || c.cost_estimate < best.cost_estimate) best = std::move(c), found = true;
         } catch (const Error& e) {
           if (e.status != QFLEX_E_PLAN) throw;
+          why = e.what();
         }
       }
+      if (!found) fail(QFLEX_E_PLAN, why);
+      return best;
     }
     P.kind = kind;
     std::vector<std::pair<bool, std::vector<int>>> segs;
@@ -801,6 +825,7 @@ std::string Plan::describe(const Model& m) const {
       << cut_bits[i] << "]";
   o << "],\"num_slices\":" << num_slices() << ",\"max_bits\":" << max_bits
     << ",\"arena_elems\":" << arena_elems << ",\"flops_all_slices\":" << flops_all_slices
+    << ",\"cost_estimate_s\":" << cost_estimate
     << ",\"steps\":[";
   for (size_t i = 0; i < steps.size(); ++i) {
     const Step& s = steps[i];

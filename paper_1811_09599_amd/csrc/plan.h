@@ -73,6 +73,11 @@ struct Plan {
   int max_bits = 0;
   int64_t arena_elems = 0;     // per bit-string
   double flops_all_slices = 0; // per bit-string, f = 1, with reuse across slices
+  // estimated seconds per bit-string at f = 1 (the automatic plan choice compares these):
+  // every step, as often as it runs over the slices, at the slower of its arithmetic (at
+  // the sustained rate of the kernel class its shape gets) and its memory traffic (operands,
+  // result and permuted copies at the device's streaming rate)
+  double cost_estimate = 0;
 
   int out_label(int q) const { return total_link_bits + q; }
   int64_t num_slices() const {

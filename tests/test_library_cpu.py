@@ -293,3 +293,28 @@ def test_fsim_half_depth_plans_like_cz_full_depth():
                                   jitter_seed=3), open_qubits=op)
     for key in ("kind", "cuts", "num_slices", "max_bits", "flops_all_slices"):
         assert cz[key] == fs[key], key
+
+
+def test_automatic_plan_is_the_cheapest_that_fits():
+    """The automatic choice builds every plan kind that fits the memory cap and keeps the one
+    with the lowest estimated time: a small grid sweeps without cuts, the 7x7 D=16 grid takes
+    the quadrant plan, the diamond the only kind that fits it, and on the 6x6 depth-32 grid,
+    where an uncut sweep fits but runs 2^20-element intermediates through every step, the
+    quadrant plan with two cuts is estimated faster and chosen."""
+    op7 = R.grid_ids((7, 7), [(5, 0), (5, 1), (5, 2), (6, 0), (6, 1), (6, 2)])
+    cases = [(R.grid_rqc(4, 4, 16, 1), (), "sweep"),
+             (R.grid_rqc(7, 7, 32, 2000), op7, "quadrant"),
+             (R.diamond_rqc(24, 4001), (), "cut_sweep"),
+             (R.grid_rqc(6, 6, 32, 77), (), "quadrant")]
+    for c, op, want in cases:
+        auto = plan_describe(c, open_qubits=op)
+        assert auto["kind"] == want
+        costs = {}
+        for k in ("sweep", "quadrant", "cut_sweep"):
+            try:
+                costs[k] = plan_describe(c, open_qubits=op, plan=k)["cost_estimate_s"]
+            except F.QflexError as e:
+                assert e.status == F.E_PLAN
+        assert auto["cost_estimate_s"] == min(costs.values()) == costs[want]
+    # an uncut sweep fits the 6x6 depth-32 grid too: the choice was a matter of cost
+    assert plan_describe(R.grid_rqc(6, 6, 32, 77), plan="sweep")["cuts"] == []
