@@ -14,6 +14,12 @@ number in [0, 1) drawn for the j-th visit.  Acceptance with probability a is rea
 with a = min(1, N p / M) and u < 1 this is u * M < N * p, the form used here (N * p is exact for
 N a power of two, so the decision is one rounding of u * M against an exactly scaled p).
 
+Fidelity-f samples by the Results' second method ("Fraction of perfect fidelity amplitudes"):
+the state f |psi><psi| + (1 - f) I / N is sampled by taking, per batch, an exact sample with
+probability f (the batch's amplitudes at full fidelity through the sampler above) and a
+uniformly random bit-string otherwise.  The coin per batch and the uniform bit-strings are
+inputs, like the sampler's random numbers.
+
 The same section gives the acceptance probability of a batch under Porter-Thomas statistics,
 1 - (1 - 1/M)^N_C, and the sampling error estimate of the next section (Methods, "Sampling
 from a non fully-thermalized Porter-Thomas distribution"): the sum of N p over the computed
@@ -78,3 +84,30 @@ def porter_thomas_acceptance(m: float, n_c: int) -> float:
 def porter_thomas_tail(m: float) -> float:
     """E[x 1(x > M)] = (M + 1) e^-M for x ~ Exp(1): the error estimate's Porter-Thomas value."""
     return (m + 1.0) * math.exp(-m)
+
+
+def fidelity_samples(exact_amps, closed_bits, open_qubits, coins, uniform_bits, order, u,
+                     n_qubits: int, m: float, fidelity: float):
+    """Per batch b: status 1 and the exact sample (closed_bits[b] with the accepted open value
+    written into open_qubits, the first open qubit most significant) when coins[b] < f and the
+    batch accepts a value; status -1 and no sample when coins[b] < f but none is accepted; status
+    0 and uniform_bits[b] otherwise.  exact_amps[b] holds batch b's amplitudes and is read only
+    where coins[b] < f."""
+    no = len(open_qubits)
+    samples, status = [], []
+    for b in range(len(coins)):
+        if float(coins[b]) < fidelity:
+            pick = frugal_sample([exact_amps[b]], [order[b]], [u[b]], n_qubits, m)[0]
+            if pick < 0:
+                samples.append(None)
+                status.append(-1)
+                continue
+            x = [int(v) for v in closed_bits[b]]
+            for t, q in enumerate(open_qubits):
+                x[q] = (pick >> (no - 1 - t)) & 1
+            samples.append(x)
+            status.append(1)
+        else:
+            samples.append([int(v) for v in uniform_bits[b]])
+            status.append(0)
+    return samples, status

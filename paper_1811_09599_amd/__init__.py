@@ -3,8 +3,8 @@
 The compute path is libqflex.so (HIP kernels behind the C ABI in include/qflex.h); this
 package only marshals arguments to it.  Nothing here falls back to a CPU implementation.
 """
-from .qflex import (Grid, build_grid, frugal_sample, plan_describe,  # noqa: F401
-                    with_fsim_angles)
+from .qflex import (Grid, build_grid, fidelity_samples, frugal_sample,  # noqa: F401
+                    plan_describe, with_fsim_angles)
 try:
     from .qflex import Amplitudes  # noqa: F401
 except ImportError:  # pragma: no cover

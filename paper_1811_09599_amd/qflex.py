@@ -345,3 +345,43 @@ def frugal_sample(amps, order, u, n_qubits: int, m: float = 10.0, stream=None, s
     if nb and bool((accepted == -2).any()):
         raise ValueError("order holds values outside [0, batch_len)")
     return accepted, float(tail.item()) if nb else 0.0
+
+
+def fidelity_samples(grid: Grid, closed_bits, coins, uniform_bits, order, u, fidelity: float,
+                     m: float = 10.0):
+    """Fidelity-f samples (paper, Results, "Fraction of perfect fidelity amplitudes") by the
+    frugal sampler: batch b (closed_bits[b], the open qubits' values ignored) gives an exact
+    sample when coins[b] < f, else uniform_bits[b].  Only the exact batches are contracted, at
+    full fidelity, and sampled on the device (qflex_contract_amplitudes, qflex_frugal_sample);
+    the accepted open value is written into the open qubits, the first open qubit most
+    significant.  One circuit per grid.  order / u: [n_batch, n_c] visit order and uniforms
+    (rows of uniform batches are not used).  Returns (samples uint8 [n_batch, n], status int8
+    [n_batch]: 1 exact sample, 0 uniform sample, -1 exact batch that accepted nothing)."""
+    import torch
+
+    if len(grid.circuits) != 1:
+        raise ValueError("fidelity_samples needs a grid of one circuit")
+    closed_bits = np.asarray(closed_bits, dtype=np.uint8)
+    uniform_bits = np.asarray(uniform_bits, dtype=np.uint8)
+    coins = np.asarray(coins, dtype=np.float64)
+    nb, n = closed_bits.shape
+    exact = np.nonzero(coins < fidelity)[0]
+    samples = uniform_bits.copy()
+    status = np.zeros(nb, dtype=np.int8)
+    if len(exact):
+        amps = grid.contract_amplitudes(closed_bits[exact])
+        o = torch.from_numpy(np.ascontiguousarray(np.asarray(order, dtype=np.int32)[exact])).cuda()
+        w = torch.from_numpy(np.ascontiguousarray(np.asarray(u, dtype=np.float64)[exact])).cuda()
+        acc, _ = frugal_sample(amps, o, w, n, m)
+        acc = acc.cpu().numpy()
+        op = list(grid.open_qubits)
+        for i, b in enumerate(exact):
+            if acc[i] < 0:
+                status[b] = -1
+                continue
+            x = closed_bits[b].copy()
+            for t, q in enumerate(op):
+                x[q] = (acc[i] >> (len(op) - 1 - t)) & 1
+            samples[b] = x
+            status[b] = 1
+    return samples, status

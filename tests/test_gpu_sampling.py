@@ -7,7 +7,7 @@ import pytest
 import rqc_inputs as R
 from oracle import sampling as S
 from oracle import statevector as E1
-from paper_1811_09599_amd import build_grid, frugal_sample
+from paper_1811_09599_amd import build_grid, fidelity_samples, frugal_sample
 
 pytestmark = pytest.mark.gpu
 
@@ -101,4 +101,36 @@ def test_sampler_on_contracted_open_batches():
     # at depth 16 the 4x4 output is close to Porter-Thomas: acceptance near 1 - 0.9^16
     rate = np.mean(np.array(acc) >= 0)
     assert abs(rate - S.batch_acceptance(10.0, 16)) < 0.1
+    g.close()
+
+
+def test_fidelity_samples_match_oracle():
+    """Fidelity-f samples of a 4x4 RQC with a 4-qubit open batch: the device path contracts only
+    the exact batches; the oracle composes the same coins, draws and uniform bit-strings with
+    the device's amplitudes (bit-exact) and with the state vector's (agreement but for ties)."""
+    _need_gpu()
+    import torch  # noqa: F401
+    _say("fidelity-f samples, 4x4")
+    c = R.grid_rqc(4, 4, 16, 1001)
+    op = [12, 13, 14, 15]
+    nb, f = 600, 0.3
+    closed = R.bitstrings(16, nb, 1600, op)
+    uniform = R.bitstrings(16, nb, 1601)
+    rng = np.random.Generator(np.random.PCG64(1602))
+    coins = rng.random(nb)
+    order, u = R.sampling_draws(nb, 16, 16, 1603)
+    g = build_grid(c, open_qubits=op)
+    samples, status = fidelity_samples(g, closed, coins, uniform, order, u, f)
+    exact = coins < f
+    assert np.array_equal(status != 0, exact)
+    dev_amps = np.zeros((nb, 16), dtype=complex)
+    dev_amps[exact] = g.contract_amplitudes(closed[exact]).cpu().numpy()
+    ref_s, ref_st = S.fidelity_samples(dev_amps, closed, op, coins, uniform, order, u, 16, 10.0, f)
+    assert status.tolist() == ref_st
+    for b in range(nb):
+        if ref_st[b] != -1:
+            assert samples[b].tolist() == ref_s[b]
+    sv = E1.amplitudes(c, closed, op)
+    _, sv_st = S.fidelity_samples(sv, closed, op, coins, uniform, order, u, 16, 10.0, f)
+    assert np.mean(np.array(sv_st) == status) >= 0.99
     g.close()

@@ -101,3 +101,39 @@ def test_sampling_draws_are_random_subsets_in_random_order():
         c = np.bincount(order[:, j], minlength=16)
         chi2 = np.sum((c - 250.0) ** 2 / 250.0)
         assert chi2 < 45.0, (j, chi2)
+
+
+def test_fidelity_samples_mix_exact_and_uniform_samples():
+    """Fraction of perfect fidelity amplitudes: a share f of the batches gives exact samples
+    (closed bits kept, the accepted open value written big-endian into the open qubits), the
+    rest give their uniform bit-string; an exact batch that accepts nothing gives no sample."""
+    n_q, blen, nb, m = 10, 8, 20000, 10.0
+    op = [7, 2, 9]
+    rng = np.random.Generator(np.random.PCG64(31))
+    closed = rng.integers(0, 2, (nb, n_q))
+    closed[:, op] = 0
+    uniform = rng.integers(0, 2, (nb, n_q))
+    coins = rng.random(nb)
+    amps = R.porter_thomas_amplitudes(nb, blen, n_q, 32)
+    order, u = R.sampling_draws(nb, blen, blen, 33)
+    for f in (0.0, 0.01, 0.25, 1.0):
+        samples, status = S.fidelity_samples(amps, closed, op, coins, uniform, order, u, n_q, m, f)
+        status = np.array(status)
+        exact = coins < f
+        assert np.array_equal(status != 0, exact)
+        # an exact batch is exhausted as often as the batch acceptance law says
+        if exact.sum() > 100:
+            miss = np.mean(status[exact] == -1)
+            want = 1 - S.porter_thomas_acceptance(m, blen)
+            assert abs(miss - want) < 4 * math.sqrt(want * (1 - want) / exact.sum()) + 1e-3
+        picks = S.frugal_sample(amps, order, u, n_q, m)
+        for b in range(0, nb, 37):
+            if status[b] == 0:
+                assert samples[b] == uniform[b].tolist()
+            elif status[b] == 1:
+                x = samples[b]
+                assert [x[q] for q in range(n_q) if q not in op] == \
+                    [int(closed[b][q]) for q in range(n_q) if q not in op]
+                assert x[op[0]] * 4 + x[op[1]] * 2 + x[op[2]] == picks[b]
+            else:
+                assert samples[b] is None and picks[b] == -1
