@@ -622,248 +622,250 @@ void contract(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets, dou
     QHIP(hipGraphLaunch(ex, s));
   };
   const bool replayed = g->graph_mode && !capturing && !tuning_pending;
-  try {
-  if (!replayed) {
-  if (g->graph_mode && g->amax) {
-    // fp16 scale slots rewritten by every call start from zero in each replay (the tags of
-    // their atomic maxima are fixed in the graph)
-    dev::fill_zero(reinterpret_cast<double*>(g->amax), 2, s);
-    for (const CircuitState& cs : g->circ)
-      for (int64_t sl : cs.xcache_slot)
-        if (sl >= 0) dev::fill_zero(reinterpret_cast<double*>(g->amax + sl), 1, s);
-    if (g->node_amax) dev::fill_zero(reinterpret_cast<double*>(g->node_amax), g->n_node_amax, s);
-  }
-  dev::fill_zero(reinterpret_cast<double*>(acc_all), 2 * amp_total, s);
-  for (int c = 0; c < nc; ++c) {
-    CircuitState& cs = g->circ[c];
-    const Plan& P = cs.plan;
-    const int64_t nbs = bs_offsets[c + 1] - bs_offsets[c];
-    if (nbs == 0) continue;
-    const int no = (int)P.open.size();
-    const int64_t namp = int64_t(1) << no;
-    const int64_t B = batch[c];
-    double2* acc = acc_all + bs_offsets[c] * namp;
-    const float2* grid = g->grid + cs.grid_offset;
-    const auto& slices = sel[c];
-    const int ncut = (int)P.cuts.size();
-    for (int64_t b0 = 0; b0 < nbs; b0 += B) {
-      const int nb = (int)std::min<int64_t>(B, nbs - b0);
-      std::vector<int64_t> digit(ncut, -1), prev(ncut, -1);
-      auto view = [&](const Operand& o) {
-        View v;
-        if (o.qubit) {
-          const QubitLayout& L = P.qubits[o.id];
-          v.base = grid + cs.qubit_offset[o.id];
-          for (auto& cshift : L.cut_shift) v.add += digit[cshift.first] << cshift.second;
-          if (L.out_shift >= 0) v.off = offs_dev + offs_base[c] + (int64_t)o.id * nbs + b0;
-        } else {
-          const Node& nd = P.nodes[o.id];
-          v.base = arena + nd.offset * B;
-          v.bs = nd.elems();
-        }
-        return v;
-      };
-      for (size_t si = 0; si < slices.size(); ++si) {
-        int64_t rem = slices[si];
-        for (int ct = ncut - 1; ct >= 0; --ct) {
-          digit[ct] = rem & ((int64_t(1) << P.cut_bits[ct]) - 1);
-          rem >>= P.cut_bits[ct];
-        }
-        uint32_t changed = 0;
-        for (int ct = 0; ct < ncut; ++ct)
-          if (digit[ct] != prev[ct]) changed |= 1u << ct;
-        prev = digit;
-        for (size_t k = 0; k < P.steps.size(); ++k) {
-          const Step& stp = P.steps[k];
-          if (si > 0 && !(stp.deps & changed)) continue;
-          View x = view(stp.x), y = view(stp.y);
-          const bool is_split = !cs.split.empty() && cs.split[k];
-          const int64_t M = int64_t(1) << stp.mb, N = int64_t(1) << stp.nb;
-          const int64_t K = int64_t(1) << stp.kb;
-          // one split product: gather = read x straight from complex64 storage (when the
-          // plan allows it), tile = output tile (-1: shape rule); `final` runs count in stats
-          auto run_split = [&](bool gather, int tile, bool final) {
-            uint16_t* sa = static_cast<uint16_t*>(g->split_scratch.p);
-            uint16_t* sb = sa + B * cs.split_a_elems;
-            dev::GemmSplit gs;
-            gs.tile = tile;
-            const bool f16 = g->amax != nullptr;
-            // fp16 scales of intermediates that a split product produced (and measured)
-            auto node_slot = [&](const Operand& o) -> uint64_t* {
-              if (!f16 || o.qubit || cs.node_slot[o.id] < 0) return nullptr;
-              return g->node_amax + cs.node_slot[o.id];
-            };
-            uint64_t* const xslot = node_slot(stp.x);
-            uint64_t* const yslot = node_slot(stp.y);
-            if (stp.x.qubit) {
-              gs.A = g->grid_split + cs.qsplit_offset[stp.x.id];
-              gs.a_add = x.add;
-              gs.a_off = x.off;
-              if (f16) gs.a_amax = g->amax + cs.qamax_slot[stp.x.id];
-            } else if (cs.xcache_offset[k] >= 0) {
-              uint16_t* xc = static_cast<uint16_t*>(g->split_cache.p) + B * cs.xcache_offset[k];
-              if (f16) gs.a_amax = xslot ? xslot : g->amax + cs.xcache_slot[k];
-              if (si == 0 || (P.nodes[stp.x.id].deps & changed)) {  // x was just recomputed
-                if (f16 && !xslot) {
+  // every launch of this call (skipped when the graph replays them)
+  auto enqueue = [&] {
+    if (g->graph_mode && g->amax) {
+      // fp16 scale slots rewritten by every call start from zero in each replay (the tags of
+      // their atomic maxima are fixed in the graph)
+      dev::fill_zero(reinterpret_cast<double*>(g->amax), 2, s);
+      for (const CircuitState& cs : g->circ)
+        for (int64_t sl : cs.xcache_slot)
+          if (sl >= 0) dev::fill_zero(reinterpret_cast<double*>(g->amax + sl), 1, s);
+      if (g->node_amax) dev::fill_zero(reinterpret_cast<double*>(g->node_amax), g->n_node_amax, s);
+    }
+    dev::fill_zero(reinterpret_cast<double*>(acc_all), 2 * amp_total, s);
+    for (int c = 0; c < nc; ++c) {
+      CircuitState& cs = g->circ[c];
+      const Plan& P = cs.plan;
+      const int64_t nbs = bs_offsets[c + 1] - bs_offsets[c];
+      if (nbs == 0) continue;
+      const int no = (int)P.open.size();
+      const int64_t namp = int64_t(1) << no;
+      const int64_t B = batch[c];
+      double2* acc = acc_all + bs_offsets[c] * namp;
+      const float2* grid = g->grid + cs.grid_offset;
+      const auto& slices = sel[c];
+      const int ncut = (int)P.cuts.size();
+      for (int64_t b0 = 0; b0 < nbs; b0 += B) {
+        const int nb = (int)std::min<int64_t>(B, nbs - b0);
+        std::vector<int64_t> digit(ncut, -1), prev(ncut, -1);
+        auto view = [&](const Operand& o) {
+          View v;
+          if (o.qubit) {
+            const QubitLayout& L = P.qubits[o.id];
+            v.base = grid + cs.qubit_offset[o.id];
+            for (auto& cshift : L.cut_shift) v.add += digit[cshift.first] << cshift.second;
+            if (L.out_shift >= 0) v.off = offs_dev + offs_base[c] + (int64_t)o.id * nbs + b0;
+          } else {
+            const Node& nd = P.nodes[o.id];
+            v.base = arena + nd.offset * B;
+            v.bs = nd.elems();
+          }
+          return v;
+        };
+        for (size_t si = 0; si < slices.size(); ++si) {
+          int64_t rem = slices[si];
+          for (int ct = ncut - 1; ct >= 0; --ct) {
+            digit[ct] = rem & ((int64_t(1) << P.cut_bits[ct]) - 1);
+            rem >>= P.cut_bits[ct];
+          }
+          uint32_t changed = 0;
+          for (int ct = 0; ct < ncut; ++ct)
+            if (digit[ct] != prev[ct]) changed |= 1u << ct;
+          prev = digit;
+          for (size_t k = 0; k < P.steps.size(); ++k) {
+            const Step& stp = P.steps[k];
+            if (si > 0 && !(stp.deps & changed)) continue;
+            View x = view(stp.x), y = view(stp.y);
+            const bool is_split = !cs.split.empty() && cs.split[k];
+            const int64_t M = int64_t(1) << stp.mb, N = int64_t(1) << stp.nb;
+            const int64_t K = int64_t(1) << stp.kb;
+            // one split product: gather = read x straight from complex64 storage (when the
+            // plan allows it), tile = output tile (-1: shape rule); `final` runs count in stats
+            auto run_split = [&](bool gather, int tile, bool final) {
+              uint16_t* sa = static_cast<uint16_t*>(g->split_scratch.p);
+              uint16_t* sb = sa + B * cs.split_a_elems;
+              dev::GemmSplit gs;
+              gs.tile = tile;
+              const bool f16 = g->amax != nullptr;
+              // fp16 scales of intermediates that a split product produced (and measured)
+              auto node_slot = [&](const Operand& o) -> uint64_t* {
+                if (!f16 || o.qubit || cs.node_slot[o.id] < 0) return nullptr;
+                return g->node_amax + cs.node_slot[o.id];
+              };
+              uint64_t* const xslot = node_slot(stp.x);
+              uint64_t* const yslot = node_slot(stp.y);
+              if (stp.x.qubit) {
+                gs.A = g->grid_split + cs.qsplit_offset[stp.x.id];
+                gs.a_add = x.add;
+                gs.a_off = x.off;
+                if (f16) gs.a_amax = g->amax + cs.qamax_slot[stp.x.id];
+              } else if (cs.xcache_offset[k] >= 0) {
+                uint16_t* xc = static_cast<uint16_t*>(g->split_cache.p) + B * cs.xcache_offset[k];
+                if (f16) gs.a_amax = xslot ? xslot : g->amax + cs.xcache_slot[k];
+                if (si == 0 || (P.nodes[stp.x.id].deps & changed)) {  // x was just recomputed
+                  if (f16 && !xslot) {
+                    g->prof.begin("absmax", 0, 8.0 * M * K * nb, s);
+                    dev::absmax(x.base, M * K * nb, g->amax + cs.xcache_slot[k],
+                                next_amax_tag(g, s), s);
+                    g->prof.end(s);
+                  }
+                  g->prof.begin("split_permute", 0, 16.0 * M * K * nb, s);
+                  dev::split_permute(x.base, xc, nb, cs.sx[k], stp.kb, gs.a_amax, s);
+                  g->prof.end(s);
+                  if (final) st.permute_bytes += 16.0 * M * K * nb, ++st.n_permute;
+                }
+                gs.A = xc;
+                gs.a_bs = M * K;
+              } else {
+                if (f16 && xslot) {
+                  gs.a_amax = xslot;
+                } else if (f16) {
+                  gs.a_amax = g->amax;
                   g->prof.begin("absmax", 0, 8.0 * M * K * nb, s);
-                  dev::absmax(x.base, M * K * nb, g->amax + cs.xcache_slot[k],
-                              next_amax_tag(g, s), s);
+                  dev::absmax(x.base, M * K * nb, g->amax, next_amax_tag(g, s), s);
                   g->prof.end(s);
                 }
-                g->prof.begin("split_permute", 0, 16.0 * M * K * nb, s);
-                dev::split_permute(x.base, xc, nb, cs.sx[k], stp.kb, gs.a_amax, s);
-                g->prof.end(s);
-                if (final) st.permute_bytes += 16.0 * M * K * nb, ++st.n_permute;
-              }
-              gs.A = xc;
-              gs.a_bs = M * K;
-            } else {
-              if (f16 && xslot) {
-                gs.a_amax = xslot;
-              } else if (f16) {
-                gs.a_amax = g->amax;
-                g->prof.begin("absmax", 0, 8.0 * M * K * nb, s);
-                dev::absmax(x.base, M * K * nb, g->amax, next_amax_tag(g, s), s);
-                g->prof.end(s);
-              }
-              if (gather) {
-                gs.Ac = x.base;
-                gs.a_bs = x.bs;
-                gs.ga = cs.gx[k];
-              } else {
-                g->prof.begin("split_permute", 0, 16.0 * M * K * nb, s);
-                dev::split_permute(x.base, sa, nb, cs.sx[k], stp.kb, gs.a_amax, s);
-                g->prof.end(s);
-                if (final) st.permute_bytes += 16.0 * M * K * nb, ++st.n_permute;
-                gs.A = sa;
-                gs.a_bs = M * K;
-              }
-            }
-            if (stp.y.qubit) {
-              gs.B = g->grid_split + cs.qsplit_offset[stp.y.id];
-              gs.b_add = y.add;
-              gs.b_off = y.off;
-              if (f16) gs.b_amax = g->amax + cs.qamax_slot[stp.y.id];
-            } else {
-              if (f16 && yslot) {
-                gs.b_amax = yslot;
-              } else if (f16) {
-                gs.b_amax = g->amax + 1;
-                g->prof.begin("absmax", 0, 8.0 * N * K * nb, s);
-                dev::absmax(y.base, N * K * nb, g->amax + 1, next_amax_tag(g, s), s);
-                g->prof.end(s);
-              }
-              g->prof.begin("split_permute", 0, 16.0 * N * K * nb, s);
-              dev::split_permute(y.base, sb, nb, cs.sy[k], stp.kb, gs.b_amax, s);
-              g->prof.end(s);
-              if (final) st.permute_bytes += 16.0 * N * K * nb, ++st.n_permute;
-              gs.B = sb;
-              gs.b_bs = N * K;
-            }
-            const Node& out = P.nodes[stp.out];
-            gs.C = arena + out.offset * B;
-            gs.c_bs = out.elems();
-            gs.M = M;
-            gs.N = N;
-            gs.K = K;
-            gs.batch = nb;
-            if (f16 && cs.node_slot[stp.out] >= 0) {
-              gs.c_amax = g->node_amax + cs.node_slot[stp.out];
-              gs.c_tag = next_amax_tag(g, s);
-            }
-            // the kernel's own arithmetic: 3 16-bit products per real product, 24*M*N*K flops
-            g->prof.begin(dev::gemm_split_name(gs), 3.0 * stp.flops() * nb,
-                          8.0 * nb * (double)(M * K + N * K + M * N), s);
-            dev::gemm_split(gs, s);
-            g->prof.end(s);
-            if (final) st.flops += stp.flops() * nb, ++st.n_gemm;
-          };
-          if (is_split) {
-            int choice = cs.tuned[k];
-            if (choice < 0 && g->autotune) {
-              // time every fitting (tile, gather) pair once on this call's operands
-              dev::GemmSplit shape;
-              shape.M = M;
-              shape.N = N;
-              float best = 0;
-              for (int gth = 0; gth < (cs.gather_x[k] ? 2 : 1); ++gth)
-                for (int t = 0; t < 3; ++t) {
-                  if (!dev::gemm_split_tile_fits(shape, t)) continue;
-                  const float ms = time_launches([&] { run_split(gth == 1, t, false); });
-                  if (choice < 0 || ms < best) choice = 2 * t + gth, best = ms;
+                if (gather) {
+                  gs.Ac = x.base;
+                  gs.a_bs = x.bs;
+                  gs.ga = cs.gx[k];
+                } else {
+                  g->prof.begin("split_permute", 0, 16.0 * M * K * nb, s);
+                  dev::split_permute(x.base, sa, nb, cs.sx[k], stp.kb, gs.a_amax, s);
+                  g->prof.end(s);
+                  if (final) st.permute_bytes += 16.0 * M * K * nb, ++st.n_permute;
+                  gs.A = sa;
+                  gs.a_bs = M * K;
                 }
-              cs.tuned[k] = choice;
+              }
+              if (stp.y.qubit) {
+                gs.B = g->grid_split + cs.qsplit_offset[stp.y.id];
+                gs.b_add = y.add;
+                gs.b_off = y.off;
+                if (f16) gs.b_amax = g->amax + cs.qamax_slot[stp.y.id];
+              } else {
+                if (f16 && yslot) {
+                  gs.b_amax = yslot;
+                } else if (f16) {
+                  gs.b_amax = g->amax + 1;
+                  g->prof.begin("absmax", 0, 8.0 * N * K * nb, s);
+                  dev::absmax(y.base, N * K * nb, g->amax + 1, next_amax_tag(g, s), s);
+                  g->prof.end(s);
+                }
+                g->prof.begin("split_permute", 0, 16.0 * N * K * nb, s);
+                dev::split_permute(y.base, sb, nb, cs.sy[k], stp.kb, gs.b_amax, s);
+                g->prof.end(s);
+                if (final) st.permute_bytes += 16.0 * N * K * nb, ++st.n_permute;
+                gs.B = sb;
+                gs.b_bs = N * K;
+              }
+              const Node& out = P.nodes[stp.out];
+              gs.C = arena + out.offset * B;
+              gs.c_bs = out.elems();
+              gs.M = M;
+              gs.N = N;
+              gs.K = K;
+              gs.batch = nb;
+              if (f16 && cs.node_slot[stp.out] >= 0) {
+                gs.c_amax = g->node_amax + cs.node_slot[stp.out];
+                gs.c_tag = next_amax_tag(g, s);
+              }
+              // the kernel's own arithmetic: 3 16-bit products per real product, 24*M*N*K flops
+              g->prof.begin(dev::gemm_split_name(gs), 3.0 * stp.flops() * nb,
+                            8.0 * nb * (double)(M * K + N * K + M * N), s);
+              dev::gemm_split(gs, s);
+              g->prof.end(s);
+              if (final) st.flops += stp.flops() * nb, ++st.n_gemm;
+            };
+            if (is_split) {
+              int choice = cs.tuned[k];
+              if (choice < 0 && g->autotune) {
+                // time every fitting (tile, gather) pair once on this call's operands
+                dev::GemmSplit shape;
+                shape.M = M;
+                shape.N = N;
+                float best = 0;
+                for (int gth = 0; gth < (cs.gather_x[k] ? 2 : 1); ++gth)
+                  for (int t = 0; t < 3; ++t) {
+                    if (!dev::gemm_split_tile_fits(shape, t)) continue;
+                    const float ms = time_launches([&] { run_split(gth == 1, t, false); });
+                    if (choice < 0 || ms < best) choice = 2 * t + gth, best = ms;
+                  }
+                cs.tuned[k] = choice;
+              }
+              if (choice >= 0) run_split(choice & 1, choice >> 1, true);
+              else run_split(cs.gather_x[k] != 0, -1, true);
+              continue;
             }
-            if (choice >= 0) run_split(choice & 1, choice >> 1, true);
-            else run_split(cs.gather_x[k] != 0, -1, true);
-            continue;
-          }
-          if (stp.scratch_x >= 0) {
-            if (stp.x.qubit) fail(QFLEX_E_DEVICE, "internal: permutation of a qubit tensor");
-            float2* dst = arena + P.nodes[stp.scratch_x].offset * B;
-            g->prof.begin("permute", 0, 16.0 * (double)P.nodes[stp.scratch_x].elems() * nb, s);
-            dev::permute(x.base, dst, nb, cs.px[k], s);
+            if (stp.scratch_x >= 0) {
+              if (stp.x.qubit) fail(QFLEX_E_DEVICE, "internal: permutation of a qubit tensor");
+              float2* dst = arena + P.nodes[stp.scratch_x].offset * B;
+              g->prof.begin("permute", 0, 16.0 * (double)P.nodes[stp.scratch_x].elems() * nb, s);
+              dev::permute(x.base, dst, nb, cs.px[k], s);
+              g->prof.end(s);
+              x.base = dst;
+              st.permute_bytes += 16.0 * (double)P.nodes[stp.scratch_x].elems() * nb;
+              ++st.n_permute;
+            }
+            if (stp.scratch_y >= 0) {
+              if (stp.y.qubit) fail(QFLEX_E_DEVICE, "internal: permutation of a qubit tensor");
+              float2* dst = arena + P.nodes[stp.scratch_y].offset * B;
+              g->prof.begin("permute", 0, 16.0 * (double)P.nodes[stp.scratch_y].elems() * nb, s);
+              dev::permute(y.base, dst, nb, cs.py[k], s);
+              g->prof.end(s);
+              y.base = dst;
+              st.permute_bytes += 16.0 * (double)P.nodes[stp.scratch_y].elems() * nb;
+              ++st.n_permute;
+            }
+            dev::Gemm gm;
+            gm.A = x.base;
+            gm.a_off = x.off;
+            gm.a_bs = x.bs;
+            gm.a_add = x.add;
+            gm.B = y.base;
+            gm.b_off = y.off;
+            gm.b_bs = y.bs;
+            gm.b_add = y.add;
+            const Node& out = P.nodes[stp.out];
+            gm.C = arena + out.offset * B;
+            gm.c_bs = out.elems();
+            gm.M = M;
+            gm.K = K;
+            gm.N = N;
+            gm.ta = stp.ta;
+            gm.tb = stp.tb;
+            gm.lda = stp.ta ? gm.M : gm.K;
+            gm.ldb = stp.tb ? gm.K : gm.N;
+            gm.ldc = gm.N;
+            gm.batch = nb;
+            gm.force_variant = cs.tuned[k];
+            if (gm.force_variant < 0 && g->autotune)  // time every fitting kernel variant once
+              gm.force_variant = cs.tuned[k] = tune_gemm(g, s, gm);
+            g->prof.begin(dev::gemm_name(gm), stp.flops() * nb,
+                          8.0 * nb * (double)(gm.M * gm.K + gm.K * gm.N + gm.M * gm.N), s);
+            dev::gemm(gm, s);
             g->prof.end(s);
-            x.base = dst;
-            st.permute_bytes += 16.0 * (double)P.nodes[stp.scratch_x].elems() * nb;
-            ++st.n_permute;
+            st.flops += stp.flops() * nb;
+            ++st.n_gemm;
           }
-          if (stp.scratch_y >= 0) {
-            if (stp.y.qubit) fail(QFLEX_E_DEVICE, "internal: permutation of a qubit tensor");
-            float2* dst = arena + P.nodes[stp.scratch_y].offset * B;
-            g->prof.begin("permute", 0, 16.0 * (double)P.nodes[stp.scratch_y].elems() * nb, s);
-            dev::permute(y.base, dst, nb, cs.py[k], s);
-            g->prof.end(s);
-            y.base = dst;
-            st.permute_bytes += 16.0 * (double)P.nodes[stp.scratch_y].elems() * nb;
-            ++st.n_permute;
-          }
-          dev::Gemm gm;
-          gm.A = x.base;
-          gm.a_off = x.off;
-          gm.a_bs = x.bs;
-          gm.a_add = x.add;
-          gm.B = y.base;
-          gm.b_off = y.off;
-          gm.b_bs = y.bs;
-          gm.b_add = y.add;
-          const Node& out = P.nodes[stp.out];
-          gm.C = arena + out.offset * B;
-          gm.c_bs = out.elems();
-          gm.M = M;
-          gm.K = K;
-          gm.N = N;
-          gm.ta = stp.ta;
-          gm.tb = stp.tb;
-          gm.lda = stp.ta ? gm.M : gm.K;
-          gm.ldb = stp.tb ? gm.K : gm.N;
-          gm.ldc = gm.N;
-          gm.batch = nb;
-          gm.force_variant = cs.tuned[k];
-          if (gm.force_variant < 0 && g->autotune)  // time every fitting kernel variant once
-            gm.force_variant = cs.tuned[k] = tune_gemm(g, s, gm);
-          g->prof.begin(dev::gemm_name(gm), stp.flops() * nb,
-                        8.0 * nb * (double)(gm.M * gm.K + gm.K * gm.N + gm.M * gm.N), s);
-          dev::gemm(gm, s);
+          View r = view(P.result);
+          g->prof.begin("accumulate", 0, 40.0 * namp * nb, s);
+          dev::accumulate(r.base, r.off, r.bs, r.add, namp, g->bidx + cs.bidx_offset,
+                          acc + b0 * namp, namp, nb, s);
           g->prof.end(s);
-          st.flops += stp.flops() * nb;
-          ++st.n_gemm;
         }
-        View r = view(P.result);
-        g->prof.begin("accumulate", 0, 40.0 * namp * nb, s);
-        dev::accumulate(r.base, r.off, r.bs, r.add, namp, g->bidx + cs.bidx_offset,
-                        acc + b0 * namp, namp, nb, s);
-        g->prof.end(s);
       }
+      st.n_slices += (int64_t)slices.size();
+      st.n_bitstrings += nbs;
     }
-    st.n_slices += (int64_t)slices.size();
-    st.n_bitstrings += nbs;
-  }
-  }  // !replayed
-  if (capturing) {
-    g->graph_stats = st;
-    end_capture(true);
-  }
+  };
+  try {
+    if (!replayed) enqueue();
+    if (capturing) {
+      g->graph_stats = st;
+      end_capture(true);
+    }
   } catch (...) {
     if (capturing) end_capture(false);
     throw;
