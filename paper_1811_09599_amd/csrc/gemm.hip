@@ -213,15 +213,18 @@ __global__ void __launch_bounds__(256) gemm_simt_kernel(const Gemm g) {
 }
 
 // Tall-skinny products (M >= 256 rows, N <= 32 columns): one output row per thread, its
-// N <= NB complex accumulators in registers.  A k-tile of 16 values of 256 rows is staged in
+// N <= NB complex accumulators in registers.  A k-tile of BK values of 256 rows is staged in
 // LDS as [k][row] (so each thread reads its own row without bank conflicts) and B's k-tile
 // as [k][NB] (every lane reads the same B values: LDS broadcast).  Such products move far more
 // bytes than they compute (HBM-bound), so the loads are 16-byte vectors along the
 // contiguous dimension of A, and the next tile's loads are issued before this tile's math.
-template <int NB, bool TA, bool TB>
+// BK = 16, or 8 for products whose K is 8.
+template <int NB, bool TA, bool TB, int BK = 16>
 __global__ void __launch_bounds__(256) gemm_rows_kernel(const Gemm g) {
-  constexpr int BM = 256, BK = 16;
+  constexpr int BM = 256;
+  constexpr int KP = BK / 2;             // 16-byte vectors (2 complex) per row of a k-tile
   constexpr int AV = BM * BK / 2 / 256;  // 16-byte (2 complex) loads of A per thread per tile
+  static_assert(2 * BK * (BM + 2) >= BM * NB, "the output staging fits the A buffers");
   __shared__ __attribute__((aligned(16))) float2 As[2][BK][BM + 2];
   __shared__ __attribute__((aligned(16))) float2 Bs[2][BK][NB];
   const int tid = threadIdx.x;
@@ -239,8 +242,8 @@ __global__ void __launch_bounds__(256) gemm_rows_kernel(const Gemm g) {
 #pragma unroll
     for (int v = 0; v < AV; ++v) {
       const int e = tid + v * 256;
-      if (!TA) {  // [M][K]: 8 vectors of 2 k per row
-        const int row = e >> 3, kp = e & 7;
+      if (!TA) {  // [M][K]: KP vectors of 2 k per row
+        const int row = e / KP, kp = e % KP;
         ra[v] = *reinterpret_cast<const f32x4*>(A + (m0 + row) * g.lda + k0 + 2 * kp);
       } else {    // [K][M]: 128 vectors of 2 rows per k
         const int kr = e >> 7, mp = e & 127;
@@ -261,7 +264,7 @@ __global__ void __launch_bounds__(256) gemm_rows_kernel(const Gemm g) {
     for (int v = 0; v < AV; ++v) {
       const int e = tid + v * 256;
       if (!TA) {
-        const int row = e >> 3, kp = e & 7;
+        const int row = e / KP, kp = e % KP;
         As[buf][2 * kp][row] = make_float2(ra[v].x, ra[v].y);
         As[buf][2 * kp + 1][row] = make_float2(ra[v].z, ra[v].w);
       } else {
@@ -304,7 +307,7 @@ __global__ void __launch_bounds__(256) gemm_rows_kernel(const Gemm g) {
   if (ldc == N && N == NB && NB >= 2) {
     // the workgroup's 256 output rows are one contiguous block of 256*NB values: stage it in
     // LDS (the A buffers are free after the last barrier) and write it with 16-byte stores
-    float2* stage = &As[0][0][0];  // 256*NB <= 2*16*258 values
+    float2* stage = &As[0][0][0];  // 256*NB <= 2*BK*258 values
 #pragma unroll
     for (int n = 0; n < NB; ++n) stage[tid * NB + ((n + tid) % NB)] = make_float2(accr[n], acci[n]);
     __syncthreads();
@@ -454,7 +457,7 @@ bool gemm_variant_fits(const Gemm& g, int v) {
     case 0: return true;
     case 1: return g.K % 16 == 0 && g.M % 64 == 0 && g.N % 64 == 0;
     case 2: return g.K % 16 == 0 && g.M % 128 == 0 && g.N % 128 == 0;
-    case 3: return g.K % 16 == 0 && g.M % 256 == 0 && g.N <= 32;
+    case 3: return (g.K % 16 == 0 || (g.K == 8 && g.N <= 16)) && g.M % 256 == 0 && g.N <= 32;
     case 4: return !g.tb && g.M <= 32 && g.N >= 4 && pow2_or_256(g.N) && g.K >= 256 && g.K % 64 == 0;
     case 5: return g.K < 16 && (g.K & (g.K - 1)) == 0 && g.N >= 32 && pow2_or_256(g.N);
     default: return false;
@@ -545,12 +548,26 @@ static void gemm_t(const Gemm& g, hipStream_t s) {
     hipLaunchKernelGGL((gemm_mfma_kernel<TA, TB, 64, 64>), grid, dim3(256), 0, s, g);
   } else if (v == 3) {
     dim3 grid((unsigned)(g.M / 256), (unsigned)g.batch, z);
-    if (g.N > 16) hipLaunchKernelGGL((gemm_rows_kernel<32, TA, TB>), grid, dim3(256), 0, s, g);
-    else if (g.N > 8) hipLaunchKernelGGL((gemm_rows_kernel<16, TA, TB>), grid, dim3(256), 0, s, g);
-    else if (g.N > 4) hipLaunchKernelGGL((gemm_rows_kernel<8, TA, TB>), grid, dim3(256), 0, s, g);
-    else if (g.N > 2) hipLaunchKernelGGL((gemm_rows_kernel<4, TA, TB>), grid, dim3(256), 0, s, g);
-    else if (g.N > 1) hipLaunchKernelGGL((gemm_rows_kernel<2, TA, TB>), grid, dim3(256), 0, s, g);
-    else hipLaunchKernelGGL((gemm_rows_kernel<1, TA, TB>), grid, dim3(256), 0, s, g);
+    if (g.K == 8) {  // N <= 16
+      auto rows8 = [&](auto kern) { hipLaunchKernelGGL(kern, grid, dim3(256), 0, s, g); };
+      if (g.N > 8) rows8(gemm_rows_kernel<16, TA, TB, 8>);
+      else if (g.N > 4) rows8(gemm_rows_kernel<8, TA, TB, 8>);
+      else if (g.N > 2) rows8(gemm_rows_kernel<4, TA, TB, 8>);
+      else if (g.N > 1) rows8(gemm_rows_kernel<2, TA, TB, 8>);
+      else rows8(gemm_rows_kernel<1, TA, TB, 8>);
+    } else if (g.N > 16) {
+      hipLaunchKernelGGL((gemm_rows_kernel<32, TA, TB>), grid, dim3(256), 0, s, g);
+    } else if (g.N > 8) {
+      hipLaunchKernelGGL((gemm_rows_kernel<16, TA, TB>), grid, dim3(256), 0, s, g);
+    } else if (g.N > 4) {
+      hipLaunchKernelGGL((gemm_rows_kernel<8, TA, TB>), grid, dim3(256), 0, s, g);
+    } else if (g.N > 2) {
+      hipLaunchKernelGGL((gemm_rows_kernel<4, TA, TB>), grid, dim3(256), 0, s, g);
+    } else if (g.N > 1) {
+      hipLaunchKernelGGL((gemm_rows_kernel<2, TA, TB>), grid, dim3(256), 0, s, g);
+    } else {
+      hipLaunchKernelGGL((gemm_rows_kernel<1, TA, TB>), grid, dim3(256), 0, s, g);
+    }
   } else if (v == 4) {
     dim3 grid((unsigned)(g.N / std::min<int64_t>(g.N, 256)), (unsigned)g.batch, z);
     if (g.M > 16) hipLaunchKernelGGL((gemm_reduce_kernel<32, TA>), grid, dim3(256), 0, s, g);

@@ -197,6 +197,8 @@ def test_gemm_variant_choice():
     assert L.qflex_gemm_variant(1 << 14, 16, 256) == 0  # 64 row blocks: SIMT tiles instead
     assert L.qflex_gemm_variant(16, 256, 1 << 16) == 4  # reduction-shaped
     assert L.qflex_gemm_variant(1 << 16, 256, 4) == 5   # short K
+    assert L.qflex_gemm_variant(1 << 16, 8, 8) == 3     # rows kernel, 8-deep k-tile
+    assert L.qflex_gemm_variant(1 << 16, 32, 8) == 5    # K = 8 rows tile only up to N = 16
 
 
 def test_split_gemm_argument_checks_run_before_any_launch():
