@@ -460,8 +460,22 @@ struct Planner {
     st.deps = x.deps | y.deps;
     const int idx = (int)P.steps.size();
     std::vector<int> xs, ys;  // final storage orders of x and y
+    // Row labels of this product, ordered for the next step where their order is free (x laid
+    // out here or permuted anyway): the output is [rows][columns] and the columns that the next
+    // step contracts come last, so the rows it contracts go last too (the output then ends
+    // with the next contraction when every column is contracted next or no row is), or, when
+    // no column is contracted next, first (the output then begins with it: a transposed
+    // operand).  Either way the next step reads the output without a permutation.
+    std::set<int> nxt(next.begin(), next.end());
+    bool cols_next = false;
+    for (int lab : pick(y.labels, S, false)) cols_next = cols_next || nxt.count(lab) > 0;
+    auto rows_for_next = [&](const std::vector<int>& rows) {
+      std::vector<int> in, out;
+      for (int lab : rows) (nxt.count(lab) ? in : out).push_back(lab);
+      return !cols_next && !in.empty() ? cat(in, out) : cat(out, in);
+    };
     auto permute_x = [&](const std::vector<int>& sigma) {
-      std::vector<int> to = cat(pick(x.labels, S, false), sigma);
+      std::vector<int> to = cat(rows_for_next(pick(x.labels, S, false)), sigma);
       st.px = perm_desc(x.labels, to);
       st.scratch_x = new_node(to, st.deps);
       P.nodes[st.scratch_x].producer = P.nodes[st.scratch_x].last_use = idx;
@@ -478,7 +492,7 @@ struct Planner {
     };
     if (x.flexible && y.flexible) {
       std::vector<int> sigma = pick(x.labels, S, true);
-      xs = cat(pick(x.labels, S, false), sigma);
+      xs = cat(rows_for_next(pick(x.labels, S, false)), sigma);
       ys = cat(sigma, for_next(pick(y.labels, S, false), next));
       fix_qubit(x.op.id, xs);
       fix_qubit(y.op.id, ys);
@@ -495,7 +509,7 @@ struct Planner {
         sigma = pick(x.labels, S, true);
         permute_y(sigma);
       }
-      xs = cat(pick(x.labels, S, false), sigma);
+      xs = cat(rows_for_next(pick(x.labels, S, false)), sigma);
       fix_qubit(x.op.id, xs);
     } else if (y.flexible) {
       std::vector<int> sigma;
