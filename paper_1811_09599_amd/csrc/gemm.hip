@@ -337,8 +337,8 @@ __global__ void __launch_bounds__(256) gemm_rows_kernel(const Gemm g) {
 // stored [K][N], as in the cotangent of a product's right operand.  Each thread owns one
 // column n of a 256-column tile (NT = min(N, 256) columns, 256 / NT k-subgroups), streams
 // B[k][n] from HBM (coalesced along n) and keeps the column's M complex sums in registers;
-// A's k-tile ([BK][M], BK = max(16, subgroups)) is broadcast from LDS.  Subgroups are summed
-// through LDS at the end.
+// A's k-tile ([BK][M], BK = 64 k) is broadcast from LDS.  Subgroups are summed through LDS
+// at the end.
 template <int MB, bool TA>
 __global__ void __launch_bounds__(256) gemm_reduce_kernel(const Gemm g) {
   constexpr int BKMAX = 64;
@@ -348,7 +348,7 @@ __global__ void __launch_bounds__(256) gemm_reduce_kernel(const Gemm g) {
   const int b = blockIdx.y, z = blockIdx.z;
   const int NT = g.N < 256 ? (int)g.N : 256;
   const int nsub = 256 / NT;
-  const int BK = nsub > 16 ? nsub : 16;
+  const int BK = BKMAX;  // K is a multiple of 64: 64 / nsub k per thread per tile
   const int col_in = tid % NT, sub = tid / NT;
   const int64_t n0 = (int64_t)blockIdx.x * NT;
   const int M = (int)g.M;
