@@ -369,14 +369,20 @@ float time_launches(qflex_grid* g, hipStream_t s, const std::function<void()>& l
   const bool on = g->prof.on;
   g->prof.on = false;
   launch();  // warm-up
-  QHIP(hipEventRecord(g->tune_ev[0], s));
-  launch();
-  QHIP(hipEventRecord(g->tune_ev[1], s));
-  QHIP(hipEventSynchronize(g->tune_ev[1]));
+  // the best of three timed runs: a single run's time varies with the clock and with other
+  // work in flight, which made the choices differ between otherwise identical grids
+  float best = 0;
+  for (int rep = 0; rep < 3; ++rep) {
+    QHIP(hipEventRecord(g->tune_ev[0], s));
+    launch();
+    QHIP(hipEventRecord(g->tune_ev[1], s));
+    QHIP(hipEventSynchronize(g->tune_ev[1]));
+    float ms = 0;
+    QHIP(hipEventElapsedTime(&ms, g->tune_ev[0], g->tune_ev[1]));
+    if (rep == 0 || ms < best) best = ms;
+  }
   g->prof.on = on;
-  float ms = 0;
-  QHIP(hipEventElapsedTime(&ms, g->tune_ev[0], g->tune_ev[1]));
-  return ms;
+  return best;
 }
 
 int tune_gemm(qflex_grid* g, hipStream_t s, const dev::Gemm& gm) {

@@ -142,8 +142,8 @@ std::vector<std::vector<int64_t>> prepare_call(qflex_grid* g, const uint8_t* bit
                                                uint64_t seed, const int64_t* slice_ids,
                                                const int64_t* slice_offsets, const void* amps,
                                                hipStream_t s);
-// Autotuning: wall time of one run of `launch` after a warm-up run (profiling off; the stream
-// is synchronised), and the fastest kernel variant of a complex64 product.
+// Autotuning: the shortest of three timed runs of `launch` after a warm-up run (profiling off;
+// the stream is synchronised), and the fastest kernel variant of a complex64 product.
 float time_launches(qflex_grid* g, hipStream_t s, const std::function<void()>& launch);
 int tune_gemm(qflex_grid* g, hipStream_t s, const dev::Gemm& gm);
 void contract(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets, double fidelity,
