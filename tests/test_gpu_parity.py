@@ -331,3 +331,41 @@ def test_split_7x7_depth32_sampled_slices_vs_oracle(prec):
                         order=E2.quadrant_order(7, 7))
     e = _check(a, ref, 49, SPLIT_TOL[prec])
     _say("  split error", e)
+
+
+@pytest.mark.parametrize("prec", ["split_bf16", "split_fp16"])
+def test_split_cut_sweep_slices_match_oracle_paths(prec):
+    """Split products on a cut-sweep layout (4x5, depth 1+32+1, four cut links under a 2^16
+    cap): gathered and pre-split operands in shapes the quadrant plans do not produce, checked
+    slice by slice against the FP64 contraction of the same paths."""
+    _need_gpu()
+    _say(prec, "cut sweep 4x5 1+32+1 per-slice parity")
+    c = R.grid_rqc(4, 5, 32, 4242)
+    op = [19, 18]
+    bits = R.bitstrings(20, 3, 93, op)
+    g = build_grid(c, plan="cut_sweep", max_tensor_elems=1 << 16, open_qubits=op,
+                   precision=prec, autotune=True)
+    S = g.num_slices()
+    ids = [0, 4097, S // 2 + 3, S - 1]
+    a = g.contract_amplitudes(bits, slice_ids=ids).cpu().numpy()
+    ref = E2.amplitudes(c, bits, op, cuts=g.plan_cuts(), slice_ids=ids)
+    e = _check(a, ref, 20, SPLIT_TOL[prec])
+    _say("  error", e)
+
+
+@pytest.mark.parametrize("prec", ["split_bf16", "split_fp16"])
+def test_split_many_circuits_in_one_call(prec):
+    """Uneven circuits in one call (one with no bit-strings) in split precision, against the
+    state vector."""
+    _need_gpu()
+    _say(prec, "batch of uneven circuits")
+    cs = [R.grid_rqc(4, 4, 24, 60), R.grid_rqc(3, 5, 24, 61), R.grid_rqc(4, 5, 24, 62)]
+    bits = [R.bitstrings(c["n_qubits"], 4 + i, 50 + i) for i, c in enumerate(cs)]
+    bits[1] = bits[1][:0]
+    g = build_grid(cs, precision=prec)
+    a = g.contract_amplitudes(bits, device=False)
+    off = 0
+    for c, b in zip(cs, bits):
+        _check(a[off:off + len(b), 0], E1.amplitudes(c, b), c["n_qubits"], SPLIT_TOL[prec])
+        off += len(b)
+    assert off == a.shape[0]
