@@ -369,3 +369,23 @@ def test_split_many_circuits_in_one_call(prec):
         _check(a[off:off + len(b), 0], E1.amplitudes(c, b), c["n_qubits"], SPLIT_TOL[prec])
         off += len(b)
     assert off == a.shape[0]
+
+
+@pytest.mark.parametrize("mode", ["random", "block"])
+def test_split_low_fidelity_subset_matches_oracle_subset(mode):
+    """A fidelity-1/4 slice subset (random or block) in split-bf16 on the 5x4 depth-32 quadrant
+    plan: intermediates reused across the subset's slices go through the split cache."""
+    _need_gpu()
+    _say("split-bf16 fidelity 1/4 on 5x4 depth 32,", mode)
+    c = R.grid_rqc(5, 4, 32, 5433)
+    op = [19, 18]
+    bits = R.bitstrings(20, 4, 3, op)
+    g = build_grid(c, plan="quadrant", open_qubits=op, precision="split_bf16", slice_mode=mode)
+    S = g.num_slices()
+    f, seed = 0.25, 2701
+    a = g.contract_amplitudes(bits, fidelity=f, seed=seed).cpu().numpy()
+    ids = OS.select(S, f, seed) if mode == "random" else OS.select_block(S, f, seed)
+    assert g.last_stats()["n_slices"] == len(ids)
+    ref = E2.amplitudes(c, bits, op, cuts=g.plan_cuts(), slice_ids=ids)
+    e = _check(a, ref, 20, SPLIT_TOL["split_bf16"])
+    _say("  error", e)
