@@ -136,3 +136,17 @@ def test_autograd_function_fits_angles():
     f_ref, g_ref = E1.linear_xeb_grad(c, bits)
     assert abs(float(f.detach()) - f_ref) < 1e-4
     assert metrics.rel_l2(ang.grad.numpy(), g_ref) < GTOL
+
+
+@pytest.mark.parametrize("precision", ["split_bf16", "split_fp16"])
+def test_gradient_on_a_split_precision_grid(precision):
+    """A grid built for split-precision amplitudes runs its adjoint in complex64 (the
+    gradient's products are complex64 whatever the grid's precision): same 1e-3 bound."""
+    _need_gpu()
+    _say("grad on a", precision, "grid")
+    c = R.grid_rqc(4, 4, 12, 616, two_qubit="fsim", jitter_sd=0.02, jitter_seed=61)
+    bits = R.bitstrings(16, 20, 617)
+    res = build_grid(c, precision=precision).contract_grad(bits)
+    f_ref, g_ref = E1.linear_xeb_grad(c, bits)
+    assert metrics.rel_l2(res["grad_params"][0][_fsim_rows(c)], g_ref) < GTOL
+    assert abs(res["loss"][0] - f_ref) < 1e-4 * max(1.0, abs(f_ref))
