@@ -18,7 +18,7 @@ under its own key: "fsim_7x7" (the headline workload with fSim couplers at depth
 one call) and "diamond" (the 70-qubit diamond at fidelity 1/8); "ceilings" holds the vendor
 GEMM and device copy rates of the same device.
 
-    python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--bitstrings 4]
+    python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--bitstrings 8]
 """
 import argparse
 import json
@@ -192,7 +192,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--bitstrings", type=int, default=4, help="bit-strings per step")
+    ap.add_argument("--bitstrings", type=int, default=8, help="bit-strings per step")
     ap.add_argument("--precision", default="all",
                     choices=["all", "c64", "split_bf16", "split_fp16"])
     ap.add_argument("--cpu-slices", type=int, default=3, help="oracle sample size (slices)")

@@ -210,16 +210,16 @@ def test_cfg2_7x7_depth32_sampled_slices_vs_oracle():
 
 
 def test_bench_launch_configuration_7x7():
-    """The headline's own configuration: the bench circuit and its first step (4 bit-strings
+    """The headline's own configuration: the bench circuit and its first step (8 bit-strings
     in one call, all 256 slices, autotuned split-bf16 products).  At that size the FP64 oracle
-    affords single slices only, so: (1) two slices of the 4-bit-string call match the oracle;
+    affords single slices only, so: (1) two slices of the 8-bit-string call match the oracle;
     (2) the all-slice call equals the sum of its 256 single-slice calls (a property at any
     size: the amplitude is the sum of its paths)."""
     _need_gpu()
-    _say("bench configuration: 7x7 1+32+1, 4 bit-strings, all slices, split-bf16, autotune")
+    _say("bench configuration: 7x7 1+32+1, 8 bit-strings, all slices, split-bf16, autotune")
     c = R.grid_rqc(7, 7, 32, 2000)
     op = R.grid_ids((7, 7), [(5, 0), (5, 1), (5, 2), (6, 0), (6, 1), (6, 2)])
-    bits = R.bitstrings(49, 1024, 2500, op)[:4]
+    bits = R.bitstrings(49, 1024, 2500, op)[:8]
     g = build_grid(c, open_qubits=op, precision="split_bf16", autotune=True)
     full = g.contract_amplitudes(bits).cpu().numpy()  # tunes on this call
     full = g.contract_amplitudes(bits).cpu().numpy()
