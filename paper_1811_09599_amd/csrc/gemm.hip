@@ -13,7 +13,7 @@ namespace dev {
 // the real instruction: Cr += ar*br + (-ai)*bi, Ci += ar*bi + ai*br.  Operand tiles of
 // BK = 16 complex k-values are staged in LDS with k contiguous for both operands (rows padded
 // to 144 bytes), double buffered with one barrier per k-tile; the global loads of tile t+1
-// are issued before the MFMAs of tile t.  Within a k-tile, lanes 0-31 take k = 0..7 and
+// are issued before the MFMAs of tile t and stored to LDS before its last k step.  Within a k-tile, lanes 0-31 take k = 0..7 and
 // lanes 32-63 take k = 8..15 (the two halves of the instruction's K=2), so each lane reads its
 // operands as 16-byte vectors.
 // =============================================================================================
@@ -143,8 +143,10 @@ __global__ void __launch_bounds__(256) gemm_mfma_kernel(const Gemm g) {
             }
           }
       }
+      // the next tile goes to the other buffer while this one still has a k step to go, so
+      // its LDS writes overlap MFMAs instead of sitting between the last MFMA and the barrier
+      if (s2 == 2 && kt + 1 < nk) sstore(buf ^ 1);
     }
-    if (kt + 1 < nk) sstore(buf ^ 1);
     __syncthreads();
   }
   // D layout of the 32x32 instruction: lane -> column r, register v -> row 8*(v/4)+4*h+(v%4)
