@@ -62,9 +62,10 @@ int64_t qflex_gemm_split_workspace(int64_t M, int64_t N, int64_t K, int64_t batc
 
 /* Kernel variant qflex_gemm_c64 uses for a shape: 0 SIMT, 1 MFMA 64x64, 2 MFMA 128x128,
  * 3 tall-skinny rows kernel (M a multiple of 256 and at least 32768, N <= 32, K a multiple
- * of 16, or K = 8 with N <= 16), 4 reduction kernel (M <= 32, N >= 4 a power of two or a multiple of 256, K >= 256 a
- * multiple of 64, B not transposed), 5 short-K kernel (K < 16 a power of two, N >= 32 as in 4).
- * Kernel-level calls pass batch = 1 to this rule. */
+ * of 16, or K = 8 with N <= 16), 4 reduction kernel (M <= 32, N >= 4 a power of two or a
+ * multiple of 256, K >= 256 a multiple of 64, B not transposed), 5 short-K kernel (K < 16 a
+ * power of two, N >= 32 as in 4), 6 MFMA 256x128 (M a multiple of 256, N of 128, K of 16, and
+ * at least 256 such tiles over the batch).  This query assumes batch = 1. */
 int32_t qflex_gemm_variant(int64_t M, int64_t N, int64_t K);
 
 /* The slice subset that qflex_contract_amplitudes sums for a fidelity (host only): writes up to

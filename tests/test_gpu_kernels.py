@@ -121,7 +121,9 @@ SHAPES = [(1, 1, 1, 1), (3, 5, 7, 2), (64, 64, 16, 1), (64, 64, 64, 3), (128, 12
           # reduction-shaped kernel (M <= 32, N >= 4, K >= 256; B stored [K][N])
           (16, 256, 1024, 2), (4, 64, 4096, 1), (32, 512, 512, 1), (1, 4, 256, 3), (3, 8, 320, 1),
           # short-K kernel (K < 16, N >= 32)
-          (1000, 64, 4, 2), (4096, 256, 8, 1), (100, 512, 2, 3), (64, 32, 1, 1)]
+          (1000, 64, 4, 2), (4096, 256, 8, 1), (100, 512, 2, 3), (64, 32, 1, 1),
+          # 256x128 MFMA tile (at least 256 tiles over the batch)
+          (4096, 2048, 32, 1), (2048, 1024, 64, 8)]
 
 
 @pytest.mark.parametrize("M,N,K,batch", SHAPES)

@@ -188,7 +188,10 @@ def test_block_slice_subset_matches_oracle(total, f, seed):
 
 def test_gemm_variant_choice():
     L = F.lib()
-    assert L.qflex_gemm_variant(4096, 4096, 4096) == 2
+    assert L.qflex_gemm_variant(4096, 4096, 4096) == 6  # 512 tiles of 256x128
+    assert L.qflex_gemm_variant(4096, 2048, 16) == 6    # 256 tiles: one per compute unit
+    assert L.qflex_gemm_variant(2048, 2048, 16) == 2    # 128: 128x128 tiles instead
+    assert L.qflex_gemm_variant(4096, 4096 + 64, 16) == 1
     assert L.qflex_gemm_variant(64, 64, 16) == 1
     assert L.qflex_gemm_variant(64, 8, 256) == 0
     assert L.qflex_gemm_variant(1 << 20, 256, 8) == 5   # short K
