@@ -388,7 +388,7 @@ float time_launches(qflex_grid* g, hipStream_t s, const std::function<void()>& l
 int tune_gemm(qflex_grid* g, hipStream_t s, const dev::Gemm& gm) {
   int best_v = -1;
   float best = 0;
-  for (int v = 0; v < 7; ++v) {
+  for (int v = 0; v < dev::kGemmVariants; ++v) {
     if (!dev::gemm_variant_fits(gm, v)) continue;
     dev::Gemm t = gm;
     t.force_variant = v;

@@ -150,7 +150,8 @@ void contract_grad(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets
     g->grad_arena.reserve(sizeof(float2) * (size_t)(top * B));
     float2* ar = static_cast<float2*>(g->grad_arena.p);
     // split-K workspace for the products of this circuit (forward, Xbar and Ybar shapes) at
-    // the batch sizes it runs: full batches and the last, partial one
+    // the batch sizes it runs (full batches and the last, partial one), for every kernel
+    // variant that fits: the autotuner must time each one as it would run
     int64_t ws_need = 0;
     for (int64_t nbv : {B, nbs % B}) {
       if (nbv <= 0) continue;
@@ -164,7 +165,11 @@ void contract_grad(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets
           q.N = sh[1];
           q.K = sh[2];
           q.batch = (int)nbv;
-          ws_need = std::max(ws_need, dev::gemm_splitk_elems(q));
+          for (int v = 0; v < dev::kGemmVariants; ++v) {
+            if (!dev::gemm_variant_fits(q, v)) continue;
+            q.force_variant = v;
+            ws_need = std::max(ws_need, dev::gemm_splitk_elems(q));
+          }
         }
       }
     }

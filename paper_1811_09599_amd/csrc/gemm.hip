@@ -469,6 +469,7 @@ bool gemm_variant_fits(const Gemm& g, int v) {
     case 4: return !g.tb && g.M <= 32 && g.N >= 4 && pow2_or_256(g.N) && g.K >= 256 && g.K % 64 == 0;
     case 5: return g.K < 16 && (g.K & (g.K - 1)) == 0 && g.N >= 32 && pow2_or_256(g.N);
     case 6: return g.K % 16 == 0 && g.M % 256 == 0 && g.N % 128 == 0;
+    case 7: return !g.tb && g.M <= 16 && g.N % 64 == 0 && g.K >= 256 && g.K % 64 == 0;
     default: return false;
   }
 }
@@ -482,13 +483,14 @@ int gemm_variant(const Gemm& g) {
   if (gemm_variant_fits(g, 1)) return 1;
   // rows kernel: one workgroup per 256 rows, so only when that fills half the chip or more
   if (gemm_variant_fits(g, 3) && (g.M / 256) * g.batch >= 128) return 3;
+  if (gemm_variant_fits(g, 7)) return 7;  // reduction-shaped, on MFMA
   if (gemm_variant_fits(g, 4)) return 4;  // reduction-shaped
   if (gemm_variant_fits(g, 5)) return 5;  // short K
   return 0;
 }
 
 const char* gemm_name(const Gemm& g) {
-  static const char* names[7][4] = {
+  static const char* names[kGemmVariants][4] = {
       {"gemm_simt_nn", "gemm_simt_nt", "gemm_simt_tn", "gemm_simt_tt"},
       {"gemm_mfma_64x64_nn", "gemm_mfma_64x64_nt", "gemm_mfma_64x64_tn", "gemm_mfma_64x64_tt"},
       {"gemm_mfma_128x128_nn", "gemm_mfma_128x128_nt", "gemm_mfma_128x128_tn",
@@ -497,7 +499,9 @@ const char* gemm_name(const Gemm& g) {
       {"gemm_reduce_nn", "gemm_reduce_nt", "gemm_reduce_tn", "gemm_reduce_tt"},
       {"gemm_smallk_nn", "gemm_smallk_nt", "gemm_smallk_tn", "gemm_smallk_tt"},
       {"gemm_mfma_256x128_nn", "gemm_mfma_256x128_nt", "gemm_mfma_256x128_tn",
-       "gemm_mfma_256x128_tt"}};
+       "gemm_mfma_256x128_tt"},
+      {"gemm_reduce_mfma_nn", "gemm_reduce_mfma_nt", "gemm_reduce_mfma_tn",
+       "gemm_reduce_mfma_tt"}};
   return names[gemm_variant(g)][(g.ta ? 2 : 0) + (g.tb ? 1 : 0)];
 }
 
@@ -505,6 +509,7 @@ const char* gemm_name(const Gemm& g) {
 static int64_t gemm_tiles(const Gemm& g) {
   switch (gemm_variant(g)) {
     case 6: return (g.M / 256) * (g.N / 128);
+    case 7: return g.N / 64;
     case 2: return (g.M / 128) * (g.N / 128);
     case 1: return (g.M / 64) * (g.N / 64);
     case 3: return g.M / 256;
@@ -536,6 +541,84 @@ int64_t gemm_splitk_elems(const Gemm& g) {
   return split > 1 ? (int64_t)split * g.batch * g.M * g.N : 0;
 }
 
+// Reduction-shaped products on MFMA (M <= 16 rows, N a multiple of 64, a long K, B stored
+// [K][N]): the same products as gemm_reduce_kernel, whose 4 M vector FMAs per element of B
+// make it as much an ALU kernel as an HBM one.  Here v_mfma_f32_16x16x4f32 does the
+// arithmetic, with A's rows padded to 16 by zeros.  A workgroup owns 64 columns (4 blocks of 16)
+// and its 4 wavefronts split K: blocks of 16 k go round robin to the wavefronts.  Per block,
+// each lane loads its 4 values of A (row i = lane % 16, k = 4 s + lane / 16) and 16 of B
+// (k likewise, column 16 c + lane % 16) straight from HBM; every load instruction of the
+// wavefront reads whole 128-byte lines.  The wavefronts' sums meet in LDS and are added in a
+// fixed order.
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+template <bool TA>
+__global__ void __launch_bounds__(256) gemm_reduce_mfma_kernel(const Gemm g) {
+  __shared__ float red[4][32][64];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int i = lane & 15, kq = lane >> 4;
+  const int b = blockIdx.y, z = blockIdx.z;
+  const int64_t n0 = (int64_t)blockIdx.x * 64;
+  const int M = (int)g.M;
+  const float2* __restrict__ A = g.A + g.a_add + (g.a_off ? g.a_off[b] : b * g.a_bs) + z * g.a_ks;
+  const float2* __restrict__ B =
+      g.B + g.b_add + (g.b_off ? g.b_off[b] : b * g.b_bs) + z * g.b_ks + n0 + i;
+  float2* __restrict__ C = g.split > 1 ? g.ws + ((int64_t)z * g.batch + b) * g.M * g.N
+                                       : g.C + b * g.c_bs;
+  const int64_t ldc = g.split > 1 ? g.N : g.ldc;
+  floatx4 cr[4], ci[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) cr[c] = ci[c] = floatx4{0.f, 0.f, 0.f, 0.f};
+  const int64_t nblk = g.K / 16;
+  for (int64_t blk = wave; blk < nblk; blk += 4) {
+    const int64_t k0 = blk * 16 + kq;
+    float2 a[4], w[4][4];
+#pragma unroll
+    for (int st = 0; st < 4; ++st) {
+      const int64_t k = k0 + 4 * st;
+      a[st] = make_float2(0.f, 0.f);
+      if (i < M) a[st] = TA ? A[k * g.lda + i] : A[(int64_t)i * g.lda + k];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) w[st][c] = B[k * g.ldb + 16 * c];
+    }
+#pragma unroll
+    for (int st = 0; st < 4; ++st) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        cr[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[st].x, w[st][c].x, cr[c], 0, 0, 0);
+        ci[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[st].x, w[st][c].y, ci[c], 0, 0, 0);
+      }
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        cr[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(-a[st].y, w[st][c].y, cr[c], 0, 0, 0);
+        ci[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[st].y, w[st][c].x, ci[c], 0, 0, 0);
+      }
+    }
+  }
+  // D layout of the 16x16 instruction: lane -> column lane % 16, register v -> row
+  // 4 (lane / 16) + v
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      red[wave][8 * c + v][lane] = cr[c][v];
+      red[wave][8 * c + 4 + v][lane] = ci[c][v];
+    }
+  __syncthreads();
+  for (int e = tid; e < 16 * 64; e += 256) {
+    const int c = e >> 8, v = (e >> 6) & 3, l = e & 63;
+    const int row = 4 * (l >> 4) + v;
+    if (row >= M) continue;
+    float re = red[0][8 * c + v][l], im = red[0][8 * c + 4 + v][l];
+#pragma unroll
+    for (int u = 1; u < 4; ++u) {
+      re += red[u][8 * c + v][l];
+      im += red[u][8 * c + 4 + v][l];
+    }
+    C[row * ldc + n0 + 16 * c + (l & 15)] = make_float2(re, im);
+  }
+}
+
 // C[b] = sum over chunks z of ws[z][b] (in chunk order), written with C's row stride
 __global__ void splitk_reduce_kernel(const float2* __restrict__ ws, int split, int batch,
                                      int64_t M, int64_t N, float2* __restrict__ C, int64_t ldc,
@@ -557,7 +640,10 @@ template <bool TA, bool TB>
 static void gemm_t(const Gemm& g, hipStream_t s) {
   const int v = gemm_variant(g);
   const unsigned z = (unsigned)g.split;
-  if (v == 6) {
+  if (v == 7) {
+    dim3 grid((unsigned)(g.N / 64), (unsigned)g.batch, z);
+    hipLaunchKernelGGL((gemm_reduce_mfma_kernel<TA>), grid, dim3(256), 0, s, g);
+  } else if (v == 6) {
     dim3 grid((unsigned)((g.M / 256) * (g.N / 128)), (unsigned)g.batch, z);
     hipLaunchKernelGGL((gemm_mfma_kernel<TA, TB, 256, 128, 4, 2>), grid, dim3(512), 0, s, g);
   } else if (v == 2) {

@@ -118,8 +118,10 @@ SHAPES = [(1, 1, 1, 1), (3, 5, 7, 2), (64, 64, 16, 1), (64, 64, 64, 3), (128, 12
           (3 << 15, 24, 32, 1), (1 << 16, 1, 16, 1), (1 << 16, 16, 32, 1),
           # ... and its 8-deep k-tile for K = 8 (N <= 16)
           (1 << 16, 8, 8, 1), (1 << 15, 16, 8, 2), (3 << 15, 1, 8, 1), (1 << 16, 3, 8, 1),
-          # reduction-shaped kernel (M <= 32, N >= 4, K >= 256; B stored [K][N])
+          # reduction-shaped kernels (M <= 32, N >= 4, K >= 256; B stored [K][N]): on MFMA
+          # for M <= 16 and N a multiple of 64, else on vector FMAs
           (16, 256, 1024, 2), (4, 64, 4096, 1), (32, 512, 512, 1), (1, 4, 256, 3), (3, 8, 320, 1),
+          (11, 192, 512, 3), (2, 64, 256, 1),
           # short-K kernel (K < 16, N >= 32)
           (1000, 64, 4, 2), (4096, 256, 8, 1), (100, 512, 2, 3), (64, 32, 1, 1),
           # 256x128 MFMA tile (at least 256 tiles over the batch)
@@ -154,7 +156,9 @@ def test_gemm_matches_fp64(M, N, K, batch, ta, tb):
 # Reduction-shaped products (few output tiles, long K: the shapes of a gradient's operand
 # cotangents) split along K into a workspace and summed in a fixed order.
 SPLITK_SHAPES = [(16, 16, 1 << 16, 4, 1, 0), (4, 16, 1 << 14, 3, 1, 0), (256, 256, 8192, 1, 1, 0),
-                 (64, 64, 4096, 2, 0, 0), (16, 8, 1 << 15, 2, 0, 1), (1, 1, 1 << 12, 1, 1, 1)]
+                 (64, 64, 4096, 2, 0, 0), (16, 8, 1 << 15, 2, 0, 1), (1, 1, 1 << 12, 1, 1, 1),
+                 # the MFMA reduction kernel in chunks
+                 (16, 256, 1 << 15, 2, 1, 0), (5, 128, 1 << 14, 3, 0, 0)]
 
 
 @pytest.mark.parametrize("M,N,K,batch,ta,tb", SPLITK_SHAPES)

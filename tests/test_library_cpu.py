@@ -198,7 +198,9 @@ def test_gemm_variant_choice():
     assert L.qflex_gemm_variant(1 << 16, 16, 256) == 3
     assert L.qflex_gemm_variant(1 << 16, 4, 16) == 3
     assert L.qflex_gemm_variant(1 << 14, 16, 256) == 0  # 64 row blocks: SIMT tiles instead
-    assert L.qflex_gemm_variant(16, 256, 1 << 16) == 4  # reduction-shaped
+    assert L.qflex_gemm_variant(16, 256, 1 << 16) == 7  # reduction-shaped, on MFMA
+    assert L.qflex_gemm_variant(32, 256, 1 << 16) == 4  # ... more than 16 rows: vector kernel
+    assert L.qflex_gemm_variant(16, 32, 1 << 16) == 4   # ... N not a multiple of 64
     assert L.qflex_gemm_variant(1 << 16, 256, 4) == 5   # short K
     assert L.qflex_gemm_variant(1 << 16, 8, 8) == 3     # rows kernel, 8-deep k-tile
     assert L.qflex_gemm_variant(1 << 16, 32, 8) == 5    # K = 8 rows tile only up to N = 16
