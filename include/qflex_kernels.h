@@ -66,7 +66,8 @@ int64_t qflex_gemm_split_workspace(int64_t M, int64_t N, int64_t K, int64_t batc
  * multiple of 256, K >= 256 a multiple of 64, B not transposed), 5 short-K kernel (K < 16 a
  * power of two, N >= 32 as in 4), 6 MFMA 256x128 (M a multiple of 256, N of 128, K of 16, and
  * at least 256 such tiles over the batch), 7 reduction kernel on MFMA (M <= 16, N a multiple
- * of 64, K >= 256 a multiple of 64, B not transposed; picked before 4).  This query assumes
+ * of 64, K >= 256 a multiple of 64, B not transposed; picked before 4), 8 rows kernel on MFMA
+ * (as 3 with K a multiple of 16 and N <= 16; picked before 3 when N > 8).  This query assumes
  * batch = 1. */
 int32_t qflex_gemm_variant(int64_t M, int64_t N, int64_t K);
 

@@ -470,6 +470,7 @@ bool gemm_variant_fits(const Gemm& g, int v) {
     case 5: return g.K < 16 && (g.K & (g.K - 1)) == 0 && g.N >= 32 && pow2_or_256(g.N);
     case 6: return g.K % 16 == 0 && g.M % 256 == 0 && g.N % 128 == 0;
     case 7: return !g.tb && g.M <= 16 && g.N % 64 == 0 && g.K >= 256 && g.K % 64 == 0;
+    case 8: return g.K % 16 == 0 && g.M % 256 == 0 && g.N <= 16;
     default: return false;
   }
 }
@@ -481,7 +482,9 @@ int gemm_variant(const Gemm& g) {
   if (gemm_variant_fits(g, 6) && (g.M / 256) * (g.N / 128) * g.batch >= 256) return 6;
   if (gemm_variant_fits(g, 2)) return 2;
   if (gemm_variant_fits(g, 1)) return 1;
-  // rows kernel: one workgroup per 256 rows, so only when that fills half the chip or more
+  // rows kernels: one workgroup per 256 rows, so only when that fills half the chip or more;
+  // on MFMA for 8 < N <= 16 (at N = 16 the vector kernel is ALU-bound, at N <= 8 it is not)
+  if (gemm_variant_fits(g, 8) && g.N > 8 && (g.M / 256) * g.batch >= 128) return 8;
   if (gemm_variant_fits(g, 3) && (g.M / 256) * g.batch >= 128) return 3;
   if (gemm_variant_fits(g, 7)) return 7;  // reduction-shaped, on MFMA
   if (gemm_variant_fits(g, 4)) return 4;  // reduction-shaped
@@ -501,7 +504,8 @@ const char* gemm_name(const Gemm& g) {
       {"gemm_mfma_256x128_nn", "gemm_mfma_256x128_nt", "gemm_mfma_256x128_tn",
        "gemm_mfma_256x128_tt"},
       {"gemm_reduce_mfma_nn", "gemm_reduce_mfma_nt", "gemm_reduce_mfma_tn",
-       "gemm_reduce_mfma_tt"}};
+       "gemm_reduce_mfma_tt"},
+      {"gemm_rows_mfma_nn", "gemm_rows_mfma_nt", "gemm_rows_mfma_tn", "gemm_rows_mfma_tt"}};
   return names[gemm_variant(g)][(g.ta ? 2 : 0) + (g.tb ? 1 : 0)];
 }
 
@@ -510,6 +514,7 @@ static int64_t gemm_tiles(const Gemm& g) {
   switch (gemm_variant(g)) {
     case 6: return (g.M / 256) * (g.N / 128);
     case 7: return g.N / 64;
+    case 8: return g.M / 256;
     case 2: return (g.M / 128) * (g.N / 128);
     case 1: return (g.M / 64) * (g.N / 64);
     case 3: return g.M / 256;
@@ -619,6 +624,95 @@ __global__ void __launch_bounds__(256) gemm_reduce_mfma_kernel(const Gemm g) {
   }
 }
 
+// Tall-skinny products on MFMA (M a multiple of 256, N <= 16, K a multiple of 16): the products
+// of gemm_rows_kernel, whose 4 N vector FMAs per element of A cap it below the copy rate at
+// N = 16.  Here v_mfma_f32_16x16x4f32 does the arithmetic with B's columns padded to 16 by
+// zeros.  Each wavefront owns 64 rows as 4 blocks of 16; per 16 k, lane (q = lane / 16,
+// i = lane % 16) holds k = 4 q + s of its rows for instruction s (the order of k within a
+// block is free, as long as A and B agree).  A is read straight from HBM in 16-byte vectors:
+// [M][K] as 4 consecutive k of one row, [K][M] as 2 consecutive rows of one k (the two rows
+// then belong to an even and an odd row block).  B is staged in LDS 64 k at a time.
+template <bool TA, bool TB>
+__global__ void __launch_bounds__(256) gemm_rows_mfma_kernel(const Gemm g) {
+  constexpr int KC = 64;
+  __shared__ float2 Bs[KC][16];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int i = lane & 15, q = lane >> 4;
+  const int b = blockIdx.y, z = blockIdx.z;
+  const int64_t mw = (int64_t)blockIdx.x * 256 + wave * 64;
+  const float2* __restrict__ A = g.A + g.a_add + (g.a_off ? g.a_off[b] : b * g.a_bs) + z * g.a_ks;
+  const float2* __restrict__ B = g.B + g.b_add + (g.b_off ? g.b_off[b] : b * g.b_bs) + z * g.b_ks;
+  float2* __restrict__ C = g.split > 1 ? g.ws + ((int64_t)z * g.batch + b) * g.M * g.N
+                                       : g.C + b * g.c_bs;
+  const int64_t ldc = g.split > 1 ? g.N : g.ldc;
+  const int N = (int)g.N;
+  floatx4 cr[4], ci[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) cr[r] = ci[r] = floatx4{0.f, 0.f, 0.f, 0.f};
+  for (int64_t kc = 0; kc < g.K; kc += KC) {
+    const int kn = g.K - kc < KC ? (int)(g.K - kc) : KC;
+    __syncthreads();  // the previous chunk's reads of Bs are done
+    for (int e = tid; e < kn * 16; e += 256) {
+      const int kr = e >> 4, n = e & 15;
+      float2 x = make_float2(0.f, 0.f);
+      if (n < N) x = TB ? B[(int64_t)n * g.ldb + kc + kr] : B[(kc + kr) * g.ldb + n];
+      Bs[kr][n] = x;
+    }
+    __syncthreads();
+    for (int kb = 0; kb < kn; kb += 16) {
+      const int64_t k0 = kc + kb;
+      float2 a[4][4];  // [row block][instruction]
+      if (!TA) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const float2* p = A + (mw + 16 * r + i) * g.lda + k0 + 4 * q;
+          const f32x4 v0 = *reinterpret_cast<const f32x4*>(p);
+          const f32x4 v1 = *reinterpret_cast<const f32x4*>(p + 2);
+          a[r][0] = make_float2(v0.x, v0.y);
+          a[r][1] = make_float2(v0.z, v0.w);
+          a[r][2] = make_float2(v1.x, v1.y);
+          a[r][3] = make_float2(v1.z, v1.w);
+        }
+      } else {
+#pragma unroll
+        for (int st = 0; st < 4; ++st)
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const f32x4 v = *reinterpret_cast<const f32x4*>(A + (k0 + 4 * q + st) * g.lda + mw +
+                                                            32 * h + 2 * i);
+            a[2 * h][st] = make_float2(v.x, v.y);
+            a[2 * h + 1][st] = make_float2(v.z, v.w);
+          }
+      }
+#pragma unroll
+      for (int st = 0; st < 4; ++st) {
+        const float2 w = Bs[kb + 4 * q + st][i];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          cr[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r][st].x, w.x, cr[r], 0, 0, 0);
+          ci[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r][st].x, w.y, ci[r], 0, 0, 0);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          cr[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(-a[r][st].y, w.y, cr[r], 0, 0, 0);
+          ci[r] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[r][st].y, w.x, ci[r], 0, 0, 0);
+        }
+      }
+    }
+  }
+  // D layout of the 16x16 instruction: lane -> column i, register v -> row 4 q + v of the block
+  if (i < N) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int rr = 4 * q + v;
+        const int64_t m = TA ? mw + 32 * (r >> 1) + 2 * rr + (r & 1) : mw + 16 * r + rr;
+        C[m * ldc + i] = make_float2(cr[r][v], ci[r][v]);
+      }
+  }
+}
+
 // C[b] = sum over chunks z of ws[z][b] (in chunk order), written with C's row stride
 __global__ void splitk_reduce_kernel(const float2* __restrict__ ws, int split, int batch,
                                      int64_t M, int64_t N, float2* __restrict__ C, int64_t ldc,
@@ -640,7 +734,10 @@ template <bool TA, bool TB>
 static void gemm_t(const Gemm& g, hipStream_t s) {
   const int v = gemm_variant(g);
   const unsigned z = (unsigned)g.split;
-  if (v == 7) {
+  if (v == 8) {
+    dim3 grid((unsigned)(g.M / 256), (unsigned)g.batch, z);
+    hipLaunchKernelGGL((gemm_rows_mfma_kernel<TA, TB>), grid, dim3(256), 0, s, g);
+  } else if (v == 7) {
     dim3 grid((unsigned)(g.N / 64), (unsigned)g.batch, z);
     hipLaunchKernelGGL((gemm_reduce_mfma_kernel<TA>), grid, dim3(256), 0, s, g);
   } else if (v == 6) {

@@ -73,8 +73,8 @@ struct Gemm {
 };
 // which kernel gemm() would pick: 0 = SIMT, 1 = MFMA 64x64 tile, 2 = MFMA 128x128 tile,
 // 3 = rows, 4 = reduction-shaped, 5 = short K, 6 = MFMA 256x128 tile, 7 = reduction-shaped
-// on MFMA
-constexpr int kGemmVariants = 8;
+// on MFMA, 8 = rows on MFMA
+constexpr int kGemmVariants = 9;
 int gemm_variant(const Gemm& g);
 bool gemm_variant_fits(const Gemm& g, int v);  // the shape meets variant v's requirements
 const char* gemm_name(const Gemm& g);  // kernel name used by the profiler

@@ -150,3 +150,30 @@ def test_gradient_on_a_split_precision_grid(precision):
     f_ref, g_ref = E1.linear_xeb_grad(c, bits)
     assert metrics.rel_l2(res["grad_params"][0][_fsim_rows(c)], g_ref) < GTOL
     assert abs(res["loss"][0] - f_ref) < 1e-4 * max(1.0, abs(f_ref))
+
+
+def test_autotuned_gradient_matches_shape_rule_gradient():
+    """An autotuned grid times every fitting kernel of each forward and backward product (the
+    MFMA rows and reduction kernels, split-K chunks included) and keeps the fastest: its
+    gradients match the shape rules' within FP32 rounding, and the state-vector adjoint."""
+    _need_gpu()
+    _say("autotuned gradient, 5x4 and 6x6 fSim")
+    c1 = R.grid_rqc(5, 4, 12, 910, two_qubit="fsim", jitter_sd=0.02, jitter_seed=11)
+    c2 = R.grid_rqc(6, 6, 12, 911, two_qubit="fsim", jitter_sd=0.02, jitter_seed=12)
+    bits = [R.bitstrings(20, 64, 912), R.bitstrings(36, 64, 913)]
+    tuned = build_grid([c1, c2], autotune=True)
+    plain = build_grid([c1, c2])
+    r_t = [tuned.contract_grad(bits) for _ in range(2)]  # the first call tunes
+    r_p = plain.contract_grad(bits)
+    for r in r_t:
+        for ci, c in enumerate((c1, c2)):
+            f = _fsim_rows(c)
+            err = metrics.rel_l2(r["grad_params"][ci][f], r_p["grad_params"][ci][f])
+            _say("  circuit", ci, "tuned vs shape rules", err)
+            assert err < 1e-5
+            assert abs(r["loss"][ci] - r_p["loss"][ci]) < 1e-5 * max(1.0, abs(r_p["loss"][ci]))
+    f_ref, g_ref = E1.linear_xeb_grad(c1, bits[0])
+    assert metrics.rel_l2(r_t[1]["grad_params"][0][_fsim_rows(c1)], g_ref) < GTOL
+    assert abs(r_t[1]["loss"][0] - f_ref) < 1e-4 * max(1.0, abs(f_ref))
+    tuned.close()
+    plain.close()

@@ -116,6 +116,8 @@ SHAPES = [(1, 1, 1, 1), (3, 5, 7, 2), (64, 64, 16, 1), (64, 64, 64, 3), (128, 12
           # least 256 row blocks over the batch
           (1 << 16, 4, 256, 2), (1 << 16, 32, 64, 1), (1 << 16, 8, 16, 1), (1 << 15, 2, 64, 2),
           (3 << 15, 24, 32, 1), (1 << 16, 1, 16, 1), (1 << 16, 16, 32, 1),
+          # ... on MFMA for 8 < N <= 16 (B staged 64 k at a time)
+          (1 << 16, 12, 48, 1), (1 << 15, 16, 80, 2), (1 << 17, 9, 16, 1),
           # ... and its 8-deep k-tile for K = 8 (N <= 16)
           (1 << 16, 8, 8, 1), (1 << 15, 16, 8, 2), (3 << 15, 1, 8, 1), (1 << 16, 3, 8, 1),
           # reduction-shaped kernels (M <= 32, N >= 4, K >= 256; B stored [K][N]): on MFMA

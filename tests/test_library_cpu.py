@@ -195,7 +195,9 @@ def test_gemm_variant_choice():
     assert L.qflex_gemm_variant(64, 64, 16) == 1
     assert L.qflex_gemm_variant(64, 8, 256) == 0
     assert L.qflex_gemm_variant(1 << 20, 256, 8) == 5   # short K
-    assert L.qflex_gemm_variant(1 << 16, 16, 256) == 3
+    assert L.qflex_gemm_variant(1 << 16, 16, 256) == 8   # rows on MFMA (8 < N <= 16)
+    assert L.qflex_gemm_variant(1 << 16, 8, 256) == 3    # rows on vector FMAs
+    assert L.qflex_gemm_variant(1 << 16, 24, 256) == 3
     assert L.qflex_gemm_variant(1 << 16, 4, 16) == 3
     assert L.qflex_gemm_variant(1 << 14, 16, 256) == 0  # 64 row blocks: SIMT tiles instead
     assert L.qflex_gemm_variant(16, 256, 1 << 16) == 7  # reduction-shaped, on MFMA
