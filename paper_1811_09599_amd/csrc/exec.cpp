@@ -793,7 +793,7 @@ void contract(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets, dou
                 shape.N = N;
                 float best = 0;
                 for (int gth = 0; gth < (cs.gather_x[k] ? 2 : 1); ++gth)
-                  for (int t = 0; t < 3; ++t) {
+                  for (int t = 0; t < dev::kSplitTiles; ++t) {
                     if (!dev::gemm_split_tile_fits(shape, t)) continue;
                     const float ms = time_launches([&] { run_split(gth == 1, t, false); });
                     if (choice < 0 || ms < best) choice = 2 * t + gth, best = ms;

@@ -7,8 +7,9 @@ namespace qflex {
 namespace dev {
 
 // Complex product on 16-bit MFMA from the compact split layout.  WM x WN wavefronts per
-// workgroup (8 for the 256x128 complex tile: two per SIMD hide each other's barrier and LDS
-// latency, and the larger tile halves the bytes loaded per MFMA), each owning a 64x64 complex
+// workgroup (8 for the 256x128 and 128x256 complex tiles: two per SIMD hide each other's
+// barrier and LDS latency, and the larger tile halves the bytes loaded per MFMA; 128x256 reads
+// a 256-column product's row operand once), each owning a 64x64 complex
 // block = 2x2 sub-tiles of v_mfma_f32_32x32x16_{bf16,f16} with separate real and imaginary
 // accumulators.  One instruction step covers 8 complex k: lanes 0-31 hold
 // k-group g, lanes 32-63 group g+1, each lane's 8 values being [re(4 k), im(4 k)] of one part:
@@ -258,30 +259,39 @@ bool gemm_split_tile_fits(const GemmSplit& g, int tile) {
     case 0: return g.M % 256 == 0 && g.N % 128 == 0;
     case 1: return g.M % 128 == 0 && g.N % 128 == 0;
     case 2: return g.M % 64 == 0 && g.N % 64 == 0;
+    case 3: return g.M % 128 == 0 && g.N % 256 == 0;
     default: return false;
   }
 }
 
 static int split_tile(const GemmSplit& g) {
   if (g.tile >= 0 && gemm_split_tile_fits(g, g.tile)) return g.tile;
+  // a gathered row operand is read from complex64 storage once per column tile: 256 columns
+  // per tile where they fit
+  if (g.Ac && gemm_split_tile_fits(g, 3)) return 3;
   return gemm_split_tile_fits(g, 0) ? 0 : gemm_split_tile_fits(g, 1) ? 1 : 2;
 }
 
 const char* gemm_split_name(const GemmSplit& g) {
-  static const char* names[2][2][3] = {
-      {{"gemm_split_bf16_256x128", "gemm_split_bf16_128x128", "gemm_split_bf16_64x64"},
-       {"gemm_split_fp16_256x128", "gemm_split_fp16_128x128", "gemm_split_fp16_64x64"}},
+  static const char* names[2][2][kSplitTiles] = {
+      {{"gemm_split_bf16_256x128", "gemm_split_bf16_128x128", "gemm_split_bf16_64x64",
+        "gemm_split_bf16_128x256"},
+       {"gemm_split_fp16_256x128", "gemm_split_fp16_128x128", "gemm_split_fp16_64x64",
+        "gemm_split_fp16_128x256"}},
       {{"gemm_split_bf16_gather_256x128", "gemm_split_bf16_gather_128x128",
-        "gemm_split_bf16_gather_64x64"},
+        "gemm_split_bf16_gather_64x64", "gemm_split_bf16_gather_128x256"},
        {"gemm_split_fp16_gather_256x128", "gemm_split_fp16_gather_128x128",
-        "gemm_split_fp16_gather_64x64"}}};
+        "gemm_split_fp16_gather_64x64", "gemm_split_fp16_gather_128x256"}}};
   return names[g.Ac != nullptr][g.a_amax != nullptr][split_tile(g)];
 }
 
 template <bool F16, bool GA>
 static void gemm_split_t(const GemmSplit& g, hipStream_t s) {
   const int tile = split_tile(g);
-  if (tile == 0) {
+  if (tile == 3) {
+    dim3 grid((unsigned)((g.M / 128) * (g.N / 256)), (unsigned)g.batch);
+    hipLaunchKernelGGL((gemm_split_kernel<128, 256, 2, 4, F16, GA>), grid, dim3(512), 0, s, g);
+  } else if (tile == 0) {
     dim3 grid((unsigned)((g.M / 256) * (g.N / 128)), (unsigned)g.batch);
     hipLaunchKernelGGL((gemm_split_kernel<256, 128, 4, 2, F16, GA>), grid, dim3(512), 0, s, g);
   } else if (tile == 1) {

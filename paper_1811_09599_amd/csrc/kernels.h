@@ -139,14 +139,16 @@ struct GemmSplit {
   // a_off / a_bs / a_add count complex64 elements of Ac); NULL: A is pre-split
   const float2* Ac = nullptr;
   SplitGather ga;
-  // output tile chosen by an autotuner: 0 = 256x128, 1 = 128x128, 2 = 64x64 (-1 or a tile the
-  // shape does not fit: the largest that fits)
+  // output tile chosen by an autotuner: 0 = 256x128, 1 = 128x128, 2 = 64x64, 3 = 128x256 (-1 or
+  // a tile the shape does not fit: 3 for a gathered A where it fits, else the largest of 0, 1,
+  // 2 that fits)
   int tile = -1;
   // fp16 products: record the largest |re|, |im| of C into *c_amax as absmax() would, with
   // tag c_tag (NULL: not recorded)
   uint64_t* c_amax = nullptr;
   uint64_t c_tag = 0;
 };
+constexpr int kSplitTiles = 4;
 bool gemm_split_ok(int64_t M, int64_t N, int64_t K);  // shape fits the tiled kernel
 bool gemm_split_tile_fits(const GemmSplit& g, int tile);
 void gemm_split(const GemmSplit& g, hipStream_t s);
