@@ -102,6 +102,32 @@ void Profiler::release() {
 // ------------------------------------------------------------------------------ grid build
 void prepare_split(qflex_grid* g, hipStream_t s);
 
+// A complex64 tall-skinny product whose intermediate x would be permuted first: the MFMA rows
+// kernel reads x in its own storage order instead, when x's 2 lowest storage labels are
+// contracted ones and x already stores the contracted labels in the product's order (so y and
+// the output keep their layouts).  Such products (N <= 16) never run as split products.
+static void c64_gather(const Step& st, dev::SplitGather& ga, char& use) {
+  if (st.x.qubit || st.scratch_x < 0 || st.kb < 4 || st.nb > 4 || st.mb < 8 ||
+      st.mb + st.kb > dev::kGatherMaxBits || st.x_in.size() < 2)
+    return;
+  const std::set<int> Ks(st.klab.begin(), st.klab.end());
+  std::vector<int> kx;
+  for (int l : st.x_in)
+    if (Ks.count(l)) kx.push_back(l);
+  if (kx != st.klab || !Ks.count(st.x_in.end()[-1]) || !Ks.count(st.x_in.end()[-2])) return;
+  std::vector<int> xa = st.mlab;
+  xa.insert(xa.end(), st.klab.begin(), st.klab.end());
+  const PermDesc pd = make_perm_desc(st.x_in, xa);
+  if (pd.perm[0] != 0 || pd.perm[1] != 1) return;
+  ga = dev::SplitGather{};
+  ga.nm = st.mb;
+  ga.nk = st.kb - 2;
+  for (int j = 0; j < ga.nk; ++j) ga.kpos[j] = (int8_t)pd.perm[2 + j];
+  for (int j = 0; j < ga.nm; ++j) ga.mpos[j] = (int8_t)pd.perm[st.kb + j];
+  use = 1;
+}
+
+
 void build_grid_device(qflex_grid* g, hipStream_t s) {
   for (CircuitState& cs : g->circ) {
     cs.tuned.assign(cs.plan.steps.size(), -1);
@@ -210,12 +236,16 @@ void build_grid_device(qflex_grid* g, hipStream_t s) {
   }
   // permutation tiles of every step
   for (auto& cs : g->circ) {
-    cs.px.assign(cs.plan.steps.size(), dev::PermTile{});
-    cs.py.assign(cs.plan.steps.size(), dev::PermTile{});
-    for (size_t i = 0; i < cs.plan.steps.size(); ++i) {
+    const size_t ns = cs.plan.steps.size();
+    cs.px.assign(ns, dev::PermTile{});
+    cs.py.assign(ns, dev::PermTile{});
+    cs.gather_x.assign(ns, 0);  // the split set-up adds the gathered split products
+    cs.gx.assign(ns, dev::SplitGather{});
+    for (size_t i = 0; i < ns; ++i) {
       const Step& st = cs.plan.steps[i];
       if (st.scratch_x >= 0) cs.px[i] = dev::make_perm_tile(st.px.nbits, st.px.perm.data());
       if (st.scratch_y >= 0) cs.py[i] = dev::make_perm_tile(st.py.nbits, st.py.perm.data());
+      c64_gather(st, cs.gx[i], cs.gather_x[i]);
     }
   }
   if (g->precision == QFLEX_PREC_SPLIT_BF16 || g->precision == QFLEX_PREC_SPLIT_FP16)
@@ -260,8 +290,6 @@ void prepare_split(qflex_grid* g, hipStream_t s) {
     cs.split.assign(ns, 0);
     cs.sx.assign(ns, dev::PermTile{});
     cs.sy.assign(ns, dev::PermTile{});
-    cs.gather_x.assign(ns, 0);
-    cs.gx.assign(ns, dev::SplitGather{});
     cs.xcache_offset.assign(ns, -1);
     cs.xcache_slot.assign(ns, -1);
     cs.xcache_elems = 0;
@@ -804,7 +832,8 @@ void contract(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets, dou
               else run_split(cs.gather_x[k] != 0, -1, true);
               continue;
             }
-            if (stp.scratch_x >= 0) {
+            const bool gather_x = !cs.gather_x.empty() && cs.gather_x[k];
+            if (stp.scratch_x >= 0 && !gather_x) {
               if (stp.x.qubit) fail(QFLEX_E_DEVICE, "internal: permutation of a qubit tensor");
               float2* dst = arena + P.nodes[stp.scratch_x].offset * B;
               g->prof.begin("permute", 0, 16.0 * (double)P.nodes[stp.scratch_x].elems() * nb, s);
@@ -845,9 +874,17 @@ void contract(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets, dou
             gm.ldb = stp.tb ? gm.K : gm.N;
             gm.ldc = gm.N;
             gm.batch = nb;
-            gm.force_variant = cs.tuned[k];
-            if (gm.force_variant < 0 && g->autotune)  // time every fitting kernel variant once
-              gm.force_variant = cs.tuned[k] = tune_gemm(g, s, gm);
+            if (gather_x) {  // x in its own storage order, on the MFMA rows kernel
+              gm.gather = true;
+              gm.ga = cs.gx[k];
+              gm.ta = 0;
+              gm.lda = gm.K;
+              gm.force_variant = 8;
+            } else {
+              gm.force_variant = cs.tuned[k];
+              if (gm.force_variant < 0 && g->autotune)  // time every fitting kernel variant once
+                gm.force_variant = cs.tuned[k] = tune_gemm(g, s, gm);
+            }
             g->prof.begin(dev::gemm_name(gm), stp.flops() * nb,
                           8.0 * nb * (double)(gm.M * gm.K + gm.K * gm.N + gm.M * gm.N), s);
             dev::gemm(gm, s);

@@ -493,6 +493,7 @@ int gemm_variant(const Gemm& g) {
 }
 
 const char* gemm_name(const Gemm& g) {
+  if (g.gather) return g.tb ? "gemm_rows_mfma_gather_nt" : "gemm_rows_mfma_gather_nn";
   static const char* names[kGemmVariants][4] = {
       {"gemm_simt_nn", "gemm_simt_nt", "gemm_simt_tn", "gemm_simt_tt"},
       {"gemm_mfma_64x64_nn", "gemm_mfma_64x64_nt", "gemm_mfma_64x64_tn", "gemm_mfma_64x64_tt"},
@@ -632,7 +633,10 @@ __global__ void __launch_bounds__(256) gemm_reduce_mfma_kernel(const Gemm g) {
 // block is free, as long as A and B agree).  A is read straight from HBM in 16-byte vectors:
 // [M][K] as 4 consecutive k of one row, [K][M] as 2 consecutive rows of one k (the two rows
 // then belong to an even and an odd row block).  B is staged in LDS 64 k at a time.
-template <bool TA, bool TB>
+// GA: A is an intermediate read in its own storage order through g.ga (element (m, k) at
+// f(m) + (k & 3) + g(k >> 2)), as [M][K]: the 4 consecutive k a lane loads are 32 contiguous
+// bytes, and no permutation pass over A is needed.
+template <bool TA, bool TB, bool GA = false>
 __global__ void __launch_bounds__(256) gemm_rows_mfma_kernel(const Gemm g) {
   constexpr int KC = 64;
   __shared__ float2 Bs[KC][16];
@@ -649,6 +653,21 @@ __global__ void __launch_bounds__(256) gemm_rows_mfma_kernel(const Gemm g) {
   floatx4 cr[4], ci[4];
 #pragma unroll
   for (int r = 0; r < 4; ++r) cr[r] = ci[r] = floatx4{0.f, 0.f, 0.f, 0.f};
+  int64_t frow[GA ? 4 : 1];  // gathered A: row offsets plus this lane's k group within 16 k
+  if constexpr (GA) {
+    const int64_t fq = (int64_t)(q & 1) << g.ga.kpos[0] | (int64_t)(q >> 1) << g.ga.kpos[1];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t m = mw + 16 * r + i;
+      int64_t f = fq;
+      if (g.ga.nmr <= kGatherRuns) {
+        f |= deposit_runs(m, g.ga.mrun, g.ga.nmr);
+      } else {
+        for (int j = 0; j < g.ga.nm; ++j) f |= ((m >> j) & 1) << g.ga.mpos[j];
+      }
+      frow[r] = f;
+    }
+  }
   for (int64_t kc = 0; kc < g.K; kc += KC) {
     const int kn = g.K - kc < KC ? (int)(g.K - kc) : KC;
     __syncthreads();  // the previous chunk's reads of Bs are done
@@ -662,7 +681,25 @@ __global__ void __launch_bounds__(256) gemm_rows_mfma_kernel(const Gemm g) {
     for (int kb = 0; kb < kn; kb += 16) {
       const int64_t k0 = kc + kb;
       float2 a[4][4];  // [row block][instruction]
-      if (!TA) {
+      if constexpr (GA) {
+        const int64_t kt = k0 >> 4;  // index of this tile of 16 k
+        int64_t gk = 0;
+        if (g.ga.nkr <= kGatherRuns) {
+          gk = deposit_runs(kt, g.ga.krun, g.ga.nkr);
+        } else {
+          for (int j = 2; j < g.ga.nk; ++j) gk |= ((kt >> (j - 2)) & 1) << g.ga.kpos[j];
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const float2* p = A + frow[r] + gk;
+          const f32x4 v0 = *reinterpret_cast<const f32x4*>(p);
+          const f32x4 v1 = *reinterpret_cast<const f32x4*>(p + 2);
+          a[r][0] = make_float2(v0.x, v0.y);
+          a[r][1] = make_float2(v0.z, v0.w);
+          a[r][2] = make_float2(v1.x, v1.y);
+          a[r][3] = make_float2(v1.z, v1.w);
+        }
+      } else if (!TA) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const float2* p = A + (mw + 16 * r + i) * g.lda + k0 + 4 * q;
@@ -707,7 +744,7 @@ __global__ void __launch_bounds__(256) gemm_rows_mfma_kernel(const Gemm g) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int rr = 4 * q + v;
-        const int64_t m = TA ? mw + 32 * (r >> 1) + 2 * rr + (r & 1) : mw + 16 * r + rr;
+        const int64_t m = TA && !GA ? mw + 32 * (r >> 1) + 2 * rr + (r & 1) : mw + 16 * r + rr;
         C[m * ldc + i] = make_float2(cr[r][v], ci[r][v]);
       }
   }
@@ -736,7 +773,10 @@ static void gemm_t(const Gemm& g, hipStream_t s) {
   const unsigned z = (unsigned)g.split;
   if (v == 8) {
     dim3 grid((unsigned)(g.M / 256), (unsigned)g.batch, z);
-    hipLaunchKernelGGL((gemm_rows_mfma_kernel<TA, TB>), grid, dim3(256), 0, s, g);
+    if (g.gather)
+      hipLaunchKernelGGL((gemm_rows_mfma_kernel<false, TB, true>), grid, dim3(256), 0, s, g);
+    else
+      hipLaunchKernelGGL((gemm_rows_mfma_kernel<TA, TB>), grid, dim3(256), 0, s, g);
   } else if (v == 7) {
     dim3 grid((unsigned)(g.N / 64), (unsigned)g.batch, z);
     hipLaunchKernelGGL((gemm_reduce_mfma_kernel<TA>), grid, dim3(256), 0, s, g);
@@ -802,6 +842,21 @@ static void gemm_t(const Gemm& g, hipStream_t s) {
 
 void gemm(const Gemm& g0, hipStream_t s) {
   if (g0.batch < 1 || g0.batch > 65535) throw std::runtime_error("gemm: bad batch");
+  if (g0.gather) {  // A read through its gather descriptor, on the MFMA rows kernel only
+    Gemm g = g0;
+    if (g.force_variant != 8 || !gemm_variant_fits(g, 8) || g.ta)
+      throw std::runtime_error("gemm: a gathered A needs the MFMA rows kernel and ta = 0");
+    if (g.ga.nm + g.ga.nk + 2 > kGatherMaxBits || g.ga.nk < 2 ||
+        (int64_t(1) << g.ga.nm) != g.M || (int64_t(4) << g.ga.nk) != g.K)
+      throw std::runtime_error("gemm: gather descriptor does not match the shape");
+    g.ga.nmr = gather_runs(g.ga.mpos, 0, g.ga.nm, g.ga.mrun);
+    g.ga.nkr = gather_runs(g.ga.kpos, 2, g.ga.nk, g.ga.krun);
+    g.split = 1;
+    g.a_ks = g.b_ks = 0;
+    if (g.tb) gemm_t<false, true>(g, s);
+    else gemm_t<false, false>(g, s);
+    return;
+  }
   Gemm g = g0;
   g.split = 1;
   g.a_ks = g.b_ks = 0;

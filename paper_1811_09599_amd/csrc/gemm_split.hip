@@ -22,21 +22,6 @@ namespace dev {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 
-// f(v) of a bit map given as runs (see SplitGather); the n <= kGatherRuns run words sit in
-// the kernel arguments at fixed offsets, so they are read once, by scalar loads
-__device__ inline int64_t deposit_runs(int64_t v, const int32_t (&runs)[kGatherRuns], int n) {
-  int64_t f = 0;
-#pragma unroll
-  for (int r = 0; r < kGatherRuns; ++r) {
-    if (r < n) {
-      const int32_t w = runs[r];
-      const int s = w & 0xff, len = (w >> 8) & 0xff, d = (w >> 16) & 0xff;
-      f |= ((v >> s) & ((int64_t(1) << len) - 1)) << d;
-    }
-  }
-  return f;
-}
-
 template <typename V>
 __device__ inline V as_vec(u32x4 v) {
   return __builtin_bit_cast(V, v);
@@ -305,7 +290,7 @@ static void gemm_split_t(const GemmSplit& g, hipStream_t s) {
 
 // Bits first .. n-1 of a map as runs of consecutive positions; bit i of the source is bit
 // (i - first) of the index the kernel deposits.  Returns kGatherRuns + 1 if they do not fit.
-static int32_t gather_runs(const int8_t* pos, int first, int n, int32_t* runs) {
+int32_t gather_runs(const int8_t* pos, int first, int n, int32_t* runs) {
   int32_t nr = 0;
   for (int i = first; i < n;) {
     int len = 1;

@@ -105,5 +105,20 @@ __device__ inline int deposit_i(int v, const int8_t* pos, int limit) {
     if (b < limit) o |= ((v >> (b - FROM)) & 1) << pos[b];
   return o;
 }
+
+// f(v) of a bit map given as runs (see SplitGather); the n <= kGatherRuns run words sit in
+// the kernel arguments at fixed offsets, so they are read once, by scalar loads
+__device__ inline int64_t deposit_runs(int64_t v, const int32_t (&runs)[kGatherRuns], int n) {
+  int64_t f = 0;
+#pragma unroll
+  for (int r = 0; r < kGatherRuns; ++r) {
+    if (r < n) {
+      const int32_t w = runs[r];
+      const int s = w & 0xff, len = (w >> 8) & 0xff, d = (w >> 16) & 0xff;
+      f |= ((v >> s) & ((int64_t(1) << len) - 1)) << d;
+    }
+  }
+  return f;
+}
 }  // namespace dev
 }  // namespace qflex

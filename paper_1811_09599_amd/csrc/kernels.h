@@ -42,6 +42,30 @@ struct PermTile {
 PermTile make_perm_tile(int nbits, const int* perm);
 void permute(const float2* in, float2* out, int64_t batch, const PermTile& t, hipStream_t s);
 
+// ---------------------------------------------------------------- gathered operands
+// Storage positions of the bits of a product operand's row index m and of k >> 2, for an
+// operand read straight from complex64 storage whose 2 lowest storage bits are k's 2 lowest
+// bits: element (m, k) sits at f(m) + (k & 3) + g(k >> 2), so every group of 4 consecutive k
+// is 32 contiguous bytes.
+constexpr int kGatherMaxBits = 40;
+constexpr int kGatherRuns = 8;
+struct SplitGather {
+  int32_t nm = 0, nk = 0;
+  int8_t mpos[kGatherMaxBits] = {};
+  int8_t kpos[kGatherMaxBits] = {};
+  // Filled by gemm_split and gemm from mpos / kpos: the same maps as runs of consecutive bits
+  // (bits s .. s+len-1 of m, or of the index of a tile of 16 k, land at storage positions
+  // d .. d+len-1), packed as s | len << 8 | d << 16.  More than kGatherRuns runs: the kernels
+  // walk the bits instead.
+  int32_t nmr = 0, nkr = 0;
+  int32_t mrun[kGatherRuns] = {};
+  int32_t krun[kGatherRuns] = {};
+};
+
+// The same maps as runs (see SplitGather), filled on the host; returns kGatherRuns + 1 when the
+// bits first .. n-1 of pos need more runs than that
+int32_t gather_runs(const int8_t* pos, int first, int n, int32_t* runs);
+
 // ---------------------------------------------------------------- complex GEMM
 // C[b] = op(A[b]) * op(B[b]); A stored [M][K] (ta=0) or [K][M] (ta=1) with row stride lda,
 // B stored [K][N] (tb=0) or [N][K] (tb=1) with row stride ldb, C stored [M][N].
@@ -70,6 +94,11 @@ struct Gemm {
   // kernel variant chosen by an autotuner (-1: the shape rule of gemm_variant); ignored when
   // the shape does not fit that variant
   int force_variant = -1;
+  // A read straight from complex64 storage through ga (its element (m, k) at
+  // f(m) + (k & 3) + g(k >> 2)) by the MFMA rows kernel, as if stored [M][K]: runs with
+  // force_variant = 8 only, ta = 0, no split-K
+  bool gather = false;
+  SplitGather ga;
 };
 // which kernel gemm() would pick: 0 = SIMT, 1 = MFMA 64x64 tile, 2 = MFMA 128x128 tile,
 // 3 = rows, 4 = reduction-shaped, 5 = short K, 6 = MFMA 256x128 tile, 7 = reduction-shaped
@@ -103,24 +132,6 @@ void split_permute(const float2* in, uint16_t* out, int64_t batch, const PermTil
 // 64-bit atomic maximum: the slot needs no clearing as long as every call on it uses a larger
 // tag than the calls before (tag >= 1; in must be 16-byte aligned).
 void absmax(const float2* in, int64_t n, uint64_t* slot, uint32_t tag, hipStream_t s);
-
-// Storage positions of the bits of a product operand's row index m and of k >> 2, for an
-// operand read straight from complex64 storage whose 2 lowest storage bits are k's 2 lowest
-// bits: element (m, k) sits at f(m) + (k & 3) + g(k >> 2), so every group of 4 consecutive k
-// is 32 contiguous bytes.
-constexpr int kGatherMaxBits = 40;
-constexpr int kGatherRuns = 8;
-struct SplitGather {
-  int32_t nm = 0, nk = 0;
-  int8_t mpos[kGatherMaxBits] = {};
-  int8_t kpos[kGatherMaxBits] = {};
-  // Filled by gemm_split from mpos / kpos: the same maps as runs of consecutive bits (bits
-  // s .. s+len-1 of m, or of the k-tile index, land at storage positions d .. d+len-1), packed
-  // as s | len << 8 | d << 16.  More than kGatherRuns runs: the kernel walks the bits instead.
-  int32_t nmr = 0, nkr = 0;
-  int32_t mrun[kGatherRuns] = {};
-  int32_t krun[kGatherRuns] = {};
-};
 
 struct GemmSplit {
   const uint16_t* A = nullptr;  // [M][K] split, row stride 4K 16-bit values

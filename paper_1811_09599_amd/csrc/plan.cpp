@@ -848,7 +848,17 @@ std::string Plan::describe(const Model& m) const {
       << ",\"kb\":" << s.kb << ",\"nb\":" << s.nb << ",\"ta\":" << (s.ta ? 1 : 0)
       << ",\"tb\":" << (s.tb ? 1 : 0) << ",\"perm_x\":" << (s.scratch_x >= 0 ? 1 : 0)
       << ",\"perm_y\":" << (s.scratch_y >= 0 ? 1 : 0) << ",\"deps\":" << s.deps
-      << ",\"flops\":" << s.flops() << "}";
+      << ",\"flops\":" << s.flops();
+    // label orders, most significant first: the product's rows, contracted labels and
+    // columns, and the storage orders of x and y as they come in (free labels of a qubit)
+    const std::pair<const char*, const std::vector<int>*> lists[] = {
+        {"mlab", &s.mlab}, {"klab", &s.klab}, {"nlab", &s.nlab}, {"x_in", &s.x_in}, {"y_in", &s.y_in}};
+    for (const auto& kv : lists) {
+      o << ",\"" << kv.first << "\":[";
+      for (size_t j = 0; j < kv.second->size(); ++j) o << (j ? "," : "") << (*kv.second)[j];
+      o << "]";
+    }
+    o << "}";
   }
   o << "],\"qubit_free_bits\":[";
   for (size_t q = 0; q < qubits.size(); ++q) o << (q ? "," : "") << qubits[q].free_bits();
