@@ -251,7 +251,12 @@ def test_fsim_7x7_depth16_sampled_slices_vs_oracle(prec):
     g = build_grid(c, open_qubits=op, precision=prec)
     assert g.num_slices() == 256
     ids = [11, 190]
+    g.set_profiling(True)
     a = g.contract_amplitudes(bits, slice_ids=ids).cpu().numpy()
+    prof = g.profile_read()
+    # the plan's two (2^16 or 2^12, 256, 16) steps read their intermediate x in its storage
+    # order (no permutation pass): this parity check covers that path
+    assert prof["gemm_rows_mfma_gather_nn"]["launches"] == 2 * len(ids), prof.keys()
     ref = E2.amplitudes(c, bits, op, cuts=g.plan_cuts(), slice_ids=ids,
                         order=E2.quadrant_order(7, 7))
     _say("oracle done")

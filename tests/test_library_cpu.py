@@ -133,6 +133,30 @@ def test_planner_7x7_quadrant_matches_the_paper_structure():
         assert [s["deps"] for s in big] == [1, 3]
 
 
+def test_plan_description_label_orders_are_consistent():
+    """Each step lists its product's row, contracted and column labels and the storage orders
+    of x and y: x holds exactly the rows and the contracted labels, y the contracted labels
+    and the columns, and an intermediate x is the output of an earlier step with the rows and
+    columns of that step."""
+    op = R.grid_ids((7, 7), [(5, 0), (5, 1), (5, 2), (6, 0), (6, 1), (6, 2)])
+    for c, kw in ((R.grid_rqc(7, 7, 32, 2000), {"open_qubits": op}),
+                  (R.grid_rqc(5, 4, 16, 7), {"plan": "sweep"}),
+                  (R.grid_rqc(4, 5, 16, 4242), {"plan": "cut_sweep", "max_tensor_elems": 1 << 8})):
+        p = plan_describe(c, **kw)
+        outs = {}
+        for st in p["steps"]:
+            assert sorted(st["x_in"]) == sorted(st["mlab"] + st["klab"])
+            assert sorted(st["y_in"]) == sorted(st["klab"] + st["nlab"])
+            assert len(st["mlab"]) == st["mb"] and len(st["klab"]) == st["kb"]
+            assert len(st["nlab"]) == st["nb"]
+            assert not set(st["mlab"]) & set(st["nlab"])
+            for side in ("x", "y"):
+                if st[side].startswith("n"):
+                    lab = outs[int(st[side][1:])]
+                    assert sorted(lab) == sorted(st[side + "_in"])
+            outs[st["out"]] = st["mlab"] + st["nlab"]
+
+
 def test_planner_small_grid_is_a_single_sweep():
     p = plan_describe(R.grid_rqc(4, 4, 16, 1))
     assert p["kind"] == "sweep" and p["num_slices"] == 1 and p["max_bits"] <= 12
