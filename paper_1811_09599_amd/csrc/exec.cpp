@@ -290,6 +290,8 @@ void prepare_split(qflex_grid* g, hipStream_t s) {
     cs.split.assign(ns, 0);
     cs.sx.assign(ns, dev::PermTile{});
     cs.sy.assign(ns, dev::PermTile{});
+    cs.gather_y.assign(ns, 0);
+    cs.gy.assign(ns, dev::SplitGather{});
     cs.xcache_offset.assign(ns, -1);
     cs.xcache_slot.assign(ns, -1);
     cs.xcache_elems = 0;
@@ -326,6 +328,18 @@ void prepare_split(qflex_grid* g, hipStream_t s) {
           gather = true;
         }
       }
+      // Failing that, the same for an intermediate y: its contracted labels ordered as y stores
+      // them, which x (from a cache, a qubit tensor's split or a permutation) then follows.
+      bool gather_y = false;
+      if (!gather && !st.y.qubit && st.kb >= 4 && st.y_in.size() >= 2) {
+        const std::set<int> K(st.klab.begin(), st.klab.end());
+        if (K.count(st.y_in.end()[-1]) && K.count(st.y_in.end()[-2])) {
+          klab.clear();
+          for (int l : st.y_in)
+            if (K.count(l)) klab.push_back(l);
+          gather_y = true;
+        }
+      }
       const std::vector<int> xa = [&] { auto v = st.mlab; v.insert(v.end(), klab.begin(), klab.end()); return v; }();
       const std::vector<int> yb = [&] { auto v = st.nlab; v.insert(v.end(), klab.begin(), klab.end()); return v; }();
       if (gather) {
@@ -338,6 +352,17 @@ void prepare_split(qflex_grid* g, hipStream_t s) {
         for (int j = 0; ok && j < ga.nk; ++j) ga.kpos[j] = (int8_t)pd.perm[2 + j];
         for (int j = 0; ok && j < ga.nm; ++j) ga.mpos[j] = (int8_t)pd.perm[st.kb + j];
         cs.gather_x[i] = ok;
+      }
+      if (gather_y) {
+        const PermDesc pd = make_perm_desc(st.y_in, yb);
+        dev::SplitGather& gb = cs.gy[i];
+        gb.nm = st.nb;
+        gb.nk = st.kb - 2;
+        bool ok = st.nb + st.kb <= dev::kGatherMaxBits;
+        for (int j = 0; j < 2 && ok; ++j) ok = pd.perm[j] == j;
+        for (int j = 0; ok && j < gb.nk; ++j) gb.kpos[j] = (int8_t)pd.perm[2 + j];
+        for (int j = 0; ok && j < gb.nm; ++j) gb.mpos[j] = (int8_t)pd.perm[st.kb + j];
+        cs.gather_y[i] = ok;
       }
       for (int side = 0; side < 2; ++side) {
         const Operand& o = side ? st.y : st.x;
@@ -714,9 +739,10 @@ void contract(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets, dou
             const bool is_split = !cs.split.empty() && cs.split[k];
             const int64_t M = int64_t(1) << stp.mb, N = int64_t(1) << stp.nb;
             const int64_t K = int64_t(1) << stp.kb;
-            // one split product: gather = read x straight from complex64 storage (when the
-            // plan allows it), tile = output tile (-1: shape rule); `final` runs count in stats
-            auto run_split = [&](bool gather, int tile, bool final) {
+            // one split product: gather (gather_y) = read x (y) straight from complex64 storage
+            // (when the plan allows it), tile = output tile (-1: shape rule); `final` runs count
+            // in stats
+            auto run_split = [&](bool gather, bool gather_y, int tile, bool final) {
               uint16_t* sa = static_cast<uint16_t*>(g->split_scratch.p);
               uint16_t* sb = sa + B * cs.split_a_elems;
               dev::GemmSplit gs;
@@ -787,12 +813,18 @@ void contract(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets, dou
                   dev::absmax(y.base, N * K * nb, g->amax + 1, next_amax_tag(g, s), s);
                   g->prof.end(s);
                 }
-                g->prof.begin("split_permute", 0, 16.0 * N * K * nb, s);
-                dev::split_permute(y.base, sb, nb, cs.sy[k], stp.kb, gs.b_amax, s);
-                g->prof.end(s);
-                if (final) st.permute_bytes += 16.0 * N * K * nb, ++st.n_permute;
-                gs.B = sb;
-                gs.b_bs = N * K;
+                if (gather_y) {
+                  gs.Bc = y.base;
+                  gs.b_bs = y.bs;
+                  gs.gb = cs.gy[k];
+                } else {
+                  g->prof.begin("split_permute", 0, 16.0 * N * K * nb, s);
+                  dev::split_permute(y.base, sb, nb, cs.sy[k], stp.kb, gs.b_amax, s);
+                  g->prof.end(s);
+                  if (final) st.permute_bytes += 16.0 * N * K * nb, ++st.n_permute;
+                  gs.B = sb;
+                  gs.b_bs = N * K;
+                }
               }
               const Node& out = P.nodes[stp.out];
               gs.C = arena + out.offset * B;
@@ -815,21 +847,23 @@ void contract(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets, dou
             if (is_split) {
               int choice = cs.tuned[k];
               if (choice < 0 && g->autotune) {
-                // time every fitting (tile, gather) pair once on this call's operands
+                // time every fitting (tile, gathered x, gathered y) once on this call's operands
                 dev::GemmSplit shape;
                 shape.M = M;
                 shape.N = N;
                 float best = 0;
-                for (int gth = 0; gth < (cs.gather_x[k] ? 2 : 1); ++gth)
-                  for (int t = 0; t < dev::kSplitTiles; ++t) {
-                    if (!dev::gemm_split_tile_fits(shape, t)) continue;
-                    const float ms = time_launches([&] { run_split(gth == 1, t, false); });
-                    if (choice < 0 || ms < best) choice = 2 * t + gth, best = ms;
-                  }
+                for (int gy = 0; gy < (cs.gather_y[k] ? 2 : 1); ++gy)
+                  for (int gth = 0; gth < (cs.gather_x[k] ? 2 : 1); ++gth)
+                    for (int t = 0; t < dev::kSplitTiles; ++t) {
+                      if (!dev::gemm_split_tile_fits(shape, t)) continue;
+                      const float ms =
+                          time_launches([&] { run_split(gth == 1, gy == 1, t, false); });
+                      if (choice < 0 || ms < best) choice = 4 * t + 2 * gy + gth, best = ms;
+                    }
                 cs.tuned[k] = choice;
               }
-              if (choice >= 0) run_split(choice & 1, choice >> 1, true);
-              else run_split(cs.gather_x[k] != 0, -1, true);
+              if (choice >= 0) run_split(choice & 1, (choice >> 1) & 1, choice >> 2, true);
+              else run_split(cs.gather_x[k] != 0, cs.gather_y[k] != 0, -1, true);
               continue;
             }
             const bool gather_x = !cs.gather_x.empty() && cs.gather_x[k];

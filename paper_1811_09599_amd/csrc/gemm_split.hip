@@ -39,9 +39,11 @@ __device__ inline floatx16 mfma16(f16x8 a, f16x8 b, floatx16 c) {
 //
 // At least two wavefronts per SIMD: left to itself the compiler gives the fp16 128x128 tile
 // 300 registers, which leaves one.
-template <int BM, int BN, int WM, int WN, bool F16, bool GA>
+// GB: the same for B (the column operand), through g.gb, when A is not gathered.
+template <int BM, int BN, int WM, int WN, bool F16, bool GA, bool GB = false>
 __global__ void __launch_bounds__(64 * WM * WN) __attribute__((amdgpu_waves_per_eu(2)))
 gemm_split_kernel(const GemmSplit g) {
+  static_assert(!(GA && GB), "one gathered operand per product");
   using V = typename std::conditional<F16, f16x8, bf16x8>::type;
   constexpr int NT = 64 * WM * WN;       // threads: WM x WN wavefronts
   constexpr int BK = 16;                 // complex k per tile
@@ -59,7 +61,8 @@ gemm_split_kernel(const GemmSplit g) {
   const int64_t tm = (int64_t)blockIdx.x / tiles_n, tn = (int64_t)blockIdx.x % tiles_n;
   const int b = blockIdx.y;
   const uint16_t* __restrict__ A = g.A + 4 * (g.a_add + (g.a_off ? g.a_off[b] : b * g.a_bs));
-  const uint16_t* __restrict__ B = g.B + 4 * (g.b_add + (g.b_off ? g.b_off[b] : b * g.b_bs));
+  const uint16_t* __restrict__ B =
+      GB ? nullptr : g.B + 4 * (g.b_add + (g.b_off ? g.b_off[b] : b * g.b_bs));
   float2* __restrict__ C = g.C + b * g.c_bs;
   const int64_t lda = 4 * g.K, ldb = 4 * g.K;
   const int64_t m0 = tm * BM, n0 = tn * BN;
@@ -87,6 +90,28 @@ gemm_split_kernel(const GemmSplit g) {
     }
     if constexpr (F16) ascale = fp16_scale(*g.a_amax);
   }
+  // gathered B: BG groups of 4 k per thread per tile, columns fixed for the whole k loop
+  constexpr int BG = BN * (BK / 4) / NT;
+  f32x4 rd[GB ? BG : 1][2];
+  int64_t fcol[GB ? BG : 1];
+  const float2* __restrict__ Bc =
+      GB ? g.Bc + g.b_add + (g.b_off ? g.b_off[b] : b * g.b_bs) : nullptr;
+  float bscale = 1.f;
+  if constexpr (GB) {
+#pragma unroll
+    for (int u = 0; u < BG; ++u) {
+      const int64_t n = n0 + ((tid + u * NT) >> 2);
+      const int grp = (tid + u * NT) & 3;
+      int64_t f = (int64_t)(grp & 1) << g.gb.kpos[0] | (int64_t)(grp >> 1) << g.gb.kpos[1];
+      if (g.gb.nmr <= kGatherRuns) {
+        f |= deposit_runs(n, g.gb.mrun, g.gb.nmr);
+      } else {
+        for (int i = 0; i < g.gb.nm; ++i) f |= ((n >> i) & 1) << g.gb.mpos[i];
+      }
+      fcol[u] = f;
+    }
+    if constexpr (F16) bscale = fp16_scale(*g.b_amax);
+  }
   auto gload = [&](int64_t k0) {  // k0 in 16-bit units along the row
     if constexpr (GA) {
       const int64_t kt = k0 / ROW;
@@ -109,10 +134,26 @@ gemm_split_kernel(const GemmSplit g) {
         ra[v] = *reinterpret_cast<const u32x4*>(A + (m0 + row) * lda + k0 + 8 * ch);
       }
     }
+    if constexpr (GB) {
+      const int64_t kt = k0 / ROW;
+      int64_t gk = 0;
+      if (g.gb.nkr <= kGatherRuns) {
+        gk = deposit_runs(kt, g.gb.krun, g.gb.nkr);
+      } else {
+        for (int j = 2; j < g.gb.nk; ++j) gk |= ((kt >> (j - 2)) & 1) << g.gb.kpos[j];
+      }
 #pragma unroll
-    for (int v = 0; v < BV; ++v) {
-      const int e = tid + v * NT, row = e >> 3, ch = e & 7;
-      rb[v] = *reinterpret_cast<const u32x4*>(B + (n0 + row) * ldb + k0 + 8 * ch);
+      for (int u = 0; u < BG; ++u) {
+        const float2* p = Bc + fcol[u] + gk;
+        rd[u][0] = *reinterpret_cast<const f32x4*>(p);
+        rd[u][1] = *reinterpret_cast<const f32x4*>(p + 2);
+      }
+    } else {
+#pragma unroll
+      for (int v = 0; v < BV; ++v) {
+        const int e = tid + v * NT, row = e >> 3, ch = e & 7;
+        rb[v] = *reinterpret_cast<const u32x4*>(B + (n0 + row) * ldb + k0 + 8 * ch);
+      }
     }
   };
   auto sstore = [&](int buf) {
@@ -138,10 +179,26 @@ gemm_split_kernel(const GemmSplit g) {
         *reinterpret_cast<u32x4*>(&As[buf][row * LDR + 8 * ch]) = ra[v];
       }
     }
+    if constexpr (GB) {
 #pragma unroll
-    for (int v = 0; v < BV; ++v) {
-      const int e = tid + v * NT, row = e >> 3, ch = e & 7;
-      *reinterpret_cast<u32x4*>(&Bs[buf][row * LDR + 8 * ch]) = rb[v];
+      for (int u = 0; u < BG; ++u) {
+        const int e = tid + u * NT, row = e >> 2, grp = e & 3;
+        const f32x4 p0 = rd[u][0] * bscale, p1 = rd[u][1] * bscale;
+        uint32_t h0, h1, h2, h3, l0, l1, l2, l3;
+        split16x2<F16>(p0.x, p0.z, h0, l0);
+        split16x2<F16>(p1.x, p1.z, h1, l1);
+        split16x2<F16>(p0.y, p0.w, h2, l2);
+        split16x2<F16>(p1.y, p1.w, h3, l3);
+        const u32x4 hi = {h0, h1, h2, h3}, lo = {l0, l1, l2, l3};
+        *reinterpret_cast<u32x4*>(&Bs[buf][row * LDR + 16 * grp]) = hi;
+        *reinterpret_cast<u32x4*>(&Bs[buf][row * LDR + 16 * grp + 8]) = lo;
+      }
+    } else {
+#pragma unroll
+      for (int v = 0; v < BV; ++v) {
+        const int e = tid + v * NT, row = e >> 3, ch = e & 7;
+        *reinterpret_cast<u32x4*>(&Bs[buf][row * LDR + 8 * ch]) = rb[v];
+      }
     }
   };
   floatx16 cr[TMI][TNI], ci[TMI][TNI];
@@ -267,24 +324,30 @@ const char* gemm_split_name(const GemmSplit& g) {
         "gemm_split_bf16_gather_64x64", "gemm_split_bf16_gather_128x256"},
        {"gemm_split_fp16_gather_256x128", "gemm_split_fp16_gather_128x128",
         "gemm_split_fp16_gather_64x64", "gemm_split_fp16_gather_128x256"}}};
+  static const char* names_gb[2][kSplitTiles] = {
+      {"gemm_split_bf16_gatherb_256x128", "gemm_split_bf16_gatherb_128x128",
+       "gemm_split_bf16_gatherb_64x64", "gemm_split_bf16_gatherb_128x256"},
+      {"gemm_split_fp16_gatherb_256x128", "gemm_split_fp16_gatherb_128x128",
+       "gemm_split_fp16_gatherb_64x64", "gemm_split_fp16_gatherb_128x256"}};
+  if (g.Bc && !g.Ac) return names_gb[g.a_amax != nullptr][split_tile(g)];
   return names[g.Ac != nullptr][g.a_amax != nullptr][split_tile(g)];
 }
 
-template <bool F16, bool GA>
+template <bool F16, bool GA, bool GB = false>
 static void gemm_split_t(const GemmSplit& g, hipStream_t s) {
   const int tile = split_tile(g);
   if (tile == 3) {
     dim3 grid((unsigned)((g.M / 128) * (g.N / 256)), (unsigned)g.batch);
-    hipLaunchKernelGGL((gemm_split_kernel<128, 256, 2, 4, F16, GA>), grid, dim3(512), 0, s, g);
+    hipLaunchKernelGGL((gemm_split_kernel<128, 256, 2, 4, F16, GA, GB>), grid, dim3(512), 0, s, g);
   } else if (tile == 0) {
     dim3 grid((unsigned)((g.M / 256) * (g.N / 128)), (unsigned)g.batch);
-    hipLaunchKernelGGL((gemm_split_kernel<256, 128, 4, 2, F16, GA>), grid, dim3(512), 0, s, g);
+    hipLaunchKernelGGL((gemm_split_kernel<256, 128, 4, 2, F16, GA, GB>), grid, dim3(512), 0, s, g);
   } else if (tile == 1) {
     dim3 grid((unsigned)((g.M / 128) * (g.N / 128)), (unsigned)g.batch);
-    hipLaunchKernelGGL((gemm_split_kernel<128, 128, 2, 2, F16, GA>), grid, dim3(256), 0, s, g);
+    hipLaunchKernelGGL((gemm_split_kernel<128, 128, 2, 2, F16, GA, GB>), grid, dim3(256), 0, s, g);
   } else {
     dim3 grid((unsigned)((g.M / 64) * (g.N / 64)), (unsigned)g.batch);
-    hipLaunchKernelGGL((gemm_split_kernel<64, 64, 2, 2, F16, GA>), grid, dim3(256), 0, s, g);
+    hipLaunchKernelGGL((gemm_split_kernel<64, 64, 2, 2, F16, GA, GB>), grid, dim3(256), 0, s, g);
   }
 }
 
@@ -308,6 +371,7 @@ void gemm_split(const GemmSplit& g_in, hipStream_t s) {
   if (g.batch < 1 || g.batch > 65535) throw std::runtime_error("gemm_split: bad batch");
   if ((g.a_amax == nullptr) != (g.b_amax == nullptr))
     throw std::runtime_error("gemm_split: both operands must use the same format");
+  if (g.Ac && g.Bc) throw std::runtime_error("gemm_split: one gathered operand per product");
   if (g.Ac) {
     // the gathered k groups need the 2 lowest k bits in the 2 lowest storage bits
     if (g.ga.nm + g.ga.nk + 2 > kGatherMaxBits || g.ga.nk < 2 || (int64_t(1) << g.ga.nm) != g.M ||
@@ -317,6 +381,14 @@ void gemm_split(const GemmSplit& g_in, hipStream_t s) {
     g.ga.nkr = gather_runs(g.ga.kpos, 2, g.ga.nk, g.ga.krun);
     if (g.a_amax) gemm_split_t<true, true>(g, s);
     else gemm_split_t<false, true>(g, s);
+  } else if (g.Bc) {
+    if (g.gb.nm + g.gb.nk + 2 > kGatherMaxBits || g.gb.nk < 2 || (int64_t(1) << g.gb.nm) != g.N ||
+        (int64_t(4) << g.gb.nk) != g.K)
+      throw std::runtime_error("gemm_split: gather descriptor does not match the shape");
+    g.gb.nmr = gather_runs(g.gb.mpos, 0, g.gb.nm, g.gb.mrun);
+    g.gb.nkr = gather_runs(g.gb.kpos, 2, g.gb.nk, g.gb.krun);
+    if (g.a_amax) gemm_split_t<true, false, true>(g, s);
+    else gemm_split_t<false, false, true>(g, s);
   } else {
     if (g.a_amax) gemm_split_t<true, false>(g, s);
     else gemm_split_t<false, false>(g, s);

@@ -31,6 +31,8 @@ struct CircuitState {
   std::vector<dev::PermTile> sx, sy; // per step: node operand -> split operand layout
   std::vector<char> gather_x;        // per step: x read from complex64 storage by the product
   std::vector<dev::SplitGather> gx;  // per step: its gather descriptor
+  std::vector<char> gather_y;        // per step: y read from complex64 storage by the product
+  std::vector<dev::SplitGather> gy;  // per step: its gather descriptor
   // per step: x is an intermediate reused across slices, kept split in split_cache (offset in
   // 16-bit values per bit-string, -1 if not) and re-split only when it is recomputed
   std::vector<int64_t> xcache_offset;

@@ -150,6 +150,11 @@ struct GemmSplit {
   // a_off / a_bs / a_add count complex64 elements of Ac); NULL: A is pre-split
   const float2* Ac = nullptr;
   SplitGather ga;
+  // B read from complex64 storage through gb the same way (its column index n in the place of
+  // m; then B is unused and b_off / b_bs / b_add count complex64 elements of Bc); not together
+  // with a gathered A
+  const float2* Bc = nullptr;
+  SplitGather gb;
   // output tile chosen by an autotuner: 0 = 256x128, 1 = 128x128, 2 = 64x64, 3 = 128x256 (-1 or
   // a tile the shape does not fit: 3 for a gathered A where it fits, else the largest of 0, 1,
   // 2 that fits)
