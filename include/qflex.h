@@ -163,8 +163,11 @@ qflex_status qflex_plan_cuts(const qflex_grid* g, int32_t circuit, int32_t* pair
                              int32_t max_cuts, int32_t* n_cuts);
 
 /* Validate and plan one circuit without touching the GPU; writes a JSON description of the
- * plan (cuts, steps with their matrix-product shapes, flops per bit-string, memory) into buf
- * (NUL-terminated, truncated to len).  *needed receives the full length + 1. */
+ * plan (cuts, steps with their matrix-product shapes, label orders and flops per bit-string,
+ * memory) into buf (NUL-terminated, truncated to len).  *needed receives the full length + 1.
+ * A step's label lists (most significant first) are the product's rows, contracted labels and
+ * columns (mlab, klab, nlab) and the storage orders of its operands as they come in (x_in,
+ * y_in; free labels only for a qubit tensor). */
 qflex_status qflex_plan_describe(const qflex_circuit* circuit, const qflex_options* opt,
                                  char* buf, int64_t len, int64_t* needed);
 
