@@ -238,7 +238,7 @@ def test_bench_launch_configuration_7x7():
     g.close()
 
 
-@pytest.mark.parametrize("prec", ["c64", "split_bf16"])
+@pytest.mark.parametrize("prec", ["c64", "split_bf16", "split_fp16"])
 def test_fsim_7x7_depth16_sampled_slices_vs_oracle(prec):
     """fSim couplers (rank-4 bonds, 2 bond bits per gate): a 1+16+1 fSim circuit has the bond
     dimensions of a 1+32+1 CZ circuit (16 per link), and its 7x7 contraction runs the same
@@ -264,7 +264,8 @@ def test_fsim_7x7_depth16_sampled_slices_vs_oracle(prec):
     # check covers those paths
     assert prof["gemm_rows_mfma_gather_nn"]["launches"] == 2 * len(ids), prof.keys()
     if prec != "c64":
-        assert prof["gemm_split_bf16_gatherb_256x128"]["launches"] >= len(ids), prof.keys()
+        fmt = prec.split("_")[1]
+        assert prof["gemm_split_%s_gatherb_256x128" % fmt]["launches"] >= len(ids), prof.keys()
 
 
 # ------------------------------------------------------------------- cut sweeps
