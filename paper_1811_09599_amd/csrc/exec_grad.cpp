@@ -175,6 +175,12 @@ void contract_grad(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets
     }
     if (ws_need) g->splitk_ws.reserve(sizeof(float2) * (size_t)ws_need);
     float2* splitk_ws = ws_need ? static_cast<float2*>(g->splitk_ws.p) : nullptr;
+    // forward products whose intermediate x the MFMA rows kernel reads in its own storage order
+    // (decided at grid build), kept to K >= 256 so that the backward X^T Zbar reads it the same
+    // way on that kernel (its rows are then a multiple of 256)
+    auto gathered = [&](size_t k) {
+      return !cs.gather_x.empty() && cs.gather_x[k] && P.steps[k].kb >= 8;
+    };
     // permutations routing each product cotangent back to its operand's storage order
     std::vector<dev::PermTile> rx(P.steps.size()), ry(P.steps.size());
     std::vector<PermDesc> dx(P.steps.size()), dy(P.steps.size());
@@ -240,7 +246,8 @@ void contract_grad(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets
         for (size_t k = 0; k < P.steps.size(); ++k) {
           const Step& stp = P.steps[k];
           GView x = view(stp.x), y = view(stp.y);
-          if (stp.scratch_x >= 0) {
+          const bool gx = gathered(k);
+          if (stp.scratch_x >= 0 && !gx) {
             float2* dst = ar + voff[stp.scratch_x] * B;
             g->prof.begin("permute", 0,
                           16.0 * (double)P.nodes[stp.scratch_x].elems() * nb, s);
@@ -278,9 +285,17 @@ void contract_grad(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets
           gm.batch = nb;
           gm.ws = splitk_ws;
           gm.ws_elems = ws_need;
-          gm.force_variant = cs.tuned_grad[3 * k + 0];
-          if (gm.force_variant < 0 && g->autotune)
-            gm.force_variant = cs.tuned_grad[3 * k + 0] = tune_gemm(g, s, gm);
+          if (gx) {  // x in its own storage order, on the MFMA rows kernel
+            gm.gather = true;
+            gm.ga = cs.gx[k];
+            gm.ta = 0;
+            gm.lda = gm.K;
+            gm.force_variant = 8;
+          } else {
+            gm.force_variant = cs.tuned_grad[3 * k + 0];
+            if (gm.force_variant < 0 && g->autotune)
+              gm.force_variant = cs.tuned_grad[3 * k + 0] = tune_gemm(g, s, gm);
+          }
           g->prof.begin(dev::gemm_name(gm), stp.flops() * nb,
                         8.0 * nb * (double)(gm.M * gm.K + gm.K * gm.N + gm.M * gm.N), s);
           dev::gemm(gm, s);
@@ -317,7 +332,8 @@ void contract_grad(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets
           const Step& stp = P.steps[kk];
           const int64_t M = int64_t(1) << stp.mb, K = int64_t(1) << stp.kb,
                         N = int64_t(1) << stp.nb;
-          GView x = stp.scratch_x >= 0 ? nodev(stp.scratch_x) : view(stp.x);
+          const bool gx = gathered(kk);
+          GView x = stp.scratch_x >= 0 && !gx ? nodev(stp.scratch_x) : view(stp.x);
           GView y = stp.scratch_y >= 0 ? nodev(stp.scratch_y) : view(stp.y);
           const float2* zbar = ar + coff[stp.out] * B;
           float2* xbar = ar + s1off * B;  // [M][K]
@@ -367,9 +383,17 @@ void contract_grad(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets
           g2.batch = nb;
           g2.ws = splitk_ws;
           g2.ws_elems = ws_need;
-          g2.force_variant = cs.tuned_grad[3 * kk + 2];
-          if (g2.force_variant < 0 && g->autotune)
-            g2.force_variant = cs.tuned_grad[3 * kk + 2] = tune_gemm(g, s, g2);
+          if (gx) {  // X^T read through the forward product's gather descriptor
+            g2.gather = true;
+            g2.ga = cs.gx[kk];
+            g2.ta = 1;
+            g2.lda = g2.M;
+            g2.force_variant = 8;
+          } else {
+            g2.force_variant = cs.tuned_grad[3 * kk + 2];
+            if (g2.force_variant < 0 && g->autotune)
+              g2.force_variant = cs.tuned_grad[3 * kk + 2] = tune_gemm(g, s, g2);
+          }
           g->prof.begin(dev::gemm_name(g2), stp.flops() * nb,
                         8.0 * nb * (double)(g2.M * g2.K + g2.K * g2.N + g2.M * g2.N), s);
           dev::gemm(g2, s);

@@ -493,7 +493,11 @@ int gemm_variant(const Gemm& g) {
 }
 
 const char* gemm_name(const Gemm& g) {
-  if (g.gather) return g.tb ? "gemm_rows_mfma_gather_nt" : "gemm_rows_mfma_gather_nn";
+  if (g.gather) {
+    static const char* gnames[4] = {"gemm_rows_mfma_gather_nn", "gemm_rows_mfma_gather_nt",
+                                    "gemm_rows_mfma_gather_tn", "gemm_rows_mfma_gather_tt"};
+    return gnames[(g.ta ? 2 : 0) + (g.tb ? 1 : 0)];
+  }
   static const char* names[kGemmVariants][4] = {
       {"gemm_simt_nn", "gemm_simt_nt", "gemm_simt_tn", "gemm_simt_tt"},
       {"gemm_mfma_64x64_nn", "gemm_mfma_64x64_nt", "gemm_mfma_64x64_tn", "gemm_mfma_64x64_tt"},
@@ -635,7 +639,10 @@ __global__ void __launch_bounds__(256) gemm_reduce_mfma_kernel(const Gemm g) {
 // then belong to an even and an odd row block).  B is staged in LDS 64 k at a time.
 // GA: A is an intermediate read in its own storage order through g.ga (element (m, k) at
 // f(m) + (k & 3) + g(k >> 2)), as [M][K]: the 4 consecutive k a lane loads are 32 contiguous
-// bytes, and no permutation pass over A is needed.
+// bytes, and no permutation pass over A is needed.  GA with TA: A is the transpose of such an
+// operand (element (m, k) at f(k) + (m & 3) + g(m >> 2)), as in the cotangent X^T Zbar of a
+// product that read X so; the 2 consecutive rows a lane loads are 16 contiguous bytes.  With
+// split-K chunks the k index runs on from z times the chunk length.
 template <bool TA, bool TB, bool GA = false>
 __global__ void __launch_bounds__(256) gemm_rows_mfma_kernel(const Gemm g) {
   constexpr int KC = 64;
@@ -654,7 +661,20 @@ __global__ void __launch_bounds__(256) gemm_rows_mfma_kernel(const Gemm g) {
 #pragma unroll
   for (int r = 0; r < 4; ++r) cr[r] = ci[r] = floatx4{0.f, 0.f, 0.f, 0.f};
   int64_t frow[GA ? 4 : 1];  // gathered A: row offsets plus this lane's k group within 16 k
-  if constexpr (GA) {
+  const int64_t kz = (int64_t)z * g.K;  // gathered A: first k of this split-K chunk
+  if constexpr (GA && TA) {  // offsets of this lane's row pairs, one per h
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int64_t v = (mw + 32 * h + 2 * i) >> 2;
+      int64_t f = (v & 1) << g.ga.kpos[0] | ((v >> 1) & 1) << g.ga.kpos[1];
+      if (g.ga.nkr <= kGatherRuns) {
+        f |= deposit_runs(v >> 2, g.ga.krun, g.ga.nkr);
+      } else {
+        for (int j = 2; j < g.ga.nk; ++j) f |= ((v >> j) & 1) << g.ga.kpos[j];
+      }
+      frow[h] = f + 2 * (i & 1);
+    }
+  } else if constexpr (GA) {
     const int64_t fq = (int64_t)(q & 1) << g.ga.kpos[0] | (int64_t)(q >> 1) << g.ga.kpos[1];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -681,8 +701,25 @@ __global__ void __launch_bounds__(256) gemm_rows_mfma_kernel(const Gemm g) {
     for (int kb = 0; kb < kn; kb += 16) {
       const int64_t k0 = kc + kb;
       float2 a[4][4];  // [row block][instruction]
-      if constexpr (GA) {
-        const int64_t kt = k0 >> 4;  // index of this tile of 16 k
+      if constexpr (GA && TA) {
+#pragma unroll
+        for (int st = 0; st < 4; ++st) {
+          const int64_t kk = kz + k0 + 4 * q + st;
+          int64_t fm = 0;
+          if (g.ga.nmr <= kGatherRuns) {
+            fm = deposit_runs(kk, g.ga.mrun, g.ga.nmr);
+          } else {
+            for (int j = 0; j < g.ga.nm; ++j) fm |= ((kk >> j) & 1) << g.ga.mpos[j];
+          }
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const f32x4 v = *reinterpret_cast<const f32x4*>(A + fm + frow[h]);
+            a[2 * h][st] = make_float2(v.x, v.y);
+            a[2 * h + 1][st] = make_float2(v.z, v.w);
+          }
+        }
+      } else if constexpr (GA) {
+        const int64_t kt = (kz + k0) >> 4;  // index of this tile of 16 k
         int64_t gk = 0;
         if (g.ga.nkr <= kGatherRuns) {
           gk = deposit_runs(kt, g.ga.krun, g.ga.nkr);
@@ -744,7 +781,7 @@ __global__ void __launch_bounds__(256) gemm_rows_mfma_kernel(const Gemm g) {
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int rr = 4 * q + v;
-        const int64_t m = TA && !GA ? mw + 32 * (r >> 1) + 2 * rr + (r & 1) : mw + 16 * r + rr;
+        const int64_t m = TA ? mw + 32 * (r >> 1) + 2 * rr + (r & 1) : mw + 16 * r + rr;
         C[m * ldc + i] = make_float2(cr[r][v], ci[r][v]);
       }
   }
@@ -774,7 +811,7 @@ static void gemm_t(const Gemm& g, hipStream_t s) {
   if (v == 8) {
     dim3 grid((unsigned)(g.M / 256), (unsigned)g.batch, z);
     if (g.gather)
-      hipLaunchKernelGGL((gemm_rows_mfma_kernel<false, TB, true>), grid, dim3(256), 0, s, g);
+      hipLaunchKernelGGL((gemm_rows_mfma_kernel<TA, TB, true>), grid, dim3(256), 0, s, g);
     else
       hipLaunchKernelGGL((gemm_rows_mfma_kernel<TA, TB>), grid, dim3(256), 0, s, g);
   } else if (v == 7) {
@@ -843,21 +880,19 @@ static void gemm_t(const Gemm& g, hipStream_t s) {
 void gemm(const Gemm& g0, hipStream_t s) {
   if (g0.batch < 1 || g0.batch > 65535) throw std::runtime_error("gemm: bad batch");
   if (g0.gather) {  // A read through its gather descriptor, on the MFMA rows kernel only
-    Gemm g = g0;
-    if (g.force_variant != 8 || !gemm_variant_fits(g, 8) || g.ta)
-      throw std::runtime_error("gemm: a gathered A needs the MFMA rows kernel and ta = 0");
-    if (g.ga.nm + g.ga.nk + 2 > kGatherMaxBits || g.ga.nk < 2 ||
-        (int64_t(1) << g.ga.nm) != g.M || (int64_t(4) << g.ga.nk) != g.K)
+    if (g0.force_variant != 8 || !gemm_variant_fits(g0, 8))
+      throw std::runtime_error("gemm: a gathered A needs the MFMA rows kernel");
+    // the descriptor's row bits index A's rows (ta = 0) or its k (ta = 1, A = X^T)
+    const int64_t rows = g0.ta ? g0.K : g0.M, cols = g0.ta ? g0.M : g0.K;
+    if (g0.ga.nm + g0.ga.nk + 2 > kGatherMaxBits || g0.ga.nk < 2 ||
+        (int64_t(1) << g0.ga.nm) != rows || (int64_t(4) << g0.ga.nk) != cols)
       throw std::runtime_error("gemm: gather descriptor does not match the shape");
-    g.ga.nmr = gather_runs(g.ga.mpos, 0, g.ga.nm, g.ga.mrun);
-    g.ga.nkr = gather_runs(g.ga.kpos, 2, g.ga.nk, g.ga.krun);
-    g.split = 1;
-    g.a_ks = g.b_ks = 0;
-    if (g.tb) gemm_t<false, true>(g, s);
-    else gemm_t<false, false>(g, s);
-    return;
   }
   Gemm g = g0;
+  if (g.gather) {
+    g.ga.nmr = gather_runs(g.ga.mpos, 0, g.ga.nm, g.ga.mrun);
+    g.ga.nkr = gather_runs(g.ga.kpos, 2, g.ga.nk, g.ga.krun);
+  }
   g.split = 1;
   g.a_ks = g.b_ks = 0;
   if (g0.ws) {
@@ -866,7 +901,8 @@ void gemm(const Gemm& g0, hipStream_t s) {
       const int64_t chunk = g0.K / split;
       g.split = split;
       g.K = chunk;
-      g.a_ks = g0.ta ? chunk * g0.lda : chunk;
+      // a gathered A has no pointer offset per chunk: the kernel runs its k index on instead
+      g.a_ks = g0.gather ? 0 : g0.ta ? chunk * g0.lda : chunk;
       g.b_ks = g0.tb ? chunk : chunk * g0.ldb;
     }
   }
