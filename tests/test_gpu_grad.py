@@ -155,7 +155,8 @@ def test_gradient_on_a_split_precision_grid(precision):
 def test_autotuned_gradient_matches_shape_rule_gradient():
     """An autotuned grid times every fitting kernel of each forward and backward product (the
     MFMA rows and reduction kernels, split-K chunks included) and keeps the fastest: its
-    gradients match the shape rules' within FP32 rounding, and the state-vector adjoint."""
+    gradients match the shape rules' within FP32 rounding, and the state-vector adjoint.  Both
+    grids read some intermediates in place (forward, and transposed in the backward pass)."""
     _need_gpu()
     _say("autotuned gradient, 5x4 and 6x6 fSim")
     c1 = R.grid_rqc(5, 4, 12, 910, two_qubit="fsim", jitter_sd=0.02, jitter_seed=11)
@@ -164,7 +165,12 @@ def test_autotuned_gradient_matches_shape_rule_gradient():
     tuned = build_grid([c1, c2], autotune=True)
     plain = build_grid([c1, c2])
     r_t = [tuned.contract_grad(bits) for _ in range(2)]  # the first call tunes
+    plain.set_profiling(True)
     r_p = plain.contract_grad(bits)
+    prof = plain.profile_read()
+    # products that read their intermediate x in place, forward and (as X^T) backward
+    assert prof["gemm_rows_mfma_gather_nn"]["launches"] > 0, prof.keys()
+    assert prof["gemm_rows_mfma_gather_tn"]["launches"] > 0, prof.keys()
     for r in r_t:
         for ci, c in enumerate((c1, c2)):
             f = _fsim_rows(c)
