@@ -127,7 +127,6 @@ static void c64_gather(const Step& st, dev::SplitGather& ga, char& use) {
   use = 1;
 }
 
-
 void build_grid_device(qflex_grid* g, hipStream_t s) {
   for (CircuitState& cs : g->circ) {
     cs.tuned.assign(cs.plan.steps.size(), -1);
