@@ -55,7 +55,7 @@ typedef enum {
                               is not an integer >= 1 */
   QFLEX_E_NOMEM = 3,       /* a device or host allocation failed */
   QFLEX_E_DEVICE = 4,      /* a HIP runtime error (also an asynchronous one from earlier work) */
-  QFLEX_E_UNSUPPORTED = 5  /* valid request this build does not implement */
+  QFLEX_E_UNSUPPORTED = 5  /* valid request the library does not implement */
 } qflex_status;
 
 typedef enum {
