@@ -157,6 +157,47 @@ def test_plan_description_label_orders_are_consistent():
             outs[st["out"]] = st["mlab"] + st["nlab"]
 
 
+@pytest.mark.parametrize("rows,cols,depth,seed,kw,n_open", [
+    (7, 7, 32, 2000, {}, 6), (5, 4, 16, 7, {"plan": "sweep"}, 0),
+    (4, 5, 16, 4242, {"plan": "cut_sweep", "max_tensor_elems": 1 << 8}, 2),
+    (6, 6, 24, 3, {"plan": "quadrant"}, 3), (3, 5, 12, 11, {"plan": "auto"}, 1)])
+def test_plan_contracts_every_tensor_once_and_counts_its_flops(rows, cols, depth, seed, kw,
+                                                              n_open):
+    """Whatever the plan kind: every qubit tensor and every intermediate is an operand of
+    exactly one product, only the last product's output is left (holding just the open output
+    labels), no tensor exceeds the plan's max_bits (nor the cap), and the plan's flops are the
+    sum of its products' flops, each counted once per value of the cuts it depends on
+    (slices are recomputed only from the first product that depends on their cut)."""
+    c = R.grid_rqc(rows, cols, depth, seed)
+    op = list(range(c["n_qubits"] - n_open, c["n_qubits"]))
+    p = plan_describe(c, open_qubits=op, **kw)
+    steps = p["steps"]
+    uses = {}
+    for st in steps:
+        for side in ("x", "y"):
+            uses[st[side]] = uses.get(st[side], 0) + 1
+    assert set(uses.values()) == {1}
+    assert sorted(int(k[1:]) for k in uses if k[0] == "q") == list(range(c["n_qubits"]))
+    consumed = {int(k[1:]) for k in uses if k[0] == "n"}
+    assert [st["out"] for st in steps if st["out"] not in consumed] == [steps[-1]["out"]]
+    assert len(steps[-1]["mlab"]) + len(steps[-1]["nlab"]) == n_open
+    for st in steps:
+        assert max(st["mb"] + st["kb"], st["kb"] + st["nb"], st["mb"] + st["nb"]) <= p["max_bits"]
+    if "max_tensor_elems" in kw:
+        assert 2 ** p["max_bits"] <= kw["max_tensor_elems"]
+    bits = [cut[2] for cut in p["cuts"]]
+    assert p["num_slices"] == 2 ** sum(bits)
+    total = 0
+    for st in steps:
+        mult = 1
+        for ci, b in enumerate(bits):
+            if st["deps"] >> ci & 1:
+                mult *= 2 ** b
+        total += st["flops"] * mult
+        assert st["flops"] == 8 * 2 ** (st["mb"] + st["kb"] + st["nb"])
+    assert total == pytest.approx(p["flops_all_slices"], rel=1e-12)
+
+
 def test_planner_small_grid_is_a_single_sweep():
     p = plan_describe(R.grid_rqc(4, 4, 16, 1))
     assert p["kind"] == "sweep" and p["num_slices"] == 1 and p["max_bits"] <= 12
