@@ -392,3 +392,48 @@ def test_automatic_plan_is_the_cheapest_that_fits():
         assert auto["cost_estimate_s"] == min(costs.values()) == costs[want]
     # an uncut sweep fits the 6x6 depth-32 grid too: the choice was a matter of cost
     assert plan_describe(R.grid_rqc(6, 6, 32, 77), plan="sweep")["cuts"] == []
+
+
+def test_gather_run_encoding_reproduces_the_bit_map():
+    """The gathered products receive each bit-deposit map (storage position of every index bit)
+    as at most 8 runs of consecutive bits, packed s | len << 8 | d << 16 by the host.  For
+    random maps, depositing an index through the runs equals depositing it bit by bit, and a map
+    of more than 8 maximal runs is reported as 9 (the kernels then walk the bits)."""
+    fn = getattr(F.lib(), "_ZN5qflex3dev11gather_runsEPKaiiPi")
+    fn.restype = C.c_int32
+    fn.argtypes = [C.POINTER(C.c_int8), C.c_int, C.c_int, C.POINTER(C.c_int32)]
+    rng = np.random.default_rng(5)
+    seen_overflow = seen_fit = 0
+    for trial in range(400):
+        n = int(rng.integers(3, 38))
+        first = int(rng.integers(0, 3))
+        if trial % 2:  # a few contiguous blocks of storage positions
+            cuts = sorted(set(rng.integers(1, n, size=int(rng.integers(0, 6))).tolist()))
+            blocks = np.split(np.arange(n), cuts)
+            posl = []
+            order = rng.permutation(len(blocks))  # the blocks land in storage in this order
+            offs = np.cumsum([0] + [len(blocks[o]) for o in order])
+            place = {int(o): int(offs[i]) for i, o in enumerate(order)}
+            for bi, blk in enumerate(blocks):
+                posl += [place[bi] + j for j in range(len(blk))]
+        else:  # arbitrary distinct positions
+            posl = rng.permutation(40)[:n].tolist()
+        pos = (C.c_int8 * 40)(*(posl + [0] * (40 - n)))
+        runs = (C.c_int32 * 8)()
+        nr = fn(pos, first, n, runs)
+        maximal = sum(1 for i in range(first, n) if i == first or posl[i] != posl[i - 1] + 1)
+        if maximal > 8:
+            assert nr == 9
+            seen_overflow += 1
+            continue
+        assert nr == maximal
+        seen_fit += 1
+        for v in rng.integers(0, 2 ** (n - first), size=20).tolist():
+            want = sum(((v >> (i - first)) & 1) << posl[i] for i in range(first, n))
+            got = 0
+            for r in range(nr):
+                w = runs[r]
+                s, ln, d = w & 0xFF, (w >> 8) & 0xFF, (w >> 16) & 0xFF
+                got |= ((v >> s) & ((1 << ln) - 1)) << d
+            assert got == want
+    assert seen_overflow > 20 and seen_fit > 100
