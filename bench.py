@@ -1,24 +1,26 @@
 """Throughput of the RQC amplitude contraction on one MI355X.
 
-Workload: 7x7 grid, depth 1+32+1 (bond dimension 16 on every link), the quadrant plan with
-2 cut bonds (256 slices, all summed: fidelity 1), a 6-qubit open batch (64 amplitudes per
-bit-string).  One step = one contraction call over the next `--bitstrings` bit-strings of a
-seeded set of 1024, every slice included.  Three precisions are measured: split-bf16 (the
-headline `value`), split-fp16 and complex64 (reported alongside), each with its error against
-the FP64 oracle on sampled slices.
+Headline workload: 7x7 grid, depth 1+40+1 (bond dimension 32 on every link), the quadrant
+plan of SI A with 2 cut bonds (1024 slices; the largest intermediate 2^30 complex elements), a
+6-qubit open batch (64 amplitudes per bit-string), fidelity f = 1/64 as 16 of the 1024 slices
+(a block subset: one right-cut value and 16 bottom-cut values, SplitMix64-seeded), complex64
+products on FP32 MFMA with FP64 slice sums.
 
-Prints one JSON line: amplitudes/s (whole job), sustained TFLOP/s of the plan (8 real flops
-per complex multiply-add), the roofline of the dominant kernel measured with HIP events around
-its launches in the timed region, and the CPU oracle timed on a bounded sample (the only part
-that runs the oracle, together with the gradient's parity check).  Further workloads, each
-under its own key: "fsim_7x7" (the headline workload with fSim couplers at depth 1+16+1),
-"sampling" (frugal rejection sampling of one bit-string per open batch),
-"gradient" (the adjoint contraction: 96 jittered-fSim circuits on 4x4 to 6x6 grids, depth
-1+12+1, linear XEB over 128 bit-strings each, amplitudes and gradients of every fSim angle in
-one call) and "diamond" (the 70-qubit diamond at fidelity 1/8); "ceilings" holds the vendor
-GEMM and device copy rates of the same device.
+A full 64-amplitude batch at f = 1/64 is ~5.8e15 flop (~40 s in complex64), so one step is one
+slice of one bit-string's batch: a contraction call that adds that slice's 64 partial
+amplitudes into the batch (accumulating output).  The library keeps the intermediates that do
+not depend on the bottom cut across calls, so 16 consecutive steps cost what one call over the
+16 slices costs.  Steps walk through the 16 slices of bit-string 0, then of bit-string 1, ...;
+`value` is amplitudes/s at fidelity 1/64 = 64 / 16 = 4 amplitudes per step.
 
-    python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--bitstrings 8]
+Split-bf16 and split-fp16 run the same steps and are reported alongside (`precisions`), each
+with its error against complex64 on the accumulated batches.  The line also carries the
+roofline of the dominant kernel (HIP events around every launch of the timed region, on the
+launching stream; 8 real flops per complex multiply-add), the 4x4 1+16+1 workload (latency
+bound: 256 amplitudes per call, eager and graph-replayed) and the CPU oracle timed on a bounded
+sample.  Further workloads are opt-in (--extra).
+
+    python bench.py [--gpus 1] [--steps 20] [--warmup 5] [--extra gradient,diamond,...]
 """
 import argparse
 import json
@@ -29,18 +31,27 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# MI355X published peaks: dense MFMA fp32 / bf16, fp32 vector without packed math, HBM3E
+# MI355X published peaks: dense MFMA fp32 / bf16 / fp16, fp32 vector without packed math, HBM3E
 PEAK = {"mfma_fp32": (157.3, "TFLOP/s"), "mfma_bf16": (2500.0, "TFLOP/s"),
         "mfma_fp16": (2500.0, "TFLOP/s"),
         "alu": (78.6, "TFLOP/s"), "hbm": (8000.0, "GB/s")}
 C64_TOL = 1e-5
-# stated bounds of the 2^(n/2)-scaled amplitude error (max over the batch)
-TOL = {"split_bf16": 2e-4, "split_fp16": 4 * C64_TOL, "c64": C64_TOL}
+# stated bounds of the 2^(n/2)-scaled amplitude error (max over the batch): split-bf16 at bond
+# dimension 16 / 32, split-fp16 on random circuits
+TOL = {"split_bf16": 2e-4, "split_bf16_d32": 1.5e-3, "split_fp16": 4 * C64_TOL, "c64": C64_TOL}
 DTYPE = {"split_bf16": "bf16x3", "split_fp16": "fp16x3", "c64": "c64"}
+EXTRAS = ("cfg2", "fsim", "sampling", "gradient", "diamond", "ceilings")
+
+# headline workload (seeds: circuit 3000, bit-strings PCG64 3500, slices SplitMix64 3700)
+ROWS = COLS = 7
+DEPTH = 40
+OPEN_PATCH = [(5, 0), (5, 1), (5, 2), (6, 0), (6, 1), (6, 2)]
+FIDELITY = 1.0 / 64
 
 
 def flop_peak(name):
-    """The arithmetic peak a kernel's flops are measured against, from its name."""
+    """The arithmetic peak a kernel's algorithmic flops are measured against, from its name:
+    a product is priced at the peak of the MFMA type it runs on."""
     if name.startswith("gemm_split_bf16"):
         return "mfma", PEAK["mfma_bf16"][0]
     if name.startswith("gemm_split_fp16"):
@@ -52,10 +63,18 @@ def flop_peak(name):
     return None, None
 
 
+def mfma_work_factor(name):
+    """16-bit MFMA flops the kernel issues per algorithmic flop: the split product of complex
+    parts hi+lo runs 3 real products (hi.hi, hi.lo, lo.hi) per real product of the 4M form."""
+    if name.startswith("gemm_split"):
+        return 3.0
+    return 1.0
+
+
 def roofline(prof):
-    """Roofline of the kernel with the most time: its algorithmic flops and bytes per launch
-    (recorded by the library with each launch) over its average launch time; the bound is the
-    resource the kernel uses the larger fraction of."""
+    """Roofline of the kernel with the most time: its algorithmic flops (8 per complex
+    multiply-add) and bytes per launch, recorded by the library with each launch, over its
+    average launch time; the bound is the resource the kernel uses the larger fraction of."""
     name = max(prof, key=lambda k: prof[k]["ms"])
     k = prof[name]
     sec = k["ms"] * 1e-3
@@ -68,11 +87,375 @@ def roofline(prof):
         bound, achieved, peak, unit = "hbm", gbps, PEAK["hbm"][0], "GB/s"
     else:
         bound, achieved, peak, unit = kind, tflops, fpeak, "TFLOP/s"
-    return name, {"bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": unit,
-                  "frac": round(achieved / peak, 4), "traffic": None,
-                  "flop_frac": round(flop_frac, 4), "hbm_frac": round(hbm_frac, 4),
-                  "avg_launch_us": round(1e3 * k["ms"] / max(k["launches"], 1), 3),
-                  "launches": k["launches"]}
+    r = {"bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": unit,
+         "frac": round(achieved / peak, 4), "traffic": None,
+         "flop_frac": round(flop_frac, 4), "hbm_frac": round(hbm_frac, 4),
+         "avg_launch_us": round(1e3 * k["ms"] / max(k["launches"], 1), 3),
+         "launches": k["launches"],
+         "flops_per_launch": k["flops"] / max(k["launches"], 1)}
+    f = mfma_work_factor(name)
+    if f != 1.0:
+        r["mfma_instruction_tflops"] = round(tflops * f, 1)
+        r["mfma_instruction_frac"] = round(tflops * f / fpeak, 4)
+    return name, r
+
+
+def kernel_table(prof, top=8):
+    return {k: {"launches": v["launches"], "ms": round(v["ms"], 3),
+                "avg_us": round(1e3 * v["ms"] / max(v["launches"], 1), 3),
+                "tflops": round(v["flops"] / max(v["ms"], 1e-9) / 1e9, 3),
+                "gbps": round(v["bytes"] / max(v["ms"], 1e-9) / 1e6, 1)}
+            for k, v in sorted(prof.items(), key=lambda kv: -kv[1]["ms"])[:top]}
+
+
+def scaled_errors(a, ref):
+    """|a - ref| / max(|ref|, rms(ref)) per amplitude (the rms floor keeps tiny amplitudes of
+    the Porter-Thomas tail from dominating): max and median."""
+    import numpy as np
+
+    a, ref = np.ravel(a), np.ravel(ref)
+    if a.size != ref.size:
+        raise ValueError("size mismatch")
+    rms = float(np.sqrt(np.mean(np.abs(ref) ** 2)))
+    e = np.abs(a - ref) / np.maximum(np.abs(ref), rms)
+    return {"max": float(e.max()), "median": float(np.median(e))}
+
+
+def headline_inputs():
+    import rqc_inputs as R
+    circ = R.grid_rqc(ROWS, COLS, DEPTH, 3000)
+    open_q = R.grid_ids((ROWS, COLS), OPEN_PATCH)
+    bits = R.bitstrings(ROWS * COLS, 256, 3500, open_q)
+    return circ, open_q, bits
+
+
+def run_headline(precision, circ, open_q, bits, ids, args):
+    """W + K steps of the headline workload in one precision; returns the accumulated batches
+    (torch complex128 [bit-strings touched, 64]) and the timing of the K timed steps."""
+    import torch
+
+    from paper_1811_09599_amd import build_grid
+
+    t0 = time.time()
+    grid = build_grid(circ, open_qubits=open_q, precision=precision, slice_mode="block",
+                      bitstring_batch=1, autotune=args.autotune)
+    torch.cuda.synchronize()
+    build_s = time.time() - t0
+    k = len(ids)
+    n_steps = args.warmup + args.steps
+    outs = torch.zeros(((n_steps + k - 1) // k, 64), dtype=torch.complex128, device="cuda")
+
+    def step(i):
+        j, s = divmod(i, k)
+        grid.contract_amplitudes(bits[j:j + 1], slice_ids=[ids[s]], out=outs[j:j + 1],
+                                 accumulate=True)
+        return grid.last_stats()["flops"]
+
+    t0 = time.time()
+    warm_flops = 0.0
+    for i in range(args.warmup):
+        warm_flops += step(i)
+    torch.cuda.synchronize()
+    warm_s = time.time() - t0
+    grid.set_profiling(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    flops = 0.0
+    for i in range(args.warmup, n_steps):
+        flops += step(i)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = grid.profile_read()
+    grid.set_profiling(False)
+    grid.close()
+    dom, roof = roofline(prof)
+    amps = args.steps * 64.0 / k  # fidelity-f amplitudes completed
+    print("[bench] %s: %d steps in %.2f s (warm-up %.1f s, grid build %.1f s)"
+          % (precision, args.steps, dt, warm_s, build_s), file=sys.stderr, flush=True)
+    return outs, {"value": amps / dt, "ms_per_step": 1e3 * dt / args.steps,
+                  "tflops": flops / dt / 1e12, "timed_flops": flops,
+                  "dominant_kernel": dom, "roofline": roof, "kernels": kernel_table(prof),
+                  "grid_build_s": round(build_s, 3), "warmup_s": round(warm_s, 3)}
+
+
+def run_cfg1(args):
+    """4x4, depth 1+16+1, 256 seeded bit-strings per call (all of them in one call), complex64,
+    no cuts: the latency-bound configuration, eager and replayed from a HIP graph."""
+    import torch
+
+    import rqc_inputs as R
+    from paper_1811_09599_amd import build_grid
+
+    circ = R.grid_rqc(4, 4, 16, 1001)
+    # two sets of 256 bit-strings, alternated: a call never repeats the previous call's
+    # bit-strings, so every call contracts (nothing is kept from the call before)
+    sets = [R.bitstrings(16, 256, 1500), R.bitstrings(16, 256, 1501)]
+    res = {"workload": "4x4 RQC depth 1+16+1, 256 amplitudes per call (no cuts), complex64",
+           "metric": "amplitudes/s", "unit": "amplitudes/s"}
+    reps = max(50, 10 * args.steps)
+    for mode in ("eager", "graph"):
+        g = build_grid(circ, graph=(mode == "graph"))
+        out = torch.empty((256, 1), dtype=torch.complex128, device="cuda")
+        for i in range(3):
+            g.contract_amplitudes(sets[i % 2], out=out)
+        torch.cuda.synchronize()
+        flops = 0.0
+        t0 = time.perf_counter()
+        for i in range(reps):
+            g.contract_amplitudes(sets[i % 2], out=out)
+            flops += g.last_stats()["flops"]
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        res[mode] = {"value": 256.0 * reps / dt, "ms_per_call": 1e3 * dt / reps,
+                     "calls": reps, "flops_per_call": flops / reps}
+        g.close()
+    res["value"] = max(res["eager"]["value"], res["graph"]["value"])
+    return res
+
+
+def cpu_info():
+    """Host CPU model, physical cores (distinct (package, core) pairs) and logical CPUs."""
+    model, pairs, logical, phys, core = "unknown", set(), 0, None, None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                k, _, v = line.partition(":")
+                k, v = k.strip(), v.strip()
+                if k == "processor":
+                    logical += 1
+                elif k == "model name":
+                    model = v
+                elif k == "physical id":
+                    phys = v
+                elif k == "core id":
+                    core = v
+                    pairs.add((phys, core))
+    except OSError:
+        pass
+    return {"cpu_model": model, "physical_cores": len(pairs) or None, "logical_cpus": logical,
+            "affinity_cpus": len(os.sched_getaffinity(0))}
+
+
+def cpu_baseline(circ_h, open_q, step_flops_fresh, k, budget_s):
+    """The FP64 oracle (E2, torch complex128 on the host cores) on a bounded sample: single
+    slices of one 64-amplitude batch of the 7x7 depth 1+32+1 circuit (bond dimension 16; the
+    oracle cannot hold a bond-32 slice's 2^30-element tensors in complex128 within the time
+    budget), as many as fit the budget.  Its rate under the plan's flop count (a slice
+    contracted from scratch, as the oracle does) is applied to the headline's slice, giving the
+    oracle's amplitudes/s at f = 1/64 (an extrapolation, stated as such).  The same slices are
+    contracted on the GPU in complex64 and compared with the oracle (parity at full 7x7 size)."""
+    import numpy as np
+    import torch
+
+    import rqc_inputs as R
+    from oracle import metrics
+    from oracle import tn as E2
+    from paper_1811_09599_amd import build_grid, plan_describe
+
+    circ = R.grid_rqc(ROWS, COLS, 32, 2000)
+    bits = R.bitstrings(ROWS * COLS, 1, 2500, open_q)
+    plan = plan_describe(circ, open_qubits=open_q)
+    slice_flops = float(sum(s["flops"] for s in plan["steps"]))
+    grid = build_grid(circ, open_qubits=open_q)
+    cuts = grid.plan_cuts()
+    S = grid.num_slices()
+    net = E2.Network(circ)
+    order = E2.quadrant_order(ROWS, COLS)
+    cand = [37, 200, 113, 250, 5, 166, 81, 222]
+    done, times, par = [], [], []
+    t_all = time.perf_counter()
+    with torch.no_grad():
+        for sid in cand:
+            t0 = time.perf_counter()
+            ref = net.amplitudes(bits, open_q, cuts=cuts, slice_ids=[sid], order=order).numpy()
+            times.append(time.perf_counter() - t0)
+            done.append(sid)
+            gpu = grid.contract_amplitudes(bits, slice_ids=[sid]).cpu().numpy()
+            par.append(metrics.amp_errors(gpu, ref, ROWS * COLS))
+            if time.perf_counter() - t_all > budget_s and len(done) >= 2:
+                break
+    grid.close()
+    t_slice = float(np.mean(times))
+    gflops = slice_flops / t_slice / 1e9
+    # the oracle contracts every slice from scratch: one fidelity-f batch = k such slices
+    t_batch = k * step_flops_fresh / (gflops * 1e9)
+    info = cpu_info()
+    return {"value": 64.0 / t_batch, "unit": "amplitudes/s", "cores": torch.get_num_threads(),
+            "kind": "oracle",
+            "sample": "%d single slices (ids %s of %d) of one 64-amplitude batch of the 7x7 "
+                      "depth 1+32+1 circuit (bond dim 16), FP64 tensor network, %.1f s in all, "
+                      "%.2f s per slice = %.1f GFLOP/s under the plan's count (%.3g flop per "
+                      "slice from scratch); extrapolated to the headline's slice (%.3g flop from "
+                      "scratch) x %d slices per fidelity-1/64 batch" %
+                      (len(done), done, S, float(np.sum(times)), t_slice, gflops, slice_flops,
+                       step_flops_fresh, k),
+            "oracle_gflops": round(gflops, 2), **info,
+            "parity_c64_vs_oracle_d16": {
+                "slices": done, "max_rel_err": max(p["max"] for p in par),
+                "median_rel_err": float(np.median([p["median"] for p in par])),
+                "l2_rel_err": max(p["l2"] for p in par), "tol": C64_TOL}}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--precision", default="all",
+                    choices=["all", "c64", "split_bf16", "split_fp16"])
+    ap.add_argument("--cpu-budget", type=float, default=15.0,
+                    help="seconds of oracle work in the CPU baseline (at least 2 slices)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cfg1", action="store_true", help="skip the 4x4 workload")
+    ap.add_argument("--autotune", action="store_true",
+                    help="let the library time kernel variants per step on first use (default: "
+                         "its shape rules)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="shape rules in the opt-in workloads too")
+    ap.add_argument("--extra", default="",
+                    help="comma-separated opt-in workloads: " + ",".join(EXTRAS) + " or all")
+    ap.add_argument("--bitstrings", type=int, default=8,
+                    help="bit-strings per step of the opt-in cfg2/fsim workloads")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="first copy 1 GiB device to device (calibrates HBM byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(--gpus %d requested; see the sharding design)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    if args.steps < 1 or args.warmup < 0:
+        print("--steps must be >= 1 and --warmup >= 0", file=sys.stderr)
+        sys.exit(2)
+    extras = set(EXTRAS) if args.extra == "all" else {e for e in args.extra.split(",") if e}
+    if extras - set(EXTRAS):
+        print("unknown --extra workloads: %s" % sorted(extras - set(EXTRAS)), file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1811_09599_amd import plan_describe, select_slices
+
+    torch.cuda.set_device(0)
+    if args.copy_probe:
+        # a plain copy of known size: reads 1 GiB and writes 1 GiB; under rocprofv3 --pmc its
+        # FETCH_SIZE / WRITE_SIZE give the scale of those counters on this device
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    ceil = ceilings() if "ceilings" in extras else None
+    circ, open_q, bits = headline_inputs()
+    plan = plan_describe(circ, open_qubits=open_q)
+    S = plan["num_slices"]
+    ids = select_slices(S, FIDELITY, 3700, "block")
+    k = len(ids)
+    step_fresh = float(sum(s["flops"] for s in plan["steps"]))
+    precs = ["c64", "split_bf16", "split_fp16"] if args.precision == "all" else [args.precision]
+    results, outs = {}, {}
+    for p in precs:
+        outs[p], results[p] = run_headline(p, circ, open_q, bits, ids, args)
+        outs[p] = outs[p].cpu().numpy()
+    head = precs[0]
+    r = results[head]
+    res = {
+        "metric": "amplitudes/s", "value": r["value"], "unit": "amplitudes/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": DTYPE[head], "data": "synthetic",
+        "config": {"workload": "7x7 RQC depth 1+40+1 (bond dim 32), quadrant plan with 2 cuts "
+                               "(%d slices, largest intermediate 2^%d), fidelity 1/64 = %d "
+                               "slices (block subset %d..%d), 6-qubit open batch (64 "
+                               "amplitudes per bit-string); one step = one slice of one "
+                               "bit-string's batch (accumulating call, intermediates kept "
+                               "across calls), value = amplitudes/s at fidelity 1/64"
+                               % (S, plan["max_bits"], k, ids[0], ids[-1]),
+                   "grid": "7x7", "depth": "1+40+1", "bond_dim": 32, "slices": S,
+                   "fidelity": FIDELITY, "slice_ids": [int(i) for i in ids],
+                   "amplitudes_per_bitstring": 64, "bitstrings_touched": int(outs[head].shape[0]),
+                   "flops_per_slice_from_scratch": step_fresh, "precision": head},
+        "tflops": r["tflops"], "dominant_kernel": r["dominant_kernel"],
+        "roofline": r["roofline"], "kernels": r["kernels"],
+        "precisions": {p: {kk: v for kk, v in results[p].items() if kk != "kernels"}
+                       for p in precs},
+    }
+    if head == "c64":
+        res["tflops_frac_fp32_mfma_peak"] = r["tflops"] / PEAK["mfma_fp32"][0]
+    for p in precs:
+        if p != "c64" and "c64" in results:
+            res["precisions"][p]["speedup_vs_c64"] = results[p]["value"] / results["c64"]["value"]
+            e = scaled_errors(outs[p], outs["c64"])
+            tol = TOL["split_bf16_d32"] if p == "split_bf16" else TOL[p]
+            res["precisions"][p]["vs_c64"] = {"max_rel_err": e["max"],
+                                              "median_rel_err": e["median"], "tol": tol,
+                                              "amplitudes": int(outs[p].size)}
+    if not args.no_cfg1:
+        res["cfg1_4x4"] = run_cfg1(args)
+    # the opt-in workloads take a few steps each, whatever the headline's count
+    xargs = argparse.Namespace(**vars(args))
+    xargs.steps, xargs.warmup = min(args.steps, 3), min(args.warmup, 1)
+    args = xargs
+    if "cfg2" in extras:
+        res["cfg2_7x7_d16"] = run_cfg2(args, "split_bf16")
+    if "fsim" in extras:
+        res["fsim_7x7"] = run_fsim(args, "split_bf16")
+    if "sampling" in extras:
+        res["sampling"] = run_sampling_leg(args)
+    grad_check = None
+    if "gradient" in extras:
+        res["gradient"], grad_check = run_gradient(args)
+    if "diamond" in extras:
+        res["diamond"] = run_diamond(args)
+    if ceil:
+        res["ceilings"] = ceil
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(circ, open_q, step_fresh, k, args.cpu_budget)
+        if grad_check is not None:
+            res["gradient"]["parity"] = gradient_parity(*grad_check)
+    print(json.dumps(res), flush=True)
+
+
+def run_cfg2(args, precision):
+    """7x7 depth 1+32+1 (bond dim 16), all 256 slices, --bitstrings per step."""
+    import rqc_inputs as R
+    circ = R.grid_rqc(ROWS, COLS, 32, 2000)
+    open_q = R.grid_ids((ROWS, COLS), OPEN_PATCH)
+    all_bits = R.bitstrings(ROWS * COLS, 1024, 2500, open_q)
+    g, r = run_precision(precision, circ, open_q, all_bits, args)
+    g.close()
+    return {"workload": "7x7 RQC depth 1+32+1 (bond dim 16), all 256 slices, %d bit-strings "
+                        "per step, %s" % (args.bitstrings, precision),
+            "metric": "amplitudes/s", "unit": "amplitudes/s",
+            **{kk: r[kk] for kk in ("value", "ms_per_step", "tflops", "dominant_kernel",
+                                    "roofline")}}
+
+
+def run_fsim(args, precision):
+    """fSim couplers at half the depth: the same bond dimensions, plan and flops (1+t/2+1)."""
+    import rqc_inputs as R
+    circ_f = R.grid_rqc(ROWS, COLS, 16, 2002, two_qubit="fsim", jitter_sd=0.02, jitter_seed=3)
+    open_q = R.grid_ids((ROWS, COLS), OPEN_PATCH)
+    all_bits = R.bitstrings(ROWS * COLS, 1024, 2500, open_q)
+    g, r = run_precision(precision, circ_f, open_q, all_bits, args)
+    g.close()
+    return {"workload": "7x7 RQC with fSim(pi/2 + N(0, 0.02), pi/6 + N(0, 0.02)) couplers, "
+                        "depth 1+16+1 (bond dim 16), all 256 slices, %s" % precision,
+            "metric": "amplitudes/s", "unit": "amplitudes/s",
+            **{kk: r[kk] for kk in ("value", "ms_per_step", "tflops", "dominant_kernel",
+                                    "roofline")}}
+
+
+def run_sampling_leg(args):
+    import rqc_inputs as R
+    from paper_1811_09599_amd import build_grid
+    circ = R.grid_rqc(ROWS, COLS, 32, 2000)
+    open_q = R.grid_ids((ROWS, COLS), OPEN_PATCH)
+    bits = R.bitstrings(ROWS * COLS, 4, 2500, open_q)
+    g = build_grid(circ, open_qubits=open_q, precision="split_bf16")
+    a = g.contract_amplitudes(bits)
+    g.close()
+    return run_sampling(a, None)
 
 
 def ceilings():
@@ -130,7 +513,7 @@ def ceilings():
                                        F.PREC["split_bf16"], C.c_void_p(ws.data_ptr()), nws,
                                        strm))
 
-    flops = 24.0 * m ** 3 * b  # 3 real products per complex product on 16-bit MFMA
+    flops = 8.0 * m ** 3 * b  # algorithmic: 8 per complex multiply-add
     out["split_bf16_4096cube_x4_random_tflops"] = round(flops / timed(split_product, 5) / 1e12, 1)
     a.fill_(complex(0.75, -0.5))
     bb.fill_(complex(0.25, 0.5))
@@ -142,6 +525,7 @@ def ceilings():
                    "operands, timed in this run: practical ceilings of this device next to the "
                    "published peaks (the product's MFMA rate depends on the data's power draw)")
     return out
+
 
 
 def run_precision(precision, circ, open_q, all_bits, args):
@@ -186,111 +570,6 @@ def run_precision(precision, circ, open_q, all_bits, args):
                   "tflops": flops / dt / 1e12, "dominant_kernel": dom, "roofline": roof,
                   "kernels": kernels, "grid_build_s": build_s}
 
-
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--bitstrings", type=int, default=8, help="bit-strings per step")
-    ap.add_argument("--precision", default="all",
-                    choices=["all", "c64", "split_bf16", "split_fp16"])
-    ap.add_argument("--cpu-slices", type=int, default=3, help="oracle sample size (slices)")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-gradient", action="store_true", help="skip the gradient workload")
-    ap.add_argument("--no-diamond", action="store_true", help="skip the diamond workload")
-    ap.add_argument("--no-sampling", action="store_true", help="skip the sampler workload")
-    ap.add_argument("--no-fsim", action="store_true", help="skip the 7x7 fSim workload")
-    ap.add_argument("--no-autotune", action="store_true",
-                    help="kernel choice by shape rules only (default: the library's autotuner "
-                         "times the variants of every step during the warm-up call)")
-    ap.add_argument("--no-ceilings", action="store_true",
-                    help="skip timing the vendor GEMM and a device copy for context")
-    ap.add_argument("--copy-probe", action="store_true",
-                    help="first copy 1 GiB device to device (calibrates HBM byte counters)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
-        sys.exit(2)
-
-    import torch
-
-    import rqc_inputs as R
-    from paper_1811_09599_amd import plan_describe
-
-    torch.cuda.set_device(0)
-    if args.copy_probe:
-        # a plain copy of known size: reads 1 GiB and writes 1 GiB; under rocprofv3 --pmc its
-        # FETCH_SIZE / WRITE_SIZE give the scale of those counters on this device
-        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
-    # measured first, on a device that has not been running the workloads yet
-    ceil = None if args.no_ceilings else ceilings()
-    rows = cols = 7
-    circ = R.grid_rqc(rows, cols, 32, 2000)
-    open_q = R.grid_ids((rows, cols), [(5, 0), (5, 1), (5, 2), (6, 0), (6, 1), (6, 2)])
-    all_bits = R.bitstrings(rows * cols, 1024, 2500, open_q)
-    plan = plan_describe(circ, open_qubits=open_q)
-    precs = ["split_bf16", "split_fp16", "c64"] if args.precision == "all" else [args.precision]
-    results, grids = {}, {}
-    for p in precs:
-        grids[p], results[p] = run_precision(p, circ, open_q, all_bits, args)
-    head = precs[0]
-    r = results[head]
-    res = {
-        "metric": "amplitudes/s", "value": r["value"], "unit": "amplitudes/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["ms_per_step"],
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": DTYPE[head], "data": "synthetic",
-        "config": {"workload": "7x7 RQC depth 1+32+1 (bond dim 16), quadrant plan with 2 cuts "
-                               "(256 slices, fidelity 1), 6-qubit open batch (64 amplitudes "
-                               "per bit-string), %d bit-strings per step" % args.bitstrings,
-                   "grid": "7x7", "depth": "1+32+1", "slices": plan["num_slices"],
-                   "fidelity": 1.0, "amplitudes_per_bitstring": 64,
-                   "bitstrings_per_step": args.bitstrings,
-                   "plan_flops_per_bitstring": plan["flops_all_slices"], "precision": head},
-        "tflops": r["tflops"], "tflops_frac_fp32_mfma_peak": r["tflops"] / PEAK["mfma_fp32"][0],
-        "dominant_kernel": r["dominant_kernel"], "roofline": r["roofline"],
-        "kernels": r["kernels"], "grid_build_s": r["grid_build_s"],
-        "precisions": {p: {k: v for k, v in results[p].items() if k != "kernels"}
-                       for p in precs},
-    }
-    for p in precs:
-        if p != "c64" and "c64" in results:
-            res["speedup_%s_vs_c64" % p] = results[p]["value"] / results["c64"]["value"]
-    if not args.no_fsim:
-        # fSim couplers at half the depth: the same bond dimensions, plan and flops (1+t/2+1)
-        circ_f = R.grid_rqc(rows, cols, 16, 2002, two_qubit="fsim", jitter_sd=0.02,
-                            jitter_seed=3)
-        g_f, r_f = run_precision(head, circ_f, open_q, all_bits, args)
-        g_f.close()
-        res["fsim_7x7"] = {
-            "workload": "7x7 RQC with fSim(pi/2 + N(0, 0.02), pi/6 + N(0, 0.02)) couplers, depth "
-                        "1+16+1 (bond dim 16, the CZ 1+32+1 plan), %s, other settings as the "
-                        "headline" % head,
-            "metric": "amplitudes/s", "unit": "amplitudes/s",
-            **{k: r_f[k] for k in ("value", "ms_per_step", "tflops", "dominant_kernel",
-                                   "roofline")}}
-    if not args.no_sampling:
-        res["sampling"] = run_sampling(grids[head].contract_amplitudes(all_bits[:4]),
-                                       r["value"])
-    grad_check = None
-    if not args.no_gradient:
-        res["gradient"], grad_check = run_gradient(args)
-    if not args.no_diamond:
-        res["diamond"] = run_diamond(args)
-    if ceil:
-        res["ceilings"] = ceil
-    if not args.no_cpu_baseline:
-        res.update(cpu_baseline(circ, grids, all_bits[:1], open_q, args.cpu_slices, rows, cols))
-        if grad_check is not None:
-            res["gradient"]["parity"] = gradient_parity(*grad_check)
-    print(json.dumps(res), flush=True)
 
 
 def run_diamond(args):
@@ -346,17 +625,6 @@ def run_diamond(args):
             "split_bf16_vs_c64": {"max_rel_err": err["max"], "median_rel_err": err["median"]}}
 
 
-def scaled_errors(a, ref):
-    """|a - ref| / max(|ref|, rms(ref)) per amplitude (the rms floor keeps tiny amplitudes of
-    the Porter-Thomas tail from dominating): max and median."""
-    import numpy as np
-
-    a, ref = np.ravel(a), np.ravel(ref)
-    rms = float(np.sqrt(np.mean(np.abs(ref) ** 2)))
-    e = np.abs(a - ref) / np.maximum(np.abs(ref), rms)
-    return {"max": float(e.max()), "median": float(np.median(e))}
-
-
 def run_sampling(amps7, amp_rate):
     """Fast frugal rejection sampling (one bit-string per 64-amplitude open batch, M = 10):
     the sampler's kernels on 2^20 synthetic Porter-Thomas batches of the 7x7 open batch (about
@@ -409,7 +677,8 @@ def run_sampling(amps7, amp_rate):
             "on_7x7_amplitudes": {"batches": int(amps7.shape[0]),
                                   "accepted": int((acc7 >= 0).sum().item()),
                                   "tail_error": tail7,
-                                  "samples_per_s_at_headline_rate": amp_rate / blen * paper_acc}}
+                                  "samples_per_s_at_headline_rate":
+                                      None if amp_rate is None else amp_rate / blen * paper_acc}}
 
 
 def grid_cuts(circ):
@@ -465,41 +734,6 @@ def run_gradient(args):
             "qubits_histogram": {str(n): int(k) for n, k in enumerate(sizes) if k},
             "tflops": flops / dt / 1e12, "dominant_kernel": dom, "roofline": roof,
             "kernels": kernels, "grid_build_s": build_s}, check
-
-
-def cpu_baseline(circ, grids, bits, open_q, n_slices, rows, cols):
-    """The FP64 oracle (E2) on a bounded sample: n_slices slices of one bit-string batch,
-    extrapolated to all slices; plus each precision's error against it on the same slices."""
-    import numpy as np
-    import torch
-
-    from oracle import metrics
-    from oracle import tn as E2
-
-    grid = next(iter(grids.values()))
-    S = grid.num_slices()
-    ids = sorted(set(int(round(x)) for x in np.linspace(0, S - 1, n_slices)))
-    cuts = grid.plan_cuts()
-    net = E2.Network(circ)
-    t0 = time.perf_counter()
-    with torch.no_grad():
-        ref = net.amplitudes(bits, open_q, cuts=cuts, slice_ids=ids,
-                             order=E2.quadrant_order(rows, cols)).numpy()
-    dt = time.perf_counter() - t0
-    parity = {"slices": ids, "amplitudes": int(ref.size)}
-    for p, g in grids.items():
-        gpu = g.contract_amplitudes(bits, slice_ids=ids).cpu().numpy()
-        err = metrics.amp_errors(gpu, ref, rows * cols)
-        parity[p] = {"max_rel_err": err["max"], "median_rel_err": err["median"],
-                     "l2_rel_err": err["l2"], "tol": TOL[p]}
-    per_slice = dt / len(ids)
-    rate = 64.0 / (per_slice * S)
-    return {"cpu_baseline": {"value": rate, "unit": "amplitudes/s",
-                             "cores": torch.get_num_threads(), "kind": "oracle",
-                             "sample": "%d of %d slices of one 64-amplitude batch (FP64 tensor "
-                                       "network, no reuse across slices), %.1f s; rate "
-                                       "extrapolated to all %d slices" % (len(ids), S, dt, S)},
-            "parity": parity}
 
 
 def gradient_parity(i, circ, bits, grad, loss):

@@ -132,6 +132,14 @@ typedef struct {
 
 typedef enum { QFLEX_SLICES_RANDOM = 0, QFLEX_SLICES_BLOCK = 1 } qflex_slice_mode;
 
+/* Flags of qflex_contract_amplitudes' amps_on_device argument: 0 = host output, 1 = device
+ * output, 1|2 = device output that the call adds its slice sums to instead of overwriting. */
+typedef enum {
+  QFLEX_OUT_HOST = 0,
+  QFLEX_OUT_DEVICE = 1,
+  QFLEX_OUT_ACCUMULATE = 2
+} qflex_out_flags;
+
 typedef struct qflex_grid qflex_grid;
 
 /* Statistics of the most recent contract call on a grid (algorithmic counts). */
@@ -144,9 +152,11 @@ typedef struct {
   int64_t n_bitstrings;  /* bit-strings contracted, over all circuits */
 } qflex_stats;
 
-/* Validate circuits, plan their contractions, collapse every qubit's gates along time on the
- * GPU and keep the per-qubit tensors in device memory.  stream: a hipStream_t (NULL = the
- * null stream).  Returns QFLEX_E_INVALID for: n_circuits < 1, a NULL pointer, coordinates
+/* Validate circuits (Methods A: gates of a cycle act on disjoint qubits, two-qubit gates on
+ * nearest neighbours), plan their contractions (Methods B.1: cuts and pairwise order), collapse
+ * every qubit's gates along time on the GPU (Methods B.1: the time direction is contracted
+ * first; bond dimension = the Schmidt rank of each gate) and keep the per-qubit tensors in
+ * device memory.  stream: a hipStream_t (NULL = the null stream).  Returns QFLEX_E_INVALID for: n_circuits < 1, a NULL pointer, coordinates
  * repeated, a qubit id out of range, a gate between qubits not at unit distance, a qubit used
  * twice in one cycle, an unknown kind, a missing matrix, n_open > 16 or an open id out of
  * range.  QFLEX_E_PLAN when no plan fits max_tensor_elems. */
@@ -171,7 +181,10 @@ qflex_status qflex_plan_cuts(const qflex_grid* g, int32_t circuit, int32_t* pair
 qflex_status qflex_plan_describe(const qflex_circuit* circuit, const qflex_options* opt,
                                  char* buf, int64_t len, int64_t* needed);
 
-/* Contract amplitudes.
+/* Contract amplitudes: psi(x) summed over the selected paths (Methods B.1, cutting indexes:
+ * the amplitude is the sum of the contributions of every value of the cut bonds; Methods C.1:
+ * a fraction f of those paths gives a fidelity-f amplitude, Eq. 1; Methods C.2 and SI A: open
+ * qubits give a batch of amplitudes per contraction).
  *   bits        uint8 rows, concatenated per circuit: circuit c contributes
  *               bs_offsets[c+1]-bs_offsets[c] rows of n_qubits(c) bytes each (host memory).
  *   bs_offsets  [n_circuits+1] prefix offsets of bit-string rows (host memory).
@@ -182,7 +195,19 @@ qflex_status qflex_plan_describe(const qflex_circuit* circuit, const qflex_optio
  *   slice_ids, slice_offsets  optional explicit slice lists per circuit (host memory,
  *               concatenated; slice_offsets has n_circuits+1 entries), else NULL.
  *   amps        complex128 [total bit-strings][2^n_open] (device if amps_on_device).
- * The sum over slices is accumulated in FP64. */
+ *   amps_on_device  qflex_out_flags: QFLEX_OUT_HOST, QFLEX_OUT_DEVICE, or
+ *               QFLEX_OUT_DEVICE | QFLEX_OUT_ACCUMULATE to add this call's sums to amps
+ *               (device) instead of overwriting them; any other value is QFLEX_E_INVALID.
+ * The sum over slices is accumulated in FP64.
+ * Reuse across calls: intermediates that depend on no cut, or only on cuts whose value is the
+ * same, are computed once per bit-string batch and reused by the later slices of a call (SI A).
+ * They stay in the grid's device memory after the call: when the next call's first batch
+ * contracts the same circuit with the same bit-strings (same batch size), its first slice
+ * reuses them as a later slice of the previous call would.  So the slices of one amplitude
+ * batch may be spread over several accumulating calls at the cost of one call over all of
+ * them (in ascending slice order; with QFLEX_SLICES_BLOCK subsets the per-right-cut
+ * intermediates are then computed once).  Results do not depend on it.  Graph mode keeps
+ * nothing across calls. */
 qflex_status qflex_contract_amplitudes(qflex_grid* g, const uint8_t* bits,
                                        const int64_t* bs_offsets, double fidelity,
                                        uint64_t slice_seed, const int64_t* slice_ids,

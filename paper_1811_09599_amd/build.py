@@ -50,9 +50,9 @@ def build(verbose: bool = False) -> str:
     for s in HIP_SOURCES:
         jobs.append([cc] + COMMON + DEVICE + ["-c", os.path.join(CSRC, s), "-o",
                                               os.path.join(OUT_DIR, s + ".o")])
-    for s in HOST_SOURCES:
-        jobs.append([cc] + COMMON + ["-c", os.path.join(CSRC, s), "-o",
-                                     os.path.join(OUT_DIR, s + ".o")])
+    for s in HOST_SOURCES:  # host code only; the target keeps hipcc off its default arch
+        jobs.append([cc] + COMMON + ["--offload-arch=" + ARCH, "-c", os.path.join(CSRC, s),
+                                     "-o", os.path.join(OUT_DIR, s + ".o")])
     with cf.ThreadPoolExecutor(max_workers=min(8, len(jobs))) as ex:
         outs = list(ex.map(_run, jobs))
     if verbose:

@@ -5,6 +5,7 @@
 #include <string>
 
 #include "../../include/qflex_kernels.h"
+#include "api_internal.h"
 #include "grid.h"
 
 namespace {
@@ -73,6 +74,87 @@ void check_options(const qflex_options& o) {
 }
 
 }  // namespace
+
+namespace qflex {
+
+qflex_status run_guarded(const std::function<void()>& f) { return guarded(f); }
+
+// Every check of the split product's arguments except the workspace's.
+void gemm_split_c64_check(const void* A, const void* B, const void* C, int64_t M, int64_t N,
+                          int64_t K, int32_t ta, int32_t tb, int64_t batch, int32_t precision) {
+  if (!A || !B || !C) fail(QFLEX_E_INVALID, "NULL argument");
+  if (precision != QFLEX_PREC_SPLIT_BF16 && precision != QFLEX_PREC_SPLIT_FP16)
+    fail(QFLEX_E_INVALID, "precision must be QFLEX_PREC_SPLIT_BF16 or QFLEX_PREC_SPLIT_FP16");
+  if ((reinterpret_cast<uintptr_t>(A) | reinterpret_cast<uintptr_t>(B)) & 15)
+    fail(QFLEX_E_INVALID, "A and B must be 16-byte aligned");
+  const int mb = log2_exact(M), nb = log2_exact(N), kb = log2_exact(K);
+  if (mb < 0 || nb < 0 || kb < 0) fail(QFLEX_E_INVALID, "M, N, K must be powers of two");
+  if (!dev::gemm_split_ok(M, N, K) || mb + kb > 40 || nb + kb > 40)
+    fail(QFLEX_E_INVALID, "shape too small or too large for the split product");
+  if (batch < 1 || batch > 65535) fail(QFLEX_E_INVALID, "batch must be in [1, 65535]");
+  if ((ta != 0 && ta != 1) || (tb != 0 && tb != 1)) fail(QFLEX_E_INVALID, "ta/tb must be 0 or 1");
+}
+
+// The split product on a workspace of the caller's (checked, then enqueued on st).
+void gemm_split_c64_run(const void* A, const void* B, void* C, int64_t M, int64_t N, int64_t K,
+                        int32_t ta, int32_t tb, int64_t batch, int32_t precision,
+                        void* workspace, int64_t workspace_bytes, hipStream_t st) {
+  gemm_split_c64_check(A, B, C, M, N, K, ta, tb, batch, precision);
+  if (!workspace) fail(QFLEX_E_INVALID, "NULL argument");
+  if (workspace_bytes < qflex_gemm_split_workspace(M, N, K, batch))
+    fail(QFLEX_E_INVALID, "workspace too small");
+  if (reinterpret_cast<uintptr_t>(workspace) & 15)
+    fail(QFLEX_E_INVALID, "workspace must be 16-byte aligned");
+  const int mb = log2_exact(M), nb = log2_exact(N), kb = log2_exact(K);
+  // bit permutation transposing [R][C] (rb, cb bits) into [C][R]
+  auto transpose = [](int rb, int cb) {
+    std::vector<int> p(rb + cb);
+    for (int j = 0; j < rb + cb; ++j) p[j] = j < rb ? cb + j : j - rb;
+    return p;
+  };
+  std::vector<int> pa(mb + kb), pbv(nb + kb);
+  for (int j = 0; j < mb + kb; ++j) pa[j] = j;
+  for (int j = 0; j < nb + kb; ++j) pbv[j] = j;
+  if (ta) pa = transpose(kb, mb);   // stored [K][M] -> [M][K]
+  if (!tb) pbv = transpose(kb, nb); // stored [K][N] -> [N][K]
+  auto* slots = static_cast<uint64_t*>(workspace);
+  auto* sa = reinterpret_cast<uint16_t*>(static_cast<char*>(workspace) + kSplitSlotBytes);
+  auto* sb = sa + 4 * batch * M * K;
+  const bool f16 = precision == QFLEX_PREC_SPLIT_FP16;
+  if (f16) {  // the workspace holds anything: clear the slots (a fill kernel), then tag 1
+    dev::fill_zero(reinterpret_cast<double*>(slots), 2, st);
+    dev::absmax(static_cast<const float2*>(A), batch * M * K, slots, 1, st);
+    dev::absmax(static_cast<const float2*>(B), batch * N * K, slots + 1, 1, st);
+  }
+  // A stored [M][K] is read by the product itself (identity gather), else permuted and split
+  if (ta)
+    dev::split_permute(static_cast<const float2*>(A), sa, batch,
+                       dev::make_perm_tile(mb + kb, pa.data()), kb, f16 ? slots : nullptr, st);
+  dev::split_permute(static_cast<const float2*>(B), sb, batch,
+                     dev::make_perm_tile(nb + kb, pbv.data()), kb, f16 ? slots + 1 : nullptr, st);
+  dev::GemmSplit g;
+  if (f16) g.a_amax = slots, g.b_amax = slots + 1;
+  if (!ta) {
+    g.Ac = static_cast<const float2*>(A);
+    g.ga.nm = mb;
+    g.ga.nk = kb - 2;
+    for (int i = 0; i < mb; ++i) g.ga.mpos[i] = (int8_t)(kb + i);
+    for (int j = 0; j < kb - 2; ++j) g.ga.kpos[j] = (int8_t)(2 + j);
+  }
+  g.A = sa;
+  g.B = sb;
+  g.C = static_cast<float2*>(C);
+  g.M = M;
+  g.N = N;
+  g.K = K;
+  g.a_bs = M * K;
+  g.b_bs = N * K;
+  g.c_bs = M * N;
+  g.batch = (int)batch;
+  dev::gemm_split(g, st);
+}
+
+}  // namespace qflex
 
 extern "C" {
 
@@ -156,7 +238,7 @@ qflex_status qflex_contract_amplitudes(qflex_grid* g, const uint8_t* bits,
   return guarded([&] {
     if (!g) qflex::fail(QFLEX_E_INVALID, "NULL grid");
     qflex::contract(g, bits, bs_offsets, fidelity, slice_seed, slice_ids, slice_offsets, amps,
-                    amps_on_device != 0, static_cast<hipStream_t>(stream));
+                    amps_on_device, static_cast<hipStream_t>(stream));
   });
 }
 
@@ -274,88 +356,19 @@ qflex_status qflex_gemm_c64(const void* A, const void* B, void* C, int64_t M, in
   });
 }
 
-// split workspace: two fp16 scale slots (padded), then the split A and B operands
-constexpr int64_t kSplitSlotBytes = 256;
-
 int64_t qflex_gemm_split_workspace(int64_t M, int64_t N, int64_t K, int64_t batch) {
   if (M < 1 || N < 1 || K < 1 || batch < 1) return 0;
-  return kSplitSlotBytes + (int64_t)sizeof(uint16_t) * 4 * batch * (M * K + N * K);
+  return qflex::kSplitSlotBytes + (int64_t)sizeof(uint16_t) * 4 * batch * (M * K + N * K);
 }
+
 
 qflex_status qflex_gemm_split_c64(const void* A, const void* B, void* C, int64_t M, int64_t N,
                                   int64_t K, int32_t ta, int32_t tb, int64_t batch,
                                   int32_t precision, void* workspace, int64_t workspace_bytes,
                                   void* stream) {
   return guarded([&] {
-    if (!A || !B || !C || !workspace) qflex::fail(QFLEX_E_INVALID, "NULL argument");
-    if (precision != QFLEX_PREC_SPLIT_BF16 && precision != QFLEX_PREC_SPLIT_FP16)
-      qflex::fail(QFLEX_E_INVALID, "precision must be QFLEX_PREC_SPLIT_BF16 or QFLEX_PREC_SPLIT_FP16");
-    if ((reinterpret_cast<uintptr_t>(A) | reinterpret_cast<uintptr_t>(B)) & 15)
-      qflex::fail(QFLEX_E_INVALID, "A and B must be 16-byte aligned");
-    auto log2i = [](int64_t v) {
-      int b = 0;
-      while ((int64_t(1) << b) < v) ++b;
-      return ((int64_t(1) << b) == v) ? b : -1;
-    };
-    const int mb = log2i(M), nb = log2i(N), kb = log2i(K);
-    if (mb < 0 || nb < 0 || kb < 0) qflex::fail(QFLEX_E_INVALID, "M, N, K must be powers of two");
-    if (!qflex::dev::gemm_split_ok(M, N, K) || mb + kb > 40 || nb + kb > 40)
-      qflex::fail(QFLEX_E_INVALID, "shape too small or too large for the split product");
-    if (batch < 1 || batch > 65535) qflex::fail(QFLEX_E_INVALID, "batch must be in [1, 65535]");
-    if ((ta != 0 && ta != 1) || (tb != 0 && tb != 1)) qflex::fail(QFLEX_E_INVALID, "ta/tb must be 0 or 1");
-    if (workspace_bytes < qflex_gemm_split_workspace(M, N, K, batch))
-      qflex::fail(QFLEX_E_INVALID, "workspace too small");
-    if (reinterpret_cast<uintptr_t>(workspace) & 15)
-      qflex::fail(QFLEX_E_INVALID, "workspace must be 16-byte aligned");
-    // bit permutation transposing [R][C] (rb, cb bits) into [C][R]
-    auto transpose = [](int rb, int cb) {
-      std::vector<int> p(rb + cb);
-      for (int j = 0; j < rb + cb; ++j) p[j] = j < rb ? cb + j : j - rb;
-      return p;
-    };
-    std::vector<int> pa(mb + kb), pbv(nb + kb);
-    for (int j = 0; j < mb + kb; ++j) pa[j] = j;
-    for (int j = 0; j < nb + kb; ++j) pbv[j] = j;
-    if (ta) pa = transpose(kb, mb);   // stored [K][M] -> [M][K]
-    if (!tb) pbv = transpose(kb, nb); // stored [K][N] -> [N][K]
-    auto* slots = static_cast<uint64_t*>(workspace);
-    auto* sa = reinterpret_cast<uint16_t*>(static_cast<char*>(workspace) + kSplitSlotBytes);
-    auto* sb = sa + 4 * batch * M * K;
-    const hipStream_t st = static_cast<hipStream_t>(stream);
-    const bool f16 = precision == QFLEX_PREC_SPLIT_FP16;
-    if (f16) {  // the caller's workspace holds anything: clear the slots, then tag 1
-      qflex::dev::fill_zero(reinterpret_cast<double*>(slots), 2, st);
-      qflex::dev::absmax(static_cast<const float2*>(A), batch * M * K, slots, 1, st);
-      qflex::dev::absmax(static_cast<const float2*>(B), batch * N * K, slots + 1, 1, st);
-    }
-    // A stored [M][K] is read by the product itself (identity gather), else permuted and split
-    if (ta)
-      qflex::dev::split_permute(static_cast<const float2*>(A), sa, batch,
-                                qflex::dev::make_perm_tile(mb + kb, pa.data()), kb,
-                                f16 ? slots : nullptr, st);
-    qflex::dev::split_permute(static_cast<const float2*>(B), sb, batch,
-                              qflex::dev::make_perm_tile(nb + kb, pbv.data()), kb,
-                              f16 ? slots + 1 : nullptr, st);
-    qflex::dev::GemmSplit g;
-    if (f16) g.a_amax = slots, g.b_amax = slots + 1;
-    if (!ta) {
-      g.Ac = static_cast<const float2*>(A);
-      g.ga.nm = mb;
-      g.ga.nk = kb - 2;
-      for (int i = 0; i < mb; ++i) g.ga.mpos[i] = (int8_t)(kb + i);
-      for (int j = 0; j < kb - 2; ++j) g.ga.kpos[j] = (int8_t)(2 + j);
-    }
-    g.A = sa;
-    g.B = sb;
-    g.C = static_cast<float2*>(C);
-    g.M = M;
-    g.N = N;
-    g.K = K;
-    g.a_bs = M * K;
-    g.b_bs = N * K;
-    g.c_bs = M * N;
-    g.batch = (int)batch;
-    qflex::dev::gemm_split(g, st);
+    qflex::gemm_split_c64_run(A, B, C, M, N, K, ta, tb, batch, precision, workspace,
+                              workspace_bytes, static_cast<hipStream_t>(stream));
   });
 }
 

@@ -262,6 +262,7 @@ static uint32_t next_amax_tag(qflex_grid* g, hipStream_t s) {
         if (sl >= 0) dev::fill_zero(reinterpret_cast<double*>(g->amax + sl), 1, s);
     if (g->node_amax) dev::fill_zero(reinterpret_cast<double*>(g->node_amax), g->n_node_amax, s);
     g->amax_tag = 0;
+    g->resume.valid = false;  // their scales are gone: nothing is reused across this point
   }
   return ++g->amax_tag;
 }
@@ -560,9 +561,14 @@ std::vector<std::vector<int64_t>> prepare_call(qflex_grid* g, const uint8_t* bit
 
 void contract(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets, double fidelity,
               uint64_t seed, const int64_t* slice_ids, const int64_t* slice_offsets,
-              double* amps, bool amps_on_device, hipStream_t s_user) {
+              double* amps, int32_t out_flags, hipStream_t s_user) {
   hipStream_t s = s_user;
   const int nc = (int)g->circ.size();
+  if (out_flags != QFLEX_OUT_HOST && out_flags != QFLEX_OUT_DEVICE &&
+      out_flags != (QFLEX_OUT_DEVICE | QFLEX_OUT_ACCUMULATE))
+    fail(QFLEX_E_INVALID, "amps_on_device must be 0, 1 or 3 (accumulating needs device output)");
+  const bool amps_on_device = (out_flags & QFLEX_OUT_DEVICE) != 0;
+  const bool accumulate = (out_flags & QFLEX_OUT_ACCUMULATE) != 0;
   const std::vector<std::vector<int64_t>> sel =
       prepare_call(g, bits, bs_offsets, fidelity, seed, slice_ids, slice_offsets, amps, s);
   qflex_stats st{};
@@ -606,9 +612,17 @@ void contract(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets, dou
     cache_need = std::max(cache_need, sizeof(uint16_t) * (size_t)batch[c] *
                                           (size_t)g->circ[c].xcache_elems);
   if (cache_need) g->split_cache.reserve(cache_need);
-  g->amps64.reserve(sizeof(double2) * std::max<int64_t>(amp_total, 1));
+  // slice sums go straight into the caller's buffer when the call accumulates into it
+  if (!accumulate) g->amps64.reserve(sizeof(double2) * std::max<int64_t>(amp_total, 1));
   float2* arena = static_cast<float2*>(g->arena.p);
-  double2* acc_all = static_cast<double2*>(g->amps64.p);
+  double2* acc_all = accumulate ? reinterpret_cast<double2*>(amps)
+                                : static_cast<double2*>(g->amps64.p);
+  // intermediates of the previous call's last batch stay usable unless a buffer moved; every
+  // path below that does not finish invalidates them
+  Resume& rs = g->resume;
+  if (rs.valid && (rs.arena != g->arena.p || rs.cache != g->split_cache.p)) rs.valid = false;
+  const Resume kept = rs;
+  rs.valid = false;
   auto time_launches = [&](const std::function<void()>& launch) {
     return qflex::time_launches(g, s, launch);
   };
@@ -633,9 +647,11 @@ void contract(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets, dou
     QHIP(hipStreamWaitEvent(g->graph_stream, g->graph_in, 0));
     s = g->graph_stream;
     key.reserve(256);
-    for (const void* p : {g->arena.p, g->split_scratch.p, g->split_cache.p, g->amps64.p,
-                          g->offs.p, g->splitk_ws.p})
+    const void* keyed[] = {g->arena.p, g->split_scratch.p, g->split_cache.p, acc_all,
+                           g->offs.p, g->splitk_ws.p};
+    for (const void* p : keyed)
       key += std::to_string(reinterpret_cast<uintptr_t>(p)) + ",";
+    key += accumulate ? "+" : "=";
     for (int c = 0; c < nc; ++c) {
       key += "|" + std::to_string(bs_offsets[c + 1] - bs_offsets[c]) + ":" +
              std::to_string(batch[c]) + ":";
@@ -691,7 +707,8 @@ void contract(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets, dou
           if (sl >= 0) dev::fill_zero(reinterpret_cast<double*>(g->amax + sl), 1, s);
       if (g->node_amax) dev::fill_zero(reinterpret_cast<double*>(g->node_amax), g->n_node_amax, s);
     }
-    dev::fill_zero(reinterpret_cast<double*>(acc_all), 2 * amp_total, s);
+    if (!accumulate) dev::fill_zero(reinterpret_cast<double*>(acc_all), 2 * amp_total, s);
+    bool first_batch = true;  // only the call's first batch can find its intermediates kept
     for (int c = 0; c < nc; ++c) {
       CircuitState& cs = g->circ[c];
       const Plan& P = cs.plan;
@@ -707,6 +724,14 @@ void contract(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets, dou
       for (int64_t b0 = 0; b0 < nbs; b0 += B) {
         const int nb = (int)std::min<int64_t>(B, nbs - b0);
         std::vector<int64_t> digit(ncut, -1), prev(ncut, -1);
+        const uint8_t* batch_bits = bits + (bs_offsets[c] + b0) * cs.model.n;
+        const size_t batch_bytes = (size_t)nb * (size_t)cs.model.n;
+        // resumed: the arena still holds this batch's intermediates for the cut values in prev
+        const bool resumed = first_batch && !g->graph_mode && kept.valid && kept.circuit == c &&
+                             kept.batch == B && kept.bits.size() == batch_bytes &&
+                             std::equal(kept.bits.begin(), kept.bits.end(), batch_bits);
+        if (resumed) prev = kept.digits;
+        first_batch = false;
         auto view = [&](const Operand& o) {
           View v;
           if (o.qubit) {
@@ -731,9 +756,11 @@ void contract(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets, dou
           for (int ct = 0; ct < ncut; ++ct)
             if (digit[ct] != prev[ct]) changed |= 1u << ct;
           prev = digit;
+          // every step runs for the first slice of a batch, unless the batch was resumed
+          const bool fresh = si == 0 && !resumed;
           for (size_t k = 0; k < P.steps.size(); ++k) {
             const Step& stp = P.steps[k];
-            if (si > 0 && !(stp.deps & changed)) continue;
+            if (!fresh && !(stp.deps & changed)) continue;
             View x = view(stp.x), y = view(stp.y);
             const bool is_split = !cs.split.empty() && cs.split[k];
             const int64_t M = int64_t(1) << stp.mb, N = int64_t(1) << stp.nb;
@@ -762,7 +789,7 @@ void contract(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets, dou
               } else if (cs.xcache_offset[k] >= 0) {
                 uint16_t* xc = static_cast<uint16_t*>(g->split_cache.p) + B * cs.xcache_offset[k];
                 if (f16) gs.a_amax = xslot ? xslot : g->amax + cs.xcache_slot[k];
-                if (si == 0 || (P.nodes[stp.x.id].deps & changed)) {  // x was just recomputed
+                if (fresh || (P.nodes[stp.x.id].deps & changed)) {  // x was just recomputed
                   if (f16 && !xslot) {
                     g->prof.begin("absmax", 0, 8.0 * M * K * nb, s);
                     dev::absmax(x.base, M * K * nb, g->amax + cs.xcache_slot[k],
@@ -836,8 +863,9 @@ void contract(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets, dou
                 gs.c_amax = g->node_amax + cs.node_slot[stp.out];
                 gs.c_tag = next_amax_tag(g, s);
               }
-              // the kernel's own arithmetic: 3 16-bit products per real product, 24*M*N*K flops
-              g->prof.begin(dev::gemm_split_name(gs), 3.0 * stp.flops() * nb,
+              // algorithmic flops, 8 per complex multiply-add as for every product (the
+              // kernel's own 16-bit MFMA work is a multiple of it that depends on its form)
+              g->prof.begin(dev::gemm_split_name(gs), stp.flops() * nb,
                             8.0 * nb * (double)(M * K + N * K + M * N), s);
               dev::gemm_split(gs, s);
               g->prof.end(s);
@@ -931,6 +959,14 @@ void contract(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets, dou
                           acc + b0 * namp, namp, nb, s);
           g->prof.end(s);
         }
+        // what the arena holds once this batch is done
+        rs.valid = !slices.empty() && !g->graph_mode;
+        rs.circuit = c;
+        rs.batch = B;
+        rs.bits.assign(batch_bits, batch_bits + batch_bytes);
+        rs.digits = digit;
+        rs.arena = g->arena.p;
+        rs.cache = g->split_cache.p;
       }
       st.n_slices += (int64_t)slices.size();
       st.n_bitstrings += nbs;
@@ -943,6 +979,7 @@ void contract(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets, dou
       end_capture(true);
     }
   } catch (...) {
+    rs.valid = false;
     if (capturing) end_capture(false);
     throw;
   }
@@ -951,7 +988,7 @@ void contract(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets, dou
     QHIP(hipStreamWaitEvent(s_user, g->graph_out, 0));
     s = s_user;
   }
-  if (amp_total > 0) {
+  if (amp_total > 0 && !accumulate) {
     QHIP(hipMemcpyAsync(amps, acc_all, sizeof(double2) * amp_total,
                         amps_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
     if (!amps_on_device) QHIP(hipStreamSynchronize(s));

@@ -73,7 +73,7 @@ void contract_grad(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets
     dev::fill_zero(reinterpret_cast<double*>(amps), 2 * total_amp, s);
   } else {
     contract(g, bits, bs_offsets, fidelity, seed, slice_ids, slice_offsets,
-             reinterpret_cast<double*>(amps), true, s);
+             reinterpret_cast<double*>(amps), QFLEX_OUT_DEVICE, s);
     fwd = g->last;
   }
   // ---- cotangent of the amplitudes, kept as dL/d(conj psi)

@@ -89,6 +89,21 @@ struct HostPinned {
   void release();
 };
 
+// What the arena holds after a contract call: the circuit and bit-strings of the last batch
+// contracted, the cut values of its last slice and the buffers it used.  Intermediates reused
+// across slices live in a part of the arena of their own, so a later call whose first batch
+// has the same circuit and bit-strings (and the same buffers) keeps every intermediate that
+// depends on no cut whose value has changed, as a later slice of the same call would.
+struct Resume {
+  bool valid = false;
+  int circuit = -1;
+  int64_t batch = 0;              // bit-strings per batch the arena was laid out for
+  std::vector<uint8_t> bits;      // the batch's bit-string rows
+  std::vector<int64_t> digits;    // cut values of the last slice
+  const void* arena = nullptr;
+  const void* cache = nullptr;
+};
+
 }  // namespace qflex
 
 struct qflex_grid {
@@ -133,6 +148,7 @@ struct qflex_grid {
   hipEvent_t offs_done = nullptr;        // the last upload out of offs_host has finished
   qflex_stats last{};
   qflex::Profiler prof;
+  qflex::Resume resume;                  // intermediates kept from the last contract call
 };
 
 namespace qflex {
@@ -150,7 +166,7 @@ float time_launches(qflex_grid* g, hipStream_t s, const std::function<void()>& l
 int tune_gemm(qflex_grid* g, hipStream_t s, const dev::Gemm& gm);
 void contract(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets, double fidelity,
               uint64_t seed, const int64_t* slice_ids, const int64_t* slice_offsets,
-              double* amps, bool amps_on_device, hipStream_t s);
+              double* amps, int32_t out_flags, hipStream_t s);
 std::vector<int64_t> select_slices(int64_t total, double fidelity, uint64_t seed, int mode);
 void contract_grad(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets,
                    double fidelity, uint64_t seed, const int64_t* slice_ids,

@@ -143,10 +143,15 @@ class Grid:
                 for i in range(min(n.value, 64))}
 
     def contract_amplitudes(self, bits, fidelity: float = 1.0, seed: int = 0, slice_ids=None,
-                            device: bool = True, stream=None, out=None):
+                            device: bool = True, stream=None, out=None,
+                            accumulate: bool = False):
         """Amplitudes [total bit-strings, 2^n_open] complex128 (a torch CUDA tensor when
         ``device``, else numpy).  ``bits``: one uint8 array [m_c, n_c] per circuit (or a
-        single array for one circuit).  ``slice_ids``: optional list per circuit."""
+        single array for one circuit).  ``slice_ids``: optional list per circuit.
+        ``accumulate``: add this call's slice sums into ``out`` (a device tensor) instead of
+        overwriting it (QFLEX_OUT_ACCUMULATE)."""
+        if accumulate and (out is None or not device):
+            raise ValueError("accumulate needs a device output tensor `out`")
         L = F.lib()
         if isinstance(bits, np.ndarray) or (len(self.circuits) == 1 and not isinstance(bits, list)):
             bits = [bits]
@@ -181,7 +186,7 @@ class Grid:
         F.check(L.qflex_contract_amplitudes(
             self._h, flat.ctypes.data_as(C.POINTER(C.c_uint8)),
             offs.ctypes.data_as(C.POINTER(C.c_int64)), float(fidelity), C.c_uint64(int(seed)),
-            sid, soff, ptr, 1 if device else 0, _stream(stream)))
+            sid, soff, ptr, (3 if accumulate else 1) if device else 0, _stream(stream)))
         return res
 
 
@@ -308,6 +313,17 @@ try:
             return gp, None, None, None, None
 except ImportError:  # pragma: no cover
     pass
+
+
+def select_slices(total: int, fidelity: float, seed: int, mode: str = "random") -> list:
+    """qflex_select_slices: the ascending slice ids a contract call sums at this fidelity
+    (host only)."""
+    L = F.lib()
+    ids = (C.c_int64 * max(1, int(total)))()
+    n = C.c_int64(0)
+    F.check(L.qflex_select_slices(int(total), float(fidelity), C.c_uint64(int(seed)),
+                                  F.SLICES[mode], ids, int(total), C.byref(n)))
+    return [int(ids[i]) for i in range(n.value)]
 
 
 def build_grid(circuits, **kw) -> Grid:
