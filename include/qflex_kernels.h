@@ -60,6 +60,24 @@ qflex_status qflex_gemm_split_c64(const void* A, const void* B, void* C, int64_t
                                   void* stream);
 int64_t qflex_gemm_split_workspace(int64_t M, int64_t N, int64_t K, int64_t batch);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): qflex_gemm_split_c64 with its workspace taken from a
+ * static device buffer of the library, QFLEX_NOALLOC_SCRATCH_BYTES per GPU, held by every GPU
+ * the library is loaded on until the process ends.  Arguments, layouts, checks and results are
+ * those of qflex_gemm_split_c64 (the same kernels, bit for bit); A, B and C stay the caller's.
+ * The call allocates and frees nothing: on its first call on a device (the current one) it
+ * looks up that device's copy of the buffer, then only enqueues kernels on `stream`; the fp16
+ * scale slots are cleared by a fill kernel on every call.
+ * QFLEX_E_INVALID, nothing launched, when qflex_gemm_split_workspace(M, N, K, batch) exceeds
+ * QFLEX_NOALLOC_SCRATCH_BYTES.  Every call on one GPU shares that GPU's buffer: calls that
+ * may overlap on one GPU (different streams without ordering, or different threads) race and
+ * give wrong results; calls ordered on one stream are safe.  `stream` must belong to the
+ * current device. */
+#define QFLEX_NOALLOC_SCRATCH_BYTES (64ll << 20)
+qflex_status qflex_gemm_split_c64_noalloc(const void* A, const void* B, void* C, int64_t M,
+                                          int64_t N, int64_t K, int32_t ta, int32_t tb,
+                                          int64_t batch, int32_t precision, void* stream);
+
 /* Kernel variant qflex_gemm_c64 uses for a shape: 0 SIMT, 1 MFMA 64x64, 2 MFMA 128x128,
  * 3 tall-skinny rows kernel (M a multiple of 256 and at least 32768, N <= 32, K a multiple
  * of 16, or K = 8 with N <= 16), 4 reduction kernel (M <= 32, N >= 4 a power of two or a

@@ -47,10 +47,13 @@ EXPORTS = ("qflex_build_grid", "qflex_num_slices", "qflex_plan_cuts", "qflex_pla
            "qflex_contract_amplitudes", "qflex_contract_grad", "qflex_last_stats",
            "qflex_set_profiling",
            "qflex_profile_read", "qflex_permute_c64", "qflex_gemm_split_c64",
+           "qflex_gemm_split_c64_noalloc",
            "qflex_gemm_c64", "qflex_select_slices", "qflex_frugal_sample",
            "qflex_gemm_split_workspace", "qflex_gemm_c64_workspace", "qflex_gemm_variant",
            "qflex_grid_free", "qflex_last_error")
 # exports that do not return a qflex_status, with their return types
+# the no-allocation split product's fixed scratch size (QFLEX_NOALLOC_SCRATCH_BYTES)
+NOALLOC_SCRATCH_BYTES = 64 << 20
 NON_STATUS = {"qflex_gemm_split_workspace": C.c_int64, "qflex_gemm_c64_workspace": C.c_int64,
               "qflex_gemm_variant": C.c_int32, "qflex_grid_free": None,
               "qflex_last_error": C.c_char_p}
@@ -104,6 +107,8 @@ def lib():
     L.qflex_gemm_split_c64.argtypes = [P, P, P, C.c_int64, C.c_int64, C.c_int64, C.c_int32,
                                        C.c_int32, C.c_int64, C.c_int32, P, C.c_int64, P]
     L.qflex_gemm_split_workspace.argtypes = [C.c_int64] * 4
+    L.qflex_gemm_split_c64_noalloc.argtypes = [P, P, P, C.c_int64, C.c_int64, C.c_int64,
+                                               C.c_int32, C.c_int32, C.c_int64, C.c_int32, P]
     for name in EXPORTS:
         getattr(L, name).restype = NON_STATUS.get(name, C.c_int)
     _lib = L

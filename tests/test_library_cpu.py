@@ -292,6 +292,27 @@ def test_split_gemm_argument_checks_run_before_any_launch():
     assert call(A=C.c_void_p((1 << 20) + 8)) == F.E_INVALID  # misaligned operand
 
 
+def test_noalloc_split_product_checks_run_before_any_launch():
+    """The no-allocation split product checks its arguments as the workspace entry point does
+    and rejects a product whose split operands exceed its fixed scratch (2048^3 needs 64 MiB +
+    256 bytes), all on the host, before touching the device."""
+    L = F.lib()
+    fake = C.c_void_p(1 << 20)  # 16-byte aligned, never dereferenced
+
+    def call(M=256, N=128, K=64, batch=1, prec=F.PREC["split_bf16"], A=fake):
+        return L.qflex_gemm_split_c64_noalloc(A, fake, fake, M, N, K, 0, 0, batch, prec, None)
+
+    assert L.qflex_gemm_split_workspace(2048, 2048, 2048, 1) > F.NOALLOC_SCRATCH_BYTES
+    assert L.qflex_gemm_split_workspace(2048, 2048, 1024, 1) <= F.NOALLOC_SCRATCH_BYTES
+    assert call(M=2048, N=2048, K=2048) == F.E_INVALID
+    assert b"scratch" in L.qflex_last_error()
+    assert call(M=1024, N=1024, K=1024, batch=5) == F.E_INVALID  # 80 MiB over the batch
+    assert call(prec=F.PREC["c64"]) == F.E_INVALID
+    assert call(M=96) == F.E_INVALID
+    assert call(A=C.c_void_p((1 << 20) + 8)) == F.E_INVALID
+    assert call(batch=0) == F.E_INVALID
+
+
 def test_split_k_workspace_only_for_reduction_shapes():
     """qflex_gemm_c64_workspace is non-zero only when a product has few output tiles and a long
     K (host-only arithmetic)."""
