@@ -64,10 +64,14 @@ def flop_peak(name):
 
 
 def mfma_work_factor(name):
-    """16-bit MFMA flops the kernel issues per algorithmic flop: the split product of complex
-    parts hi+lo runs 3 real products (hi.hi, hi.lo, lo.hi) per real product of the 4M form."""
+    """MFMA flops the kernel issues per algorithmic flop (8 per complex multiply-add): the
+    split product of complex parts hi+lo runs 3 real products (hi.hi, hi.lo, lo.hi) per real
+    product of the 4-multiplication form; the 3-multiplication (Gauss) form runs 3 real
+    products per complex one instead of 4."""
     if name.startswith("gemm_split"):
         return 3.0
+    if name.startswith("gemm_mfma3m"):
+        return 0.75
     return 1.0
 
 
@@ -88,7 +92,7 @@ def roofline(prof):
     else:
         bound, achieved, peak, unit = kind, tflops, fpeak, "TFLOP/s"
     r = {"bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": unit,
-         "frac": round(achieved / peak, 4), "traffic": None,
+         "frac": round(achieved / peak, 4), "traffic": measured_traffic(name),
          "flop_frac": round(flop_frac, 4), "hbm_frac": round(hbm_frac, 4),
          "avg_launch_us": round(1e3 * k["ms"] / max(k["launches"], 1), 3),
          "launches": k["launches"],
@@ -98,6 +102,30 @@ def roofline(prof):
         r["mfma_instruction_tflops"] = round(tflops * f, 1)
         r["mfma_instruction_frac"] = round(tflops * f / fpeak, 4)
     return name, r
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` on this workload from the committed counter summaries
+    (profiles/hbm_traffic_*.md, lines "traffic <kernel> <bytes per launch> <source>
+    <sha256 of source>", from two rocprofv3 --pmc passes, FETCH_SIZE and WRITE_SIZE, scaled
+    by what the counters read for a 1 GiB device copy), or None when there is none for it or
+    its kernel source has changed since."""
+    import glob
+    import hashlib
+
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "hbm_traffic_*.md"))):
+        with open(path) as f:
+            for line in f:
+                w = line.split()
+                if len(w) == 5 and w[0] == "traffic" and w[1] == kernel:
+                    src = os.path.join(ROOT, w[3])
+                    if not os.path.exists(src):
+                        return None
+                    with open(src, "rb") as fs:
+                        if hashlib.sha256(fs.read()).hexdigest() != w[4]:
+                            return None
+                    return float(w[2])
+    return None
 
 
 def kernel_table(prof, top=8):
@@ -193,19 +221,23 @@ def run_cfg1(args):
     res = {"workload": "4x4 RQC depth 1+16+1, 256 amplitudes per call (no cuts), complex64",
            "metric": "amplitudes/s", "unit": "amplitudes/s"}
     reps = max(50, 10 * args.steps)
+    # both modes on a stream of their own: a graph is captured and replayed on the caller's
+    # stream (the null stream would put a second stream and two events around every call)
+    side = torch.cuda.Stream()
     for mode in ("eager", "graph"):
-        g = build_grid(circ, graph=(mode == "graph"))
-        out = torch.empty((256, 1), dtype=torch.complex128, device="cuda")
-        for i in range(3):
-            g.contract_amplitudes(sets[i % 2], out=out)
-        torch.cuda.synchronize()
-        flops = 0.0
-        t0 = time.perf_counter()
-        for i in range(reps):
-            g.contract_amplitudes(sets[i % 2], out=out)
-            flops += g.last_stats()["flops"]
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
+        with torch.cuda.stream(side):
+            g = build_grid(circ, graph=(mode == "graph"))
+            out = torch.empty((256, 1), dtype=torch.complex128, device="cuda")
+            for i in range(3):
+                g.contract_amplitudes(sets[i % 2], out=out)
+            side.synchronize()
+            flops = 0.0
+            t0 = time.perf_counter()
+            for i in range(reps):
+                g.contract_amplitudes(sets[i % 2], out=out)
+                flops += g.last_stats()["flops"]
+            side.synchronize()
+            dt = time.perf_counter() - t0
         res[mode] = {"value": 256.0 * reps / dt, "ms_per_call": 1e3 * dt / reps,
                      "calls": reps, "flops_per_call": flops / reps}
         g.close()
@@ -706,7 +738,6 @@ def run_gradient(args):
     for _ in range(max(args.warmup, 0)):
         grid.contract_grad(bits)
     torch.cuda.synchronize()
-    grid.set_profiling(True)
     t0 = time.perf_counter()
     flops = 0.0
     for _ in range(steps):
@@ -714,6 +745,9 @@ def run_gradient(args):
         flops += grid.last_stats()["flops"]
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    # one more call with every launch timed by events (they add their own overhead)
+    grid.set_profiling(True)
+    grid.contract_grad(bits)
     prof = grid.profile_read()
     grid.set_profiling(False)
     dom, roof = roofline(prof)
@@ -721,6 +755,24 @@ def run_gradient(args):
     kernels = {k: {"launches": v["launches"], "ms": round(v["ms"], 3),
                    "tflops": round(v["flops"] / max(v["ms"], 1e-9) / 1e9, 3),
                    "gbps": round(v["bytes"] / max(v["ms"], 1e-9) / 1e6, 1)} for k, v in top}
+    grid.close()
+    # the same calls replayed from a HIP graph (one slice per circuit: captured by the second
+    # call, after the first has tuned), on a stream of their own, and checked against eager
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        gg = build_grid(circs, autotune=not args.no_autotune, graph=True)
+        for _ in range(2):
+            gg.contract_grad(bits)
+        side.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            rg = gg.contract_grad(bits)
+        side.synchronize()
+        dt_graph = time.perf_counter() - t0
+        gg.close()
+    graph_err = max(float(np.linalg.norm(rg["grad_params"][i] - res["grad_params"][i]) /
+                          max(np.linalg.norm(res["grad_params"][i]), 1e-300))
+                    for i in range(len(circs)))
     i4 = next(i for i, c in enumerate(circs) if c["n_qubits"] == 16)
     fsim = [j for j, gt in enumerate(circs[i4]["gates"]) if gt["kind"] == "fsim"]
     check = (i4, circs[i4], bits[i4], res["grad_params"][i4][fsim], float(res["loss"][i4]))
@@ -733,7 +785,9 @@ def run_gradient(args):
             "steps": steps, "ms_per_step": 1e3 * dt / steps,
             "qubits_histogram": {str(n): int(k) for n, k in enumerate(sizes) if k},
             "tflops": flops / dt / 1e12, "dominant_kernel": dom, "roofline": roof,
-            "kernels": kernels, "grid_build_s": build_s}, check
+            "kernels": kernels, "grid_build_s": build_s,
+            "graph": {"value": len(circs) * steps / dt_graph, "ms_per_step": 1e3 * dt_graph / steps,
+                      "max_grad_rel_diff_vs_eager": graph_err}}, check
 
 
 def gradient_parity(i, circ, bits, grad, loss):

@@ -122,7 +122,12 @@ typedef struct {
                                 ones all summed: intermediates reused across the block) */
   int32_t graph;             /* 1: qflex_contract_amplitudes captures its launches in one HIP
                                 graph and replays it for later calls with the same shapes and
-                                slices (bit-strings may differ); 0: launches every call */
+                                slices (bit-strings may differ), and so does
+                                qflex_contract_grad for calls that sum one slice per circuit
+                                (cotangents may differ too); capture and replay run on the
+                                caller's stream, or on a stream of the grid's ordered after
+                                the caller's when that is the null stream.  An autotuning grid
+                                runs its first call eagerly.  0: launches every call */
   int32_t autotune;          /* 1: the first call that runs a contraction step times every
                                 kernel variant that fits it (product tiles, kernel family, and
                                 for split products gathered vs permuted row operands) on that
@@ -150,6 +155,7 @@ typedef struct {
   int64_t n_permute;     /* permutation kernels launched */
   int64_t n_slices;      /* slices summed, over all circuits */
   int64_t n_bitstrings;  /* bit-strings contracted, over all circuits */
+  int64_t n_tuned;       /* kernel variants the autotuner timed during the call */
 } qflex_stats;
 
 /* Validate circuits (Methods A: gates of a cycle act on disjoint qubits, two-qubit gates on
@@ -271,6 +277,50 @@ qflex_status qflex_frugal_sample(const double* amps, int64_t n_batch, int64_t ba
                                  const int32_t* order, const double* u, int32_t n_c,
                                  int32_t n_qubits, double m, int32_t* accepted, double* partial,
                                  double* tail, void* stream);
+
+/* Samples at fidelity f by the fraction of perfect-fidelity amplitudes (paper, Results,
+ * "Fraction of perfect fidelity amplitudes": a sampler that returns an exact sample with
+ * probability f and a uniformly random bit-string otherwise has fidelity f), each exact
+ * sample drawn by frugal rejection sampling over an open-qubit batch (qflex_frugal_sample).
+ * The grid must hold one circuit; all pointers are host memory.
+ *   closed_bits  uint8 [n_batch][n_qubits]: batch b's closed-qubit bits (its open qubits'
+ *                entries are ignored).
+ *   coins        float64 [n_batch]: batch b is exact when coins[b] < fidelity (the caller's
+ *                uniform draws in [0, 1)).
+ *   fidelity     f in [0, 1].
+ *   uniform_bits uint8 [n_batch][n_qubits]: the sample of a batch that is not exact (the
+ *                caller's uniformly random bit-strings).
+ *   order, u     int32 / float64 [n_batch][n_c]: visit order and uniforms of
+ *                qflex_frugal_sample (rows of batches that are not exact are not read).
+ *   m            M of the frugal sampler.
+ *   samples      uint8 [n_batch][n_qubits] out: uniform_bits[b], or for an exact batch that
+ *                accepts, closed_bits[b] with its accepted open value written into the open
+ *                qubits (the first open qubit most significant).
+ *   status       int8 [n_batch] out: 1 exact sample, 0 uniform sample, -1 exact batch whose
+ *                n_c visits accepted nothing (its sample is then uniform_bits[b]).
+ * Only the exact batches are contracted, at full fidelity, in one qflex_contract_amplitudes
+ * pass; the call returns when the outputs are written.  QFLEX_E_INVALID, nothing launched, for
+ * a grid of several circuits, NULL pointers, n_batch < 0, n_c < 0, fidelity outside [0, 1],
+ * M <= 0 or not finite, or an order value of an exact batch outside [0, 2^n_open). */
+qflex_status qflex_fidelity_samples(qflex_grid* g, const uint8_t* closed_bits, int64_t n_batch,
+                                    const double* coins, double fidelity,
+                                    const uint8_t* uniform_bits, const int32_t* order,
+                                    const double* u, int32_t n_c, double m, uint8_t* samples,
+                                    int8_t* status, void* stream);
+
+/* The autotuner's choices (qflex_options.autotune), one table per process shared by every
+ * grid: a product whose device, kind, shape and operand sources match an entry takes that
+ * entry's kernel variant without being timed; every choice a grid times is added.  Saving
+ * writes the table to a text file (one "<key> <variant>" line per entry, keys naming the
+ * device's architecture and compute units), loading merges such a file into it (its entries
+ * win), so runs that load one file pick the same kernels.  Load: *n_loaded (may be NULL)
+ * receives the number of entries read; QFLEX_E_INVALID for a NULL path, a file that cannot be
+ * opened or a malformed line (the table is then unchanged).  The library adds no choice
+ * beyond shape rules unless a grid autotunes. */
+qflex_status qflex_autotune_cache_save(const char* path);
+qflex_status qflex_autotune_cache_load(const char* path, int64_t* n_loaded);
+int64_t qflex_autotune_cache_size(void);
+void qflex_autotune_cache_clear(void);
 
 /* Statistics of the last contract call. */
 qflex_status qflex_last_stats(const qflex_grid* g, qflex_stats* out);

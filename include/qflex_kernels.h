@@ -85,8 +85,10 @@ qflex_status qflex_gemm_split_c64_noalloc(const void* A, const void* B, void* C,
  * power of two, N >= 32 as in 4), 6 MFMA 256x128 (M a multiple of 256, N of 128, K of 16, and
  * at least 256 such tiles over the batch), 7 reduction kernel on MFMA (M <= 16, N a multiple
  * of 64, K >= 256 a multiple of 64, B not transposed; picked before 4), 8 rows kernel on MFMA
- * (as 3 with K a multiple of 16 and N <= 16; picked before 3 when N > 8).  This query assumes
- * batch = 1. */
+ * (as 3 with K a multiple of 16 and N <= 16; picked before 3 when N > 8), 9 and 10 the
+ * 256x128 and 128x128 MFMA tiles in the 3-multiplication (Gauss) form: P1 = Ar Br, P2 = Ai Bi,
+ * P3 = (Ar + Ai)(Br + Bi), C = (P1 - P2) + i (P3 - P1 - P2), three real products instead of
+ * four, picked in place of 6 and 2.  This query assumes batch = 1. */
 int32_t qflex_gemm_variant(int64_t M, int64_t N, int64_t K);
 
 /* The slice subset that qflex_contract_amplitudes sums for a fidelity (host only): writes up to

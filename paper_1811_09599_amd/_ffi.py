@@ -35,7 +35,8 @@ class Options(C.Structure):
 
 class Stats(C.Structure):
     _fields_ = [("flops", C.c_double), ("permute_bytes", C.c_double), ("n_gemm", C.c_int64),
-                ("n_permute", C.c_int64), ("n_slices", C.c_int64), ("n_bitstrings", C.c_int64)]
+                ("n_permute", C.c_int64), ("n_slices", C.c_int64), ("n_bitstrings", C.c_int64),
+                ("n_tuned", C.c_int64)]
 
 
 class KernelStat(C.Structure):
@@ -48,13 +49,16 @@ EXPORTS = ("qflex_build_grid", "qflex_num_slices", "qflex_plan_cuts", "qflex_pla
            "qflex_set_profiling",
            "qflex_profile_read", "qflex_permute_c64", "qflex_gemm_split_c64",
            "qflex_gemm_split_c64_noalloc",
-           "qflex_gemm_c64", "qflex_select_slices", "qflex_frugal_sample",
+           "qflex_gemm_c64", "qflex_select_slices", "qflex_frugal_sample", "qflex_fidelity_samples",
+           "qflex_autotune_cache_save", "qflex_autotune_cache_load", "qflex_autotune_cache_size",
+           "qflex_autotune_cache_clear",
            "qflex_gemm_split_workspace", "qflex_gemm_c64_workspace", "qflex_gemm_variant",
            "qflex_grid_free", "qflex_last_error")
 # exports that do not return a qflex_status, with their return types
 # the no-allocation split product's fixed scratch size (QFLEX_NOALLOC_SCRATCH_BYTES)
 NOALLOC_SCRATCH_BYTES = 64 << 20
-NON_STATUS = {"qflex_gemm_split_workspace": C.c_int64, "qflex_gemm_c64_workspace": C.c_int64,
+NON_STATUS = {"qflex_autotune_cache_size": C.c_int64, "qflex_autotune_cache_clear": None,
+              "qflex_gemm_split_workspace": C.c_int64, "qflex_gemm_c64_workspace": C.c_int64,
               "qflex_gemm_variant": C.c_int32, "qflex_grid_free": None,
               "qflex_last_error": C.c_char_p}
 
@@ -103,6 +107,12 @@ def lib():
                                       C.POINTER(C.c_int64), C.c_int64, C.POINTER(C.c_int64)]
     L.qflex_frugal_sample.argtypes = [P, C.c_int64, C.c_int64, P, P, C.c_int32, C.c_int32,
                                       C.c_double, P, P, P, P]
+    L.qflex_fidelity_samples.argtypes = [P, P, C.c_int64, P, C.c_double, P, P, P, C.c_int32,
+                                         C.c_double, P, P, P]
+    L.qflex_autotune_cache_save.argtypes = [C.c_char_p]
+    L.qflex_autotune_cache_load.argtypes = [C.c_char_p, C.POINTER(C.c_int64)]
+    L.qflex_autotune_cache_size.argtypes = []
+    L.qflex_autotune_cache_clear.argtypes = []
     L.qflex_grid_free.argtypes = [P]
     L.qflex_gemm_split_c64.argtypes = [P, P, P, C.c_int64, C.c_int64, C.c_int64, C.c_int32,
                                        C.c_int32, C.c_int64, C.c_int32, P, C.c_int64, P]

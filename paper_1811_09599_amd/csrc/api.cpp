@@ -41,6 +41,7 @@ void release(qflex_grid* g) {
   if (g->amax) (void)hipFree(g->amax);
   if (g->node_amax) (void)hipFree(g->node_amax);
   if (g->graph_exec) (void)hipGraphExecDestroy(g->graph_exec);
+  if (g->grad_graph_exec) (void)hipGraphExecDestroy(g->grad_graph_exec);
   if (g->graph_in) (void)hipEventDestroy(g->graph_in);
   for (hipEvent_t e : g->tune_ev)
     if (e) (void)hipEventDestroy(e);
@@ -49,12 +50,14 @@ void release(qflex_grid* g) {
   g->split_scratch.release();
   g->split_cache.release();
   for (qflex::DevBuf* b : {&g->gq, &g->gpieces, &g->gmats, &g->gpos, &g->grad_arena, &g->tbar,
-                           &g->pbar, &g->gbar, &g->amps_dev, &g->xeb, &g->splitk_ws})
+                           &g->pbar, &g->gbar, &g->amps_dev, &g->xeb, &g->splitk_ws,
+                           &g->fs_buf})
     b->release();
   g->arena.release();
   g->amps64.release();
   g->offs.release();
   g->offs_host.release();
+  g->grad_host.release();
   if (g->offs_done) (void)hipEventDestroy(g->offs_done);
   g->prof.release();
   delete g;
@@ -182,6 +185,7 @@ qflex_status qflex_build_grid(const qflex_circuit* circuits, int32_t n_circuits,
       hipError_t e = hipGetDevice(&dev);
       if (e != hipSuccess) qflex::fail(QFLEX_E_DEVICE, std::string("no HIP device: ") + hipGetErrorString(e));
       g->device = dev;
+      g->device_sig = qflex::device_signature(dev);
       qflex::build_grid_device(g, static_cast<hipStream_t>(stream));
     } catch (...) {
       release(g);
@@ -405,6 +409,94 @@ qflex_status qflex_frugal_sample(const double* amps, int64_t n_batch, int64_t ba
     qflex::dev::frugal_sample(reinterpret_cast<const double2*>(amps), n_batch, batch_len, order,
                               u, n_c, n_qubits, m, accepted, partial, tail,
                               static_cast<hipStream_t>(stream));
+  });
+}
+
+qflex_status qflex_fidelity_samples(qflex_grid* g, const uint8_t* closed_bits, int64_t n_batch,
+                                    const double* coins, double fidelity,
+                                    const uint8_t* uniform_bits, const int32_t* order,
+                                    const double* u, int32_t n_c, double m, uint8_t* samples,
+                                    int8_t* status, void* stream) {
+  return guarded([&] {
+    if (!g) qflex::fail(QFLEX_E_INVALID, "NULL grid");
+    if (g->circ.size() != 1) qflex::fail(QFLEX_E_INVALID, "the grid must hold one circuit");
+    if (n_batch < 0 || n_c < 0) qflex::fail(QFLEX_E_INVALID, "need n_batch >= 0 and n_c >= 0");
+    if (n_batch > 0 && (!closed_bits || !coins || !uniform_bits || !samples || !status ||
+                        (n_c > 0 && (!order || !u))))
+      qflex::fail(QFLEX_E_INVALID, "NULL argument");
+    if (!(fidelity >= 0.0 && fidelity <= 1.0))
+      qflex::fail(QFLEX_E_INVALID, "fidelity must be in [0, 1]");
+    if (!(m > 0.0) || !std::isfinite(m)) qflex::fail(QFLEX_E_INVALID, "M must be finite and > 0");
+    const qflex::CircuitState& cs = g->circ[0];
+    const int n = cs.model.n;
+    const std::vector<int>& open = cs.plan.open;
+    const int no = (int)open.size();
+    const int64_t blen = int64_t(1) << no;
+    // the batches that get an exact sample, and their rows of every input
+    std::vector<int64_t> exact;
+    for (int64_t b = 0; b < n_batch; ++b)
+      if (coins[b] < fidelity) exact.push_back(b);
+    const int64_t ne = (int64_t)exact.size();
+    std::vector<uint8_t> eb((size_t)(ne * n));
+    std::vector<int32_t> eo((size_t)(ne * n_c));
+    std::vector<double> eu((size_t)(ne * n_c));
+    for (int64_t i = 0; i < ne; ++i) {
+      const int64_t b = exact[i];
+      std::memcpy(&eb[i * n], closed_bits + b * n, (size_t)n);
+      for (int j = 0; j < n_c; ++j) {
+        const int32_t v = order[b * n_c + j];
+        if (v < 0 || v >= blen)
+          qflex::fail(QFLEX_E_INVALID, "order holds a value outside [0, 2^n_open)");
+        eo[i * n_c + j] = v;
+        eu[i * n_c + j] = u[b * n_c + j];
+      }
+    }
+    // open qubits' bits of the exact batches do not matter: the contraction leaves them open
+    for (int64_t i = 0; i < ne; ++i)
+      for (int q : open) eb[i * n + q] = 0;
+    std::vector<int32_t> acc((size_t)ne);
+    if (ne > 0) {
+      const hipStream_t st = static_cast<hipStream_t>(stream);
+      auto up = [](int64_t bytes) { return (bytes + 255) & ~int64_t(255); };
+      const int64_t b_amps = up(16 * ne * blen), b_ord = up(4 * ne * std::max(n_c, 1)),
+                    b_u = up(8 * ne * std::max(n_c, 1)), b_acc = up(4 * ne), b_part = up(8 * ne);
+      g->fs_buf.reserve((size_t)(b_amps + b_ord + b_u + b_acc + b_part + 256));
+      char* base = static_cast<char*>(g->fs_buf.p);
+      double* amps = reinterpret_cast<double*>(base);
+      int32_t* d_ord = reinterpret_cast<int32_t*>(base + b_amps);
+      double* d_u = reinterpret_cast<double*>(base + b_amps + b_ord);
+      int32_t* d_acc = reinterpret_cast<int32_t*>(base + b_amps + b_ord + b_u);
+      double* d_part = reinterpret_cast<double*>(base + b_amps + b_ord + b_u + b_acc);
+      double* d_tail = reinterpret_cast<double*>(base + b_amps + b_ord + b_u + b_acc + b_part);
+      const int64_t offs[2] = {0, ne};
+      qflex::contract(g, eb.data(), offs, 1.0, 0, nullptr, nullptr, amps, QFLEX_OUT_DEVICE, st);
+      auto check = [](hipError_t e, const char* what) {
+        if (e != hipSuccess)
+          qflex::fail(QFLEX_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+      };
+      if (n_c > 0) {
+        check(hipMemcpyAsync(d_ord, eo.data(), 4 * ne * n_c, hipMemcpyHostToDevice, st), "upload");
+        check(hipMemcpyAsync(d_u, eu.data(), 8 * ne * n_c, hipMemcpyHostToDevice, st), "upload");
+      }
+      qflex::dev::frugal_sample(reinterpret_cast<const double2*>(amps), ne, blen, d_ord, d_u, n_c,
+                                n, m, d_acc, d_part, d_tail, st);
+      check(hipMemcpyAsync(acc.data(), d_acc, 4 * ne, hipMemcpyDeviceToHost, st), "download");
+      check(hipStreamSynchronize(st), "stream");
+    }
+    // compose: uniform samples by default; an exact batch writes its accepted open value into
+    // the open qubits (the first open qubit most significant)
+    std::memcpy(samples, uniform_bits, (size_t)(n_batch * n));
+    std::memset(status, 0, (size_t)n_batch);
+    for (int64_t i = 0; i < ne; ++i) {
+      const int64_t b = exact[i];
+      if (acc[i] < 0) {
+        status[b] = -1;
+        continue;
+      }
+      std::memcpy(samples + b * n, closed_bits + b * n, (size_t)n);
+      for (int t = 0; t < no; ++t) samples[b * n + open[t]] = (uint8_t)((acc[i] >> (no - 1 - t)) & 1);
+      status[b] = 1;
+    }
   });
 }
 

@@ -421,6 +421,7 @@ float time_launches(qflex_grid* g, hipStream_t s, const std::function<void()>& l
   }
   const bool on = g->prof.on;
   g->prof.on = false;
+  ++g->n_tuned;
   launch();  // warm-up
   // the best of three timed runs: a single run's time varies with the clock and with other
   // work in flight, which made the choices differ between otherwise identical grids
@@ -439,7 +440,16 @@ float time_launches(qflex_grid* g, hipStream_t s, const std::function<void()>& l
 }
 
 int tune_gemm(qflex_grid* g, hipStream_t s, const dev::Gemm& gm) {
+  // a choice made before for this device and shape (this process, or a loaded cache file)
+  const std::string key = g->device_sig + "|c64|" + std::to_string(gm.M) + "x" +
+                          std::to_string(gm.N) + "x" + std::to_string(gm.K) + "|t" +
+                          std::to_string(gm.ta) + std::to_string(gm.tb) + "|b" +
+                          std::to_string(gm.batch) + "|ws" + std::to_string(gm.ws ? 1 : 0);
   int best_v = -1;
+  if (tune_cache_get(key, &best_v) && best_v < dev::kGemmVariants &&
+      dev::gemm_variant_fits(gm, best_v))
+    return best_v;
+  best_v = -1;
   float best = 0;
   for (int v = 0; v < dev::kGemmVariants; ++v) {
     if (!dev::gemm_variant_fits(gm, v)) continue;
@@ -448,6 +458,7 @@ int tune_gemm(qflex_grid* g, hipStream_t s, const dev::Gemm& gm) {
     const float ms = time_launches(g, s, [&] { dev::gemm(t, s); });
     if (best_v < 0 || ms < best) best_v = v, best = ms;
   }
+  if (best_v >= 0) tune_cache_put(key, best_v);
   return best_v;
 }
 
@@ -572,6 +583,7 @@ void contract(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets, dou
   const std::vector<std::vector<int64_t>> sel =
       prepare_call(g, bits, bs_offsets, fidelity, seed, slice_ids, slice_offsets, amps, s);
   qflex_stats st{};
+  const int64_t tuned0 = g->n_tuned;
   std::vector<int64_t> offs_base(nc + 1, 0);
   for (int c = 0; c < nc; ++c)
     offs_base[c + 1] = offs_base[c] + (bs_offsets[c + 1] - bs_offsets[c]) * g->circ[c].model.n;
@@ -637,18 +649,21 @@ void contract(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets, dou
   bool capturing = false;
   const bool prof_was_on = g->prof.on;
   if (g->graph_mode) {
-    // the launches go to the grid's own stream, ordered after the caller's earlier work
-    if (!g->graph_stream) {
-      QHIP(hipStreamCreateWithFlags(&g->graph_stream, hipStreamNonBlocking));
-      QHIP(hipEventCreateWithFlags(&g->graph_in, hipEventDisableTiming));
-      QHIP(hipEventCreateWithFlags(&g->graph_out, hipEventDisableTiming));
+    // capture and replay on the caller's stream; the null stream cannot capture, so then the
+    // launches go to the grid's own stream, ordered after the caller's earlier work
+    if (!s_user) {
+      if (!g->graph_stream) {
+        QHIP(hipStreamCreateWithFlags(&g->graph_stream, hipStreamNonBlocking));
+        QHIP(hipEventCreateWithFlags(&g->graph_in, hipEventDisableTiming));
+        QHIP(hipEventCreateWithFlags(&g->graph_out, hipEventDisableTiming));
+      }
+      QHIP(hipEventRecord(g->graph_in, s_user));
+      QHIP(hipStreamWaitEvent(g->graph_stream, g->graph_in, 0));
+      s = g->graph_stream;
     }
-    QHIP(hipEventRecord(g->graph_in, s_user));
-    QHIP(hipStreamWaitEvent(g->graph_stream, g->graph_in, 0));
-    s = g->graph_stream;
     key.reserve(256);
     const void* keyed[] = {g->arena.p, g->split_scratch.p, g->split_cache.p, acc_all,
-                           g->offs.p, g->splitk_ws.p};
+                           g->offs.p, g->splitk_ws.p, s};
     for (const void* p : keyed)
       key += std::to_string(reinterpret_cast<uintptr_t>(p)) + ",";
     key += accumulate ? "+" : "=";
@@ -873,6 +888,19 @@ void contract(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets, dou
             };
             if (is_split) {
               int choice = cs.tuned[k];
+              // a choice made before for this device, shape and operand sources
+              const std::string tkey =
+                  g->autotune ? g->device_sig + "|split" + (g->amax ? "16" : "bf") + "|" +
+                                    std::to_string(M) + "x" + std::to_string(N) + "x" +
+                                    std::to_string(K) + "|b" + std::to_string(nb) + "|g" +
+                                    std::to_string((int)cs.gather_x[k]) +
+                                    std::to_string((int)cs.gather_y[k]) + "|q" +
+                                    std::to_string((int)stp.x.qubit) +
+                                    std::to_string((int)stp.y.qubit) + "|c" +
+                                    std::to_string(cs.xcache_offset[k] >= 0 ? 1 : 0)
+                              : std::string();
+              if (choice < 0 && g->autotune && tune_cache_get(tkey, &choice))
+                cs.tuned[k] = choice;
               if (choice < 0 && g->autotune) {
                 // time every fitting (tile, gathered x, gathered y) once on this call's operands
                 dev::GemmSplit shape;
@@ -888,6 +916,7 @@ void contract(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets, dou
                       if (choice < 0 || ms < best) choice = 4 * t + 2 * gy + gth, best = ms;
                     }
                 cs.tuned[k] = choice;
+                if (choice >= 0) tune_cache_put(tkey, choice);
               }
               if (choice >= 0) run_split(choice & 1, (choice >> 1) & 1, choice >> 2, true);
               else run_split(cs.gather_x[k] != 0, cs.gather_y[k] != 0, -1, true);
@@ -983,7 +1012,7 @@ void contract(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets, dou
     if (capturing) end_capture(false);
     throw;
   }
-  if (g->graph_mode) {  // the caller's later work waits for the graph
+  if (g->graph_mode && s != s_user) {  // the caller's later work waits for the graph
     QHIP(hipEventRecord(g->graph_out, s));
     QHIP(hipStreamWaitEvent(s_user, g->graph_out, 0));
     s = s_user;
@@ -997,6 +1026,7 @@ void contract(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets, dou
     QHIP(hipStreamSynchronize(s));
     g->prof.resolve();
   }
+  st.n_tuned = g->n_tuned - tuned0;
   g->last = st;
 }
 

@@ -19,9 +19,15 @@ namespace dev {
 // 16-byte vectors.  The 256x128 tile (one workgroup of 8 wavefronts per compute unit, two per
 // SIMD) loads 25% fewer operand bytes per MFMA than 128x128 and runs large products at about
 // 0.91 of the FP32 peak, against 0.89.
+//
+// G3: the same tiles in the 3-multiplication (Gauss) form: P1 += ar*br, P2 += ai*bi,
+// P3 += (ar + ai)*(br + bi), then Cr = P1 - P2 and Ci = P3 - P1 - P2.  Three MFMAs per pair of
+// complex k instead of four (the sums are two vector adds per operand value), for a third more
+// accumulator registers.  Ci loses the accuracy that the cancellation in P3 - P1 - P2 costs:
+// its FP32 rounding error is about 1.7 times that of the 4-multiplication form on random data.
 // =============================================================================================
 
-template <bool TA, bool TB, int BM, int BN, int WM = 2, int WN = 2>
+template <bool TA, bool TB, int BM, int BN, int WM = 2, int WN = 2, bool G3 = false>
 __global__ void __launch_bounds__(64 * WM * WN) gemm_mfma_kernel(const Gemm g) {
   constexpr int NT = 64 * WM * WN;
   constexpr int BK = 16, LDK = BK + 2;
@@ -35,7 +41,8 @@ __global__ void __launch_bounds__(64 * WM * WN) gemm_mfma_kernel(const Gemm g) {
   const int wm = wave / WN, wn = wave % WN;
   const int h = lane >> 5, r = lane & 31;
   const int64_t tiles_n = g.N / BN;
-  const int64_t tm = (int64_t)blockIdx.x / tiles_n, tn = (int64_t)blockIdx.x % tiles_n;
+  int64_t tm, tn;
+  grouped_tile(blockIdx.x, g.M / BM, tiles_n, tm, tn);
   const int b = blockIdx.y, z = blockIdx.z;
   const float2* __restrict__ A = g.A + g.a_add + (g.a_off ? g.a_off[b] : b * g.a_bs) + z * g.a_ks;
   const float2* __restrict__ B = g.B + g.b_add + (g.b_off ? g.b_off[b] : b * g.b_bs) + z * g.b_ks;
@@ -97,13 +104,22 @@ __global__ void __launch_bounds__(64 * WM * WN) gemm_mfma_kernel(const Gemm g) {
     }
   };
 
-  floatx16 cr[TMI][TNI], ci[TMI][TNI];
+  // 4M: cr, ci are the real and imaginary parts; 3M: cr, ci, c3 hold P1, P2, P3
+  floatx16 cr[TMI][TNI], ci[TMI][TNI], c3[G3 ? TMI : 1][G3 ? TNI : 1];
 #pragma unroll
   for (int i = 0; i < TMI; ++i)
 #pragma unroll
     for (int j = 0; j < TNI; ++j)
 #pragma unroll
       for (int v = 0; v < 16; ++v) cr[i][j][v] = ci[i][j][v] = 0.f;
+  if constexpr (G3) {
+#pragma unroll
+    for (int i = 0; i < TMI; ++i)
+#pragma unroll
+      for (int j = 0; j < TNI; ++j)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) c3[i][j][v] = 0.f;
+  }
 
   const int nk = (int)(g.K / BK);
   gload(0);
@@ -125,29 +141,65 @@ __global__ void __launch_bounds__(64 * WM * WN) gemm_mfma_kernel(const Gemm g) {
       for (int j = 0; j < TNI; ++j)
         bf[j] = *reinterpret_cast<const f32x4*>(
             &bs[(wn * WTN + j * 32 + r) * LDK + h * 8 + 2 * s2]);
-      // the two terms of each part are issued in separate passes over the sub-tiles, so that
-      // consecutive MFMAs never feed the same accumulator
+      if constexpr (G3) {
+        // one pass over the sub-tiles per product, so that consecutive MFMAs never feed the
+        // same accumulator
 #pragma unroll
-      for (int u = 0; u < 2; ++u) {
-#pragma unroll
-        for (int pass = 0; pass < 2; ++pass)
+        for (int u = 0; u < 2; ++u) {
+          float ar[TMI], ai[TMI], sa[TMI], br[TNI], bi[TNI], sb[TNI];
 #pragma unroll
           for (int i = 0; i < TMI; ++i) {
-            const float ar = u ? af[i].z : af[i].x;
-            const float ai = u ? af[i].w : af[i].y;
+            ar[i] = u ? af[i].z : af[i].x;
+            ai[i] = u ? af[i].w : af[i].y;
+            sa[i] = ar[i] + ai[i];
+          }
 #pragma unroll
-            for (int j = 0; j < TNI; ++j) {
-              const float br = u ? bf[j].z : bf[j].x;
-              const float bi = u ? bf[j].w : bf[j].y;
-              if (pass == 0) {
-                cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, br, cr[i][j], 0, 0, 0);
-                ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, bi, ci[i][j], 0, 0, 0);
-              } else {
-                cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(-ai, bi, cr[i][j], 0, 0, 0);
-                ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai, br, ci[i][j], 0, 0, 0);
+          for (int j = 0; j < TNI; ++j) {
+            br[j] = u ? bf[j].z : bf[j].x;
+            bi[j] = u ? bf[j].w : bf[j].y;
+            sb[j] = br[j] + bi[j];
+          }
+#pragma unroll
+          for (int i = 0; i < TMI; ++i)
+#pragma unroll
+            for (int j = 0; j < TNI; ++j)
+              cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar[i], br[j], cr[i][j], 0, 0, 0);
+#pragma unroll
+          for (int i = 0; i < TMI; ++i)
+#pragma unroll
+            for (int j = 0; j < TNI; ++j)
+              ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai[i], bi[j], ci[i][j], 0, 0, 0);
+#pragma unroll
+          for (int i = 0; i < TMI; ++i)
+#pragma unroll
+            for (int j = 0; j < TNI; ++j)
+              c3[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(sa[i], sb[j], c3[i][j], 0, 0, 0);
+        }
+      } else {
+        // the two terms of each part are issued in separate passes over the sub-tiles, so that
+        // consecutive MFMAs never feed the same accumulator
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+#pragma unroll
+          for (int pass = 0; pass < 2; ++pass)
+#pragma unroll
+            for (int i = 0; i < TMI; ++i) {
+              const float ar = u ? af[i].z : af[i].x;
+              const float ai = u ? af[i].w : af[i].y;
+#pragma unroll
+              for (int j = 0; j < TNI; ++j) {
+                const float br = u ? bf[j].z : bf[j].x;
+                const float bi = u ? bf[j].w : bf[j].y;
+                if (pass == 0) {
+                  cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, br, cr[i][j], 0, 0, 0);
+                  ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, bi, ci[i][j], 0, 0, 0);
+                } else {
+                  cr[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(-ai, bi, cr[i][j], 0, 0, 0);
+                  ci[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(ai, br, ci[i][j], 0, 0, 0);
+                }
               }
             }
-          }
+        }
       }
       // the next tile goes to the other buffer while this one still has a k step to go, so
       // its LDS writes overlap MFMAs instead of sitting between the last MFMA and the barrier
@@ -164,7 +216,9 @@ __global__ void __launch_bounds__(64 * WM * WN) gemm_mfma_kernel(const Gemm g) {
       for (int v = 0; v < 16; ++v) {
         const int row = wm * WTM + i * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
         const int col = wn * WTN + j * 32 + r;
-        C[(m0 + row) * ldc + n0 + col] = make_float2(cr[i][j][v], ci[i][j][v]);
+        float re = cr[i][j][v], im = ci[i][j][v];
+        if constexpr (G3) re = cr[i][j][v] - ci[i][j][v], im = c3[i][j][v] - cr[i][j][v] - ci[i][j][v];
+        C[(m0 + row) * ldc + n0 + col] = make_float2(re, im);
       }
 }
 
@@ -471,6 +525,8 @@ bool gemm_variant_fits(const Gemm& g, int v) {
     case 6: return g.K % 16 == 0 && g.M % 256 == 0 && g.N % 128 == 0;
     case 7: return !g.tb && g.M <= 16 && g.N % 64 == 0 && g.K >= 256 && g.K % 64 == 0;
     case 8: return g.K % 16 == 0 && g.M % 256 == 0 && g.N <= 16;
+    case 9: return gemm_variant_fits(g, 6);
+    case 10: return gemm_variant_fits(g, 2);
     default: return false;
   }
 }
@@ -479,8 +535,9 @@ int gemm_variant(const Gemm& g) {
   if (g.force_variant >= 0 && gemm_variant_fits(g, g.force_variant)) return g.force_variant;
   // the 256x128 tile once its workgroups cover every compute unit (one each: the tile's LDS
   // leaves room for no second); below that, 128x128 tiles give twice as many workgroups
-  if (gemm_variant_fits(g, 6) && (g.M / 256) * (g.N / 128) * g.batch >= 256) return 6;
-  if (gemm_variant_fits(g, 2)) return 2;
+  // (in the 3-multiplication form: three MFMAs per complex multiply-add pair instead of four)
+  if (gemm_variant_fits(g, 9) && (g.M / 256) * (g.N / 128) * g.batch >= 256) return 9;
+  if (gemm_variant_fits(g, 10)) return 10;
   if (gemm_variant_fits(g, 1)) return 1;
   // rows kernels: one workgroup per 256 rows, so only when that fills half the chip or more;
   // on MFMA for 8 < N <= 16 (at N = 16 the vector kernel is ALU-bound, at N <= 8 it is not)
@@ -510,17 +567,23 @@ const char* gemm_name(const Gemm& g) {
        "gemm_mfma_256x128_tt"},
       {"gemm_reduce_mfma_nn", "gemm_reduce_mfma_nt", "gemm_reduce_mfma_tn",
        "gemm_reduce_mfma_tt"},
-      {"gemm_rows_mfma_nn", "gemm_rows_mfma_nt", "gemm_rows_mfma_tn", "gemm_rows_mfma_tt"}};
+      {"gemm_rows_mfma_nn", "gemm_rows_mfma_nt", "gemm_rows_mfma_tn", "gemm_rows_mfma_tt"},
+      {"gemm_mfma3m_256x128_nn", "gemm_mfma3m_256x128_nt", "gemm_mfma3m_256x128_tn",
+       "gemm_mfma3m_256x128_tt"},
+      {"gemm_mfma3m_128x128_nn", "gemm_mfma3m_128x128_nt", "gemm_mfma3m_128x128_tn",
+       "gemm_mfma3m_128x128_tt"}};
   return names[gemm_variant(g)][(g.ta ? 2 : 0) + (g.tb ? 1 : 0)];
 }
 
 // Output tiles of the kernel gemm() picks (one workgroup each, per batch element).
 static int64_t gemm_tiles(const Gemm& g) {
   switch (gemm_variant(g)) {
-    case 6: return (g.M / 256) * (g.N / 128);
+    case 6:
+    case 9: return (g.M / 256) * (g.N / 128);
     case 7: return g.N / 64;
     case 8: return g.M / 256;
-    case 2: return (g.M / 128) * (g.N / 128);
+    case 2:
+    case 10: return (g.M / 128) * (g.N / 128);
     case 1: return (g.M / 64) * (g.N / 64);
     case 3: return g.M / 256;
     case 4: return g.N / std::min<int64_t>(g.N, 256);
@@ -538,7 +601,7 @@ static int64_t gemm_tiles(const Gemm& g) {
 int gemm_splitk(const Gemm& g) {
   constexpr int64_t kTarget = 2048, kMinChunk = 256, kMaxSplit = 64;
   // the 256x128 tile is only picked by shape once it fills the chip, one workgroup per unit
-  if (gemm_variant(g) == 6) return 1;
+  if (gemm_variant(g) == 6 || gemm_variant(g) == 9) return 1;
   const int64_t wgs = gemm_tiles(g) * g.batch;
   if (wgs >= kTarget / 2 || g.K < 2 * kMinChunk || (g.K & (g.K - 1))) return 1;
   int split = 1;
@@ -820,6 +883,14 @@ static void gemm_t(const Gemm& g, hipStream_t s) {
   } else if (v == 6) {
     dim3 grid((unsigned)((g.M / 256) * (g.N / 128)), (unsigned)g.batch, z);
     hipLaunchKernelGGL((gemm_mfma_kernel<TA, TB, 256, 128, 4, 2>), grid, dim3(512), 0, s, g);
+  } else if (v == 9) {
+    dim3 grid((unsigned)((g.M / 256) * (g.N / 128)), (unsigned)g.batch, z);
+    hipLaunchKernelGGL((gemm_mfma_kernel<TA, TB, 256, 128, 4, 2, true>), grid, dim3(512), 0, s,
+                       g);
+  } else if (v == 10) {
+    dim3 grid((unsigned)((g.M / 128) * (g.N / 128)), (unsigned)g.batch, z);
+    hipLaunchKernelGGL((gemm_mfma_kernel<TA, TB, 128, 128, 2, 2, true>), grid, dim3(256), 0, s,
+                       g);
   } else if (v == 2) {
     dim3 grid((unsigned)((g.M / 128) * (g.N / 128)), (unsigned)g.batch, z);
     hipLaunchKernelGGL((gemm_mfma_kernel<TA, TB, 128, 128>), grid, dim3(256), 0, s, g);

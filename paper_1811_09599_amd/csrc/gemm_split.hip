@@ -58,7 +58,8 @@ gemm_split_kernel(const GemmSplit g) {
   const int wm = wave / WN, wn = wave % WN;
   const int h = lane >> 5, r = lane & 31;
   const int64_t tiles_n = g.N / BN;
-  const int64_t tm = (int64_t)blockIdx.x / tiles_n, tn = (int64_t)blockIdx.x % tiles_n;
+  int64_t tm, tn;
+  grouped_tile(blockIdx.x, g.M / BM, tiles_n, tm, tn);
   const int b = blockIdx.y;
   const uint16_t* __restrict__ A = g.A + 4 * (g.a_add + (g.a_off ? g.a_off[b] : b * g.a_bs));
   const uint16_t* __restrict__ B =

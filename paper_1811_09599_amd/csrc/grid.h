@@ -48,6 +48,8 @@ struct CircuitState {
   std::vector<int64_t> qsplit_offset;// per qubit: offset in grid_split (16-bit values), -1 if none
   std::vector<int64_t> qamax_slot;   // per qubit: fp16 scale slot in amax, -1 if none
   int64_t split_a_elems = 0, split_b_elems = 0;  // scratch per bit-string (16-bit values)
+  GradLayout grad_layout;            // the adjoint's memory layout (made on first use)
+  bool grad_layout_ready = false;
 };
 
 // Device buffer that only grows; freed with the grid.
@@ -108,18 +110,25 @@ struct Resume {
 
 struct qflex_grid {
   int device = 0;
+  std::string device_sig;                // architecture and compute units (autotuner keys)
   int precision = QFLEX_PREC_C64;
   int bitstring_batch = 0;
   int slice_mode = QFLEX_SLICES_RANDOM;
   // graph mode: the captured launches of the last call and the call shape they belong to
   bool graph_mode = false;
   bool autotune = false;                 // time kernel variants per step on first use
+  int64_t n_tuned = 0;                   // kernel variants timed so far (time_launches calls)
   hipEvent_t tune_ev[2] = {nullptr, nullptr};
   hipGraphExec_t graph_exec = nullptr;
   hipStream_t graph_stream = nullptr;    // captures and replays (the null stream cannot capture)
   hipEvent_t graph_in = nullptr, graph_out = nullptr;
   std::string graph_key;
   qflex_stats graph_stats{};
+  // the same for qflex_contract_grad (calls with one slice per circuit)
+  hipGraphExec_t grad_graph_exec = nullptr;
+  std::string grad_graph_key;
+  qflex_stats grad_graph_stats{};
+  bool grad_tuned = false;               // an autotuning gradient call has run
   std::vector<qflex::CircuitState> circ;
   float2* grid = nullptr;                // all qubit tensors
   int64_t grid_elems = 0;
@@ -139,12 +148,14 @@ struct qflex_grid {
   // gradient buffers
   qflex::DevBuf grad_arena, tbar, pbar, gbar, amps_dev, xeb;
   qflex::DevBuf splitk_ws;               // partial products of split-K complex64 products
+  qflex::DevBuf fs_buf;                  // qflex_fidelity_samples: amplitudes, draws, results
   qflex::DevBuf split_scratch;           // split operands of intermediates
   qflex::DevBuf split_cache;             // split copies of intermediates reused across slices
   qflex::DevBuf arena;                   // intermediates
   qflex::DevBuf amps64;                  // FP64 amplitude accumulator
   qflex::DevBuf offs;                    // per-bit-string output offsets of the qubit tensors
   qflex::HostPinned offs_host;
+  qflex::HostPinned grad_host;           // piece cotangents and cross-entropy sums, on the host
   hipEvent_t offs_done = nullptr;        // the last upload out of offs_host has finished
   qflex_stats last{};
   qflex::Profiler prof;
@@ -164,6 +175,11 @@ std::vector<std::vector<int64_t>> prepare_call(qflex_grid* g, const uint8_t* bit
 // the stream is synchronised), and the fastest kernel variant of a complex64 product.
 float time_launches(qflex_grid* g, hipStream_t s, const std::function<void()>& launch);
 int tune_gemm(qflex_grid* g, hipStream_t s, const dev::Gemm& gm);
+// The process-wide table of autotuner choices (qflex_autotune_cache_*): keys name the device
+// (device_signature) and everything the timing depended on.
+std::string device_signature(int device);
+bool tune_cache_get(const std::string& key, int* choice);
+void tune_cache_put(const std::string& key, int choice);
 void contract(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets, double fidelity,
               uint64_t seed, const int64_t* slice_ids, const int64_t* slice_offsets,
               double* amps, int32_t out_flags, hipStream_t s);

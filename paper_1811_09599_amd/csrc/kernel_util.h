@@ -108,6 +108,24 @@ __device__ inline int deposit_i(int v, const int8_t* pos, int limit) {
 
 // f(v) of a bit map given as runs (see SplitGather); the n <= kGatherRuns run words sit in
 // the kernel arguments at fixed offsets, so they are read once, by scalar loads
+// Output tile (tm, tn) of workgroup `bid` of a tiled product, in grouped order: groups of up to
+// 16 row tiles sweep the column tiles together.  The 256 workgroups resident at once (one per
+// compute unit) then cover a 16 x 16 block of tiles, whose 16 row and 16 column panels are
+// shared through the caches, instead of one row panel against 256 column panels that stream
+// from HBM for every row panel.  Workgroups go to the 8 XCDs round robin, so each XCD gets 2 of
+// the block's row tiles against all 16 column tiles.
+__device__ inline void grouped_tile(int64_t bid, int64_t tiles_m, int64_t tiles_n, int64_t& tm,
+                                    int64_t& tn) {
+  constexpr int64_t GM = 16;
+  const int64_t per_group = GM * tiles_n;
+  const int64_t group = bid / per_group;
+  const int64_t first = group * GM;
+  const int64_t gsz = tiles_m - first < GM ? tiles_m - first : GM;
+  const int64_t r = bid - group * per_group;
+  tm = first + r % gsz;
+  tn = r / gsz;
+}
+
 __device__ inline int64_t deposit_runs(int64_t v, const int32_t (&runs)[kGatherRuns], int n) {
   int64_t f = 0;
 #pragma unroll

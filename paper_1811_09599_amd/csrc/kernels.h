@@ -102,8 +102,9 @@ struct Gemm {
 };
 // which kernel gemm() would pick: 0 = SIMT, 1 = MFMA 64x64 tile, 2 = MFMA 128x128 tile,
 // 3 = rows, 4 = reduction-shaped, 5 = short K, 6 = MFMA 256x128 tile, 7 = reduction-shaped
-// on MFMA, 8 = rows on MFMA
-constexpr int kGemmVariants = 9;
+// on MFMA, 8 = rows on MFMA, 9 / 10 = the 256x128 / 128x128 MFMA tiles in the
+// 3-multiplication form
+constexpr int kGemmVariants = 11;
 int gemm_variant(const Gemm& g);
 bool gemm_variant_fits(const Gemm& g, int v);  // the shape meets variant v's requirements
 const char* gemm_name(const Gemm& g);  // kernel name used by the profiler

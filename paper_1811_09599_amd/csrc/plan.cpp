@@ -827,6 +827,144 @@ Plan make_plan(const Model& m, const qflex_options& opt) {
   return p.run();
 }
 
+// Extra memory, as a fraction of the least a segmentation of the adjoint needs, that it may
+// take to recompute fewer flops.
+constexpr double kGradMemSlack = 0.25;
+
+GradLayout make_grad_layout(const Plan& P, int64_t namp) {
+  auto pad = [](int64_t e) { return (e + 63) & ~int64_t(63); };
+  const int n = (int)P.steps.size();
+  const int nn = (int)P.nodes.size();
+  GradLayout G;
+  G.ckpt.assign(nn, 0);
+  G.voff.assign(nn, -1);
+  G.coff.assign(nn, -1);
+  // producer and consumer step of every node; a permuted copy of an operand (scratch node)
+  // is made and used by one step and has no cotangent of its own
+  std::vector<int> prod(nn, -1), cons(nn, -1);
+  std::vector<char> scratch(nn, 0);
+  for (int k = 0; k < n; ++k) {
+    const Step& s = P.steps[k];
+    prod[s.out] = k;
+    if (!s.x.qubit) cons[s.x.id] = k;
+    if (!s.y.qubit) cons[s.y.id] = k;
+    for (int sc : {s.scratch_x, s.scratch_y})
+      if (sc >= 0) prod[sc] = cons[sc] = k, scratch[sc] = 1;
+  }
+  if (!P.result.qubit) cons[P.result.id] = prod[P.result.id];
+  int64_t s1 = pad(namp), s2 = 0;
+  for (const Step& s : P.steps) {
+    s1 = std::max(s1, pad(int64_t(1) << (s.mb + s.kb)));
+    s2 = std::max(s2, pad(int64_t(1) << (s.kb + s.nb)));
+  }
+  std::vector<int64_t> value(nn, 0), both(nn, 0);
+  for (int v = 0; v < nn; ++v)
+    if (prod[v] >= 0) {
+      value[v] = pad(P.nodes[v].elems());
+      both[v] = scratch[v] ? value[v] : 2 * value[v];
+      G.store_all_elems += both[v];
+    }
+  G.store_all_elems += s1 + s2;
+  // per range of steps [a, b): the values and cotangents of the nodes it makes and uses
+  // itself (seg), and of those it makes for a later range (checkpoints, ck)
+  std::vector<std::vector<int64_t>> seg(n + 1, std::vector<int64_t>(n + 1, 0)), ck = seg;
+  for (int v = 0; v < nn; ++v) {
+    if (prod[v] < 0) continue;
+    for (int a = 0; a <= prod[v]; ++a)
+      for (int b = prod[v] + 1; b <= n; ++b) {
+        if (cons[v] < b) seg[a][b] += both[v];
+        else ck[a][b] += 2 * value[v];
+      }
+  }
+  // Under a cap on every segment but the last, the least checkpoint memory of segmenting
+  // steps [0, b) (f[b]; from[b] = start of its last segment), for every cap a range reaches.
+  std::vector<int64_t> caps;
+  for (int a = 0; a < n; ++a)
+    for (int b = a + 1; b <= n; ++b) caps.push_back(seg[a][b]);
+  std::sort(caps.begin(), caps.end());
+  caps.erase(std::unique(caps.begin(), caps.end()), caps.end());
+  const int64_t kInf = std::numeric_limits<int64_t>::max() / 4;
+  auto solve = [&](int64_t cap, std::vector<int64_t>& f, std::vector<int>& from) {
+    std::vector<int> nseg(n + 1, 0);
+    f.assign(n + 1, kInf);
+    from.assign(n + 1, -1);
+    f[0] = 0;
+    for (int b = 1; b <= n; ++b)
+      for (int a = 0; a < b; ++a) {
+        if (f[a] >= kInf || seg[a][b] > cap) continue;
+        const int64_t c = f[a] + ck[a][b];
+        if (c < f[b] || (c == f[b] && nseg[a] + 1 < nseg[b]))
+          f[b] = c, from[b] = a, nseg[b] = nseg[a] + 1;
+      }
+  };
+  // the least memory of any segmentation: checkpoints plus the largest segment
+  int64_t mem_min = kInf;
+  std::vector<int64_t> f;
+  std::vector<int> from;
+  for (int64_t cap : caps) {
+    if (cap >= mem_min) break;
+    solve(cap, f, from);
+    if (f[n] < kInf) mem_min = std::min(mem_min, f[n] + cap);
+  }
+  // Within kGradMemSlack of that, the segmentation that recomputes the fewest flops: the
+  // longest last segment [a, n) (never recomputed) whose prefix [0, a) segments within the
+  // cap and the budget; ties go to less memory.
+  std::vector<double> pf(n + 1, 0.0);
+  for (int k = 0; k < n; ++k) pf[k + 1] = pf[k] + P.steps[k].flops();
+  const int64_t budget = n ? (int64_t)((1.0 + kGradMemSlack) * (double)mem_min) : 0;
+  double best_rc = std::numeric_limits<double>::infinity();
+  int64_t best_mem = kInf;
+  std::vector<int> best_cut;
+  for (int64_t cap : caps) {
+    if (cap > budget) break;
+    solve(cap, f, from);
+    for (int a = 0; a < n; ++a) {
+      if (f[a] >= kInf || seg[a][n] > cap || f[a] + cap > budget) continue;
+      const int64_t mem = f[a] + cap;
+      if (pf[a] < best_rc || (pf[a] == best_rc && mem < best_mem)) {
+        best_rc = pf[a], best_mem = mem;
+        best_cut.assign(1, n);
+        for (int b = a; b > 0; b = from[b]) best_cut.push_back(b);
+      }
+    }
+  }
+  if (n == 0) best_cut.clear();
+  std::reverse(best_cut.begin(), best_cut.end());
+  int a = 0;
+  for (int b : best_cut) G.segs.push_back({a, b}), a = b;
+  std::vector<int> seg_of(n, 0);
+  for (size_t i = 0; i < G.segs.size(); ++i)
+    for (int k = G.segs[i].first; k < G.segs[i].second; ++k) seg_of[k] = (int)i;
+  // layout: checkpoint values, checkpoint cotangents, the segment area, then s1 and s2
+  int64_t top = 0;
+  for (int v = 0; v < nn; ++v)
+    if (prod[v] >= 0 && seg_of[prod[v]] != seg_of[cons[v]]) {
+      G.ckpt[v] = 1;
+      G.voff[v] = top;
+      top += value[v];
+    }
+  for (int v = 0; v < nn; ++v)
+    if (G.ckpt[v]) G.coff[v] = top, top += value[v];
+  G.ckpt_elems = top;
+  for (const auto& sg : G.segs) {
+    int64_t off = top;
+    for (int v = 0; v < nn; ++v) {
+      if (prod[v] < sg.first || prod[v] >= sg.second || G.ckpt[v]) continue;
+      G.voff[v] = off;
+      off += value[v];
+      if (!scratch[v]) G.coff[v] = off, off += value[v];
+    }
+    G.segment_elems = std::max(G.segment_elems, off - top);
+  }
+  top += G.segment_elems;
+  G.s1off = top;
+  G.s2off = top + s1;
+  G.elems = top + s1 + s2;
+  for (size_t i = 0; i + 1 < G.segs.size(); ++i)
+    for (int k = G.segs[i].first; k < G.segs[i].second; ++k) G.recompute_flops += P.steps[k].flops();
+  return G;
+}
+
 std::string Plan::describe(const Model& m) const {
   std::ostringstream o;
   o.precision(17);
@@ -839,15 +977,33 @@ std::string Plan::describe(const Model& m) const {
       << cut_bits[i] << "]";
   o << "],\"num_slices\":" << num_slices() << ",\"max_bits\":" << max_bits
     << ",\"arena_elems\":" << arena_elems << ",\"flops_all_slices\":" << flops_all_slices
-    << ",\"cost_estimate_s\":" << cost_estimate
-    << ",\"steps\":[";
+    << ",\"cost_estimate_s\":" << cost_estimate;
+  // memory of the adjoint (gradient) contraction of one slice, per bit-string
+  const GradLayout G = make_grad_layout(*this, int64_t(1) << open.size());
+  o << ",\"grad\":{\"elems\":" << G.elems << ",\"ckpt_elems\":" << G.ckpt_elems
+    << ",\"segment_elems\":" << G.segment_elems << ",\"store_all_elems\":" << G.store_all_elems
+    << ",\"recompute_flops\":" << G.recompute_flops << ",\"segments\":[";
+  for (size_t i = 0; i < G.segs.size(); ++i)
+    o << (i ? "," : "") << "[" << G.segs[i].first << "," << G.segs[i].second << "]";
+  o << "],\"checkpoints\":[";
+  bool first = true;
+  for (size_t v = 0; v < G.ckpt.size(); ++v)
+    if (G.ckpt[v]) o << (first ? "" : ",") << v, first = false;
+  o << "],\"s1off\":" << G.s1off << ",\"s2off\":" << G.s2off << ",\"voff\":[";
+  for (size_t v = 0; v < G.voff.size(); ++v) o << (v ? "," : "") << G.voff[v];
+  o << "],\"coff\":[";
+  for (size_t v = 0; v < G.coff.size(); ++v) o << (v ? "," : "") << G.coff[v];
+  o << "],\"node_elems\":[";
+  for (size_t v = 0; v < nodes.size(); ++v) o << (v ? "," : "") << nodes[v].elems();
+  o << "]},\"steps\":[";
   for (size_t i = 0; i < steps.size(); ++i) {
     const Step& s = steps[i];
     o << (i ? "," : "") << "{\"x\":\"" << (s.x.qubit ? "q" : "n") << s.x.id << "\",\"y\":\""
       << (s.y.qubit ? "q" : "n") << s.y.id << "\",\"out\":" << s.out << ",\"mb\":" << s.mb
       << ",\"kb\":" << s.kb << ",\"nb\":" << s.nb << ",\"ta\":" << (s.ta ? 1 : 0)
       << ",\"tb\":" << (s.tb ? 1 : 0) << ",\"perm_x\":" << (s.scratch_x >= 0 ? 1 : 0)
-      << ",\"perm_y\":" << (s.scratch_y >= 0 ? 1 : 0) << ",\"deps\":" << s.deps
+      << ",\"perm_y\":" << (s.scratch_y >= 0 ? 1 : 0) << ",\"sx\":" << s.scratch_x
+      << ",\"sy\":" << s.scratch_y << ",\"deps\":" << s.deps
       << ",\"flops\":" << s.flops();
     // label orders, most significant first: the product's rows, contracted labels and
     // columns, and the storage orders of x and y as they come in (free labels of a qubit)

@@ -90,6 +90,27 @@ struct Plan {
 
 Plan make_plan(const Model& m, const qflex_options& opt);
 
+// Memory of the adjoint contraction of one slice, per bit-string, in complex elements.  The
+// steps are cut into segments of consecutive steps.  The forward pass keeps only the
+// intermediates that a later segment consumes (the checkpoints) and the whole last segment;
+// the reverse sweep takes the segments last to first, recomputes each one (but the last) from
+// the checkpoints and the qubit tensors, and reverses its steps.  Every step is recomputed at
+// most once; the segmentation is the one with the least memory (checkpoint values and
+// cotangents, plus the largest segment's values and cotangents, plus the cotangent scratch of
+// one product's two operands), fewer segments on ties.
+struct GradLayout {
+  std::vector<std::pair<int, int>> segs;  // [first, end) steps of each segment, in order
+  std::vector<char> ckpt;                 // per node: a checkpoint
+  std::vector<int64_t> voff, coff;        // per node: value / cotangent offset, -1 if none
+  int64_t s1off = 0, s2off = 0;           // cotangent scratch of a product's x and of its y
+  int64_t elems = 0;                      // everything, per bit-string
+  int64_t ckpt_elems = 0;                 // checkpoint values and cotangents
+  int64_t segment_elems = 0;              // the largest segment's values and cotangents
+  int64_t store_all_elems = 0;            // keeping every value and cotangent instead
+  double recompute_flops = 0;             // products run again (segments but the last)
+};
+GradLayout make_grad_layout(const Plan& P, int64_t namp);
+
 // Permutation taking a tensor stored with labels `in` to storage order `out` (same labels).
 PermDesc make_perm_desc(const std::vector<int>& in, const std::vector<int>& out);
 

@@ -368,36 +368,28 @@ def fidelity_samples(grid: Grid, closed_bits, coins, uniform_bits, order, u, fid
     """Fidelity-f samples (paper, Results, "Fraction of perfect fidelity amplitudes") by the
     frugal sampler: batch b (closed_bits[b], the open qubits' values ignored) gives an exact
     sample when coins[b] < f, else uniform_bits[b].  Only the exact batches are contracted, at
-    full fidelity, and sampled on the device (qflex_contract_amplitudes, qflex_frugal_sample);
-    the accepted open value is written into the open qubits, the first open qubit most
-    significant.  One circuit per grid.  order / u: [n_batch, n_c] visit order and uniforms
+    full fidelity, and sampled on the device; the accepted open value is written into the open
+    qubits, the first open qubit most significant (all in qflex_fidelity_samples).  One
+    circuit per grid.  order / u: [n_batch, n_c] visit order and uniforms
     (rows of uniform batches are not used).  Returns (samples uint8 [n_batch, n], status int8
     [n_batch]: 1 exact sample, 0 uniform sample, -1 exact batch that accepted nothing)."""
-    import torch
-
-    if len(grid.circuits) != 1:
-        raise ValueError("fidelity_samples needs a grid of one circuit")
-    closed_bits = np.asarray(closed_bits, dtype=np.uint8)
-    uniform_bits = np.asarray(uniform_bits, dtype=np.uint8)
-    coins = np.asarray(coins, dtype=np.float64)
+    closed_bits = np.ascontiguousarray(closed_bits, dtype=np.uint8)
+    uniform_bits = np.ascontiguousarray(uniform_bits, dtype=np.uint8)
+    coins = np.ascontiguousarray(coins, dtype=np.float64)
     nb, n = closed_bits.shape
-    exact = np.nonzero(coins < fidelity)[0]
-    samples = uniform_bits.copy()
-    status = np.zeros(nb, dtype=np.int8)
-    if len(exact):
-        amps = grid.contract_amplitudes(closed_bits[exact])
-        o = torch.from_numpy(np.ascontiguousarray(np.asarray(order, dtype=np.int32)[exact])).cuda()
-        w = torch.from_numpy(np.ascontiguousarray(np.asarray(u, dtype=np.float64)[exact])).cuda()
-        acc, _ = frugal_sample(amps, o, w, n, m)
-        acc = acc.cpu().numpy()
-        op = list(grid.open_qubits)
-        for i, b in enumerate(exact):
-            if acc[i] < 0:
-                status[b] = -1
-                continue
-            x = closed_bits[b].copy()
-            for t, q in enumerate(op):
-                x[q] = (acc[i] >> (len(op) - 1 - t)) & 1
-            samples[b] = x
-            status[b] = 1
+    if uniform_bits.shape != (nb, n) or coins.shape != (nb,):
+        raise ValueError("closed_bits, uniform_bits [n_batch, n] and coins [n_batch] must agree")
+    order = np.ascontiguousarray(order, dtype=np.int32)
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    if order.ndim != 2 or order.shape[0] != nb:
+        raise ValueError("order and u must both be [n_batch, n_c]")
+    if order.shape != u.shape:
+        raise ValueError("order and u must both be [n_batch, n_c]")
+    samples = np.empty((nb, n), dtype=np.uint8)
+    status = np.empty(nb, dtype=np.int8)
+    P = C.c_void_p
+    F.check(F.lib().qflex_fidelity_samples(
+        grid._h, P(closed_bits.ctypes.data), nb, P(coins.ctypes.data), float(fidelity),
+        P(uniform_bits.ctypes.data), P(order.ctypes.data), P(u.ctypes.data), int(order.shape[1]),
+        float(m), P(samples.ctypes.data), P(status.ctypes.data), _stream(None)))
     return samples, status

@@ -1,6 +1,8 @@
 """GPU: autotuned grids (qflex_options.autotune = 1).  Every kernel variant the tuner may pick
 computes the same products, so tuned results must match the FP64 oracle to the same bounds;
 a tuned grid in graph mode tunes on its first call, captures on the next and replays after."""
+import ctypes
+
 import numpy as np
 import pytest
 
@@ -74,3 +76,39 @@ def test_autotuned_gradients_match_state_vector_adjoint():
             rows = [j for j, gt in enumerate(c["gates"]) if gt["kind"] == "fsim"]
             assert metrics.rel_l2(res["grad_params"][i][rows], g_ref) < 1e-3, (rep, i)
             assert abs(res["loss"][i] - f_ref) < 1e-4 * max(1.0, abs(f_ref)), (rep, i)
+
+
+def test_autotune_cache_reproduces_choices(tmp_path):
+    """A grid that tunes fills the process-wide table; saved, cleared and loaded again, it lets
+    a new grid take the same kernels without timing any (n_tuned = 0), bit for bit the same
+    amplitudes, in complex64 and split-bf16."""
+    import torch
+
+    from paper_1811_09599_amd import _ffi as F
+
+    _need_gpu()
+    L = F.lib()
+    c = R.grid_rqc(5, 4, 32, 5432)
+    op = [19, 18, 15]
+    bits = R.bitstrings(20, 5, 41, op)
+    for precision in ("c64", "split_bf16"):
+        _say("autotune cache,", precision)
+        L.qflex_autotune_cache_clear()
+        g1 = build_grid(c, plan="quadrant", open_qubits=op, precision=precision, autotune=True)
+        a1 = g1.contract_amplitudes(bits)
+        assert g1.last_stats()["n_tuned"] > 0
+        n_entries = L.qflex_autotune_cache_size()
+        assert n_entries > 0
+        path = str(tmp_path / ("tune_%s.txt" % precision)).encode()
+        F.check(L.qflex_autotune_cache_save(path))
+        L.qflex_autotune_cache_clear()
+        n = ctypes.c_int64(0)
+        F.check(L.qflex_autotune_cache_load(path, ctypes.byref(n)))
+        assert n.value == n_entries
+        g2 = build_grid(c, plan="quadrant", open_qubits=op, precision=precision, autotune=True)
+        a2 = g2.contract_amplitudes(bits)
+        assert g2.last_stats()["n_tuned"] == 0
+        assert torch.equal(a1, a2)
+        g1.close()
+        g2.close()
+    L.qflex_autotune_cache_clear()

@@ -121,6 +121,36 @@ def test_6x6_gradient_vs_autograd_oracle():
     assert abs(res["loss"][0] - f_ref) < 1e-4 * max(1.0, abs(f_ref))
 
 
+def test_7x7_one_slice_gradient_vs_autograd_oracle():
+    """7x7 fSim depth 1+16+1 (bond 16): the quadrant plan with two cuts, one slice, a 64-amplitude
+    open batch and a random cotangent.  The adjoint keeps only its checkpoints (the plan's
+    gradient layout has several segments, each recomputed before it is reversed) and matches
+    the FP64 autograd oracle on that slice."""
+    from paper_1811_09599_amd import plan_describe
+
+    _need_gpu()
+    _say("7x7 fSim one-slice grad vs E3")
+    c = R.grid_rqc(7, 7, 16, 7700, two_qubit="fsim", jitter_sd=0.02, jitter_seed=77)
+    op = R.grid_ids((7, 7), [(5, 0), (5, 1), (5, 2), (6, 0), (6, 1), (6, 2)])
+    lay = plan_describe(c, open_qubits=op)["grad"]
+    assert len(lay["segments"]) >= 2 and lay["recompute_flops"] > 0
+    assert 2 * lay["elems"] < lay["store_all_elems"]
+    bits = R.bitstrings(49, 1, 7701, op)
+    rng = np.random.default_rng(5)
+    cot = rng.standard_normal((1, 64)) + 1j * rng.standard_normal((1, 64))
+    g = build_grid(c, open_qubits=op)
+    res = g.contract_grad(bits, cotangent=cot, slice_ids=[37])
+    cuts = g.plan_cuts()
+    order = E2.quadrant_order(7, 7)
+    ref = E2.amplitude_gate_grads(c, bits, cot, op, cuts, [37], order=order)
+    got = res["grad_params"][0][_fsim_rows(c)]
+    err = metrics.rel_l2(got, ref)
+    _say("  rel err", err)
+    assert err < GTOL
+    amp_ref = E2.amplitudes(c, bits, op, cuts=cuts, slice_ids=[37], order=order)
+    assert metrics.amp_errors(res["amps"], amp_ref, 49)["max"] < 1e-5
+
+
 def test_autograd_function_fits_angles():
     _need_gpu()
     import torch

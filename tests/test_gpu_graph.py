@@ -62,3 +62,64 @@ def test_graph_mode_with_many_circuits():
         want = ge.contract_amplitudes(bits).cpu().numpy()
         got = gg.contract_amplitudes(bits).cpu().numpy()
         assert np.array_equal(got, want), rep
+
+
+def test_graph_mode_on_the_callers_stream():
+    """A grid in graph mode captures and replays on a caller's stream that is not the null
+    stream (no stream of its own in between); replays equal eager launches bit for bit."""
+    _need_gpu()
+    import torch
+    _say("graph replay on a side stream")
+    c = R.grid_rqc(4, 4, 16, 1001)
+    ge = build_grid(c)
+    gg = build_grid(c, graph=True)
+    side = torch.cuda.Stream()
+    for rep in range(4):
+        bits = R.bitstrings(16, 64, 1500 + rep)
+        want = ge.contract_amplitudes(bits).cpu().numpy()
+        with torch.cuda.stream(side):
+            got = gg.contract_amplitudes(bits)
+        side.synchronize()
+        assert np.array_equal(got.cpu().numpy(), want), rep
+    ge.close()
+    gg.close()
+
+
+@pytest.mark.parametrize("side_stream", [False, True])
+def test_gradient_graph_replays_match_eager(side_stream):
+    """qflex_contract_grad in graph mode (one slice per circuit: 10 uneven fSim circuits, no
+    cuts): the first call captures, later calls with new bit-strings and cotangents replay.
+    Amplitudes equal the eager call's bit for bit; gradients and cross-entropies agree to
+    1e-12 (their FP64 sums are atomic, so their order may differ)."""
+    _need_gpu()
+    import torch
+    _say("gradient graph replay, side stream:", side_stream)
+    cs = R.fsim_batch(10, depth=12, sizes=(3, 4), seed=9400, jitter_seed0=9500)
+    ge = build_grid(cs)
+    gg = build_grid(cs, graph=True)
+    side = torch.cuda.Stream() if side_stream else None
+    x = torch.randn(256, 256, device="cuda")
+    rng = np.random.default_rng(9)
+    for rep in range(4):
+        bits = [R.bitstrings(c["n_qubits"], 12, 9600 + 17 * rep + i) for i, c in enumerate(cs)]
+        cot = None
+        if rep == 3:  # a given cotangent: a graph of its own
+            cot = rng.standard_normal((120, 1)) + 1j * rng.standard_normal((120, 1))
+        want = ge.contract_grad(bits, cotangent=cot)
+        if side is not None:
+            with torch.cuda.stream(side):
+                got = gg.contract_grad(bits, cotangent=cot)
+            side.synchronize()
+        else:
+            got = gg.contract_grad(bits, cotangent=cot)
+        assert np.array_equal(np.asarray(got["amps"]), np.asarray(want["amps"])), rep
+        for i in range(len(cs)):
+            gw, gr = np.asarray(want["grad_params"][i]), np.asarray(got["grad_params"][i])
+            assert np.linalg.norm(gr - gw) <= 1e-12 * max(np.linalg.norm(gw), 1e-300), (rep, i)
+        if cot is None:
+            assert np.allclose(got["loss"], want["loss"], rtol=1e-12, atol=1e-14), rep
+        y = x @ x  # unrelated eager work between replays
+        torch.cuda.synchronize()
+        assert torch.isfinite(y).all()
+    ge.close()
+    gg.close()

@@ -134,3 +134,37 @@ def test_fidelity_samples_match_oracle():
     _, sv_st = S.fidelity_samples(sv, closed, op, coins, uniform, order, u, 16, 10.0, f)
     assert np.mean(np.array(sv_st) == status) >= 0.99
     g.close()
+
+
+def test_fidelity_samples_checks_arguments_before_any_launch():
+    """An order value outside the open batch in an exact batch, a fidelity outside [0, 1] or a
+    grid of several circuits is rejected on the host; the same value in a batch that is not
+    exact is never read.  No batch at all returns empty results."""
+    from paper_1811_09599_amd import _ffi as F
+
+    _need_gpu()
+    _say("fidelity-f samples: argument checks")
+    c = R.grid_rqc(4, 4, 16, 1001)
+    op = [12, 13, 14, 15]
+    g = build_grid(c, open_qubits=op)
+    closed = R.bitstrings(16, 4, 1700, op)
+    uniform = R.bitstrings(16, 4, 1701)
+    order, u = R.sampling_draws(4, 16, 16, 1702)
+    coins = np.array([0.1, 0.9, 0.1, 0.9])
+    bad = order.copy()
+    bad[1, 3] = 16  # batch 1 is not exact at f = 0.5: never read
+    samples, status = fidelity_samples(g, closed, coins, uniform, bad, u, 0.5)
+    assert status[1] == 0 and samples[1].tolist() == uniform[1].tolist()
+    bad[0, 3] = 16  # batch 0 is exact
+    with pytest.raises(F.QflexError) as e:
+        fidelity_samples(g, closed, coins, uniform, bad, u, 0.5)
+    assert e.value.status == F.E_INVALID
+    with pytest.raises(F.QflexError):
+        fidelity_samples(g, closed, coins, uniform, order, u, 1.5)
+    s0, st0 = fidelity_samples(g, closed[:0], coins[:0], uniform[:0], order[:0], u[:0], 0.5)
+    assert s0.shape == (0, 16) and st0.shape == (0,)
+    g.close()
+    g2 = build_grid([c, c], open_qubits=op)
+    with pytest.raises(F.QflexError):
+        fidelity_samples(g2, closed, coins, uniform, order, u, 0.5)
+    g2.close()

@@ -253,9 +253,10 @@ def test_block_slice_subset_matches_oracle(total, f, seed):
 
 def test_gemm_variant_choice():
     L = F.lib()
-    assert L.qflex_gemm_variant(4096, 4096, 4096) == 6  # 512 tiles of 256x128
-    assert L.qflex_gemm_variant(4096, 2048, 16) == 6    # 256 tiles: one per compute unit
-    assert L.qflex_gemm_variant(2048, 2048, 16) == 2    # 128: 128x128 tiles instead
+    # the 256x128 and 128x128 tiles in the 3-multiplication form
+    assert L.qflex_gemm_variant(4096, 4096, 4096) == 9  # 512 tiles of 256x128
+    assert L.qflex_gemm_variant(4096, 2048, 16) == 9    # 256 tiles: one per compute unit
+    assert L.qflex_gemm_variant(2048, 2048, 16) == 10   # 128: 128x128 tiles instead
     assert L.qflex_gemm_variant(4096, 4096 + 64, 16) == 1
     assert L.qflex_gemm_variant(64, 64, 16) == 1
     assert L.qflex_gemm_variant(64, 8, 256) == 0
@@ -311,6 +312,33 @@ def test_noalloc_split_product_checks_run_before_any_launch():
     assert call(M=96) == F.E_INVALID
     assert call(A=C.c_void_p((1 << 20) + 8)) == F.E_INVALID
     assert call(batch=0) == F.E_INVALID
+
+
+def test_autotune_cache_file_round_trip(tmp_path):
+    """The autotuner's table: loading a file merges its entries, saving writes them back line
+    for line, a malformed file is rejected and leaves the table as it was."""
+    L = F.lib()
+    L.qflex_autotune_cache_clear()
+    assert L.qflex_autotune_cache_size() == 0
+    lines = ["gfx950_cu256|c64|4096x4096x4096|t00|b1|ws0 9",
+             "gfx950_cu256|splitbf|65536x256x256|b8|g11|q01|c0 6",
+             "gfx942_cu304|c64|256x16x65536|t10|b25|ws1 8"]
+    src = tmp_path / "tune.txt"
+    src.write_text("\n".join(lines) + "\n")
+    n = C.c_int64(-1)
+    F.check(L.qflex_autotune_cache_load(str(src).encode(), C.byref(n)))
+    assert n.value == 3 and L.qflex_autotune_cache_size() == 3
+    out = tmp_path / "out.txt"
+    F.check(L.qflex_autotune_cache_save(str(out).encode()))
+    assert sorted(out.read_text().splitlines()) == sorted(lines)
+    for bad in ("key 3\nbroken\n", "key -1\n", "key 2 extra\n"):
+        (tmp_path / "bad.txt").write_text(bad)
+        assert L.qflex_autotune_cache_load(str(tmp_path / "bad.txt").encode(), None) == F.E_INVALID
+        assert L.qflex_autotune_cache_size() == 3
+    assert L.qflex_autotune_cache_load(str(tmp_path / "missing.txt").encode(), None) == F.E_INVALID
+    assert L.qflex_autotune_cache_load(None, None) == F.E_INVALID
+    L.qflex_autotune_cache_clear()
+    assert L.qflex_autotune_cache_size() == 0
 
 
 def test_split_k_workspace_only_for_reduction_shapes():
