@@ -169,6 +169,18 @@ typedef struct {
 qflex_status qflex_build_grid(const qflex_circuit* circuits, int32_t n_circuits,
                               const qflex_options* opt, void* stream, qflex_grid** out);
 
+/* Replace the gates of circuit `circuit` of a grid by those of `updated` and collapse its qubit
+ * tensors along time again (Methods B.1), e.g. for new fSim angles in a fitting loop.  The
+ * update must keep the circuit's structure: the same qubits and coordinates, and gates of the
+ * same kinds on the same qubits in the same cycles and order, with the same bond ranks (an fSim
+ * gate whose off-diagonal blocks become exactly zero, theta = 0, changes rank).  The plan,
+ * the autotuner's choices, graphs and buffers are kept; intermediates kept from earlier calls
+ * are dropped.  stream: as for qflex_build_grid; the call returns when the tensors are
+ * rebuilt.  QFLEX_E_INVALID (the grid unchanged) for a bad index, an invalid circuit or a
+ * different structure. */
+qflex_status qflex_update_gates(qflex_grid* g, int32_t circuit, const qflex_circuit* updated,
+                                void* stream);
+
 /* Number of slices S (paths) of circuit `circuit`'s plan (1 when it has no cuts). */
 qflex_status qflex_num_slices(const qflex_grid* g, int32_t circuit, int64_t* total);
 

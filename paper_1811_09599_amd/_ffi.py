@@ -44,7 +44,7 @@ class KernelStat(C.Structure):
                 ("flops", C.c_double), ("bytes", C.c_double)]
 
 
-EXPORTS = ("qflex_build_grid", "qflex_num_slices", "qflex_plan_cuts", "qflex_plan_describe",
+EXPORTS = ("qflex_build_grid", "qflex_update_gates", "qflex_num_slices", "qflex_plan_cuts", "qflex_plan_describe",
            "qflex_contract_amplitudes", "qflex_contract_grad", "qflex_last_stats",
            "qflex_set_profiling",
            "qflex_profile_read", "qflex_permute_c64", "qflex_gemm_split_c64",
@@ -85,6 +85,7 @@ def lib():
     L.qflex_build_grid.argtypes = [C.POINTER(Circuit), C.c_int32, C.POINTER(Options), P,
                                    C.POINTER(P)]
     L.qflex_num_slices.argtypes = [P, C.c_int32, C.POINTER(C.c_int64)]
+    L.qflex_update_gates.argtypes = [P, C.c_int32, C.POINTER(Circuit), P]
     L.qflex_plan_cuts.argtypes = [P, C.c_int32, C.POINTER(C.c_int32), C.c_int32,
                                   C.POINTER(C.c_int32)]
     L.qflex_plan_describe.argtypes = [C.POINTER(Circuit), C.POINTER(Options), C.c_char_p,

@@ -195,6 +195,14 @@ qflex_status qflex_build_grid(const qflex_circuit* circuits, int32_t n_circuits,
   });
 }
 
+qflex_status qflex_update_gates(qflex_grid* g, int32_t circuit, const qflex_circuit* updated,
+                                void* stream) {
+  return guarded([&] {
+    if (!g || !updated) qflex::fail(QFLEX_E_INVALID, "NULL argument");
+    qflex::update_gates(g, circuit, *updated, static_cast<hipStream_t>(stream));
+  });
+}
+
 qflex_status qflex_num_slices(const qflex_grid* g, int32_t circuit, int64_t* total) {
   return guarded([&] {
     if (!g || !total) qflex::fail(QFLEX_E_INVALID, "NULL argument");

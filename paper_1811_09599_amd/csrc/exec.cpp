@@ -101,6 +101,7 @@ void Profiler::release() {
 
 // ------------------------------------------------------------------------------ grid build
 void prepare_split(qflex_grid* g, hipStream_t s);
+void split_qubits(qflex_grid* g, int c, hipStream_t s);
 
 // A complex64 tall-skinny product whose intermediate x would be permuted first: the MFMA rows
 // kernel reads x in its own storage order instead, when x's 2 lowest storage labels are
@@ -277,6 +278,7 @@ void prepare_split(qflex_grid* g, hipStream_t s) {
   int64_t n_slots = 2;
   int64_t n_node_slots = 0;
   struct Job {
+    int circuit;
     int64_t src, dst;
     int nfixed, nbits, kbits;
     bool role_b;
@@ -371,8 +373,8 @@ void prepare_split(qflex_grid* g, hipStream_t s) {
         const PermDesc pd = make_perm_desc(in, want);
         if (o.qubit) {
           const QubitLayout& L = P.qubits[o.id];
-          Job j{cs.grid_offset + cs.qubit_offset[o.id], total, L.n_fixed, L.free_bits(), st.kb,
-                side == 1, pd, f16 ? n_slots : -1};
+          Job j{(int)(&cs - &g->circ[0]), cs.grid_offset + cs.qubit_offset[o.id], total,
+                L.n_fixed, L.free_bits(), st.kb, side == 1, pd, f16 ? n_slots : -1};
           if (f16) cs.qamax_slot[o.id] = n_slots++;
           cs.qsplit_offset[o.id] = total;
           total += ((int64_t(4) << L.storage.size()) + 63) & ~int64_t(63);
@@ -399,17 +401,81 @@ void prepare_split(qflex_grid* g, hipStream_t s) {
       dev::fill_zero(reinterpret_cast<double*>(g->node_amax), n_node_slots, s);
     }
   }
+  g->qsplit_jobs.clear();
   if (total == 0) return;
   QHIP(hipMalloc(&g->grid_split, sizeof(uint16_t) * total));
   for (const Job& j : jobs) {
-    const dev::PermTile t = dev::make_perm_tile(j.nbits, j.pd.perm.data());
+    QubitSplitJob q;
+    q.circuit = j.circuit;
+    q.src = j.src;
+    q.dst = j.dst;
+    q.nfixed = j.nfixed;
+    q.nbits = j.nbits;
+    q.kbits = j.kbits;
+    q.tile = dev::make_perm_tile(j.nbits, j.pd.perm.data());
+    q.slot = j.slot;
+    g->qsplit_jobs.push_back(q);
+  }
+  split_qubits(g, -1, s);
+  QHIP(hipStreamSynchronize(s));
+}
+
+// Pre-split the qubit tensors of circuit c (every circuit for c < 0) for 16-bit products.
+void split_qubits(qflex_grid* g, int c, hipStream_t s) {
+  for (const QubitSplitJob& j : g->qsplit_jobs) {
+    if (c >= 0 && j.circuit != c) continue;
     const int64_t n = int64_t(1) << (j.nfixed + j.nbits);
     uint64_t* slot = j.slot >= 0 ? g->amax + j.slot : nullptr;
-    // one scale per qubit tensor, over every value of its fixed (bit-string / cut) indexes
-    if (slot) dev::absmax(g->grid + j.src, n, slot, next_amax_tag(g, s), s);
-    dev::split_permute(g->grid + j.src, g->grid_split + j.dst, int64_t(1) << j.nfixed, t,
+    // one scale per qubit tensor, over every value of its fixed (bit-string / cut) indexes;
+    // the slot is cleared first, since its previous tag may exceed the next one after a wrap
+    if (slot) {
+      dev::fill_zero(reinterpret_cast<double*>(slot), 1, s);
+      dev::absmax(g->grid + j.src, n, slot, next_amax_tag(g, s), s);
+    }
+    dev::split_permute(g->grid + j.src, g->grid_split + j.dst, int64_t(1) << j.nfixed, j.tile,
                        j.kbits, slot, s);
   }
+}
+
+void update_gates(qflex_grid* g, int c, const qflex_circuit& circuit, hipStream_t s) {
+  if (c < 0 || c >= (int)g->circ.size()) fail(QFLEX_E_INVALID, "bad circuit index");
+  CircuitState& cs = g->circ[c];
+  Model m = build_model(circuit);
+  const Model& o = cs.model;
+  // the plan, the tensor layouts and the piece tables hold as long as the structure does
+  bool same = m.n == o.n && m.xy == o.xy && m.gates.size() == o.gates.size() &&
+              m.links.size() == o.links.size() && m.mats.size() == o.mats.size() &&
+              m.timeline.size() == o.timeline.size();
+  for (size_t i = 0; same && i < m.gates.size(); ++i) {
+    const Gate &a = m.gates[i], &b = o.gates[i];
+    same = a.cycle == b.cycle && a.kind == b.kind && a.q0 == b.q0 && a.q1 == b.q1;
+  }
+  for (size_t l = 0; same && l < m.links.size(); ++l)
+    same = m.links[l].lo == o.links[l].lo && m.links[l].hi == o.links[l].hi &&
+           m.links[l].gate_ids == o.links[l].gate_ids && m.links[l].rank == o.links[l].rank;
+  for (size_t q = 0; same && q < m.timeline.size(); ++q) {
+    same = m.timeline[q].size() == o.timeline[q].size();
+    for (size_t i = 0; same && i < m.timeline[q].size(); ++i) {
+      const Piece &a = m.timeline[q][i], &b = o.timeline[q][i];
+      same = a.gate == b.gate && a.link == b.link && a.kbits == b.kbits && a.koff == b.koff &&
+             a.mat == b.mat && a.hi_side == b.hi_side;
+    }
+  }
+  if (!same)
+    fail(QFLEX_E_INVALID, "the updated circuit differs in structure (qubits, couplers, cycles, "
+                          "kinds or bond ranks); build a new grid for it");
+  std::vector<double2> mats;
+  for (const cdouble& z : m.mats) mats.push_back(make_double2(z.real(), z.imag()));
+  // nothing kept from earlier calls depends on the old tensors after this
+  g->resume.valid = false;
+  QHIP(hipMemcpyAsync(static_cast<double2*>(g->gmats.p) + 4 * (int64_t)cs.mat_base, mats.data(),
+                      sizeof(double2) * mats.size(), hipMemcpyHostToDevice, s));
+  dev::grid_build(static_cast<const dev::GridQubit*>(g->gq.p) + cs.qdesc_base, m.n, cs.max_nlb,
+                  static_cast<const dev::GridPiece*>(g->gpieces.p),
+                  static_cast<const double2*>(g->gmats.p), static_cast<const int32_t*>(g->gpos.p),
+                  g->grid, s);
+  if (g->grid_split) split_qubits(g, c, s);
+  cs.model = std::move(m);
   QHIP(hipStreamSynchronize(s));
 }
 

@@ -84,6 +84,16 @@ struct Profiler {
   void release();
 };
 
+// Pre-split of one qubit tensor for 16-bit products (made at grid build, repeated when the
+// circuit's gates are updated).
+struct QubitSplitJob {
+  int circuit = 0;
+  int64_t src = 0, dst = 0;  // grid element offset, grid_split offset (16-bit values)
+  int nfixed = 0, nbits = 0, kbits = 0;
+  dev::PermTile tile;
+  int64_t slot = -1;         // fp16 scale slot, -1 for bf16
+};
+
 struct HostPinned {
   void* p = nullptr;
   size_t bytes = 0;
@@ -143,6 +153,7 @@ struct qflex_grid {
   uint32_t amax_tag = 0;
   // time-collapse descriptors, kept for the adjoint of the grid build
   qflex::DevBuf gq, gpieces, gmats, gpos;
+  std::vector<qflex::QubitSplitJob> qsplit_jobs;
   int64_t n_mats = 0;
   int max_pieces = 0;                    // longest qubit time line
   // gradient buffers
@@ -164,6 +175,10 @@ struct qflex_grid {
 
 namespace qflex {
 void build_grid_device(qflex_grid* g, hipStream_t s);
+// New gates for circuit c (same qubits, couplers, cycles, kinds and bond ranks): its qubit
+// tensors are collapsed again (and split again for 16-bit products); plan, tuned kernels and
+// buffers stay.
+void update_gates(qflex_grid* g, int c, const qflex_circuit& circuit, hipStream_t s);
 // Host checks of a contract call, the slices each circuit sums, and the upload of the
 // per-bit-string output offsets (g->offs); everything contract() does before its launches.
 std::vector<std::vector<int64_t>> prepare_call(qflex_grid* g, const uint8_t* bits,

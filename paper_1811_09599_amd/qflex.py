@@ -115,6 +115,13 @@ class Grid:
         except Exception:
             pass
 
+    def update_gates(self, circuit_dict: dict, circuit: int = 0, stream=None):
+        """qflex_update_gates: new gates (same structure) for circuit `circuit`; its qubit
+        tensors are collapsed again, the plan and tuned kernels are kept."""
+        pack = _CircuitPack([circuit_dict])
+        F.check(F.lib().qflex_update_gates(self._h, int(circuit), pack.arr, _stream(stream)))
+        self.circuits[circuit] = circuit_dict
+
     def num_slices(self, circuit: int = 0) -> int:
         t = C.c_int64()
         F.check(F.lib().qflex_num_slices(self._h, circuit, C.byref(t)))
@@ -297,17 +304,42 @@ try:
         ``angles`` ([n_fsim, 2] real tensor of (theta, phi)); differentiable in ``angles``
         through the adjoint contraction of libqflex."""
 
+        # grids by circuit structure: a fitting loop changes only angles, so the plan and the
+        # tensor layouts of its first call serve every later one (qflex_update_gates)
+        _grids: dict = {}
+
+        @staticmethod
+        def _grid(circ, open_qubits, plan):
+            key = (circ["n_qubits"], tuple(tuple(p) for p in circ["xy"]),
+                   tuple((g["cycle"], g["kind"], tuple(g["qubits"])) for g in circ["gates"]),
+                   tuple(open_qubits), plan)
+            grid = Amplitudes._grids.get(key)
+            if grid is not None:
+                try:
+                    grid.update_gates(circ)
+                    return grid
+                except F.QflexError:  # a rank change (e.g. theta = 0): build anew
+                    Amplitudes._grids.pop(key, None)
+            grid = Grid(circ, plan=plan, open_qubits=open_qubits)
+            if len(Amplitudes._grids) >= 4:
+                Amplitudes._grids.pop(next(iter(Amplitudes._grids)))
+            Amplitudes._grids[key] = grid
+            return grid
+
         @staticmethod
         def forward(ctx, angles, circuit, bits, open_qubits=(), plan="auto"):
             circ = with_fsim_angles(circuit, angles.detach().cpu().numpy())
-            grid = Grid(circ, plan=plan, open_qubits=open_qubits)
+            grid = Amplitudes._grid(circ, open_qubits, plan)
             ctx.grid, ctx.bits, ctx.rows = grid, np.asarray(bits, np.uint8), _fsim_rows(circ)
+            ctx.circ = circ
             ctx.dtype, ctx.device = angles.dtype, angles.device
             amps = grid.contract_amplitudes(ctx.bits, device=torch.cuda.is_available())
             return amps.to(angles.device) if hasattr(amps, "to") else torch.from_numpy(amps)
 
         @staticmethod
         def backward(ctx, grad_amps):
+            if ctx.grid.circuits[0] is not ctx.circ:  # a later forward updated the shared grid
+                ctx.grid.update_gates(ctx.circ)
             res = ctx.grid.contract_grad(ctx.bits, cotangent=grad_amps)
             gp = torch.from_numpy(res["grad_params"][0][ctx.rows]).to(ctx.dtype).to(ctx.device)
             return gp, None, None, None, None

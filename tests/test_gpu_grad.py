@@ -213,3 +213,61 @@ def test_autotuned_gradient_matches_shape_rule_gradient():
     assert abs(r_t[1]["loss"][0] - f_ref) < 1e-4 * max(1.0, abs(f_ref))
     tuned.close()
     plain.close()
+
+
+@pytest.mark.parametrize("precision", ["c64", "split_bf16", "split_fp16"])
+def test_update_gates_matches_a_fresh_grid(precision):
+    """qflex_update_gates: the same fSim circuit with other angles, collapsed again in place,
+    gives the amplitudes a grid built for it gives, bit for bit (same plan, same kernels); a
+    circuit of another structure is rejected and leaves the grid as it was."""
+    import torch
+
+    from paper_1811_09599_amd import _ffi as F
+    from paper_1811_09599_amd.qflex import with_fsim_angles
+
+    _need_gpu()
+    _say("update gates,", precision)
+    c = R.grid_rqc(4, 4, 12, 4343, two_qubit="fsim", jitter_sd=0.02, jitter_seed=43)
+    op = [15, 14]
+    bits = R.bitstrings(16, 8, 44, op)
+    rng = np.random.default_rng(45)
+    c2 = with_fsim_angles(c, R.fsim_params(c) + rng.normal(0, 0.3, R.fsim_params(c).shape))
+    g = build_grid(c, plan="quadrant", open_qubits=op, precision=precision)
+    before = g.contract_amplitudes(bits, fidelity=0.5, seed=3)
+    g.update_gates(c2)
+    got = g.contract_amplitudes(bits, fidelity=0.5, seed=3)
+    fresh = build_grid(c2, plan="quadrant", open_qubits=op, precision=precision)
+    want = fresh.contract_amplitudes(bits, fidelity=0.5, seed=3)
+    assert torch.equal(got, want)
+    assert not torch.equal(got, before)
+    cz = R.grid_rqc(4, 4, 12, 4343)  # CZ couplers: other kinds and ranks
+    with pytest.raises(F.QflexError) as e:
+        g.update_gates(cz)
+    assert e.value.status == F.E_INVALID
+    assert torch.equal(g.contract_amplitudes(bits, fidelity=0.5, seed=3), want)
+    g.close()
+    fresh.close()
+
+
+def test_autograd_function_reuses_its_grid_across_angles():
+    """Two forward passes at different angles share one grid (the second updates its gates);
+    the backward pass of the first still differentiates at its own angles."""
+    _need_gpu()
+    import torch
+    from paper_1811_09599_amd import Amplitudes
+    from paper_1811_09599_amd.qflex import with_fsim_angles
+    _say("autograd, shared grid")
+    c = R.grid_rqc(3, 3, 12, 4242, two_qubit="fsim", jitter_sd=0.02, jitter_seed=42)
+    bits = R.bitstrings(9, 16, 9)
+    p0 = R.fsim_params(c)
+    p1 = p0 + 0.1
+    a0 = torch.tensor(p0, dtype=torch.float64, requires_grad=True)
+    a1 = torch.tensor(p1, dtype=torch.float64, requires_grad=True)
+    f0 = (2.0 ** 9) * torch.mean(Amplitudes.apply(a0, c, bits).abs() ** 2) - 1.0
+    f1 = (2.0 ** 9) * torch.mean(Amplitudes.apply(a1, c, bits).abs() ** 2) - 1.0
+    f0.backward()
+    f1.backward()
+    for a, p, f in ((a0, p0, f0), (a1, p1, f1)):
+        f_ref, g_ref = E1.linear_xeb_grad(with_fsim_angles(c, p), bits)
+        assert abs(float(f.detach()) - f_ref) < 1e-4
+        assert metrics.rel_l2(a.grad.numpy(), g_ref) < GTOL
