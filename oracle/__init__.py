@@ -11,8 +11,9 @@ Engines (FP64 throughout):
   E3  ``tn.linear_xeb_grad`` gradient of linear cross-entropy by autograd through E2.
 ``slices`` draws the seeded fraction of paths; ``metrics`` holds the error measures;
 ``sampling`` is the fast frugal rejection sampler over open-qubit batches and its error
-estimate.
+estimate; ``gf2`` gives exact per-path amplitudes of CZ-only circuits at any size (exponential
+sums of quadratic forms over GF(2)).
 Every function is pinned by a test under ``tests/`` against something other than itself
 (closed forms, special cases, the other engine, finite differences, the paper's numbers).
 """
-from . import gates, metrics, sampling, slices, statevector, tn  # noqa: F401
+from . import gates, gf2, metrics, sampling, slices, statevector, tn  # noqa: F401

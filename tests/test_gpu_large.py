@@ -153,3 +153,40 @@ def test_diamond70_rqc_split_bf16_agrees_with_c64_on_a_slice():
     e = metrics.amp_errors(res["split_bf16"], res["c64"], 70)
     _say("  split vs c64", e)
     assert e["max"] < SPLIT_TOL_D32
+
+
+# A CZ-only circuit (every X^1/2, Y^1/2 and T removed) keeps the bond dimensions, the plan and
+# every product of the 7x7 1+40+1 workload (5 CZ per link, bond 32, 1024 slices), but each of
+# its paths has an exact closed form at 49 qubits (oracle/gf2.py): an entangled state, unlike
+# the product state of identity couplings.  Paths whose cut gates' k differ vanish; of the four
+# others, two carry these bit-strings' amplitudes, whose entries partly cancel between paths.
+CZ_BITS_SEEDS = (3503, 3506, 3510)
+CZ_SLICES = (0, 31, 992, 1023, 500)
+
+
+@pytest.mark.parametrize("precision,tol", [("c64", 1e-5), ("split_bf16", SPLIT_TOL_D32),
+                                           ("split_fp16", SPLIT_FP16_TOL_PRODUCT_STATE)])
+def test_d32_cz_only_slices_match_gf2_closed_form(precision, tol):
+    from oracle import gf2
+
+    _need_gpu()
+    _say("7x7 1+40+1 CZ-only, closed form per slice,", precision)
+    c = R.without_kinds(R.grid_rqc(7, 7, 40, 3000), ("x12", "y12", "t"))
+    bits = np.concatenate([R.bitstrings(49, 1, s, OPEN7) for s in CZ_BITS_SEEDS])
+    g = build_grid(c, open_qubits=OPEN7, precision=precision)
+    assert g.num_slices() == 1024
+    cuts = g.plan_cuts()
+    refs = {s: gf2.cz_only_slice_amplitudes(c, bits, OPEN7, cuts, s) for s in CZ_SLICES}
+    scale = 2.0 ** 24.5  # 2^(n/2)
+    rms = np.sqrt(np.mean(np.concatenate([np.abs(r.ravel()) ** 2 for r in refs.values()])))
+    assert sum(np.count_nonzero(r) for r in refs.values()) >= 16
+    for s in CZ_SLICES:
+        a = g.contract_amplitudes(bits, slice_ids=[s]).cpu().numpy()
+        ref = refs[s]
+        # the error of every entry against the larger of its reference and the rms over all
+        # the slices' entries (a vanishing path has only zeros)
+        e = np.abs(a - ref) / np.maximum(np.abs(ref), rms)
+        _say("  slice", s, "non-zero", np.count_nonzero(ref), "max error", e.max(),
+             "scaled rms", rms * scale)
+        assert e.max() < tol, s
+    g.close()
