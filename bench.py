@@ -49,6 +49,10 @@ OPEN_PATCH = [(5, 0), (5, 1), (5, 2), (6, 0), (6, 1), (6, 2)]
 FIDELITY = 1.0 / 64
 
 
+# key of the headline workload in the committed HBM-traffic summaries
+HEADLINE_WORKLOAD = "7x7_depth40_bond32_f1-64"
+
+
 def flop_peak(name):
     """The arithmetic peak a kernel's algorithmic flops are measured against, from its name:
     a product is priced at the peak of the MFMA type it runs on."""
@@ -75,10 +79,11 @@ def mfma_work_factor(name):
     return 1.0
 
 
-def roofline(prof):
+def roofline(prof, workload=None):
     """Roofline of the kernel with the most time: its algorithmic flops (8 per complex
     multiply-add) and bytes per launch, recorded by the library with each launch, over its
-    average launch time; the bound is the resource the kernel uses the larger fraction of."""
+    average launch time; the bound is the resource the kernel uses the larger fraction of.
+    `traffic` is the counted HBM bytes per launch of that kernel on `workload`, if measured."""
     name = max(prof, key=lambda k: prof[k]["ms"])
     k = prof[name]
     sec = k["ms"] * 1e-3
@@ -92,7 +97,7 @@ def roofline(prof):
     else:
         bound, achieved, peak, unit = kind, tflops, fpeak, "TFLOP/s"
     r = {"bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": unit,
-         "frac": round(achieved / peak, 4), "traffic": measured_traffic(name),
+         "frac": round(achieved / peak, 4), "traffic": measured_traffic(name, workload),
          "flop_frac": round(flop_frac, 4), "hbm_frac": round(hbm_frac, 4),
          "avg_launch_us": round(1e3 * k["ms"] / max(k["launches"], 1), 3),
          "launches": k["launches"],
@@ -104,12 +109,12 @@ def roofline(prof):
     return name, r
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` on this workload from the committed counter summaries
-    (profiles/hbm_traffic_*.md, lines "traffic <kernel> <bytes per launch> <source>
-    <sha256 of source>", from two rocprofv3 --pmc passes, FETCH_SIZE and WRITE_SIZE, scaled
-    by what the counters read for a 1 GiB device copy), or None when there is none for it or
-    its kernel source has changed since."""
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` on `workload` from the committed counter summaries
+    (profiles/hbm_traffic_*.md, lines "traffic <workload> <kernel> <bytes per launch>
+    <source> <sha256 of source>", from two rocprofv3 --pmc passes, FETCH_SIZE and WRITE_SIZE,
+    scaled by what the counters read for a 1 GiB device copy), or None when there is none for
+    that pair or the kernel's source has changed since."""
     import glob
     import hashlib
 
@@ -117,14 +122,15 @@ def measured_traffic(kernel):
         with open(path) as f:
             for line in f:
                 w = line.split()
-                if len(w) == 5 and w[0] == "traffic" and w[1] == kernel:
-                    src = os.path.join(ROOT, w[3])
+                if (len(w) == 6 and w[0] == "traffic" and w[1] == workload
+                        and w[2] == kernel):
+                    src = os.path.join(ROOT, w[4])
                     if not os.path.exists(src):
                         return None
                     with open(src, "rb") as fs:
-                        if hashlib.sha256(fs.read()).hexdigest() != w[4]:
+                        if hashlib.sha256(fs.read()).hexdigest() != w[5]:
                             return None
-                    return float(w[2])
+                    return float(w[3])
     return None
 
 
@@ -196,7 +202,7 @@ def run_headline(precision, circ, open_q, bits, ids, args):
     prof = grid.profile_read()
     grid.set_profiling(False)
     grid.close()
-    dom, roof = roofline(prof)
+    dom, roof = roofline(prof, HEADLINE_WORKLOAD)
     amps = args.steps * 64.0 / k  # fidelity-f amplitudes completed
     print("[bench] %s: %d steps in %.2f s (warm-up %.1f s, grid build %.1f s)"
           % (precision, args.steps, dt, warm_s, build_s), file=sys.stderr, flush=True)
@@ -428,8 +434,9 @@ def main():
     xargs = argparse.Namespace(**vars(args))
     xargs.steps, xargs.warmup = min(args.steps, 3), min(args.warmup, 1)
     args = xargs
-    if "cfg2" in extras:
-        res["cfg2_7x7_d16"] = run_cfg2(args, "split_bf16")
+    if "cfg2" in extras:  # the plain complex64 path of that configuration, and split-bf16
+        res["cfg2_7x7_d16"] = run_cfg2(args, "c64")
+        res["cfg2_7x7_d16_split_bf16"] = run_cfg2(args, "split_bf16")
     if "fsim" in extras:
         res["fsim_7x7"] = run_fsim(args, "split_bf16")
     if "sampling" in extras:
