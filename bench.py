@@ -56,9 +56,9 @@ HEADLINE_WORKLOAD = "7x7_depth40_bond32_f1-64"
 def flop_peak(name):
     """The arithmetic peak a kernel's algorithmic flops are measured against, from its name:
     a product is priced at the peak of the MFMA type it runs on."""
-    if name.startswith("gemm_split_bf16"):
+    if name.startswith(("gemm_split_bf16", "gemm_split3m_bf16")):
         return "mfma", PEAK["mfma_bf16"][0]
-    if name.startswith("gemm_split_fp16"):
+    if name.startswith(("gemm_split_fp16", "gemm_split3m_fp16")):
         return "mfma", PEAK["mfma_fp16"][0]
     if name.startswith("gemm_mfma"):
         return "mfma", PEAK["mfma_fp32"][0]
@@ -72,6 +72,8 @@ def mfma_work_factor(name):
     split product of complex parts hi+lo runs 3 real products (hi.hi, hi.lo, lo.hi) per real
     product of the 4-multiplication form; the 3-multiplication (Gauss) form runs 3 real
     products per complex one instead of 4."""
+    if name.startswith("gemm_split3m"):
+        return 2.25
     if name.startswith("gemm_split"):
         return 3.0
     if name.startswith("gemm_mfma3m"):

@@ -43,7 +43,9 @@ int64_t qflex_gemm_c64_workspace(int64_t M, int64_t N, int64_t K, int64_t batch)
 
 /* The same product in split precision: each real part x of a complex64 operand is split into
  * two 16-bit parts, hi = round(x) and lo = round(x - hi); the three products hi*hi + hi*lo +
- * lo*hi run on 16-bit MFMA with FP32 accumulation (lo*lo is dropped).
+ * lo*hi run on 16-bit MFMA with FP32 accumulation (lo*lo is dropped).  The complex product
+ * takes the 3-multiplication form (see qflex_gemm_split_c64_tile) where its tiles fit (M a
+ * multiple of 256 and N of 128, or of 128 and 256), else the packed form.
  *   precision = QFLEX_PREC_SPLIT_BF16: bf16 parts, about 16 significant bits per operand.
  *   precision = QFLEX_PREC_SPLIT_FP16: fp16 parts of the operand times 2^k, k chosen from the
  *     operand's largest magnitude m (over the whole batch) so that m 2^k is in [2^14, 2^15);
@@ -59,6 +61,22 @@ qflex_status qflex_gemm_split_c64(const void* A, const void* B, void* C, int64_t
                                   int32_t precision, void* workspace, int64_t workspace_bytes,
                                   void* stream);
 int64_t qflex_gemm_split_workspace(int64_t M, int64_t N, int64_t K, int64_t batch);
+
+/* qflex_gemm_split_c64 with the kernel's output tile and complex form chosen by the caller (an
+ * autotuner's candidates).  The packed form computes Re C and Im C each as one real product over
+ * 2K terms ([Ar Ai].[Br; -Bi] and [Ar Ai].[Bi; Br]: 12 16-bit MFMAs per 32x32 block and 16
+ * complex k); the 3-multiplication (Gauss) form computes P1 = Ar.Br, P2 = Ai.Bi and
+ * P3 = (Ar + Ai).(Br + Bi) and takes Re C = P1 - P2, Im C = P3 - P1 - P2 (9 MFMAs; Im C's error
+ * grows with |Ar + Ai| |Br + Bi| + |Ar Br| + |Ai Bi| rather than with |A| |B|).
+ *   tile = 0: 256x128, 1: 128x128, 2: 64x64, 3: 128x256, packed form;
+ *          4: 256x128, 5: 128x256, 3-multiplication form;
+ *         -1: the choice qflex_gemm_split_c64 makes.
+ * QFLEX_E_INVALID, nothing launched, for any other tile or one M, N do not fit (multiples of the
+ * tile's sides); every other argument and error as qflex_gemm_split_c64. */
+qflex_status qflex_gemm_split_c64_tile(const void* A, const void* B, void* C, int64_t M,
+                                       int64_t N, int64_t K, int32_t ta, int32_t tb,
+                                       int64_t batch, int32_t precision, int32_t tile,
+                                       void* workspace, int64_t workspace_bytes, void* stream);
 
 /* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
  * loops, harnesses that forbid hipMalloc): qflex_gemm_split_c64 with its workspace taken from a

@@ -48,7 +48,7 @@ EXPORTS = ("qflex_build_grid", "qflex_update_gates", "qflex_num_slices", "qflex_
            "qflex_contract_amplitudes", "qflex_contract_grad", "qflex_last_stats",
            "qflex_set_profiling",
            "qflex_profile_read", "qflex_permute_c64", "qflex_gemm_split_c64",
-           "qflex_gemm_split_c64_noalloc",
+           "qflex_gemm_split_c64_noalloc", "qflex_gemm_split_c64_tile",
            "qflex_gemm_c64", "qflex_select_slices", "qflex_frugal_sample", "qflex_fidelity_samples",
            "qflex_autotune_cache_save", "qflex_autotune_cache_load", "qflex_autotune_cache_size",
            "qflex_autotune_cache_clear",
@@ -120,6 +120,9 @@ def lib():
     L.qflex_gemm_split_workspace.argtypes = [C.c_int64] * 4
     L.qflex_gemm_split_c64_noalloc.argtypes = [P, P, P, C.c_int64, C.c_int64, C.c_int64,
                                                C.c_int32, C.c_int32, C.c_int64, C.c_int32, P]
+    L.qflex_gemm_split_c64_tile.argtypes = [P, P, P, C.c_int64, C.c_int64, C.c_int64,
+                                            C.c_int32, C.c_int32, C.c_int64, C.c_int32,
+                                            C.c_int32, P, C.c_int64, P]
     for name in EXPORTS:
         getattr(L, name).restype = NON_STATUS.get(name, C.c_int)
     _lib = L

@@ -100,9 +100,17 @@ void gemm_split_c64_check(const void* A, const void* B, const void* C, int64_t M
 
 // The split product on a workspace of the caller's (checked, then enqueued on st).
 void gemm_split_c64_run(const void* A, const void* B, void* C, int64_t M, int64_t N, int64_t K,
-                        int32_t ta, int32_t tb, int64_t batch, int32_t precision,
+                        int32_t ta, int32_t tb, int64_t batch, int32_t precision, int32_t tile,
                         void* workspace, int64_t workspace_bytes, hipStream_t st) {
   gemm_split_c64_check(A, B, C, M, N, K, ta, tb, batch, precision);
+  if (tile != -1) {
+    dev::GemmSplit shape;
+    shape.M = M;
+    shape.N = N;
+    shape.K = K;
+    if (tile < 0 || tile >= dev::kSplitTiles || !dev::gemm_split_tile_fits(shape, tile))
+      fail(QFLEX_E_INVALID, "tile out of range or not fitting M, N");
+  }
   if (!workspace) fail(QFLEX_E_INVALID, "NULL argument");
   if (workspace_bytes < qflex_gemm_split_workspace(M, N, K, batch))
     fail(QFLEX_E_INVALID, "workspace too small");
@@ -122,7 +130,7 @@ void gemm_split_c64_run(const void* A, const void* B, void* C, int64_t M, int64_
   if (!tb) pbv = transpose(kb, nb); // stored [K][N] -> [N][K]
   auto* slots = static_cast<uint64_t*>(workspace);
   auto* sa = reinterpret_cast<uint16_t*>(static_cast<char*>(workspace) + kSplitSlotBytes);
-  auto* sb = sa + 4 * batch * M * K;
+  auto* sb = sa + dev::kSplitValues * batch * M * K;
   const bool f16 = precision == QFLEX_PREC_SPLIT_FP16;
   if (f16) {  // the workspace holds anything: clear the slots (a fill kernel), then tag 1
     dev::fill_zero(reinterpret_cast<double*>(slots), 2, st);
@@ -154,6 +162,7 @@ void gemm_split_c64_run(const void* A, const void* B, void* C, int64_t M, int64_
   g.b_bs = N * K;
   g.c_bs = M * N;
   g.batch = (int)batch;
+  g.tile = tile;
   dev::gemm_split(g, st);
 }
 
@@ -370,7 +379,8 @@ qflex_status qflex_gemm_c64(const void* A, const void* B, void* C, int64_t M, in
 
 int64_t qflex_gemm_split_workspace(int64_t M, int64_t N, int64_t K, int64_t batch) {
   if (M < 1 || N < 1 || K < 1 || batch < 1) return 0;
-  return qflex::kSplitSlotBytes + (int64_t)sizeof(uint16_t) * 4 * batch * (M * K + N * K);
+  return qflex::kSplitSlotBytes +
+         (int64_t)sizeof(uint16_t) * qflex::dev::kSplitValues * batch * (M * K + N * K);
 }
 
 
@@ -379,7 +389,17 @@ qflex_status qflex_gemm_split_c64(const void* A, const void* B, void* C, int64_t
                                   int32_t precision, void* workspace, int64_t workspace_bytes,
                                   void* stream) {
   return guarded([&] {
-    qflex::gemm_split_c64_run(A, B, C, M, N, K, ta, tb, batch, precision, workspace,
+    qflex::gemm_split_c64_run(A, B, C, M, N, K, ta, tb, batch, precision, -1, workspace,
+                              workspace_bytes, static_cast<hipStream_t>(stream));
+  });
+}
+
+qflex_status qflex_gemm_split_c64_tile(const void* A, const void* B, void* C, int64_t M,
+                                       int64_t N, int64_t K, int32_t ta, int32_t tb,
+                                       int64_t batch, int32_t precision, int32_t tile,
+                                       void* workspace, int64_t workspace_bytes, void* stream) {
+  return guarded([&] {
+    qflex::gemm_split_c64_run(A, B, C, M, N, K, ta, tb, batch, precision, tile, workspace,
                               workspace_bytes, static_cast<hipStream_t>(stream));
   });
 }

@@ -26,7 +26,7 @@ qflex_status run_guarded(const std::function<void()>& f);
 void gemm_split_c64_check(const void* A, const void* B, const void* C, int64_t M, int64_t N,
                           int64_t K, int32_t ta, int32_t tb, int64_t batch, int32_t precision);
 void gemm_split_c64_run(const void* A, const void* B, void* C, int64_t M, int64_t N, int64_t K,
-                        int32_t ta, int32_t tb, int64_t batch, int32_t precision,
+                        int32_t ta, int32_t tb, int64_t batch, int32_t precision, int32_t tile,
                         void* workspace, int64_t workspace_bytes, hipStream_t st);
 
 }  // namespace qflex

@@ -318,7 +318,8 @@ void prepare_split(qflex_grid* g, hipStream_t s) {
       const bool cached = !st.x.qubit && P.nodes[st.x.id].deps != st.deps;
       if (cached) {
         cs.xcache_offset[i] = cs.xcache_elems;
-        cs.xcache_elems += ((int64_t(4) << P.nodes[st.x.id].labels.size()) + 63) & ~int64_t(63);
+        cs.xcache_elems +=
+            ((int64_t(dev::kSplitValues) << P.nodes[st.x.id].labels.size()) + 63) & ~int64_t(63);
         if (f16) cs.xcache_slot[i] = n_slots++;
       }
       if (!cached && !st.x.qubit && st.kb >= 4 && st.x_in.size() >= 2) {
@@ -377,13 +378,13 @@ void prepare_split(qflex_grid* g, hipStream_t s) {
                 L.n_fixed, L.free_bits(), st.kb, side == 1, pd, f16 ? n_slots : -1};
           if (f16) cs.qamax_slot[o.id] = n_slots++;
           cs.qsplit_offset[o.id] = total;
-          total += ((int64_t(4) << L.storage.size()) + 63) & ~int64_t(63);
+          total += ((int64_t(dev::kSplitValues) << L.storage.size()) + 63) & ~int64_t(63);
           jobs.push_back(j);
         } else if (side == 0 && cached) {
           cs.sx[i] = dev::make_perm_tile(pd.nbits, pd.perm.data());
         } else {  // also for a gathered x: the autotuner may prefer permuting it
           (side ? cs.sy[i] : cs.sx[i]) = dev::make_perm_tile(pd.nbits, pd.perm.data());
-          const int64_t e = int64_t(4) << P.nodes[o.id].labels.size();
+          const int64_t e = int64_t(dev::kSplitValues) << P.nodes[o.id].labels.size();
           if (side) cs.split_b_elems = std::max(cs.split_b_elems, e);
           else cs.split_a_elems = std::max(cs.split_a_elems, e);
         }
@@ -972,6 +973,7 @@ void contract(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets, dou
                 dev::GemmSplit shape;
                 shape.M = M;
                 shape.N = N;
+                shape.K = K;
                 float best = 0;
                 for (int gy = 0; gy < (cs.gather_y[k] ? 2 : 1); ++gy)
                   for (int gth = 0; gth < (cs.gather_x[k] ? 2 : 1); ++gth)

@@ -127,6 +127,7 @@ void gemm(const Gemm& g, hipStream_t s);
 //    fewer below (lo parts turn subnormal), and the product is multiplied back by 2^-(kA+kB).
 // Permute (as permute()) into [rows][K] order, K the low kbits bits, and split.  amax = NULL
 // selects bf16; otherwise fp16, with the scale taken from the slot absmax() filled.
+constexpr int kSplitValues = 4;  // 16-bit values per complex element in the split layout
 void split_permute(const float2* in, uint16_t* out, int64_t batch, const PermTile& t, int kbits,
                    const uint64_t* amax, hipStream_t s);
 // Record max(|re|, |im|) over n complex values into *slot as (tag << 32) | float bits, by a
@@ -156,8 +157,9 @@ struct GemmSplit {
   // with a gathered A
   const float2* Bc = nullptr;
   SplitGather gb;
-  // output tile chosen by an autotuner: 0 = 256x128, 1 = 128x128, 2 = 64x64, 3 = 128x256 (-1 or
-  // a tile the shape does not fit: 3 for a gathered A where it fits, else the largest of 0, 1,
+  // output tile chosen by an autotuner: 0 = 256x128, 1 = 128x128, 2 = 64x64, 3 = 128x256, and in
+  // the 3-multiplication form 4 = 256x128, 5 = 128x256 (-1 or a tile the shape does not fit: 5
+  // for a gathered A where it fits, else 4, else 3 for a gathered A, else the largest of 0, 1,
   // 2 that fits)
   int tile = -1;
   // fp16 products: record the largest |re|, |im| of C into *c_amax as absmax() would, with
@@ -165,7 +167,7 @@ struct GemmSplit {
   uint64_t* c_amax = nullptr;
   uint64_t c_tag = 0;
 };
-constexpr int kSplitTiles = 4;
+constexpr int kSplitTiles = 6;
 bool gemm_split_ok(int64_t M, int64_t N, int64_t K);  // shape fits the tiled kernel
 bool gemm_split_tile_fits(const GemmSplit& g, int tile);
 void gemm_split(const GemmSplit& g, hipStream_t s);

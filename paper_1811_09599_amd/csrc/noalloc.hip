@@ -58,7 +58,7 @@ extern "C" qflex_status qflex_gemm_split_c64_noalloc(const void* A, const void* 
                       " bytes of scratch, more than the library's " +
                       std::to_string((long long)QFLEX_NOALLOC_SCRATCH_BYTES) +
                       "; use qflex_gemm_split_c64 with a workspace");
-    qflex::gemm_split_c64_run(A, B, C, M, N, K, ta, tb, batch, precision,
+    qflex::gemm_split_c64_run(A, B, C, M, N, K, ta, tb, batch, precision, -1,
                               scratch_for_current_device(), QFLEX_NOALLOC_SCRATCH_BYTES,
                               static_cast<hipStream_t>(stream));
   });

@@ -186,7 +186,7 @@ SPLIT_SHAPES = [(128, 64, 16, 1), (256, 128, 64, 2), (512, 256, 256, 1), (128, 5
                 (1024, 1024, 512, 1), (2048, 64, 4096, 1)]
 
 
-def _split_gemm(a, b, M, N, K, ta, tb, batch, prec):
+def _split_gemm(a, b, M, N, K, ta, tb, batch, prec, tile=None):
     torch = _torch()
     A = torch.from_numpy(a).cuda()
     B = torch.from_numpy(b).cuda()
@@ -196,8 +196,11 @@ def _split_gemm(a, b, M, N, K, ta, tb, batch, prec):
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
     args = (C.c_void_p(A.data_ptr()), C.c_void_p(B.data_ptr()), C.c_void_p(Cm.data_ptr()),
             M, N, K, ta, tb, batch, F.PREC[prec], C.c_void_p(ws.data_ptr()))
-    assert L.qflex_gemm_split_c64(*args, ws_bytes - 1, None) == F.E_INVALID
-    F.check(L.qflex_gemm_split_c64(*args, ws_bytes, None))
+    if tile is None:
+        assert L.qflex_gemm_split_c64(*args, ws_bytes - 1, None) == F.E_INVALID
+        F.check(L.qflex_gemm_split_c64(*args, ws_bytes, None))
+    else:
+        F.check(L.qflex_gemm_split_c64_tile(*args[:10], tile, args[10], ws_bytes, None))
     torch.cuda.synchronize()
     return Cm.cpu().numpy()
 
@@ -234,6 +237,55 @@ def test_split_gemm_error_bound(M, N, K, batch, ta, tb, prec):
     rel = np.linalg.norm(got - want) / np.linalg.norm(want)
     _say("  rel_l2", rel)
     assert rel < SPLIT_BOUND[prec], rel
+
+
+# The 3-multiplication form's imaginary part P3 - P1 - P2 subtracts products whose rounding
+# errors scale with |Ar + Ai| |Br + Bi|, |Ar Br| and |Ai Bi|: on random data about 1.5x the
+# packed form's relative error, bounded here by twice the packed bound.
+SPLIT_TILE_SIDES = {0: (256, 128), 1: (128, 128), 2: (64, 64), 3: (128, 256), 4: (256, 128),
+                    5: (128, 256)}
+
+
+@pytest.mark.parametrize("prec", ["split_bf16", "split_fp16"])
+@pytest.mark.parametrize("tile", sorted(SPLIT_TILE_SIDES))
+@pytest.mark.parametrize("M,N,K,batch,ta,tb", [(256, 256, 16, 2, 0, 0), (512, 256, 1024, 1, 1, 1),
+                                              (256, 512, 256, 3, 0, 1), (1024, 256, 64, 1, 1, 0)])
+def test_split_gemm_every_tile_and_form(M, N, K, batch, ta, tb, tile, prec):
+    """Each output tile of the split product, packed and 3-multiplication forms, with the row
+    operand gathered from complex64 (ta = 0) and pre-split (ta = 1), against FP64; one k-tile
+    (K = 16) and several."""
+    _say("split gemm tile", tile, prec, M, N, K, batch, ta, tb)
+    rng = np.random.default_rng(M + 3 * N + 7 * K + batch + 17 * tile)
+    sa = (batch, K, M) if ta else (batch, M, K)
+    sb = (batch, N, K) if tb else (batch, K, N)
+    a = (rng.standard_normal(sa) + 1j * rng.standard_normal(sa)).astype(np.complex64)
+    b = (rng.standard_normal(sb) + 1j * rng.standard_normal(sb)).astype(np.complex64)
+    got = _split_gemm(a, b, M, N, K, ta, tb, batch, prec, tile=tile)
+    want = _ref(a, b, ta, tb)
+    rel = np.linalg.norm(got - want) / np.linalg.norm(want)
+    rel_re = np.linalg.norm(got.real - want.real) / np.linalg.norm(want.real)
+    _say("  rel_l2", rel, "real part", rel_re)
+    assert rel < SPLIT_BOUND[prec] * (2 if tile >= 4 else 1), rel
+    assert rel_re < SPLIT_BOUND[prec], rel_re
+
+
+def test_split_gemm_tile_entry_rejects_tiles_that_do_not_fit():
+    torch = _torch()
+    L = F.lib()
+    M, N, K = 128, 128, 64
+    A = torch.zeros((M, K), dtype=torch.complex64, device="cuda")
+    B = torch.zeros((K, N), dtype=torch.complex64, device="cuda")
+    Cm = torch.zeros((M, N), dtype=torch.complex64, device="cuda")
+    ws_bytes = L.qflex_gemm_split_workspace(M, N, K, 1)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+    P = C.c_void_p
+    for tile, ok in [(-1, True), (1, True), (2, True), (0, False), (3, False), (4, False),
+                     (5, False), (6, False), (-2, False)]:
+        st = L.qflex_gemm_split_c64_tile(P(A.data_ptr()), P(B.data_ptr()), P(Cm.data_ptr()), M,
+                                         N, K, 0, 0, 1, F.PREC["split_bf16"], tile,
+                                         P(ws.data_ptr()), ws_bytes, None)
+        assert (st == 0) == ok, (tile, st)
+    torch.cuda.synchronize()
 
 
 @pytest.mark.parametrize("prec", ["split_bf16", "split_fp16"])

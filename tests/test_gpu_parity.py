@@ -265,7 +265,7 @@ def test_fsim_7x7_depth16_sampled_slices_vs_oracle(prec):
     assert prof["gemm_rows_mfma_gather_nn"]["launches"] == 2 * len(ids), prof.keys()
     if prec != "c64":
         fmt = prec.split("_")[1]
-        assert prof["gemm_split_%s_gatherb_256x128" % fmt]["launches"] >= len(ids), prof.keys()
+        assert prof["gemm_split3m_%s_gatherb_256x128" % fmt]["launches"] >= len(ids), prof.keys()
 
 
 # ------------------------------------------------------------------- cut sweeps

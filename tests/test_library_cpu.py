@@ -293,6 +293,27 @@ def test_split_gemm_argument_checks_run_before_any_launch():
     assert call(A=C.c_void_p((1 << 20) + 8)) == F.E_INVALID  # misaligned operand
 
 
+def test_split_tile_entry_checks_the_tile_before_any_launch():
+    """The split product with a caller's tile rejects tiles out of range or not fitting M, N on
+    the host, like every other argument check (nothing is launched)."""
+    L = F.lib()
+    fake = C.c_void_p(1 << 20)
+    ws = L.qflex_gemm_split_workspace(256, 256, 64, 1)
+
+    def call(tile, M=256, N=256):
+        return L.qflex_gemm_split_c64_tile(fake, fake, fake, M, N, 64, 0, 0, 1,
+                                           F.PREC["split_bf16"], tile, fake, ws, None)
+
+    for tile in (-2, 6, 100):
+        assert call(tile) == F.E_INVALID
+    assert b"tile" in L.qflex_last_error()
+    assert call(0, M=128) == F.E_INVALID   # 256x128
+    assert call(4, M=128) == F.E_INVALID   # 256x128, 3-multiplication form
+    assert call(3, N=128) == F.E_INVALID   # 128x256
+    assert call(5, N=128) == F.E_INVALID
+    assert call(4, M=256, N=64) == F.E_INVALID
+
+
 def test_noalloc_split_product_checks_run_before_any_launch():
     """The no-allocation split product checks its arguments as the workspace entry point does
     and rejects a product whose split operands exceed its fixed scratch (2048^3 needs 64 MiB +
