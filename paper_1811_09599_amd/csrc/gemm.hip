@@ -52,6 +52,27 @@ __global__ void __launch_bounds__(64 * WM * WN) gemm_mfma_kernel(const Gemm g) {
   const int64_t ldc = g.split > 1 ? g.N : g.ldc;
   const int64_t m0 = tm * BM, n0 = tn * BN;
 
+  // An operand stored k-major (B [K][N], or A [K][M]) is transposed while staging: pair e of a
+  // tile (2 consecutive columns of one k row) goes to LDS rows 2np and 2np + 1 at column kr.
+  // With A stored k-major too, groups of 8 lanes take 8 consecutive pairs of one k row (128
+  // contiguous bytes) and the wave's 8 groups 8 consecutive k, for both operands: the 8-byte
+  // writes of a wave then spread over the banks (rows of 144 bytes), where a whole wave on one k
+  // row put its 64 writes 288 bytes apart, on 8 banks; on (32768^2, 4096) this took the
+  // transposed-A product from 162 to 184 TFLOP/s.  With A stored row-major, B keeps whole k
+  // rows per wave: the same mapping of B alone cost that product 5% (179 -> 169 TFLOP/s).
+  auto t_slot = [](int e, int pairs, int& kr, int& np) {
+    static_assert(BK == 16, "16 k rows per tile");
+    if (pairs >= 8) {
+      kr = (e >> 3) & 15;
+      np = (e & 7) + 8 * (e >> 7);
+    } else {  // whole k rows per wave: pairs = 0 stands for BN / 2
+      const int w = pairs > 0 ? pairs : BN / 2;
+      kr = e / w;
+      np = e % w;
+    }
+  };
+  auto b_slot = [&](int e, int& kr, int& np) { t_slot(e, TA ? BN / 2 : 0, kr, np); };
+  auto a_slot = [&](int e, int& kr, int& mp) { t_slot(e, BM / 2, kr, mp); };
   f32x4 ra[AV], rb[BV];
   auto gload = [&](int64_t k0) {
 #pragma unroll
@@ -61,7 +82,8 @@ __global__ void __launch_bounds__(64 * WM * WN) gemm_mfma_kernel(const Gemm g) {
         const int row = e >> 3, kp = e & 7;
         ra[v] = *reinterpret_cast<const f32x4*>(A + (m0 + row) * g.lda + k0 + 2 * kp);
       } else {
-        const int kr = e / (BM / 2), mp = e % (BM / 2);
+        int kr, mp;
+        a_slot(e, kr, mp);
         ra[v] = *reinterpret_cast<const f32x4*>(A + (k0 + kr) * g.lda + m0 + 2 * mp);
       }
     }
@@ -69,7 +91,8 @@ __global__ void __launch_bounds__(64 * WM * WN) gemm_mfma_kernel(const Gemm g) {
     for (int v = 0; v < BV; ++v) {
       const int e = tid + v * NT;
       if (!TB) {
-        const int kr = e / (BN / 2), np = e % (BN / 2);
+        int kr, np;
+        b_slot(e, kr, np);
         rb[v] = *reinterpret_cast<const f32x4*>(B + (k0 + kr) * g.ldb + n0 + 2 * np);
       } else {
         const int row = e >> 3, kp = e & 7;
@@ -85,7 +108,8 @@ __global__ void __launch_bounds__(64 * WM * WN) gemm_mfma_kernel(const Gemm g) {
         const int row = e >> 3, kp = e & 7;
         *reinterpret_cast<f32x4*>(&As[buf][row * LDK + 2 * kp]) = ra[v];
       } else {
-        const int kr = e / (BM / 2), mp = e % (BM / 2);
+        int kr, mp;
+        a_slot(e, kr, mp);
         As[buf][(2 * mp) * LDK + kr] = make_float2(ra[v].x, ra[v].y);
         As[buf][(2 * mp + 1) * LDK + kr] = make_float2(ra[v].z, ra[v].w);
       }
@@ -94,7 +118,8 @@ __global__ void __launch_bounds__(64 * WM * WN) gemm_mfma_kernel(const Gemm g) {
     for (int v = 0; v < BV; ++v) {
       const int e = tid + v * NT;
       if (!TB) {
-        const int kr = e / (BN / 2), np = e % (BN / 2);
+        int kr, np;
+        b_slot(e, kr, np);
         Bs[buf][(2 * np) * LDK + kr] = make_float2(rb[v].x, rb[v].y);
         Bs[buf][(2 * np + 1) * LDK + kr] = make_float2(rb[v].z, rb[v].w);
       } else {
