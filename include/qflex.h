@@ -133,6 +133,17 @@ typedef struct {
                                 for split products gathered vs permuted row operands) on that
                                 call's operands and keeps the fastest for the grid's lifetime;
                                 results do not depend on the choice beyond rounding order */
+  int32_t fused;             /* complex64 grids: 0 (default) contracts every circuit whose plan
+                                fits one workgroup's LDS per bit-string (intermediates and the
+                                qubit tensors' free parts within 144 KiB, at most 128 steps,
+                                at most 10 contracted labels per step, the result an
+                                intermediate) in one kernel launch per call and up to 64 slices:
+                                one workgroup per bit-string runs every step in LDS, its
+                                operands read in place (no permutation), and adds the result
+                                to the FP64 amplitudes; other circuits take the step-by-step
+                                path.  1: every circuit must fit (QFLEX_E_INVALID at build
+                                otherwise).  -1: never.  Split precisions ignore 0 and reject
+                                1. */
 } qflex_options;
 
 typedef enum { QFLEX_SLICES_RANDOM = 0, QFLEX_SLICES_BLOCK = 1 } qflex_slice_mode;

@@ -30,7 +30,8 @@ class Options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("plan_kind", C.c_int32),
                 ("max_tensor_elems", C.c_int64), ("open_qubits", C.POINTER(C.c_int32)),
                 ("n_open", C.c_int32), ("bitstring_batch", C.c_int32),
-                ("slice_mode", C.c_int32), ("graph", C.c_int32), ("autotune", C.c_int32)]
+                ("slice_mode", C.c_int32), ("graph", C.c_int32), ("autotune", C.c_int32),
+                ("fused", C.c_int32)]
 
 
 class Stats(C.Structure):

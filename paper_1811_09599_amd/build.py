@@ -17,6 +17,7 @@ OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libqflex.so")
 
 HIP_SOURCES = ["grid_kernels.hip", "permute.hip", "gemm.hip", "gemm_split.hip", "reduce.hip",
+               "fused.hip",
                "sample.hip", "noalloc.hip"]
 HOST_SOURCES = ["model.cpp", "plan.cpp", "exec.cpp", "exec_grad.cpp", "api.cpp", "tune_cache.cpp"]
 ARCH = "gfx950"

@@ -58,6 +58,7 @@ void release(qflex_grid* g) {
   g->offs.release();
   g->offs_host.release();
   g->grad_host.release();
+  g->fused_prog.release();
   if (g->offs_done) (void)hipEventDestroy(g->offs_done);
   g->prof.release();
   delete g;
@@ -74,6 +75,9 @@ void check_options(const qflex_options& o) {
     qflex::fail(QFLEX_E_INVALID, "unknown slice_mode");
   if (o.graph != 0 && o.graph != 1) qflex::fail(QFLEX_E_INVALID, "graph must be 0 or 1");
   if (o.autotune != 0 && o.autotune != 1) qflex::fail(QFLEX_E_INVALID, "autotune must be 0 or 1");
+  if (o.fused < -1 || o.fused > 1) qflex::fail(QFLEX_E_INVALID, "fused must be -1, 0 or 1");
+  if (o.fused == 1 && o.precision != QFLEX_PREC_C64)
+    qflex::fail(QFLEX_E_INVALID, "the fused contraction runs in complex64 only");
 }
 
 }  // namespace
@@ -184,6 +188,7 @@ qflex_status qflex_build_grid(const qflex_circuit* circuits, int32_t n_circuits,
       g->slice_mode = opt->slice_mode;
       g->graph_mode = opt->graph != 0;
       g->autotune = opt->autotune != 0;
+      g->fused_opt = opt->fused;
       for (int c = 0; c < n_circuits; ++c) {
         qflex::CircuitState cs;
         cs.model = qflex::build_model(circuits[c]);

@@ -45,6 +45,9 @@ struct CircuitState {
   // steps the kernel variant; and for the adjoint, per step its forward, Xbar and Ybar products
   std::vector<int> tuned;
   std::vector<int> tuned_grad;
+  // the fused small-plan program (device tables in qflex_grid::fused_prog), when the plan fits
+  dev::FusedPlan fused;
+  bool fused_ok = false;
   std::vector<int64_t> qsplit_offset;// per qubit: offset in grid_split (16-bit values), -1 if none
   std::vector<int64_t> qamax_slot;   // per qubit: fp16 scale slot in amax, -1 if none
   int64_t split_a_elems = 0, split_b_elems = 0;  // scratch per bit-string (16-bit values)
@@ -127,6 +130,7 @@ struct qflex_grid {
   // graph mode: the captured launches of the last call and the call shape they belong to
   bool graph_mode = false;
   bool autotune = false;                 // time kernel variants per step on first use
+  int fused_opt = 0;                     // qflex_options.fused: 0 where the plan fits, 1 required, -1 never
   int64_t n_tuned = 0;                   // kernel variants timed so far (time_launches calls)
   hipEvent_t tune_ev[2] = {nullptr, nullptr};
   hipGraphExec_t graph_exec = nullptr;
@@ -165,6 +169,7 @@ struct qflex_grid {
   qflex::DevBuf arena;                   // intermediates
   qflex::DevBuf amps64;                  // FP64 amplitude accumulator
   qflex::DevBuf offs;                    // per-bit-string output offsets of the qubit tensors
+  qflex::DevBuf fused_prog;              // fused small-plan programs: steps, then qubit tables
   qflex::HostPinned offs_host;
   qflex::HostPinned grad_host;           // piece cotangents and cross-entropy sums, on the host
   hipEvent_t offs_done = nullptr;        // the last upload out of offs_host has finished

@@ -173,6 +173,63 @@ bool gemm_split_tile_fits(const GemmSplit& g, int tile);
 void gemm_split(const GemmSplit& g, hipStream_t s);
 const char* gemm_split_name(const GemmSplit& g);
 
+// ---------------------------------------------------------------- fused small-plan contraction
+// A whole contraction plan in one launch, one workgroup per bit-string, for plans whose
+// intermediates and qubit tensors (their free parts, for the bit-string and slice) fit in the
+// workgroup's LDS.  Every step is C[m][n] = sum_k X[m,k] Y[k,n] in complex64 (FP32 sums), its
+// operands read in place through index tables (the bit-deposit maps of their storage orders,
+// the same for every bit-string, built on the host; no permutation), C stored [M][N]; the
+// result tensor is added to the FP64 amplitudes, slice after slice, with the steps whose cuts
+// did not change skipped (their intermediates stay in LDS).  LDS holds the tensor image, then
+// the step descriptors and index tables.
+constexpr int kFusedMaxSteps = 128;
+constexpr int kFusedMaxQubits = 128;
+constexpr int kFusedMaxBits = 24;      // labels of one operand
+constexpr int kFusedMaxKBits = 10;     // contracted labels of one step
+constexpr int kFusedMaxQubitCuts = 8;  // cuts one qubit tensor depends on
+constexpr int kFusedMaxCuts = 32;
+constexpr int kFusedMaxSlices = 64;    // slices per launch (more: several launches)
+constexpr int kFusedThreads = 1024;    // 16 waves: one bit-string's steps hide each other's latency
+constexpr int64_t kFusedMaxLdsElems = 18432;  // 144 KiB of complex64 per workgroup
+
+struct FusedQubit {
+  int64_t grid_off = 0;  // the tensor in the grid (elements)
+  int32_t lds = 0;       // its free part in LDS (elements)
+  int32_t free_bits = 0;
+  int32_t out_row = -1;  // row of the per-bit-string offsets table (closed qubits), else -1
+  int32_t ncut = 0;
+  int8_t cut[kFusedMaxQubitCuts] = {};    // cut index
+  int8_t shift[kFusedMaxQubitCuts] = {};  // bit position of the cut's lowest label
+  uint32_t deps = 0;
+};
+struct FusedStep {
+  int32_t x = 0, y = 0, out = 0;  // LDS offsets (elements)
+  int32_t mb = 0, kb = 0, nb = 0;
+  uint32_t deps = 0;
+  // the step's index tables (16-bit, in the plan's table block): X index of (m, k) =
+  // xm[m] + xk[k], Y index of (k, n) = yk[k] + yn[n], laid out [xm | yn | xk | yk]
+  int32_t tab = 0;
+};
+struct FusedPlan {
+  const FusedStep* steps = nullptr;  // device
+  const FusedQubit* qubits = nullptr;
+  const uint16_t* tables = nullptr;  // every step's index tables
+  int32_t nsteps = 0, nq = 0, ntab = 0;
+  int32_t lds_elems = 0;  // per workgroup
+  int32_t result = 0;     // LDS offset of the result tensor
+  int32_t namp = 0;       // its elements
+  const uint32_t* bidx = nullptr;  // result element -> open-batch index (device)
+  int32_t ncut = 0;
+  int8_t cut_bits[kFusedMaxCuts] = {};
+};
+// Contract bit-strings b0 .. b0 + nb - 1 of a circuit over `nslices` slices: offs = the
+// circuit's per-bit-string offsets table ([qubit][nbs]), acc = its FP64 amplitudes
+// ([bit-string][namp], added to).
+void fused_setup();  // once per process and device before the first fused_contract
+void fused_contract(const FusedPlan& p, const float2* grid, const int64_t* offs, int64_t nbs,
+                    int64_t b0, int64_t nb, const int64_t* slices, int nslices, double2* acc,
+                    hipStream_t s);
+
 // ---------------------------------------------------------------- adjoint (gradients)
 constexpr int kMaxPiecesGrad = 64;  // pieces per qubit time line supported by grid_adjoint
 // Cotangent of the grid build: given tbar (FP64 cotangent of every qubit tensor, laid out like

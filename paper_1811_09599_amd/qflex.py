@@ -45,7 +45,7 @@ class _CircuitPack:
 
 
 def _options(precision="c64", plan="auto", max_tensor_elems=0, open_qubits=(),
-             bitstring_batch=0, slice_mode="random", graph=False, autotune=False):
+             bitstring_batch=0, slice_mode="random", graph=False, autotune=False, fused="auto"):
     o = F.Options()
     o.precision = F.PREC[precision]
     o.plan_kind = F.PLAN[plan]
@@ -57,6 +57,7 @@ def _options(precision="c64", plan="auto", max_tensor_elems=0, open_qubits=(),
     o.slice_mode = F.SLICES[slice_mode]
     o.graph = 1 if graph else 0
     o.autotune = 1 if autotune else 0
+    o.fused = {"auto": 0, True: 1, "require": 1, False: -1, "never": -1}[fused]
     return o, op
 
 
@@ -89,7 +90,7 @@ class Grid:
 
     def __init__(self, circuits, precision="c64", plan="auto", max_tensor_elems=0,
                  open_qubits=(), bitstring_batch=0, slice_mode="random", graph=False,
-                 autotune=False, stream=None):
+                 autotune=False, stream=None, fused="auto"):
         L = F.lib()
         if isinstance(circuits, dict):
             circuits = [circuits]
@@ -98,7 +99,7 @@ class Grid:
         self.open_qubits = list(open_qubits)
         pack = _CircuitPack(self.circuits)
         o, keep = _options(precision, plan, max_tensor_elems, open_qubits, bitstring_batch,
-                           slice_mode, graph, autotune)
+                           slice_mode, graph, autotune, fused)
         h = C.c_void_p()
         F.check(L.qflex_build_grid(pack.arr, len(self.circuits), C.byref(o), _stream(stream),
                                    C.byref(h)))

@@ -507,3 +507,21 @@ def test_gather_run_encoding_reproduces_the_bit_map():
                 got |= ((v >> s) & ((1 << ln) - 1)) << d
             assert got == want
     assert seen_overflow > 20 and seen_fit > 100
+
+def test_fused_option_checked_before_any_device_work():
+    """qflex_options.fused must be -1, 0 or 1, and 1 needs complex64: both are rejected by the
+    option check, before the grid touches a device."""
+    from paper_1811_09599_amd import qflex as Q
+    L = F.lib()
+    c = R.grid_rqc(2, 2, 4, 3)
+    pack = Q._CircuitPack([c])
+    for prec, fused in (("split_bf16", "require"), ("split_fp16", "require")):
+        o, keep = Q._options(precision=prec, fused=fused)
+        h = C.c_void_p()
+        assert L.qflex_build_grid(pack.arr, 1, C.byref(o), None, C.byref(h)) == F.E_INVALID
+        assert b"complex64" in L.qflex_last_error()
+    o, keep = Q._options()
+    o.fused = 2
+    h = C.c_void_p()
+    assert L.qflex_build_grid(pack.arr, 1, C.byref(o), None, C.byref(h)) == F.E_INVALID
+    assert b"fused" in L.qflex_last_error()
