@@ -965,7 +965,13 @@ void contract(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets, dou
           if (sl >= 0) dev::fill_zero(reinterpret_cast<double*>(g->amax + sl), 1, s);
       if (g->node_amax) dev::fill_zero(reinterpret_cast<double*>(g->node_amax), g->n_node_amax, s);
     }
-    if (!accumulate) dev::fill_zero(reinterpret_cast<double*>(acc_all), 2 * amp_total, s);
+    // the sums start from zero, unless every circuit's fused kernel writes its own first
+    // (a circuit with no slice selected writes nothing)
+    bool all_fused = true;
+    for (int c = 0; c < nc; ++c)
+      all_fused = all_fused && g->circ[c].fused_ok && !sel[c].empty();
+    if (!accumulate && !all_fused)
+      dev::fill_zero(reinterpret_cast<double*>(acc_all), 2 * amp_total, s);
     bool first_batch = true;  // only the call's first batch can find its intermediates kept
     for (int c = 0; c < nc; ++c) {
       CircuitState& cs = g->circ[c];
@@ -998,7 +1004,7 @@ void contract(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets, dou
         }
         g->prof.begin("fused_contract", flops * nbs, 8.0 * nbs * (double)P.arena_elems, s);
         dev::fused_contract(cs.fused, g->grid, offs_dev + offs_base[c], nbs, 0, nbs,
-                            slices.data(), (int)slices.size(), acc, s);
+                            slices.data(), (int)slices.size(), acc, !accumulate && all_fused, s);
         g->prof.end(s);
         st.flops += flops * nbs;
         st.n_slices += (int64_t)slices.size();

@@ -12,6 +12,7 @@ struct FusedArgs {
   const int64_t* offs;
   int64_t nbs, b0;
   double2* acc;
+  int32_t overwrite;  // 1: the first slice writes the amplitudes instead of adding to them
   int32_t nslices;
   int64_t slices[kFusedMaxSlices];
 };
@@ -139,8 +140,12 @@ __global__ void __launch_bounds__(kFusedThreads) fused_contract_kernel(const Fus
     for (int32_t e = tid; e < p.namp; e += kFusedThreads) {
       const float2 r = lds[p.result + e];
       double2& d = a.acc[bs * p.namp + p.bidx[e]];
-      d.x += (double)r.x;
-      d.y += (double)r.y;
+      if (si == 0 && a.overwrite) {
+        d = make_double2((double)r.x, (double)r.y);
+      } else {
+        d.x += (double)r.x;
+        d.y += (double)r.y;
+      }
     }
     __syncthreads();
   }
@@ -158,7 +163,7 @@ void fused_setup() {
 
 void fused_contract(const FusedPlan& p, const float2* grid, const int64_t* offs, int64_t nbs,
                     int64_t b0, int64_t nb, const int64_t* slices, int nslices, double2* acc,
-                    hipStream_t s) {
+                    bool overwrite, hipStream_t s) {
   if (nb < 1 || nslices < 1) return;
   if (p.lds_elems < 1 || p.lds_elems > kFusedMaxLdsElems || p.nsteps > kFusedMaxSteps ||
       p.nq > kFusedMaxQubits || p.ncut > kFusedMaxCuts || b0 < 0 || b0 + nb > nbs)
@@ -174,6 +179,7 @@ void fused_contract(const FusedPlan& p, const float2* grid, const int64_t* offs,
   a.nbs = nbs;
   a.acc = acc;
   for (int s0 = 0; s0 < nslices; s0 += kFusedMaxSlices) {
+    a.overwrite = overwrite && s0 == 0;
     a.nslices = std::min(kFusedMaxSlices, nslices - s0);
     for (int i = 0; i < a.nslices; ++i) a.slices[i] = slices[s0 + i];
     for (int64_t c0 = 0; c0 < nb; c0 += 65535) {

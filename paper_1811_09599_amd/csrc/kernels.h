@@ -224,11 +224,11 @@ struct FusedPlan {
 };
 // Contract bit-strings b0 .. b0 + nb - 1 of a circuit over `nslices` slices: offs = the
 // circuit's per-bit-string offsets table ([qubit][nbs]), acc = its FP64 amplitudes
-// ([bit-string][namp], added to).
+// ([bit-string][namp]), added to, or with `overwrite` set by the first slice (nslices >= 1).
 void fused_setup();  // once per process and device before the first fused_contract
 void fused_contract(const FusedPlan& p, const float2* grid, const int64_t* offs, int64_t nbs,
                     int64_t b0, int64_t nb, const int64_t* slices, int nslices, double2* acc,
-                    hipStream_t s);
+                    bool overwrite, hipStream_t s);
 
 // ---------------------------------------------------------------- adjoint (gradients)
 constexpr int kMaxPiecesGrad = 64;  // pieces per qubit time line supported by grid_adjoint
