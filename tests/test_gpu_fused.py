@@ -141,3 +141,15 @@ def test_fused_profile_and_stats():
     assert prof["fused_contract"]["launches"] == 1, prof
     assert prof["fused_contract"]["flops"] == pytest.approx(st["flops"], rel=1e-12)
     assert st["n_slices"] == g.num_slices() == 1024 and st["n_permute"] == 0
+
+
+def test_fused_more_bitstrings_than_one_launch_holds():
+    """More than 65535 bit-strings: the fused contraction launches in chunks of 65535
+    workgroups (one per bit-string), each chunk writing its own bit-strings' amplitudes."""
+    _need_gpu()
+    c = R.grid_rqc(2, 3, 8, 31)
+    bits = R.bitstrings(6, 70000, 4)
+    g = build_grid(c, fused="require")
+    a = g.contract_amplitudes(bits).cpu().numpy()[:, 0]
+    _check(a, E1.amplitudes(c, bits), 6)
+    assert g.last_stats()["n_bitstrings"] == 70000
