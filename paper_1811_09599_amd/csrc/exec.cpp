@@ -340,7 +340,8 @@ static std::string build_fused(const qflex_grid* g, const CircuitState& cs,
     fs.kb = st.kb;
     fs.nb = st.nb;
     fs.deps = st.deps;
-    // index tables: every index is below the operand's size, at most the LDS image (< 2^15)
+    // index tables: an index is below its operand's size, which the 16-bit entries bound to
+    // 2^16 elements (the LDS image itself holds fewer)
     if (x.second > 65536 || y.second > 65536) return "an operand of more than 2^16 elements";
     auto deposit = [](int64_t v, const int8_t* pos, int n) {
       int64_t o = 0;
