@@ -206,7 +206,10 @@ qflex_status qflex_plan_cuts(const qflex_grid* g, int32_t circuit, int32_t* pair
  * memory) into buf (NUL-terminated, truncated to len).  *needed receives the full length + 1.
  * A step's label lists (most significant first) are the product's rows, contracted labels and
  * columns (mlab, klab, nlab) and the storage orders of its operands as they come in (x_in,
- * y_in; free labels only for a qubit tensor). */
+ * y_in; free labels only for a qubit tensor).  "fused" tells whether the plan fits the fused
+ * small-plan kernel (one workgroup per bit-string, every step in LDS; complex64 grids use it
+ * unless qflex_options.fused is -1): {"fits":1,"lds_bytes","steps","table_entries"} or
+ * {"fits":0,"why"}. */
 qflex_status qflex_plan_describe(const qflex_circuit* circuit, const qflex_options* opt,
                                  char* buf, int64_t len, int64_t* needed);
 

@@ -19,7 +19,7 @@ LIB = os.path.join(HERE, "libqflex.so")
 HIP_SOURCES = ["grid_kernels.hip", "permute.hip", "gemm.hip", "gemm_split.hip", "reduce.hip",
                "fused.hip",
                "sample.hip", "noalloc.hip"]
-HOST_SOURCES = ["model.cpp", "plan.cpp", "exec.cpp", "exec_grad.cpp", "api.cpp", "tune_cache.cpp"]
+HOST_SOURCES = ["model.cpp", "plan.cpp", "fused_plan.cpp", "exec.cpp", "exec_grad.cpp", "api.cpp", "tune_cache.cpp"]
 ARCH = "gfx950"
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result",

@@ -6,6 +6,7 @@
 
 #include "../../include/qflex_kernels.h"
 #include "api_internal.h"
+#include "fused_plan.h"
 #include "grid.h"
 
 namespace {
@@ -246,7 +247,10 @@ qflex_status qflex_plan_describe(const qflex_circuit* circuit, const qflex_optio
     check_options(*opt);
     qflex::Model m = qflex::build_model(*circuit);
     qflex::Plan p = qflex::make_plan(m, *opt);
-    const std::string s = p.describe(m);
+    std::string s = p.describe(m);
+    // whether the plan fits the fused small-plan kernel (complex64 grids use it unless the
+    // fused option is -1)
+    s.insert(s.size() - 1, ",\"fused\":" + qflex::describe_fused(p, m));
     if (needed) *needed = (int64_t)s.size() + 1;
     if (buf && len > 0) {
       const size_t n = std::min<size_t>(s.size(), (size_t)len - 1);

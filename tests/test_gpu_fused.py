@@ -12,7 +12,7 @@ from oracle import slices as OS
 from oracle import statevector as E1
 from oracle import tn as E2
 from paper_1811_09599_amd import _ffi as F
-from paper_1811_09599_amd import build_grid
+from paper_1811_09599_amd import build_grid, plan_describe
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-5
@@ -112,13 +112,20 @@ def test_fused_graph_replay_and_accumulate():
 
 
 def test_fused_and_step_path_circuits_in_one_grid():
-    """A grid whose circuits take different paths (one fits the fused kernel, one does not)."""
+    """A grid whose circuits take different paths (one fits the fused kernel, one does not,
+    as plan_describe reports beforehand)."""
     _need_gpu()
     small = R.grid_rqc(3, 3, 16, 12)
     big = R.grid_rqc(6, 6, 16, 13)  # 54336 LDS elements per bit-string: the step path
+    assert plan_describe(small)["fused"]["fits"] == 1
+    assert plan_describe(big)["fused"]["fits"] == 0
     bits = [R.bitstrings(9, 5, 1), R.bitstrings(36, 3, 2)]
     g = build_grid([small, big])
+    g.set_profiling(True)
     a = g.contract_amplitudes(bits).cpu().numpy()[:, 0]
+    prof = g.profile_read()
+    g.set_profiling(False)
+    assert prof["fused_contract"]["launches"] == 1 and len(prof) > 1, prof
     _check(a[:5], E1.amplitudes(small, bits[0]), 9)
     _check(a[5:], E2.amplitudes(big, bits[1]), 36)
     with pytest.raises(RuntimeError, match="does not fit"):

@@ -525,3 +525,25 @@ def test_fused_option_checked_before_any_device_work():
     h = C.c_void_p()
     assert L.qflex_build_grid(pack.arr, 1, C.byref(o), None, C.byref(h)) == F.E_INVALID
     assert b"fused" in L.qflex_last_error()
+
+
+def test_plan_describe_reports_the_fused_fit():
+    """The fused small-plan kernel holds one bit-string's tensors in LDS: the arena, the free
+    part of every qubit tensor, 32-byte step descriptors and 16-bit index tables (per step,
+    2^mb + 2^nb + 2 * 2^kb entries), at most 144 KiB.  plan_describe reports the fit with these
+    figures, recomputed here from the plan's own description; larger plans report why not."""
+    cases = [((4, 4, 16, 1), {}), ((4, 4, 16, 1), {"open_qubits": [0, 5]}),
+             ((4, 4, 16, 1), {"plan": "quadrant"}), ((3, 4, 24, 1), {"plan": "quadrant"}),
+             ((6, 5, 16, 1), {}), ((4, 4, 16, 1), {"plan": "cut_sweep", "max_tensor_elems": 128})]
+    for args, kw in cases:
+        p = plan_describe(R.grid_rqc(*args), **kw)
+        f = p["fused"]
+        assert f["fits"] == 1, (args, kw, f)
+        tab = sum(2 ** s["mb"] + 2 ** s["nb"] + 2 * 2 ** s["kb"] for s in p["steps"])
+        image = p["arena_elems"] + sum(2 ** b for b in p["qubit_free_bits"])
+        assert f["steps"] == len(p["steps"]) and f["table_entries"] == tab
+        assert f["lds_bytes"] == 8 * image + 32 * len(p["steps"]) + 2 * tab
+        assert f["lds_bytes"] <= 144 * 1024
+    for args in ((6, 6, 16, 1), (7, 7, 40, 1)):
+        f = plan_describe(R.grid_rqc(*args))["fused"]
+        assert f["fits"] == 0 and "LDS" in f["why"], (args, f)
