@@ -127,7 +127,10 @@ typedef struct {
                                 (cotangents may differ too); capture and replay run on the
                                 caller's stream, or on a stream of the grid's ordered after
                                 the caller's when that is the null stream.  An autotuning grid
-                                runs its first call eagerly.  0: launches every call */
+                                runs its first call eagerly.  A call whose circuits all run the
+                                fused small-plan kernel is launched directly (one kernel per
+                                circuit and 64 slices: a graph saves no launch).  0: launches
+                                every call */
   int32_t autotune;          /* 1: the first call that runs a contraction step times every
                                 kernel variant that fits it (product tiles, kernel family, and
                                 for split products gathered vs permuted row operands) on that

@@ -766,13 +766,21 @@ void contract(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets, dou
     for (const CircuitState& cs : g->circ)
       if (!cs.fused_ok)  // the fused kernel has no variants to time
         for (int v : cs.tuned) tuning_pending = tuning_pending || v < 0;
+  // every circuit runs the fused small-plan kernel (a circuit with no slice selected would
+  // launch nothing)
+  bool all_fused = true;
+  for (int c = 0; c < nc; ++c)
+    all_fused = all_fused && g->circ[c].fused_ok && !sel[c].empty();
   // ---- graph mode: every launch below depends only on the call's shape (bit-strings per
   // circuit, their batching, the slices) and on buffer addresses, so an identical call replays
-  // the graph captured the first time; the bit-strings themselves travel in g->offs
+  // the graph captured the first time; the bit-strings themselves travel in g->offs.  A call
+  // whose circuits are all fused is launched directly: one kernel per circuit and 64 slices,
+  // which a graph would not shorten (its own launch costs more than the launches it saves).
+  const bool graph = g->graph_mode && !all_fused;
   std::string key;
   bool capturing = false;
   const bool prof_was_on = g->prof.on;
-  if (g->graph_mode) {
+  if (graph) {
     // capture and replay on the caller's stream; the null stream cannot capture, so then the
     // launches go to the grid's own stream, ordered after the caller's earlier work
     if (!s_user) {
@@ -834,10 +842,10 @@ void contract(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets, dou
     g->graph_key = key;
     QHIP(hipGraphLaunch(ex, s));
   };
-  const bool replayed = g->graph_mode && !capturing && !tuning_pending;
+  const bool replayed = graph && !capturing && !tuning_pending;
   // every launch of this call (skipped when the graph replays them)
   auto enqueue = [&] {
-    if (g->graph_mode && g->amax) {
+    if (graph && g->amax) {
       // fp16 scale slots rewritten by every call start from zero in each replay (the tags of
       // their atomic maxima are fixed in the graph)
       dev::fill_zero(reinterpret_cast<double*>(g->amax), 2, s);
@@ -847,10 +855,6 @@ void contract(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets, dou
       if (g->node_amax) dev::fill_zero(reinterpret_cast<double*>(g->node_amax), g->n_node_amax, s);
     }
     // the sums start from zero, unless every circuit's fused kernel writes its own first
-    // (a circuit with no slice selected writes nothing)
-    bool all_fused = true;
-    for (int c = 0; c < nc; ++c)
-      all_fused = all_fused && g->circ[c].fused_ok && !sel[c].empty();
     if (!accumulate && !all_fused)
       dev::fill_zero(reinterpret_cast<double*>(acc_all), 2 * amp_total, s);
     bool first_batch = true;  // only the call's first batch can find its intermediates kept
@@ -895,10 +899,12 @@ void contract(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets, dou
       for (int64_t b0 = 0; b0 < nbs; b0 += B) {
         const int nb = (int)std::min<int64_t>(B, nbs - b0);
         std::vector<int64_t> digit(ncut, -1), prev(ncut, -1);
-        const uint8_t* batch_bits = bits + (bs_offsets[c] + b0) * cs.model.n;
+        // the batch's rows: circuit c's rows start after every earlier circuit's (each of
+        // its own width n), which is where its offsets start too
+        const uint8_t* batch_bits = bits + offs_base[c] + b0 * cs.model.n;
         const size_t batch_bytes = (size_t)nb * (size_t)cs.model.n;
         // resumed: the arena still holds this batch's intermediates for the cut values in prev
-        const bool resumed = first_batch && !g->graph_mode && kept.valid && kept.circuit == c &&
+        const bool resumed = first_batch && !graph && kept.valid && kept.circuit == c &&
                              kept.batch == B && kept.bits.size() == batch_bytes &&
                              std::equal(kept.bits.begin(), kept.bits.end(), batch_bits);
         if (resumed) prev = kept.digits;
@@ -1146,7 +1152,7 @@ void contract(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets, dou
           g->prof.end(s);
         }
         // what the arena holds once this batch is done
-        rs.valid = !slices.empty() && !g->graph_mode;
+        rs.valid = !slices.empty() && !graph;
         rs.circuit = c;
         rs.batch = B;
         rs.bits.assign(batch_bits, batch_bits + batch_bytes);
@@ -1169,7 +1175,7 @@ void contract(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets, dou
     if (capturing) end_capture(false);
     throw;
   }
-  if (g->graph_mode && s != s_user) {  // the caller's later work waits for the graph
+  if (graph && s != s_user) {  // the caller's later work waits for the graph
     QHIP(hipEventRecord(g->graph_out, s));
     QHIP(hipStreamWaitEvent(s_user, g->graph_out, 0));
     s = s_user;

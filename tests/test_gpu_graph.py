@@ -71,8 +71,9 @@ def test_graph_mode_on_the_callers_stream():
     import torch
     _say("graph replay on a side stream")
     c = R.grid_rqc(4, 4, 16, 1001)
-    ge = build_grid(c)
-    gg = build_grid(c, graph=True)
+    # the step path: a call of fused circuits is launched directly, not captured
+    ge = build_grid(c, fused="never")
+    gg = build_grid(c, graph=True, fused="never")
     side = torch.cuda.Stream()
     for rep in range(4):
         bits = R.bitstrings(16, 64, 1500 + rep)
@@ -81,6 +82,45 @@ def test_graph_mode_on_the_callers_stream():
             got = gg.contract_amplitudes(bits)
         side.synchronize()
         assert np.array_equal(got.cpu().numpy(), want), rep
+    ge.close()
+    gg.close()
+
+
+def test_graph_mode_launches_fused_calls_directly():
+    """A call whose circuits all run the fused small-plan kernel is one launch per circuit: in
+    graph mode it is launched directly (its launches show in the profile, which a capture
+    would switch off), with the eager grid's results; a grid that also holds a circuit on the
+    step path still captures and replays."""
+    _need_gpu()
+    _say("graph mode, fused calls")
+    c = R.grid_rqc(4, 4, 16, 1001)
+    ge = build_grid(c)
+    gg = build_grid(c, graph=True)
+    gg.set_profiling(True)
+    for rep in range(3):
+        bits = R.bitstrings(16, 64, 1600 + rep)
+        want = ge.contract_amplitudes(bits).cpu().numpy()
+        got = gg.contract_amplitudes(bits).cpu().numpy()
+        assert np.array_equal(got, want), rep
+    prof = gg.profile_read()
+    gg.set_profiling(False)
+    assert prof["fused_contract"]["launches"] == 3, prof
+    ge.close()
+    gg.close()
+    # mixed: captured by the first call, replayed by the later ones (no profiled launches)
+    small, big = R.grid_rqc(3, 3, 16, 12), R.grid_rqc(6, 6, 16, 13)
+    ge = build_grid([small, big])
+    gg = build_grid([small, big], graph=True)
+    for rep in range(3):
+        bits = [R.bitstrings(9, 4, 1700 + rep), R.bitstrings(36, 2, 1800 + rep)]
+        want = ge.contract_amplitudes(bits).cpu().numpy()
+        if rep == 2:
+            gg.set_profiling(True)
+        got = gg.contract_amplitudes(bits).cpu().numpy()
+        assert np.array_equal(got, want), rep
+    prof = gg.profile_read()
+    gg.set_profiling(False)
+    assert "fused_contract" not in prof, prof
     ge.close()
     gg.close()
 

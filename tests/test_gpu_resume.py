@@ -134,3 +134,23 @@ def test_output_flags_are_checked():
     g.contract_amplitudes(bits, out=out, accumulate=True)
     assert torch.equal(out, 2 * ref)
     g.close()
+
+
+def test_resume_reads_each_circuits_own_rows():
+    """A call resumes a batch only when its bit-strings equal the kept batch's, read from the
+    circuit's own rows of the concatenated input (each circuit's rows are its own width).
+    Here circuit 0 (30 qubits, fused kernel) keeps its bit-strings between two calls and
+    circuit 1 (20 qubits, step path, whose last batch is the one kept) changes them; reading
+    circuit 1's rows at 20 bytes per earlier row would compare bytes of circuit 0 instead
+    (equal in both calls) and return the first call's amplitudes."""
+    _need_gpu()
+    _say("resume: rows of circuits of different widths")
+    c0, c1 = R.grid_rqc(6, 5, 16, 21), R.grid_rqc(4, 5, 24, 22)
+    g = build_grid([c0, c1])
+    b0 = R.bitstrings(30, 4, 2301)
+    first = g.contract_amplitudes([b0, R.bitstrings(20, 2, 2302)]).cpu().numpy()[:, 0]
+    b1 = R.bitstrings(20, 2, 2303)
+    second = g.contract_amplitudes([b0, b1]).cpu().numpy()[:, 0]
+    assert metrics.amp_errors(second[4:], E1.amplitudes(c1, b1), 20)["max"] < TOL["c64"]
+    assert np.array_equal(second[:4], first[:4])  # circuit 0: same bit-strings, same kernel
+    g.close()
