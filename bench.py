@@ -584,7 +584,8 @@ def run_precision(precision, circ, open_q, all_bits, args):
 
     def step(i):
         lo = (i * B) % len(all_bits)
-        grid.contract_amplitudes(all_bits[lo:lo + B], out=out)
+        chunk = all_bits[lo:lo + B]
+        grid.contract_amplitudes(chunk, out=out[:len(chunk)])
         return grid.last_stats()["flops"]
 
     for i in range(args.warmup):

@@ -61,6 +61,64 @@ def _options(precision="c64", plan="auto", max_tensor_elems=0, open_qubits=(),
     return o, op
 
 
+def _pack_bits(circuits, bits):
+    """Concatenated uint8 rows and their prefix offsets (bit-strings per circuit) for one
+    bit-string array per circuit, each [m, n_qubits] of that circuit (one bit-string may be
+    given as [n_qubits]).  The library reads circuit c's rows at its own width, so a
+    mis-shaped array would shift every later circuit's rows: it is rejected here."""
+    if isinstance(bits, np.ndarray) or (len(circuits) == 1 and not isinstance(bits, list)):
+        bits = [bits]
+    if len(bits) != len(circuits):
+        raise ValueError("need one bit-string array per circuit (%d circuits, %d arrays)"
+                         % (len(circuits), len(bits)))
+    rows = []
+    for i, (circ, b) in enumerate(zip(circuits, bits)):
+        b = np.asarray(b, dtype=np.uint8)
+        n = int(circ["n_qubits"])
+        if b.size == 0:
+            b = b.reshape(0, n)
+        elif b.ndim == 1 and b.size == n:
+            b = b.reshape(1, n)
+        if b.ndim != 2 or b.shape[1] != n:
+            raise ValueError("circuit %d: bit-strings must be [m, %d], got shape %s"
+                             % (i, n, tuple(b.shape)))
+        rows.append(np.ascontiguousarray(b))
+    offs = np.zeros(len(rows) + 1, dtype=np.int64)
+    for i, b in enumerate(rows):
+        offs[i + 1] = offs[i] + b.shape[0]
+    flat = np.concatenate([b.ravel() for b in rows]) if offs[-1] else np.zeros(1, np.uint8)
+    return flat, offs
+
+
+def _pack_slices(circuits, slice_ids):
+    """Concatenated slice ids and their prefix offsets, one list per circuit (a single list
+    for a one-circuit grid)."""
+    if len(circuits) == 1 and (len(slice_ids) == 0 or np.isscalar(slice_ids[0])):
+        slice_ids = [slice_ids]
+    if len(slice_ids) != len(circuits):
+        raise ValueError("need one slice list per circuit (%d circuits, %d lists)"
+                         % (len(circuits), len(slice_ids)))
+    so = np.zeros(len(slice_ids) + 1, dtype=np.int64)
+    for i, sl in enumerate(slice_ids):
+        so[i + 1] = so[i] + len(sl)
+    si = np.concatenate([np.asarray(sl, dtype=np.int64).ravel() for sl in slice_ids]) \
+        if so[-1] else np.zeros(1, np.int64)
+    return si, so
+
+
+def _check_device_array(t, shape, name):
+    """A contiguous complex128 CUDA tensor of `shape` (the library writes or reads exactly
+    that many elements at its address)."""
+    import torch
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.complex128:
+        raise ValueError("%s must be a complex128 tensor" % name)
+    if tuple(t.shape) != tuple(shape) or not t.is_contiguous():
+        raise ValueError("%s must be a contiguous tensor of shape %s, got %s"
+                         % (name, tuple(shape), tuple(t.shape)))
+    if not t.is_cuda:
+        raise ValueError("%s must be a CUDA tensor" % name)
+
+
 def _stream(stream):
     if stream is not None:
         return C.c_void_p(int(stream))
@@ -161,30 +219,20 @@ class Grid:
         if accumulate and (out is None or not device):
             raise ValueError("accumulate needs a device output tensor `out`")
         L = F.lib()
-        if isinstance(bits, np.ndarray) or (len(self.circuits) == 1 and not isinstance(bits, list)):
-            bits = [bits]
-        bits = [np.ascontiguousarray(np.asarray(b, dtype=np.uint8)) for b in bits]
-        if len(bits) != len(self.circuits):
-            raise ValueError("need one bit-string array per circuit")
-        offs = np.zeros(len(bits) + 1, dtype=np.int64)
-        for i, b in enumerate(bits):
-            offs[i + 1] = offs[i] + (b.shape[0] if b.size else 0)
-        flat = np.concatenate([b.ravel() for b in bits]) if offs[-1] else np.zeros(1, np.uint8)
+        flat, offs = _pack_bits(self.circuits, bits)
         namp = 1 << self.n_open
         sid = soff = None
         if slice_ids is not None:
-            if len(self.circuits) == 1 and (len(slice_ids) == 0 or np.isscalar(slice_ids[0])):
-                slice_ids = [slice_ids]
-            so = np.zeros(len(slice_ids) + 1, dtype=np.int64)
-            for i, s in enumerate(slice_ids):
-                so[i + 1] = so[i] + len(s)
-            si = np.concatenate([np.asarray(s, dtype=np.int64) for s in slice_ids]) \
-                if so[-1] else np.zeros(1, np.int64)
+            si, so = _pack_slices(self.circuits, slice_ids)
             sid = si.ctypes.data_as(C.POINTER(C.c_int64))
             soff = so.ctypes.data_as(C.POINTER(C.c_int64))
         total = int(offs[-1])
+        if out is not None and not device:
+            raise ValueError("out is a device tensor: it needs device=True")
         if device:
             import torch
+            if out is not None:
+                _check_device_array(out, (total, namp), "out")
             res = out if out is not None else torch.empty((total, namp), dtype=torch.complex128,
                                                           device="cuda")
             ptr = C.c_void_p(res.data_ptr())
@@ -210,25 +258,13 @@ def _contract_grad(self, bits, cotangent=None, fidelity: float = 1.0, seed: int 
     linear XEB when no cotangent is given).  ``cotangent``: dL/dRe(amp) + i dL/dIm(amp) (what
     torch autograd passes for a complex tensor), numpy or torch (CPU or CUDA)."""
     L = F.lib()
-    if isinstance(bits, np.ndarray) or (len(self.circuits) == 1 and not isinstance(bits, list)):
-        bits = [bits]
-    bits = [np.ascontiguousarray(np.asarray(b, dtype=np.uint8)) for b in bits]
-    offs = np.zeros(len(bits) + 1, dtype=np.int64)
-    for i, b in enumerate(bits):
-        offs[i + 1] = offs[i] + (b.shape[0] if b.size else 0)
-    flat = np.concatenate([b.ravel() for b in bits]) if offs[-1] else np.zeros(1, np.uint8)
+    flat, offs = _pack_bits(self.circuits, bits)
     namp = 1 << self.n_open
     total = int(offs[-1])
     sid = soff = None
     keep = []
     if slice_ids is not None:
-        if len(self.circuits) == 1 and (len(slice_ids) == 0 or np.isscalar(slice_ids[0])):
-            slice_ids = [slice_ids]
-        so = np.zeros(len(slice_ids) + 1, dtype=np.int64)
-        for i, sl in enumerate(slice_ids):
-            so[i + 1] = so[i] + len(sl)
-        si = np.concatenate([np.asarray(sl, dtype=np.int64) for sl in slice_ids]) \
-            if so[-1] else np.zeros(1, np.int64)
+        si, so = _pack_slices(self.circuits, slice_ids)
         keep += [so, si]
         sid = si.ctypes.data_as(C.POINTER(C.c_int64))
         soff = so.ctypes.data_as(C.POINTER(C.c_int64))
@@ -237,6 +273,9 @@ def _contract_grad(self, bits, cotangent=None, fidelity: float = 1.0, seed: int 
         if hasattr(cotangent, "is_cuda") and cotangent.is_cuda:
             import torch
             cotangent = cotangent.to(torch.complex128).contiguous()
+            if cotangent.numel() != total * namp:
+                raise ValueError("cotangent must hold [%d, %d] values, got shape %s"
+                                 % (total, namp, tuple(cotangent.shape)))
             keep.append(cotangent)
             cot_ptr, cot_dev = C.c_void_p(cotangent.data_ptr()), 1
         else:
@@ -409,6 +448,8 @@ def fidelity_samples(grid: Grid, closed_bits, coins, uniform_bits, order, u, fid
     closed_bits = np.ascontiguousarray(closed_bits, dtype=np.uint8)
     uniform_bits = np.ascontiguousarray(uniform_bits, dtype=np.uint8)
     coins = np.ascontiguousarray(coins, dtype=np.float64)
+    if closed_bits.ndim != 2 or closed_bits.shape[1] != int(grid.circuits[0]["n_qubits"]):
+        raise ValueError("closed_bits must be [n_batch, %d]" % int(grid.circuits[0]["n_qubits"]))
     nb, n = closed_bits.shape
     if uniform_bits.shape != (nb, n) or coins.shape != (nb,):
         raise ValueError("closed_bits, uniform_bits [n_batch, n] and coins [n_batch] must agree")

@@ -154,3 +154,30 @@ def test_resume_reads_each_circuits_own_rows():
     assert metrics.amp_errors(second[4:], E1.amplitudes(c1, b1), 20)["max"] < TOL["c64"]
     assert np.array_equal(second[:4], first[:4])  # circuit 0: same bit-strings, same kernel
     g.close()
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_heterogeneous_grid_over_calls(graph):
+    """One grid of circuits of 9, 20, 6 and 16 qubits (the 9- and 6-qubit ones on the fused
+    kernel, the others on the step path), called repeatedly with bit-string counts that
+    include 0 and with some circuits' bit-strings kept and others changed from one call to the
+    next: every call's amplitudes match the state vector, in eager and in graph mode."""
+    _need_gpu()
+    _say("heterogeneous grid over calls, graph:", graph)
+    cs = [R.grid_rqc(3, 3, 12, 31, two_qubit="fsim"), R.grid_rqc(4, 5, 24, 32),
+          R.grid_rqc(2, 3, 8, 33), R.grid_rqc(4, 4, 20, 34)]
+    g = build_grid(cs, graph=graph)
+    counts = [[3, 2, 0, 4], [3, 2, 0, 4], [0, 2, 5, 1], [3, 2, 0, 4], [3, 2, 0, 4]]
+    seeds = [[1, 2, 3, 4], [1, 5, 3, 4], [6, 7, 8, 9], [1, 7, 3, 10], [11, 7, 3, 10]]
+    for call, (cnt, sd) in enumerate(zip(counts, seeds)):
+        bits = [R.bitstrings(c["n_qubits"], m, 2400 + s) for c, m, s in zip(cs, cnt, sd)]
+        got = g.contract_amplitudes(bits).cpu().numpy()[:, 0]
+        at = 0
+        for c, b in zip(cs, bits):
+            m = len(b)
+            if m:
+                e = metrics.amp_errors(got[at:at + m], E1.amplitudes(c, b), c["n_qubits"])
+                assert e["max"] < TOL["c64"], (call, c["n_qubits"], e)
+            at += m
+        assert at == len(got)
+    g.close()

@@ -133,6 +133,10 @@ def test_fidelity_samples_match_oracle():
     sv = E1.amplitudes(c, closed, op)
     _, sv_st = S.fidelity_samples(sv, closed, op, coins, uniform, order, u, 16, 10.0, f)
     assert np.mean(np.array(sv_st) == status) >= 0.99
+    # rows of another width than the circuit's are refused before any call (the library
+    # reads n_qubits bytes per batch)
+    with pytest.raises(ValueError, match="closed_bits"):
+        fidelity_samples(g, closed[:, :15], coins, uniform[:, :15], order, u, f)
     g.close()
 
 

@@ -547,3 +547,36 @@ def test_plan_describe_reports_the_fused_fit():
     for args in ((6, 6, 16, 1), (7, 7, 40, 1)):
         f = plan_describe(R.grid_rqc(*args))["fused"]
         assert f["fits"] == 0 and "LDS" in f["why"], (args, f)
+
+
+def test_python_marshalling_rejects_misshaped_inputs():
+    """The library reads each circuit's bit-string rows at that circuit's width and writes or
+    reads exactly [total, 2^n_open] values at an output or cotangent address, so the binding
+    checks shapes before any call: one array per circuit, rows of n_qubits (one bit-string may
+    be a 1-D row), empty arrays allowed, one slice list per circuit, a complex128 contiguous
+    output of the exact shape."""
+    import torch
+
+    from paper_1811_09599_amd.qflex import _check_device_array, _pack_bits, _pack_slices
+    cs = [R.grid_rqc(2, 2, 4, 1), R.grid_rqc(2, 3, 4, 2)]
+    a, b = R.bitstrings(4, 3, 1), R.bitstrings(6, 2, 2)
+    flat, offs = _pack_bits(cs, [a, b])
+    assert list(offs) == [0, 3, 5] and flat.size == 3 * 4 + 2 * 6
+    assert np.array_equal(flat[12:], b.ravel())  # circuit 1's rows after circuit 0's, at width 6
+    flat, offs = _pack_bits(cs, [a[0], np.zeros((0,), np.uint8)])  # a 1-D row; an empty array
+    assert list(offs) == [0, 1, 1] and flat.size == 4
+    for bad in ([a], [a, a], [b, b], [a, b[:, :5]], [a.ravel(), b]):
+        with pytest.raises(ValueError):
+            _pack_bits(cs, bad)
+    si, so = _pack_slices(cs, [[3, 1], []])
+    assert list(so) == [0, 2, 2] and list(si[:2]) == [3, 1]
+    with pytest.raises(ValueError):
+        _pack_slices(cs, [[0]])
+    si, so = _pack_slices(cs[:1], [2, 0])  # one circuit: a single list
+    assert list(so) == [0, 2]
+    for t in (torch.zeros((5, 2), dtype=torch.complex64), torch.zeros((5, 1), dtype=torch.complex128),
+              torch.zeros((2, 5), dtype=torch.complex128).t()):
+        with pytest.raises(ValueError, match="complex128|shape"):
+            _check_device_array(t, (5, 2), "out")
+    with pytest.raises(ValueError, match="CUDA"):  # right shape and type, host memory
+        _check_device_array(torch.zeros((5, 2), dtype=torch.complex128), (5, 2), "out")
