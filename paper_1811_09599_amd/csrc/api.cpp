@@ -61,6 +61,13 @@ void release(qflex_grid* g) {
   g->grad_host.release();
   g->fused_prog.release();
   if (g->offs_done) (void)hipEventDestroy(g->offs_done);
+  for (int k = 0; k < 2; ++k) {
+    if (g->offs_pinned_done[k]) {
+      (void)hipEventSynchronize(g->offs_pinned_done[k]);
+      (void)hipEventDestroy(g->offs_pinned_done[k]);
+    }
+    g->offs_pinned[k].release();
+  }
   g->prof.release();
   delete g;
 }

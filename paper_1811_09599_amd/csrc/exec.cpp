@@ -636,7 +636,7 @@ std::vector<std::vector<int64_t>> prepare_call(qflex_grid* g, const uint8_t* bit
                                                const int64_t* bs_offsets, double fidelity,
                                                uint64_t seed, const int64_t* slice_ids,
                                                const int64_t* slice_offsets, const void* amps,
-                                               hipStream_t s) {
+                                               hipStream_t s, bool pinned_ok) {
   const int nc = (int)g->circ.size();
   // ---- validation (host only)
   if (!bs_offsets) fail(QFLEX_E_INVALID, "NULL argument");
@@ -672,10 +672,33 @@ std::vector<std::vector<int64_t>> prepare_call(qflex_grid* g, const uint8_t* bit
   for (int c = 0; c < nc; ++c)
     offs_base[c + 1] = offs_base[c] + (bs_offsets[c + 1] - bs_offsets[c]) * g->circ[c].model.n;
   const size_t offs_bytes = sizeof(int64_t) * std::max<int64_t>(offs_base[nc], 1);
-  if (g->offs_done) QHIP(hipEventSynchronize(g->offs_done));
-  g->offs_host.reserve(offs_bytes);
-  g->offs.reserve(offs_bytes);
-  int64_t* oh = static_cast<int64_t*>(g->offs_host.p);
+  // a call whose circuits all run the fused kernel reads the table in place from pinned host
+  // memory: each kernel reads its bit-string's entries once, and no copy precedes it
+  bool pinned = pinned_ok;
+  for (int c = 0; c < nc; ++c) pinned = pinned && g->circ[c].fused_ok && !sel[c].empty();
+  int64_t* oh = nullptr;
+  g->offs_pinned_slot = -1;
+  if (pinned) {
+    const int k = g->offs_pinned_next;
+    g->offs_pinned_next ^= 1;
+    // the call before last read this buffer: wait for its launches before rewriting it
+    if (g->offs_pinned_done[k]) QHIP(hipEventSynchronize(g->offs_pinned_done[k]));
+    else QHIP(hipEventCreateWithFlags(&g->offs_pinned_done[k], hipEventDisableTiming));
+    g->offs_pinned[k].reserve(offs_bytes);
+    if (g->offs_pinned_at[k] != g->offs_pinned[k].p) {
+      QHIP(hipHostGetDevicePointer(&g->offs_pinned_dev[k], g->offs_pinned[k].p, 0));
+      g->offs_pinned_at[k] = g->offs_pinned[k].p;
+    }
+    oh = static_cast<int64_t*>(g->offs_pinned[k].p);
+    g->offs_cur = static_cast<const int64_t*>(g->offs_pinned_dev[k]);
+    g->offs_pinned_slot = k;
+  } else {
+    if (g->offs_done) QHIP(hipEventSynchronize(g->offs_done));
+    g->offs_host.reserve(offs_bytes);
+    g->offs.reserve(offs_bytes);
+    oh = static_cast<int64_t*>(g->offs_host.p);
+    g->offs_cur = static_cast<const int64_t*>(g->offs.p);
+  }
   for (int c = 0; c < nc; ++c) {
     const CircuitState& cs = g->circ[c];
     const int n = cs.model.n;
@@ -687,9 +710,11 @@ std::vector<std::vector<int64_t>> prepare_call(qflex_grid* g, const uint8_t* bit
             sh < 0 ? 0 : (int64_t)bits[byte_off[c] + b * n + q] << sh;
     }
   }
-  QHIP(hipMemcpyAsync(g->offs.p, oh, offs_bytes, hipMemcpyHostToDevice, s));
-  if (!g->offs_done) QHIP(hipEventCreateWithFlags(&g->offs_done, hipEventDisableTiming));
-  QHIP(hipEventRecord(g->offs_done, s));
+  if (!pinned) {
+    QHIP(hipMemcpyAsync(g->offs.p, oh, offs_bytes, hipMemcpyHostToDevice, s));
+    if (!g->offs_done) QHIP(hipEventCreateWithFlags(&g->offs_done, hipEventDisableTiming));
+    QHIP(hipEventRecord(g->offs_done, s));
+  }
   return sel;
 }
 
@@ -703,17 +728,41 @@ void contract(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets, dou
     fail(QFLEX_E_INVALID, "amps_on_device must be 0, 1 or 3 (accumulating needs device output)");
   const bool amps_on_device = (out_flags & QFLEX_OUT_DEVICE) != 0;
   const bool accumulate = (out_flags & QFLEX_OUT_ACCUMULATE) != 0;
-  const std::vector<std::vector<int64_t>> sel =
-      prepare_call(g, bits, bs_offsets, fidelity, seed, slice_ids, slice_offsets, amps, s);
+  const std::vector<std::vector<int64_t>> sel = prepare_call(
+      g, bits, bs_offsets, fidelity, seed, slice_ids, slice_offsets, amps, s, true);
+  // the pinned offsets buffer this call's kernels read in place, if any: its event is
+  // recorded after them, also when a launch fails part-way
+  struct PinnedRelease {
+    qflex_grid* g;
+    hipStream_t s;
+    ~PinnedRelease() {
+      if (g->offs_pinned_slot >= 0)
+        (void)hipEventRecord(g->offs_pinned_done[g->offs_pinned_slot], s);
+      g->offs_pinned_slot = -1;
+    }
+  } pinned_release{g, s};
   qflex_stats st{};
   const int64_t tuned0 = g->n_tuned;
   std::vector<int64_t> offs_base(nc + 1, 0);
   for (int c = 0; c < nc; ++c)
     offs_base[c + 1] = offs_base[c] + (bs_offsets[c + 1] - bs_offsets[c]) * g->circ[c].model.n;
-  const int64_t* offs_dev = static_cast<const int64_t*>(g->offs.p);
+  const int64_t* offs_dev = g->offs_cur;
 
+  // every circuit runs the fused small-plan kernel (a circuit with no slice selected would
+  // launch nothing)
+  bool all_fused = true;
+  for (int c = 0; c < nc; ++c)
+    all_fused = all_fused && g->circ[c].fused_ok && !sel[c].empty();
+  // graph mode (below) captures and replays the call's launches; a call whose circuits are all
+  // fused is launched directly: one kernel per circuit and 64 slices, which a graph would not
+  // shorten (its own launch costs more than the launches it saves)
+  const bool graph = g->graph_mode && !all_fused;
+  // free device memory sizes the step path's batches of bit-strings (fused circuits take
+  // every bit-string in one launch and no arena)
   size_t free_b = 0, total_b = 0;
-  QHIP(hipMemGetInfo(&free_b, &total_b));
+  bool need_free = false;
+  for (int c = 0; c < nc; ++c) need_free = need_free || !g->circ[c].fused_ok;
+  if (need_free && g->bitstring_batch <= 0) QHIP(hipMemGetInfo(&free_b, &total_b));
   // ---- batch of bit-strings contracted together, per circuit; one arena for the largest
   std::vector<int64_t> batch(nc, 1);
   size_t arena_need = sizeof(float2);
@@ -722,6 +771,7 @@ void contract(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets, dou
     const Plan& P = g->circ[c].plan;
     const int64_t nbs = bs_offsets[c + 1] - bs_offsets[c];
     amp_total += nbs * (int64_t(1) << P.open.size());
+    if (g->circ[c].fused_ok) continue;
     int64_t B = g->bitstring_batch > 0 ? g->bitstring_batch : 0;
     if (B == 0) {
       const double per = 8.0 * (double)std::max<int64_t>(P.arena_elems, 1);
@@ -747,11 +797,14 @@ void contract(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets, dou
     cache_need = std::max(cache_need, sizeof(uint16_t) * (size_t)batch[c] *
                                           (size_t)g->circ[c].xcache_elems);
   if (cache_need) g->split_cache.reserve(cache_need);
-  // slice sums go straight into the caller's buffer when the call accumulates into it
-  if (!accumulate) g->amps64.reserve(sizeof(double2) * std::max<int64_t>(amp_total, 1));
+  // slice sums go straight into the caller's buffer when the call accumulates into it, or
+  // when it is device memory and no graph is captured (a graph keeps the grid's own buffer,
+  // so that a replay does not depend on the caller's output address)
+  const bool direct = accumulate || (amps_on_device && !graph);
+  if (!direct) g->amps64.reserve(sizeof(double2) * std::max<int64_t>(amp_total, 1));
   float2* arena = static_cast<float2*>(g->arena.p);
-  double2* acc_all = accumulate ? reinterpret_cast<double2*>(amps)
-                                : static_cast<double2*>(g->amps64.p);
+  double2* acc_all = direct ? reinterpret_cast<double2*>(amps)
+                            : static_cast<double2*>(g->amps64.p);
   // intermediates of the previous call's last batch stay usable unless a buffer moved; every
   // path below that does not finish invalidates them
   Resume& rs = g->resume;
@@ -766,17 +819,6 @@ void contract(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets, dou
     for (const CircuitState& cs : g->circ)
       if (!cs.fused_ok)  // the fused kernel has no variants to time
         for (int v : cs.tuned) tuning_pending = tuning_pending || v < 0;
-  // every circuit runs the fused small-plan kernel (a circuit with no slice selected would
-  // launch nothing)
-  bool all_fused = true;
-  for (int c = 0; c < nc; ++c)
-    all_fused = all_fused && g->circ[c].fused_ok && !sel[c].empty();
-  // ---- graph mode: every launch below depends only on the call's shape (bit-strings per
-  // circuit, their batching, the slices) and on buffer addresses, so an identical call replays
-  // the graph captured the first time; the bit-strings themselves travel in g->offs.  A call
-  // whose circuits are all fused is launched directly: one kernel per circuit and 64 slices,
-  // which a graph would not shorten (its own launch costs more than the launches it saves).
-  const bool graph = g->graph_mode && !all_fused;
   std::string key;
   bool capturing = false;
   const bool prof_was_on = g->prof.on;
@@ -1180,7 +1222,7 @@ void contract(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets, dou
     QHIP(hipStreamWaitEvent(s_user, g->graph_out, 0));
     s = s_user;
   }
-  if (amp_total > 0 && !accumulate) {
+  if (amp_total > 0 && !direct) {
     QHIP(hipMemcpyAsync(amps, acc_all, sizeof(double2) * amp_total,
                         amps_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
     if (!amps_on_device) QHIP(hipStreamSynchronize(s));

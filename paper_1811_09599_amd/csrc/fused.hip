@@ -21,6 +21,7 @@ __global__ void __launch_bounds__(kFusedThreads) fused_contract_kernel(const Fus
   extern __shared__ __attribute__((aligned(16))) float2 lds[];
   __shared__ int32_t digit[kFusedMaxCuts];
   __shared__ uint32_t changed_s;
+  __shared__ int64_t boff[kFusedMaxQubits];  // this bit-string's offset of each qubit tensor
   static_assert(sizeof(FusedStep) == 32, "step descriptors of 32 bytes");
   const int tid = threadIdx.x;
   const int64_t bs = a.b0 + blockIdx.x;  // the bit-string, within the circuit's
@@ -34,6 +35,12 @@ __global__ void __launch_bounds__(kFusedThreads) fused_contract_kernel(const Fus
     int32_t* dst = reinterpret_cast<int32_t*>(steps);
     for (int32_t i = tid; i < words; i += kFusedThreads) dst[i] = src[i];
     for (int32_t i = tid; i < p.ntab; i += kFusedThreads) tabs[i] = p.tables[i];
+    // the offsets table may live in host memory: each entry is read once (the first slice's
+    // barrier orders these writes before their use)
+    for (int32_t q = tid; q < p.nq; q += kFusedThreads) {
+      const int32_t row = p.qubits[q].out_row;
+      boff[q] = row >= 0 ? a.offs[row * a.nbs + bs] : 0;
+    }
   }
   for (int si = 0; si < a.nslices; ++si) {
     // cut values of the slice (the last cut least significant) and the cuts that changed
@@ -68,7 +75,7 @@ __global__ void __launch_bounds__(kFusedThreads) fused_contract_kernel(const Fus
           if (fresh || (Q.deps & changed)) {
             int64_t o = Q.grid_off;
             for (int c = 0; c < Q.ncut; ++c) o += (int64_t)digit[Q.cut[c]] << Q.shift[c];
-            if (Q.out_row >= 0) o += a.offs[Q.out_row * a.nbs + bs];
+            o += boff[q];
             off[j] = o;
             n[j] = 1 << Q.free_bits;
           }

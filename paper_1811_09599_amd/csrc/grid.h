@@ -173,6 +173,16 @@ struct qflex_grid {
   qflex::HostPinned offs_host;
   qflex::HostPinned grad_host;           // piece cotangents and cross-entropy sums, on the host
   hipEvent_t offs_done = nullptr;        // the last upload out of offs_host has finished
+  // offsets tables that fused kernels read in place from host memory (no upload), used in
+  // turn; each one's event is recorded after the launches of the call that read it
+  qflex::HostPinned offs_pinned[2];
+  void* offs_pinned_dev[2] = {nullptr, nullptr};   // their device addresses
+  const void* offs_pinned_at[2] = {nullptr, nullptr};  // the host buffer those belong to
+  hipEvent_t offs_pinned_done[2] = {nullptr, nullptr};
+  int offs_pinned_next = 0;
+  // the current call's offsets table (device address) and the pinned buffer it is, or -1
+  const int64_t* offs_cur = nullptr;
+  int offs_pinned_slot = -1;
   qflex_stats last{};
   qflex::Profiler prof;
   qflex::Resume resume;                  // intermediates kept from the last contract call
@@ -184,13 +194,16 @@ void build_grid_device(qflex_grid* g, hipStream_t s);
 // tensors are collapsed again (and split again for 16-bit products); plan, tuned kernels and
 // buffers stay.
 void update_gates(qflex_grid* g, int c, const qflex_circuit& circuit, hipStream_t s);
-// Host checks of a contract call, the slices each circuit sums, and the upload of the
-// per-bit-string output offsets (g->offs); everything contract() does before its launches.
+// Host checks of a contract call, the slices each circuit sums, and the per-bit-string
+// output offsets of the qubit tensors (g->offs_cur): uploaded to g->offs, or, when
+// `pinned_ok` and every circuit of the call runs the fused kernel, written into one of the
+// pinned buffers that the kernel reads in place (g->offs_pinned_slot; the caller records
+// that buffer's event after its launches).  Everything contract() does before its launches.
 std::vector<std::vector<int64_t>> prepare_call(qflex_grid* g, const uint8_t* bits,
                                                const int64_t* bs_offsets, double fidelity,
                                                uint64_t seed, const int64_t* slice_ids,
                                                const int64_t* slice_offsets, const void* amps,
-                                               hipStream_t s);
+                                               hipStream_t s, bool pinned_ok = false);
 // Autotuning: the shortest of three timed runs of `launch` after a warm-up run (profiling off;
 // the stream is synchronised), and the fastest kernel variant of a complex64 product.
 float time_launches(qflex_grid* g, hipStream_t s, const std::function<void()>& launch);

@@ -160,3 +160,27 @@ def test_fused_more_bitstrings_than_one_launch_holds():
     a = g.contract_amplitudes(bits).cpu().numpy()[:, 0]
     _check(a, E1.amplitudes(c, bits), 6)
     assert g.last_stats()["n_bitstrings"] == 70000
+
+
+def test_fused_calls_queued_back_to_back():
+    """Calls of a fused grid read their bit-strings' offsets in place from pinned host buffers
+    used in turn, each rewritten only after the launches that read it two calls earlier: 12
+    calls queued without any synchronisation (different bit-strings each, their own outputs)
+    all equal the step path's results for the same bit-strings."""
+    _need_gpu()
+    import torch
+    _say("fused: 12 queued calls")
+    c = R.grid_rqc(4, 4, 16, 1001)
+    sets = [R.bitstrings(16, 64 + 8 * i, 2600 + i) for i in range(12)]
+    gs = build_grid(c, fused="never")
+    want = [gs.contract_amplitudes(b).cpu().numpy() for b in sets]
+    g = build_grid(c, fused="require")
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        outs = [g.contract_amplitudes(b) for b in sets]
+    side.synchronize()
+    for i, (o, w) in enumerate(zip(outs, want)):
+        e = metrics.amp_errors(o.cpu().numpy(), w, 16)
+        assert e["max"] < 1e-5, (i, e)
+    gs.close()
+    g.close()
