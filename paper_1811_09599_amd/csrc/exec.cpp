@@ -1123,8 +1123,17 @@ void contract(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets, dou
                 cs.tuned[k] = choice;
                 if (choice >= 0) tune_cache_put(tkey, choice);
               }
-              if (choice >= 0) run_split(choice & 1, (choice >> 1) & 1, choice >> 2, true);
-              else run_split(cs.gather_x[k] != 0, cs.gather_y[k] != 0, -1, true);
+              if (choice >= 0) {
+                run_split(choice & 1, (choice >> 1) & 1, choice >> 2, true);
+              } else {
+                // shape rules: a gathered operand is read again for every output tile along
+                // the other dimension and split while staging; from 8192 rows (columns) on,
+                // splitting it once and reading the compact layout costs less (32768^3: the
+                // 3-multiplication 256x128 tile 515-518 against 545-547 ms per launch gathered,
+                // the split pass of 2^30 elements about 3 ms; at 4096 the two are about even)
+                run_split(cs.gather_x[k] != 0 && N < 8192, cs.gather_y[k] != 0 && M < 8192, -1,
+                          true);
+              }
               continue;
             }
             const bool gather_x = !cs.gather_x.empty() && cs.gather_x[k];

@@ -76,8 +76,16 @@ def test_d32_rqc_split_agrees_with_c64_on_a_slice():
     res = {}
     for p in ("c64", "split_bf16", "split_fp16"):
         g = build_grid(c, open_qubits=OPEN7, precision=p)
+        g.set_profiling(True)
         res[p] = g.contract_amplitudes(bits, slice_ids=[300]).cpu().numpy()
+        prof = g.profile_read()
         g.close()
+        if p != "c64":
+            # AB.D (32768^3): its column operand D is split once and read in the compact
+            # layout, not read from complex64 storage by every row tile (the shape rules)
+            fmt = p.split("_")[1]
+            assert prof["gemm_split3m_%s_256x128" % fmt]["launches"] >= 1, prof.keys()
+            assert not any("gatherb" in k and "256x128" in k for k in prof), prof.keys()
     e = metrics.amp_errors(res["split_bf16"], res["c64"], 49)
     _say("  split-bf16 vs c64", e)
     assert e["max"] < SPLIT_TOL_D32
