@@ -422,6 +422,20 @@ def main():
     }
     if head == "c64":
         res["tflops_frac_fp32_mfma_peak"] = r["tflops"] / PEAK["mfma_fp32"][0]
+    # the paper's CPU clusters, as context only (Results; table of effective runtimes of one
+    # perfect-fidelity amplitude): a different machine and a different unit of work
+    res["paper_context"] = {
+        "clusters_peak_tflops_fp32": 20000.0,
+        "clusters_peak_note": "NASA Pleiades + Electra combined, single precision, 64% of their "
+                              "achievable peak",
+        "this_gpu_tflops_over_clusters_peak": r["tflops"] / 20000.0,
+        "perfect_fidelity_amplitude_7x7_d40_s": {"pleiades": 1.22e-2 * 3600,
+                                                 "electra": 1.16e-2 * 3600},
+        "this_gpu_all_1024_slices_s_estimate": {
+            p: 1024.0 * results[p]["ms_per_step"] / 1e3 for p in precs},
+        "note": "estimate = 1024 slices x this run's ms per step (a slice of one 64-amplitude "
+                "batch, slice-independent intermediates kept); not measured end to end",
+    }
     for p in precs:
         if p != "c64" and "c64" in results:
             res["precisions"][p]["speedup_vs_c64"] = results[p]["value"] / results["c64"]["value"]
