@@ -389,6 +389,28 @@ void contract_grad(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets
               g1.force_variant = cs.tuned_grad[3 * kk + 1];
               if (g1.force_variant < 0 && g->autotune)
                 g1.force_variant = cs.tuned_grad[3 * kk + 1] = tune_gemm(g, s, g1);
+              // Xbar of an intermediate x goes straight to x's cotangent in x's storage order
+              // when its product runs on an MFMA tile (the tile writes through the bit-deposit
+              // maps of that order; x is consumed by this step only, so nothing else writes
+              // there): no scratch copy, no routing pass
+              const bool xbar_direct =
+                  !stp.x.qubit && dev::gemm_scatter_variant(dev::gemm_variant(g1));
+              if (xbar_direct) {
+                g1.scatter = true;
+                g1.ws = nullptr;
+                g1.ws_elems = 0;
+                g1.C = ar + coff[stp.x.id] * B;
+                g1.c_bs = P.nodes[stp.x.id].elems();
+                // output (m, k): bit i of k and of m go where dx[kk] puts product-order bits
+                // i and kb + i of cat(mlab, klab)
+                const PermDesc& d = dx[kk];
+                std::vector<int> dest(d.nbits, -1);
+                for (int j = 0; j < d.nbits; ++j) dest[d.perm[j]] = j;
+                g1.om.nn = stp.kb;
+                g1.om.nm = stp.mb;
+                for (int i = 0; i < stp.kb; ++i) g1.om.npos[i] = (int8_t)dest[i];
+                for (int i = 0; i < stp.mb; ++i) g1.om.mpos[i] = (int8_t)dest[stp.kb + i];
+              }
               g->prof.begin(dev::gemm_name(g1), stp.flops() * nb,
                             8.0 * nb * (double)(g1.M * g1.K + g1.K * g1.N + g1.M * g1.N), s);
               dev::gemm(g1, s);
@@ -429,7 +451,7 @@ void contract_grad(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets
               g->prof.end(s);
               st.flops += 2.0 * stp.flops() * nb;
               st.n_gemm += 2;
-              route(stp.x, xbar, dx[kk], rx[kk]);
+              if (!xbar_direct) route(stp.x, xbar, dx[kk], rx[kk]);
               route(stp.y, ybar, dy[kk], ry[kk]);
             }
           }

@@ -27,7 +27,10 @@ namespace dev {
 // its FP32 rounding error is about 1.7 times that of the 4-multiplication form on random data.
 // =============================================================================================
 
-template <bool TA, bool TB, int BM, int BN, int WM = 2, int WN = 2, bool G3 = false>
+// SC: C written through g.om (a separate instantiation, so that the plain epilogue compiles as
+// it would alone)
+template <bool TA, bool TB, int BM, int BN, int WM = 2, int WN = 2, bool G3 = false,
+          bool SC = false>
 __global__ void __launch_bounds__(64 * WM * WN) gemm_mfma_kernel(const Gemm g) {
   constexpr int NT = 64 * WM * WN;
   constexpr int BK = 16, LDK = BK + 2;
@@ -233,6 +236,36 @@ __global__ void __launch_bounds__(64 * WM * WN) gemm_mfma_kernel(const Gemm g) {
     __syncthreads();
   }
   // D layout of the 32x32 instruction: lane -> column r, register v -> row 8*(v/4)+4*h+(v%4)
+  if constexpr (SC) {
+    // C through its bit-deposit maps: the tile's row and column offsets, computed once into
+    // the LDS that the k loop no longer reads (its last barrier has passed)
+    int32_t* roff = reinterpret_cast<int32_t*>(&As[0][0]);
+    int32_t* coff = roff + BM;
+    for (int t = tid; t < BM + BN; t += NT) {
+      const bool row = t < BM;
+      const int64_t v = row ? m0 + t : n0 + (t - BM);
+      const int8_t* pos = row ? g.om.mpos : g.om.npos;
+      const int nb = row ? g.om.nm : g.om.nn;
+      int32_t o = 0;
+      for (int i = 0; i < nb; ++i) o |= (int32_t)((v >> i) & 1) << pos[i];
+      if (row) roff[t] = o;
+      else coff[t - BM] = o;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < TMI; ++i)
+#pragma unroll
+      for (int j = 0; j < TNI; ++j)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+          const int row = wm * WTM + i * 32 + 8 * (v >> 2) + 4 * h + (v & 3);
+          const int col = wn * WTN + j * 32 + r;
+          float re = cr[i][j][v], im = ci[i][j][v];
+          if constexpr (G3) re = cr[i][j][v] - ci[i][j][v], im = c3[i][j][v] - cr[i][j][v] - ci[i][j][v];
+          C[roff[row] + coff[col]] = make_float2(re, im);
+        }
+    return;
+  }
 #pragma unroll
   for (int i = 0; i < TMI; ++i)
 #pragma unroll
@@ -905,6 +938,30 @@ static void gemm_t(const Gemm& g, hipStream_t s) {
   } else if (v == 7) {
     dim3 grid((unsigned)(g.N / 64), (unsigned)g.batch, z);
     hipLaunchKernelGGL((gemm_reduce_mfma_kernel<TA>), grid, dim3(256), 0, s, g);
+  } else if (gemm_scatter_variant(v) && g.scatter) {
+    // the output-mapped tiles, instantiated for A stored [M][K] only (an operand cotangent
+    // Xbar = Zbar Y^T)
+    if constexpr (TA) {
+      throw std::runtime_error("gemm: an output map needs A stored [M][K]");
+    } else {
+      const int bm = v == 6 || v == 9 ? 256 : v == 1 ? 64 : 128, bn = v == 1 ? 64 : 128;
+      dim3 grid((unsigned)((g.M / bm) * (g.N / bn)), (unsigned)g.batch, z);
+      if (v == 6)
+        hipLaunchKernelGGL((gemm_mfma_kernel<false, TB, 256, 128, 4, 2, false, true>), grid,
+                           dim3(512), 0, s, g);
+      else if (v == 9)
+        hipLaunchKernelGGL((gemm_mfma_kernel<false, TB, 256, 128, 4, 2, true, true>), grid,
+                           dim3(512), 0, s, g);
+      else if (v == 10)
+        hipLaunchKernelGGL((gemm_mfma_kernel<false, TB, 128, 128, 2, 2, true, true>), grid,
+                           dim3(256), 0, s, g);
+      else if (v == 2)
+        hipLaunchKernelGGL((gemm_mfma_kernel<false, TB, 128, 128, 2, 2, false, true>), grid,
+                           dim3(256), 0, s, g);
+      else
+        hipLaunchKernelGGL((gemm_mfma_kernel<false, TB, 64, 64, 2, 2, false, true>), grid,
+                           dim3(256), 0, s, g);
+    }
   } else if (v == 6) {
     dim3 grid((unsigned)((g.M / 256) * (g.N / 128)), (unsigned)g.batch, z);
     hipLaunchKernelGGL((gemm_mfma_kernel<TA, TB, 256, 128, 4, 2>), grid, dim3(512), 0, s, g);
@@ -973,8 +1030,26 @@ static void gemm_t(const Gemm& g, hipStream_t s) {
   check_launch("gemm");
 }
 
+bool gemm_scatter_variant(int v) { return v == 1 || v == 2 || v == 6 || v == 9 || v == 10; }
+
 void gemm(const Gemm& g0, hipStream_t s) {
   if (g0.batch < 1 || g0.batch > 65535) throw std::runtime_error("gemm: bad batch");
+  if (g0.scatter) {  // C through its bit-deposit maps, on the MFMA tiles only
+    if (g0.gather || g0.ta || !gemm_scatter_variant(gemm_variant(g0)))
+      throw std::runtime_error("gemm: an output map needs an MFMA tile and A stored [M][K]");
+    const int nb = g0.om.nm + g0.om.nn;
+    if (g0.om.nm < 0 || g0.om.nn < 0 || nb > 31 || (int64_t(1) << g0.om.nm) != g0.M ||
+        (int64_t(1) << g0.om.nn) != g0.N || int64_t(1) << nb > g0.c_bs)
+      throw std::runtime_error("gemm: output map does not match the shape");
+    // every offset below 2^nb <= c_bs: the positions are a permutation of 0 .. nb - 1
+    uint32_t seen = 0;
+    for (int i = 0; i < nb; ++i) {
+      const int p = i < g0.om.nm ? g0.om.mpos[i] : g0.om.npos[i - g0.om.nm];
+      if (p < 0 || p >= nb || (seen >> p) & 1)
+        throw std::runtime_error("gemm: output map positions are not a permutation");
+      seen |= 1u << p;
+    }
+  }
   if (g0.gather) {  // A read through its gather descriptor, on the MFMA rows kernel only
     if (g0.force_variant != 8 || !gemm_variant_fits(g0, 8))
       throw std::runtime_error("gemm: a gathered A needs the MFMA rows kernel");
@@ -991,7 +1066,7 @@ void gemm(const Gemm& g0, hipStream_t s) {
   }
   g.split = 1;
   g.a_ks = g.b_ks = 0;
-  if (g0.ws) {
+  if (g0.ws && !g0.scatter) {
     const int split = gemm_splitk(g0);
     if (split > 1 && (int64_t)split * g0.batch * g0.M * g0.N <= g0.ws_elems) {
       const int64_t chunk = g0.K / split;

@@ -70,6 +70,13 @@ int32_t gather_runs(const int8_t* pos, int first, int n, int32_t* runs);
 // C[b] = op(A[b]) * op(B[b]); A stored [M][K] (ta=0) or [K][M] (ta=1) with row stride lda,
 // B stored [K][N] (tb=0) or [N][K] (tb=1) with row stride ldb, C stored [M][N].
 // Batch element b starts at A + (a_off ? a_off[b] : b*a_bs) (same for B); C + b*c_bs.
+// An output stored through bit-deposit maps: element (m, n) at f(m) + g(n), where f puts bit i
+// of m at position mpos[i] and g bit i of n at npos[i] (one storage order of the output's
+// binary labels: the positions are a permutation of 0 .. nm + nn - 1)
+struct OutMap {
+  int32_t nm = 0, nn = 0;
+  int8_t mpos[32] = {}, npos[32] = {};
+};
 struct Gemm {
   const float2* A = nullptr;
   const float2* B = nullptr;
@@ -99,7 +106,12 @@ struct Gemm {
   // force_variant = 8 only, ta = 0, no split-K
   bool gather = false;
   SplitGather ga;
+  // C written through om (the complex64 MFMA tiles only: variants 1, 2, 6, 9 and 10, and no
+  // split-K): element (m, n) of batch element b at C + b * c_bs + f(m) + g(n); ldc unused
+  bool scatter = false;
+  OutMap om;
 };
+bool gemm_scatter_variant(int v);  // variant v can write through an OutMap
 // which kernel gemm() would pick: 0 = SIMT, 1 = MFMA 64x64 tile, 2 = MFMA 128x128 tile,
 // 3 = rows, 4 = reduction-shaped, 5 = short K, 6 = MFMA 256x128 tile, 7 = reduction-shaped
 // on MFMA, 8 = rows on MFMA, 9 / 10 = the 256x128 / 128x128 MFMA tiles in the
