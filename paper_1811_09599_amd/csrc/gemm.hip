@@ -527,8 +527,8 @@ __global__ void __launch_bounds__(256) gemm_reduce_kernel(const Gemm g) {
 // Products with a short K (K < 16) and N >= 32 columns, which write far more than they read:
 // each thread owns one output column of a 256-column tile and a set of rows, keeps its
 // column of B (K values) in registers, and reads each row of A from LDS (broadcast); the
-// stores are coalesced along the row.
-template <int KB, bool TA, bool TB>
+// stores are coalesced along the row.  SC: C written through g.om (see gemm_mfma_kernel).
+template <int KB, bool TA, bool TB, bool SC = false>
 __global__ void __launch_bounds__(256) gemm_smallk_kernel(const Gemm g) {
   constexpr int BM = 64;
   __shared__ float2 As[BM][KB];
@@ -554,6 +554,19 @@ __global__ void __launch_bounds__(256) gemm_smallk_kernel(const Gemm g) {
     if (m0 + r < g.M && k < K) v = TA ? A[(int64_t)k * g.lda + m0 + r] : A[(m0 + r) * g.lda + k];
     As[r][k] = v;
   }
+  // output through the bit-deposit maps: the tile's row offsets in LDS, this thread's column
+  // offset in a register
+  __shared__ int32_t roff[SC ? BM : 1];
+  int32_t coff = 0;
+  if constexpr (SC) {
+    auto dep = [](int64_t v, const int8_t* pos, int nb) {
+      int32_t o = 0;
+      for (int i = 0; i < nb; ++i) o |= (int32_t)((v >> i) & 1) << pos[i];
+      return o;
+    };
+    if (tid < BM) roff[tid] = dep(m0 + tid, g.om.mpos, g.om.nm);
+    coff = dep(n0 + col_in, g.om.npos, g.om.nn);
+  }
   __syncthreads();
   for (int r = rsub; r < BM; r += nrs) {
     if (m0 + r >= g.M) break;
@@ -566,7 +579,8 @@ __global__ void __launch_bounds__(256) gemm_smallk_kernel(const Gemm g) {
       im = fmaf(a.x, w[k].y, im);
       im = fmaf(a.y, w[k].x, im);
     }
-    C[(m0 + r) * g.ldc + n0 + col_in] = make_float2(re, im);
+    if constexpr (SC) C[roff[r] + coff] = make_float2(re, im);
+    else C[(m0 + r) * g.ldc + n0 + col_in] = make_float2(re, im);
   }
 }
 
@@ -943,6 +957,14 @@ static void gemm_t(const Gemm& g, hipStream_t s) {
     // Xbar = Zbar Y^T)
     if constexpr (TA) {
       throw std::runtime_error("gemm: an output map needs A stored [M][K]");
+    } else if (v == 5) {
+      dim3 grid((unsigned)(((g.M + 63) / 64) * (g.N / std::min<int64_t>(g.N, 256))),
+                (unsigned)g.batch);
+      auto sk = [&](auto kern) { hipLaunchKernelGGL(kern, grid, dim3(256), 0, s, g); };
+      if (g.K > 4) sk(gemm_smallk_kernel<8, false, TB, true>);
+      else if (g.K > 2) sk(gemm_smallk_kernel<4, false, TB, true>);
+      else if (g.K > 1) sk(gemm_smallk_kernel<2, false, TB, true>);
+      else sk(gemm_smallk_kernel<1, false, TB, true>);
     } else {
       const int bm = v == 6 || v == 9 ? 256 : v == 1 ? 64 : 128, bn = v == 1 ? 64 : 128;
       dim3 grid((unsigned)((g.M / bm) * (g.N / bn)), (unsigned)g.batch, z);
@@ -1030,7 +1052,9 @@ static void gemm_t(const Gemm& g, hipStream_t s) {
   check_launch("gemm");
 }
 
-bool gemm_scatter_variant(int v) { return v == 1 || v == 2 || v == 6 || v == 9 || v == 10; }
+bool gemm_scatter_variant(int v) {
+  return v == 1 || v == 2 || v == 5 || v == 6 || v == 9 || v == 10;
+}
 
 void gemm(const Gemm& g0, hipStream_t s) {
   if (g0.batch < 1 || g0.batch > 65535) throw std::runtime_error("gemm: bad batch");

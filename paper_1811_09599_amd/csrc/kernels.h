@@ -106,8 +106,9 @@ struct Gemm {
   // force_variant = 8 only, ta = 0, no split-K
   bool gather = false;
   SplitGather ga;
-  // C written through om (the complex64 MFMA tiles only: variants 1, 2, 6, 9 and 10, and no
-  // split-K): element (m, n) of batch element b at C + b * c_bs + f(m) + g(n); ldc unused
+  // C written through om (the complex64 MFMA tiles and the short-K kernel: variants 1, 2, 5,
+  // 6, 9 and 10, with A stored [M][K] and no split-K): element (m, n) of batch element b at
+  // C + b * c_bs + f(m) + g(n); ldc unused
   bool scatter = false;
   OutMap om;
 };
