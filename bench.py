@@ -60,7 +60,7 @@ def flop_peak(name):
         return "mfma", PEAK["mfma_bf16"][0]
     if name.startswith(("gemm_split_fp16", "gemm_split3m_fp16")):
         return "mfma", PEAK["mfma_fp16"][0]
-    if name.startswith("gemm_mfma"):
+    if name.startswith(("gemm_mfma", "gemm_rows_mfma", "gemm_reduce_mfma")):
         return "mfma", PEAK["mfma_fp32"][0]
     if name.startswith("gemm_"):  # SIMT, rows, reduce and short-K products: FP32 vector ALU
         return "alu", PEAK["alu"][0]
