@@ -86,6 +86,37 @@ def test_uneven_circuits_in_one_call():
         assert abs(res["loss"][i] - f_ref) < 1e-4 * max(1.0, abs(f_ref)), i
 
 
+def test_uneven_circuits_with_several_slices():
+    """Circuits of 16, 12 and 9 qubits in one grid, each summing its own subset of several
+    slices (the amplitudes first, through the contraction path of each circuit: the 9-qubit one
+    on the fused kernel; then one reverse sweep per slice), an open qubit and a given
+    cotangent: every circuit's angle gradients and amplitudes against the FP64 network's."""
+    _need_gpu()
+    _say("uneven circuits, several slices each")
+    cs = [R.grid_rqc(4, 4, 12, 31, two_qubit="fsim", jitter_sd=0.02, jitter_seed=31),
+          R.grid_rqc(3, 4, 12, 32, two_qubit="fsim", jitter_sd=0.02, jitter_seed=32),
+          R.grid_rqc(3, 3, 12, 33, two_qubit="fsim", jitter_sd=0.02, jitter_seed=33)]
+    op = [0]
+    bits = [R.bitstrings(c["n_qubits"], m, 3100 + i, op) for i, (c, m) in enumerate(zip(cs, (3, 4, 2)))]
+    g = build_grid(cs, plan="quadrant", open_qubits=op)
+    ids = [[0, 7, 100, 255], [1, 9, 15], [3, 128]]
+    assert [g.num_slices(i) for i in range(3)] == [256, 16, 256]
+    rng = np.random.default_rng(31)
+    cot = rng.standard_normal((9, 2)) + 1j * rng.standard_normal((9, 2))
+    res = g.contract_grad(bits, cotangent=cot, slice_ids=ids)
+    at = 0
+    for i, c in enumerate(cs):
+        m = len(bits[i])
+        cuts = g.plan_cuts(i)
+        ref = E2.amplitude_gate_grads(c, bits[i], cot[at:at + m], op, cuts, ids[i])
+        got = res["grad_params"][i][_fsim_rows(c)]
+        assert metrics.rel_l2(got, ref) < GTOL, i
+        amp_ref = E2.amplitudes(c, bits[i], op, cuts=cuts, slice_ids=ids[i])
+        assert metrics.amp_errors(res["amps"][at:at + m], amp_ref, c["n_qubits"])["max"] < 1e-5, i
+        at += m
+    g.close()
+
+
 @pytest.mark.parametrize("one_slice", [False, True])
 def test_gradient_with_open_batch_and_fidelity_subset(one_slice):
     """Several slices (amplitudes first, then one reverse sweep per slice) and a single slice
