@@ -43,8 +43,6 @@ std::vector<int> cat(std::vector<int> a, const std::vector<int>& b) {
   return a;
 }
 
-int64_t pad64(int64_t e) { return (e + 63) & ~int64_t(63); }
-
 }  // namespace
 
 void contract_grad(qflex_grid* g, const uint8_t* bits, const int64_t* bs_offsets,
