@@ -398,3 +398,21 @@ def test_split_low_fidelity_subset_matches_oracle_subset(mode):
     ref = E2.amplitudes(c, bits, op, cuts=g.plan_cuts(), slice_ids=ids)
     e = _check(a, ref, 20, SPLIT_TOL["split_bf16"])
     _say("  error", e)
+
+
+@pytest.mark.parametrize("prec", ["c64", "split_bf16"])
+def test_degenerate_one_and_two_qubit_grids(prec):
+    """The smallest grids: one qubit (no product at all: the amplitude is the collapsed qubit
+    tensor itself) and two qubits in a row or a column (one product), with every qubit closed
+    or open, against the state vector."""
+    _need_gpu()
+    _say("1x1, 1x2, 2x1 grids,", prec)
+    for rows, cols in ((1, 1), (1, 2), (2, 1)):
+        c = R.grid_rqc(rows, cols, 4, 70 + 10 * rows + cols)
+        n = c["n_qubits"]
+        for op in ([], [0], list(range(n))):
+            bits = R.bitstrings(n, 3, 90 + len(op), op)
+            g = build_grid(c, open_qubits=op, precision=prec)
+            a = g.contract_amplitudes(bits).cpu().numpy()
+            g.close()
+            _check(a, E1.amplitudes(c, bits, op), n, SPLIT_TOL.get(prec, TOL))
