@@ -302,3 +302,50 @@ def test_autograd_function_reuses_its_grid_across_angles():
         f_ref, g_ref = E1.linear_xeb_grad(with_fsim_angles(c, p), bits)
         assert abs(float(f.detach()) - f_ref) < 1e-4
         assert metrics.rel_l2(a.grad.numpy(), g_ref) < GTOL
+
+
+def _closed_expansion(bits, cot, op):
+    """The open-batch amplitudes psi[b, i] as closed bit-strings: row b with the open qubits
+    set to the big-endian digits of i, and the conjugated cotangent flattened the same way."""
+    rows = []
+    for b in range(len(bits)):
+        for i in range(1 << len(op)):
+            r = bits[b].copy()
+            for j, q in enumerate(op):
+                r[q] = (i >> (len(op) - 1 - j)) & 1
+            rows.append(r)
+    return np.array(rows, dtype=np.uint8), np.conj(cot).reshape(-1)
+
+
+def test_degenerate_one_and_two_qubit_grid_gradients():
+    """The adjoint on the smallest grids: one qubit (the result is the qubit tensor itself, its
+    cotangent routed straight back into the gates) and two qubits in a row or a column (one
+    product between two qubit tensors), closed and with open qubits, under a given cotangent:
+    every gate's entry gradient and every fSim angle gradient against the state-vector
+    adjoint."""
+    _need_gpu()
+    for rows, cols in ((1, 1), (1, 2), (2, 1)):
+        c = R.grid_rqc(rows, cols, 8, 170 + 10 * rows + cols, two_qubit="fsim", jitter_sd=0.05,
+                       jitter_seed=4)
+        n = c["n_qubits"]
+        for op in [[], [n - 1]] + ([list(range(n))] if n > 1 else []):
+            _say("grad", rows, cols, "open", op)
+            bits = R.bitstrings(n, 5, 40 + len(op), op)
+            rng = np.random.default_rng(2 + len(op))
+            cot = (rng.standard_normal((5, 1 << len(op)))
+                   + 1j * rng.standard_normal((5, 1 << len(op))))
+            g = build_grid(c, open_qubits=op)
+            res = g.contract_grad(bits, cotangent=cot)
+            g.close()
+            full, w = _closed_expansion(bits, cot, op)
+            amp = E1.amplitudes(c, full).reshape(5, 1 << len(op))
+            assert metrics.amp_errors(res["amps"], amp, n)["max"] < 1e-5
+            dgate = E1.vjp_gates(c, full, w)
+            for i, gt in enumerate(c["gates"]):
+                if gt["kind"] != "cz":
+                    assert metrics.rel_l2(np.conj(res["grad_gates"][0][i]), dgate[i]) < GTOL, i
+            fs = _fsim_rows(c)
+            if fs:
+                dth, dph, _ = E1.vjp_params(c, full, w)
+                ref = np.stack([dth.real, dph.real], axis=1)
+                assert metrics.rel_l2(res["grad_params"][0][fs], ref) < GTOL
